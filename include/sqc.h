@@ -1,0 +1,325 @@
+/*
+ * sqc.h -- cut-circuit reconstruction on one AMD Instinct MI355X (gfx950).
+ *
+ * C interface of libsqc.  The library reconstructs the output distribution of
+ * a quantum circuit that was cut into subcircuits (ScaleQC, arXiv 2207.00933)
+ * from the measured outputs of the subcircuit variants:
+ *
+ *   attribution  (Sec. 2.1, Eq. 1 and Fig. 1): variant probabilities ->
+ *                per-subcircuit entries T_i[sigma, x] for every I/X/Y/Z label
+ *                assignment sigma of the subcircuit's cuts;
+ *   merging      (Sec. 4, Algorithm 2): sum the entries of the data states that
+ *                fall into one bin;
+ *   contraction  (Sec. 6.1-6.2): contract the compute graph -- a tensor network
+ *                whose cut indices have dimension 4 -- into the 2^a bin vector;
+ *   recursion    (Sec. 3, Algorithm 1): bin assignment, merge, contraction,
+ *                top-R bins and the bin-sum invariant for one states-merging
+ *                recursion, and the whole search loop.
+ *
+ * Conventions used by every call
+ * ------------------------------
+ * Subcircuit i has n_wires wires; wire t is bit t of its measured outcome
+ * index.  Every wire ends either in a circuit output (a data wire, listed in
+ * data_wire[]) or in an out-cut (measured into a cut).  Data bit j of the
+ * subcircuit is wire data_wire[j].
+ *
+ * A cut joins wire up_wire of subcircuit up_sub (measured) to wire down_wire
+ * of subcircuit down_sub (initialised).  The cuts incident to a subcircuit are
+ * taken in the order of the cuts[] array; the first incident cut is the least
+ * significant digit of:
+ *   - the variant index: radix 4 for in-cuts (preparations |0>,|1>,|+>,|+i>
+ *     numbered 0..3) and radix 3 for out-cuts (measurement bases Z, X, Y
+ *     numbered 0..2; outcome bit 0 is the +1 eigenvalue);
+ *   - the label index sigma: radix 4, labels I, X, Y, Z numbered 0..3.
+ *
+ * Reconstructed bins are indexed subcircuit-major: subcircuit 0's active bits
+ * are the least significant, and within a subcircuit active data bits keep
+ * their ascending order.  Mapping to original qubit order is the caller's
+ * (each data bit's qubit is known to it).
+ *
+ * The normalisation 2^-K of the K-cut sum is folded into attribution as a
+ * factor 1/2 per out-cut of each subcircuit (exact in floating point).
+ *
+ * Ownership and asynchrony
+ * ------------------------
+ * Every device buffer is allocated by the caller (the Python binding uses
+ * PyTorch's allocator).  Device pointers are plain addresses on the context's
+ * device.  Calls validate their arguments synchronously on the host; on any
+ * error nothing is enqueued, outputs are untouched, and a message is kept for
+ * sqc_last_error().  Calls that launch kernels enqueue them on the context's
+ * stream and return without waiting, unless documented otherwise.  No call
+ * keeps a caller pointer after it returns, except the context's workspace.
+ * A context is used by one host thread at a time; distinct contexts are
+ * independent.
+ */
+#ifndef SQC_H
+#define SQC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SQC_OK = 0,
+  SQC_E_ARG = 1,         /* null pointer, bad enum value, bad count          */
+  SQC_E_SHAPE = 2,       /* inconsistent graph or tensor shape; degree > 15  */
+  SQC_E_NOMEM = 3,       /* workspace or buffer too small for the request    */
+  SQC_E_DEVICE = 4,      /* HIP runtime error, or no usable GPU              */
+  SQC_E_NUMERIC = 5,     /* non-finite value found by an opt-in check        */
+  SQC_E_BUSY = 6,        /* serving engine: no free slot for a request       */
+  SQC_E_UNSUPPORTED = 7  /* valid input outside this build's limits          */
+} sqc_status;
+
+typedef enum {
+  SQC_F64 = 0,     /* IEEE binary64                                         */
+  SQC_F32 = 1,     /* IEEE binary32; as a contraction precision: FP32 MFMA  */
+  SQC_BF16X3 = 2   /* contraction only: each FP32 operand split into bf16
+                      hi + lo, three bf16 MFMA products (hi*hi + hi*lo +
+                      lo*hi) accumulated in FP32                            */
+} sqc_prec;
+
+/* Largest compute-graph degree (cuts on one subcircuit), Sec. 6.2. */
+#define SQC_MAX_DEGREE 15
+/* Largest number of data bits of one subcircuit. */
+#define SQC_MAX_DATA_BITS 62
+/* Largest top-R of one recursion. */
+#define SQC_MAX_TOPR 64
+
+typedef struct {
+  int32_t up_sub, up_wire;      /* measured side (upstream)                 */
+  int32_t down_sub, down_wire;  /* initialised side (downstream)            */
+} sqc_cut;
+
+typedef struct {
+  int32_t n_wires;              /* wires of the subcircuit (<= 32)          */
+  int32_t n_data;               /* wires that end in a circuit output       */
+  const int32_t *data_wire;     /* n_data wire indices; data bit j = wire   */
+} sqc_sub;
+
+/* Bit masks over one subcircuit's data bits (bit j = data bit j).  fixed,
+ * active and merged are disjoint and cover all data bits; fixed_val holds the
+ * values of the fixed bits (zero elsewhere).  A bin is the set of data states
+ * with x & fixed == fixed_val and a given value of the active bits. */
+typedef struct {
+  uint64_t fixed, fixed_val, active, merged;
+} sqc_masks;
+
+/* Tensor layouts. */
+#define SQC_LAYOUT_ATTRIBUTED 0 /* [2^n_bits][4^n_labels]: element (sigma, x)
+                                   at x * 4^n_labels + sigma                */
+#define SQC_LAYOUT_MERGED 1     /* [4^n_labels][2^n_bits]: element (sigma, b)
+                                   at sigma * 2^n_bits + b                  */
+
+typedef struct {
+  void *data;          /* device buffer owned by the caller                 */
+  int32_t n_labels;    /* c_i: incident cuts                                */
+  int32_t n_bits;      /* data bits (attributed) or active bits (merged)    */
+  sqc_prec prec;       /* storage: SQC_F64 or SQC_F32                       */
+  int32_t layout;      /* SQC_LAYOUT_*                                      */
+} sqc_tensor;
+
+typedef struct sqc_ctx sqc_ctx;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` using `hip_stream` (a hipStream_t,
+ * NULL = the default stream).  Fails with SQC_E_DEVICE when no GPU is usable. */
+sqc_status sqc_ctx_create(int device, void *hip_stream, sqc_ctx **out);
+sqc_status sqc_ctx_destroy(sqc_ctx *ctx);
+/* Replace the stream later calls enqueue on. */
+sqc_status sqc_ctx_set_stream(sqc_ctx *ctx, void *hip_stream);
+/* Give the context a caller-owned device workspace used by merge, contract,
+ * recurse and search for intermediates and scratch.  The context keeps the
+ * pointer until it is replaced or the context is destroyed; the caller must
+ * keep the buffer alive that long.  The buffer is initialised on the stream. */
+sqc_status sqc_ctx_set_workspace(sqc_ctx *ctx, void *dev, size_t bytes);
+/* Message describing the last error of this context (or of the calling
+ * thread's last context-less call when ctx is NULL).  Never NULL. */
+const char *sqc_last_error(const sqc_ctx *ctx);
+/* Library version string. */
+const char *sqc_version(void);
+
+/* ---- host-only helpers (no GPU needed) ------------------------------------ */
+
+/* Validate a compute graph: cut ids and wires in range, every wire is either a
+ * data wire or measured into exactly one cut, at most one cut initialises a
+ * wire, no cut joins a subcircuit to itself, degree <= SQC_MAX_DEGREE. */
+sqc_status sqc_check_graph(const sqc_sub *subs, int32_t n_sub,
+                           const sqc_cut *cuts, int32_t n_cuts);
+
+/* Algorithm 2 (states assignment) as masks.  `scope` gives, per subcircuit,
+ * the states under analysis as fixed / fixed_val (NULL: recursion 0, nothing
+ * fixed).  Each subcircuit starts with l_i = 2^(unfixed bits) bins; while the
+ * product exceeds M, the largest l'_i (lowest index on ties) is halved.  The
+ * resulting per-subcircuit masks keep the scope's fixed bits, make the lowest
+ * log2(l'_i) unfixed bits active and the remaining unfixed bits merged (the
+ * bins of the printed rule "state j goes to bin j mod l'_i" over states in
+ * ascending order).  `n_data[i]` is d_i.  Writes n_sub masks to `out`. */
+sqc_status sqc_assign_bins(int32_t n_sub, const int32_t *n_data,
+                           const sqc_masks *scope, uint64_t max_bins_M,
+                           sqc_masks *out);
+
+/* Scope (fixed / fixed_val) of bin `bin` (subcircuit-major index) of a
+ * recursion run with `masks`: fixed' = fixed | active, fixed_val' = fixed_val
+ * with the bin's active bits deposited.  Writes n_sub masks (active = 0,
+ * merged = unfixed bits) to `scope_out`. */
+sqc_status sqc_bin_scope(int32_t n_sub, const sqc_masks *masks, uint64_t bin,
+                         sqc_masks *scope_out);
+
+/* Cost model of Sec. 6.2 for contracting a compute graph whose subcircuit i
+ * has out_bits[i] output bits (2^out_bits entries per label assignment).
+ * Only up_sub / down_sub of the cuts are used.  `order` gives n_sub-1 pairs
+ * (2*(n_sub-1) ints) of positions in a working list (the result replaces the
+ * first position, the second is removed), or NULL for the library's planner.
+ * Results: input floats, total multiplications of the plan (product of all
+ * dimensions of each pairwise step), the largest step's operand floats, the
+ * largest intermediate, and the multiplications of evaluating Eq. 1 directly
+ * (4^K times the successive outer products). */
+typedef struct {
+  double input_floats;
+  double plan_mults;
+  double max_step_operand_floats;
+  double max_intermediate_floats;
+  double naive_mults;
+  int32_t n_steps;
+  int32_t order[2 * 64]; /* the pairs used (planner's or the given ones)   */
+} sqc_cost;
+sqc_status sqc_plan_cost(int32_t n_sub, const int32_t *out_bits,
+                         const sqc_cut *cuts, int32_t n_cuts,
+                         const int32_t *order, sqc_cost *out);
+
+/* First-level index slicing heuristic of Sec. 6.3: repeatedly write out the
+ * cut whose removal reduces the total input floats the most (lowest cut id on
+ * ties) until the total is <= budget_floats.  Writes the chosen cut ids to
+ * `sliced` (capacity n_cuts) and their count to `n_sliced`. */
+sqc_status sqc_slice_plan(int32_t n_sub, const int32_t *out_bits,
+                          const sqc_cut *cuts, int32_t n_cuts,
+                          double budget_floats, int32_t *sliced,
+                          int32_t *n_sliced);
+
+/* ---- attribution (Sec. 2.1, Fig. 1) ---------------------------------------- */
+
+/* Bytes of subcircuit sub_id's attributed tensor: 4^c * 2^d elements of
+ * out_prec.  Returns 0 on invalid input. */
+size_t sqc_attribute_bytes(const sqc_sub *subs, int32_t n_sub, int32_t sub_id,
+                           const sqc_cut *cuts, int32_t n_cuts,
+                           sqc_prec out_prec);
+
+/* Attribute the variants of subcircuit sub_id.  `variants_dev` holds
+ * [V][2^n_wires] probabilities of in_prec (SQC_F64 or SQC_F32), V = product
+ * over incident cuts of 4 (in) or 3 (out).  `out->data` must hold
+ * sqc_attribute_bytes() bytes and `out->prec` selects the stored precision
+ * (SQC_F64 or SQC_F32); the call fills the other fields of *out.  Arithmetic
+ * is FP64.  For every label assignment sigma of the incident cuts and data
+ * state x:
+ *   T[sigma, x] = 2^-out * sum_s prod_in c(sigma_e, s_e)
+ *                         * sum_b prod_out g(sigma_e, b_e) * p_(s, beta(sigma))(x, b)
+ * with c(I) = (1,1,0,0), c(X) = (-1,-1,2,0), c(Y) = (-1,-1,0,2),
+ * c(Z) = (1,-1,0,0) over the preparations, beta(I) = beta(Z) = Z,
+ * beta(X) = X, beta(Y) = Y, and g(I, b) = 1, g(X|Y|Z, b) = (-1)^b.
+ * Output layout SQC_LAYOUT_ATTRIBUTED. */
+sqc_status sqc_attribute(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub,
+                         int32_t sub_id, const sqc_cut *cuts, int32_t n_cuts,
+                         const void *variants_dev, sqc_prec in_prec,
+                         sqc_tensor *out);
+
+/* ---- merging (Sec. 4) ------------------------------------------------------ */
+
+/* Merge an attributed tensor over the bins described by `masks`:
+ *   out[sigma, b] = sum over x with x & fixed == fixed_val, the active bits
+ *                   of x equal to b (compacted, ascending), of T[sigma, x].
+ * `out->data` must hold 4^c * 2^popcount(active) elements of out->prec;
+ * the call fills the other fields (layout SQC_LAYOUT_MERGED).  Sums are
+ * accumulated in FP64 in a fixed order (deterministic).  May use the
+ * context workspace (sqc_merge_workspace_bytes). */
+size_t sqc_merge_workspace_bytes(const sqc_tensor *attributed,
+                                 const sqc_masks *masks);
+sqc_status sqc_merge(sqc_ctx *ctx, const sqc_tensor *attributed,
+                     const sqc_masks *masks, sqc_tensor *out);
+
+/* ---- contraction (Sec. 6.1-6.2) ---------------------------------------------- */
+
+/* Contract merged tensors (one per subcircuit, layout SQC_LAYOUT_MERGED,
+ * n_labels equal to each subcircuit's degree) over every cut label into the
+ * 2^(sum of n_bits) bin vector `bins_dev` (bins_prec SQC_F64 or SQC_F32).
+ * `prec` selects the arithmetic of the pairwise GEMMs: SQC_F64 (FP64 MFMA,
+ * FP64 tensors), SQC_F32 (FP32 MFMA) or SQC_BF16X3; for the last two the
+ * final step sums its K axis in FP32 chunks added into FP64 accumulators with
+ * Neumaier compensation.  Order: the library's planner (greedy pairwise,
+ * Sec. 6.4 notes any order gives the same result up to rounding).
+ * Intermediates live in the context workspace
+ * (sqc_contract_workspace_bytes). */
+size_t sqc_contract_workspace_bytes(const sqc_tensor *merged, int32_t n_sub,
+                                    const sqc_cut *cuts, int32_t n_cuts,
+                                    sqc_prec prec);
+sqc_status sqc_contract(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n_sub,
+                        const sqc_cut *cuts, int32_t n_cuts, sqc_prec prec,
+                        void *bins_dev, sqc_prec bins_prec);
+
+/* ---- one states-merging recursion (Algorithm 1 body) ------------------------- */
+
+/* One recursion: sqc_assign_bins on `scope` (NULL at recursion 0), merge of
+ * every attributed tensor, contraction into `bins_dev` (2^a elements of
+ * bins_prec, a = sum of active bits), then on the device the top_r largest
+ * bins (value descending, lower index first on ties) and the FP64
+ * (compensated) sum of all bins.  Results go to `topr_dev` (top_r records of
+ * {double value; uint64_t index}) and `sum_dev` (one double).  The masks used
+ * are written to `masks_out` (host, n_sub entries) before the call returns;
+ * the device results are ready when the stream reaches them.
+ * `attributed[i].prec` may differ from `prec` (SQC_F64 attributed with an
+ * FP32 path is allowed). */
+size_t sqc_recurse_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub,
+                                   const sqc_cut *cuts, int32_t n_cuts,
+                                   const sqc_masks *masks, sqc_prec prec);
+sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
+                       const sqc_cut *cuts, int32_t n_cuts,
+                       const sqc_masks *scope, uint64_t max_bins_M,
+                       int32_t top_r, sqc_prec prec, void *bins_dev,
+                       sqc_prec bins_prec, sqc_masks *masks_out,
+                       void *topr_dev, void *sum_dev);
+
+/* ---- the search loop (Algorithm 1) ------------------------------------------- */
+
+typedef struct {
+  double prob;          /* reconstructed probability of the bin            */
+  int32_t recursion;    /* recursion that produced it                      */
+  int32_t pad;
+  uint64_t bin;         /* bin index within that recursion                 */
+} sqc_found;
+
+typedef struct {
+  double bins_sum;      /* FP64 sum of the recursion's bins                */
+  double parent_prob;   /* probability of the expanded bin (1 at r = 0)    */
+  double top_prob;      /* largest bin                                     */
+  int32_t active_bits;  /* a = log2 of the bin count                       */
+  int32_t leaf;         /* 1 when every bin is a single state              */
+} sqc_recursion_info;
+
+/* Algorithm 1 with R = max_recursions: run recursions while r < R and the
+ * list L of candidate bins is not empty.  After each recursion the R largest
+ * bins that still hold more than one state are appended to L, L is sorted
+ * (probability descending, then earlier recursion, then lower bin index) and
+ * truncated to R, and the first entry is popped for the next recursion.  Bins
+ * of single states are reported as solutions (the R largest of each leaf
+ * recursion).  Waits for the device after every recursion.
+ * `solutions` / `solution_states` receive up to max_solutions entries; for
+ * solution k, solution_states[k * n_sub + i] is subcircuit i's data state.
+ * `info` (optional) receives one record per recursion run (capacity
+ * max_recursions).  `bins_dev` must hold 2^a elements of bins_prec for the
+ * largest a the search uses (at most floor(log2 M)). */
+sqc_status sqc_search(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
+                      const sqc_cut *cuts, int32_t n_cuts, uint64_t max_bins_M,
+                      int32_t max_recursions, sqc_prec prec, void *bins_dev,
+                      sqc_prec bins_prec, sqc_found *solutions,
+                      uint64_t *solution_states, int32_t max_solutions,
+                      int32_t *n_solutions, sqc_recursion_info *info,
+                      int32_t *n_recursions);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SQC_H */

@@ -56,10 +56,11 @@ def _bits_to_index(o: np.ndarray, positions: Sequence[int]) -> np.ndarray:
     return out
 
 
-def attribute(cc, i: int, variants: np.ndarray) -> np.ndarray:
+def attribute(cc, i: int, variants: np.ndarray, sigmas=None) -> np.ndarray:
     """Entries T_i[sigma, x] (float64, shape [4^c_i][2^d_i]) of subcircuit i
     for every label assignment of its incident cuts (Sec. 2.1, p_i(k) of
-    Eq. 1, without the 1/2-per-cut factor).
+    Eq. 1, without the 1/2-per-cut factor).  With ``sigmas`` (a list of label
+    indices) only those rows are evaluated, shape [len(sigmas)][2^d_i].
 
     ``variants[v][o]``: probability of outcome o (wire t = bit t) in variant v
     (mixed radix over incident cuts: radix 4 preparations for in-cuts, radix 3
@@ -78,8 +79,9 @@ def attribute(cc, i: int, variants: np.ndarray) -> np.ndarray:
         if role == "out":
             bits_out[j] = (o >> cc.cuts[k].up_wire) & 1
     variants = np.asarray(variants, dtype=np.float64)
-    T = np.zeros((4 ** c, 1 << d), dtype=np.float64)
-    for sigma in range(4 ** c):
+    rows = range(4 ** c) if sigmas is None else list(sigmas)
+    T = np.zeros((len(rows), 1 << d), dtype=np.float64)
+    for row, sigma in enumerate(rows):
         lab = [(sigma >> (2 * j)) & 3 for j in range(c)]
         # outcome weights of the out-cuts and the fixed part of the variant id
         wgt = np.ones(1 << w)
@@ -98,8 +100,8 @@ def attribute(cc, i: int, variants: np.ndarray) -> np.ndarray:
             for (j, s, cf) in combo:
                 coef *= cf
                 v += s * place[j]
-            T[sigma] += coef * np.bincount(x_of_o, weights=wgt * variants[v],
-                                           minlength=1 << d)
+            T[row] += coef * np.bincount(x_of_o, weights=wgt * variants[v],
+                                         minlength=1 << d)
     return T
 
 

@@ -1,0 +1,723 @@
+// C entry points of libsqc that use the GPU: context and workspace,
+// attribution, merging, contraction, one recursion and the search loop.
+#include <algorithm>
+#include <cstring>
+#include <sstream>
+
+#include "common.hpp"
+
+namespace sqc {
+
+namespace {
+
+__global__ void cast_copy(const void *src, int src_f32, void *dst, int dst_f32, int64_t n) {
+  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n;
+       q += int64_t(gridDim.x) * blockDim.x) {
+    double v = src_f32 ? (double)static_cast<const float *>(src)[q] : static_cast<const double *>(src)[q];
+    if (dst_f32) static_cast<float *>(dst)[q] = (float)v;
+    else static_cast<double *>(dst)[q] = v;
+  }
+}
+
+__global__ void set_unit(double *p) {
+  p[0] = 1.0;
+  reinterpret_cast<float *>(p + 1)[0] = 1.0f;
+}
+
+}  // namespace
+
+}  // namespace sqc
+
+using namespace sqc;
+
+struct sqc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err;
+  void *pinned = nullptr;  // host staging for small device results
+};
+
+namespace {
+
+// Control region at the start of the workspace.
+constexpr size_t kCtlBytes = 4096;
+constexpr size_t kOffGemmCounter = 0;    // uint32
+constexpr size_t kOffTopCounters = 16;   // 2 x uint32
+constexpr size_t kOffTauSum = 64;        // 2 x double
+constexpr size_t kOffUnit = 128;         // double 1.0 then float 1.0
+constexpr size_t kOffSearchTop = 256;    // SQC_MAX_TOPR x 16 bytes
+constexpr size_t kOffSearchSum = 256 + 16 * SQC_MAX_TOPR;
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+struct Bump {
+  size_t off = kCtlBytes;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  }
+};
+
+[[noreturn]] void raise(sqc_status c, const std::string &m) { throw Error{c, m}; }
+
+void check_hip(hipError_t e, const char *what) {
+  if (e != hipSuccess) {
+    std::ostringstream s;
+    s << what << ": " << hipGetErrorString(e);
+    raise(SQC_E_DEVICE, s.str());
+  }
+}
+
+void use_device(sqc_ctx *ctx) { check_hip(hipSetDevice(ctx->device), "hipSetDevice"); }
+
+void after_launch(const char *what) { check_hip(hipGetLastError(), what); }
+
+int elem_bytes(sqc_prec p) { return p == SQC_F64 ? 8 : 4; }
+
+void check_storage_prec(sqc_prec p, const char *name) {
+  if (p != SQC_F64 && p != SQC_F32) {
+    std::ostringstream s;
+    s << name << " must be SQC_F64 or SQC_F32";
+    raise(SQC_E_ARG, s.str());
+  }
+}
+
+void check_path_prec(sqc_prec p) {
+  if (p != SQC_F64 && p != SQC_F32 && p != SQC_BF16X3) raise(SQC_E_ARG, "unknown contraction precision");
+}
+
+void check_masks(const sqc_masks &m, int d, int i) {
+  uint64_t dmask = d == 64 ? ~0ull : ((uint64_t(1) << d) - 1);
+  std::ostringstream s;
+  if ((m.fixed & m.active) || (m.fixed & m.merged) || (m.active & m.merged)) {
+    s << "masks of subcircuit " << i << " overlap";
+    raise(SQC_E_SHAPE, s.str());
+  }
+  if ((m.fixed | m.active | m.merged) != dmask) {
+    s << "masks of subcircuit " << i << " do not cover exactly its " << d << " data bits";
+    raise(SQC_E_SHAPE, s.str());
+  }
+  if (m.fixed_val & ~m.fixed) {
+    s << "fixed_val of subcircuit " << i << " has bits outside fixed";
+    raise(SQC_E_SHAPE, s.str());
+  }
+}
+
+void check_size(int lbits, int dbits) {
+  if (lbits + dbits > 40) raise(SQC_E_UNSUPPORTED, "tensor larger than 2^40 elements");
+}
+
+// ---------------------------------------------------------------------------
+// shared pieces of merge / contract / recurse
+// ---------------------------------------------------------------------------
+
+void enqueue_merge(sqc_ctx *ctx, const sqc_tensor &at, const sqc_masks &mk, void *out,
+                   int out_f32, double *partial) {
+  MergeArgs a{};
+  a.in = at.data;
+  a.out = out;
+  a.partial = partial;
+  a.in_f32 = at.prec == SQC_F32;
+  a.out_f32 = out_f32;
+  a.d = at.n_bits;
+  a.lbits = 2 * at.n_labels;
+  a.abits = __builtin_popcountll(mk.active);
+  a.mbits = __builtin_popcountll(mk.merged);
+  a.fixed_val = mk.fixed_val;
+  a.active = mk.active;
+  a.merged = mk.merged;
+  launch_merge(a, ctx->stream);
+  after_launch("merge kernel launch");
+}
+
+size_t merge_ws(const sqc_tensor &at, const sqc_masks &mk) {
+  int64_t e = merge_partial_elems(__builtin_popcountll(mk.active), 2 * at.n_labels,
+                                  __builtin_popcountll(mk.merged));
+  return (size_t)e * sizeof(double);
+}
+
+struct Contraction {
+  Plan plan;
+  int path_f32 = 1;
+  bool unit = false;  // single subcircuit: contract with a one-element tensor
+};
+
+Contraction plan_for(const Graph &g, const std::vector<int> &bits, sqc_prec prec) {
+  Contraction c;
+  c.path_f32 = prec != SQC_F64;
+  c.plan = make_plan(g, bits, nullptr, c.path_f32 ? 4 : 8);
+  c.unit = c.plan.steps.empty();
+  return c;
+}
+
+GemmArgs step_args(const Contraction &c, size_t si, const std::vector<const void *> &inputs,
+                   char *ws, size_t inter_base, void *bins, int bins_f32, const void *unit) {
+  GemmArgs g{};
+  const Plan &p = c.plan;
+  if (c.unit) {
+    g.A = inputs[0];
+    g.B = unit;
+    g.C = bins;
+    g.mbits = p.tensors[0].elems() > 1 ? p.out_bits : 0;
+    g.nbits = g.kbits = 0;
+    if (g.mbits) {
+      g.m.nruns = 1;
+      g.m.bits[0] = g.mbits;
+      g.m.sx[0] = 1;
+      g.m.sy[0] = 1;
+    }
+    g.out_f32 = bins_f32;
+    g.final_step = 1;
+    return g;
+  }
+  const Step &st = p.steps[si];
+  auto ptr = [&](int t) -> const void * {
+    const PTensor &pt = p.tensors[t];
+    if (pt.input_sub >= 0) return inputs[pt.input_sub];
+    return ws + inter_base + pt.ws_offset;
+  };
+  g.A = ptr(st.a);
+  g.B = ptr(st.b);
+  bool last = si + 1 == p.steps.size();
+  g.C = last ? bins : (void *)(ws + inter_base + p.tensors[st.c].ws_offset);
+  g.mbits = st.mbits;
+  g.nbits = st.nbits;
+  g.kbits = st.kbits;
+  g.m = st.m;
+  g.n = st.n;
+  g.k = st.k;
+  g.out_f32 = last ? bins_f32 : c.path_f32;
+  g.final_step = last ? 1 : 0;
+  return g;
+}
+
+int chunk_bits_for(sqc_prec prec) { return prec == SQC_BF16X3 ? 5 : 5; }
+
+// Workspace needed after the control region: intermediates + statistics.
+size_t contraction_ws(const Contraction &c, int top_r, bool stats, int prec) {
+  size_t b = align256(c.plan.inter_bytes);
+  if (stats) {
+    GemmArgs dummy{};
+    if (c.unit) {
+      dummy.mbits = c.plan.out_bits;
+    } else {
+      const Step &st = c.plan.steps.back();
+      dummy.mbits = st.mbits;
+      dummy.nbits = st.nbits;
+    }
+    size_t nblk = (size_t)gemm_blocks(dummy, prec);
+    b += 2 * align256(nblk * sizeof(double));
+    b += 2 * align256(nblk * (size_t)top_r * 8);
+  }
+  return b;
+}
+
+struct StatsBufs {
+  double *blk_sum, *blk_max, *cand_val;
+  uint64_t *cand_idx;
+};
+
+// Enqueue every GEMM of a contraction.  With `top_dev` non-null, the final
+// step gathers statistics and the top-R kernel follows.
+void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<const void *> &inputs,
+                         size_t base, void *bins, int bins_f32, sqc_prec prec, int top_r,
+                         void *top_dev, void *sum_dev) {
+  char *ws = ctx->ws;
+  const void *unit = ws + kOffUnit + (c.path_f32 ? 8 : 0);
+  size_t inter_base = base;
+  size_t stats_base = base + align256(c.plan.inter_bytes);
+  size_t nsteps = c.unit ? 1 : c.plan.steps.size();
+  for (size_t si = 0; si < nsteps; ++si) {
+    GemmArgs g = step_args(c, si, inputs, ws, inter_base, bins, bins_f32, unit);
+    g.chunk_bits = chunk_bits_for(prec);
+    bool last = si + 1 == nsteps;
+    if (last && top_dev) {
+      size_t nblk = (size_t)gemm_blocks(g, prec);
+      Bump bp;
+      bp.off = stats_base;
+      g.stats = 1;
+      g.blk_sum = reinterpret_cast<double *>(ws + bp.take(nblk * sizeof(double)));
+      g.blk_max = reinterpret_cast<double *>(ws + bp.take(nblk * sizeof(double)));
+      g.counter = reinterpret_cast<unsigned int *>(ws + kOffGemmCounter);
+      g.tau_sum = reinterpret_cast<double *>(ws + kOffTauSum);
+      g.top_r = top_r;
+      launch_gemm(g, prec, ctx->stream);
+      after_launch("contraction kernel launch");
+      TopRArgs t{};
+      t.C = bins;
+      t.out_f32 = bins_f32;
+      t.mbits = g.mbits;
+      t.nbits = g.nbits;
+      t.m = g.m;
+      t.n = g.n;
+      t.nblk = (int)nblk;
+      t.prec = prec;
+      t.blk_max = g.blk_max;
+      t.tau_sum = g.tau_sum;
+      t.cand_val = reinterpret_cast<double *>(ws + bp.take(nblk * (size_t)top_r * 8));
+      t.cand_idx = reinterpret_cast<uint64_t *>(ws + bp.take(nblk * (size_t)top_r * 8));
+      t.counter = reinterpret_cast<unsigned int *>(ws + kOffTopCounters);
+      t.top_r = top_r;
+      t.top_out = static_cast<double *>(top_dev);
+      t.sum_out = static_cast<double *>(sum_dev);
+      launch_topr(t, ctx->stream);
+      after_launch("top-R kernel launch");
+    } else {
+      launch_gemm(g, prec, ctx->stream);
+      after_launch("contraction kernel launch");
+    }
+  }
+}
+
+void need_ws(sqc_ctx *ctx, size_t bytes) {
+  if (!ctx->ws) raise(SQC_E_NOMEM, "no workspace: call sqc_ctx_set_workspace first");
+  if (bytes > ctx->ws_bytes) {
+    std::ostringstream s;
+    s << "workspace of " << ctx->ws_bytes << " bytes is smaller than the " << bytes
+      << " bytes this call needs";
+    raise(SQC_E_NOMEM, s.str());
+  }
+}
+
+std::vector<int> degrees_match(const Graph &g, const sqc_tensor *t, int layout) {
+  std::vector<int> bits(g.n_sub);
+  for (int i = 0; i < g.n_sub; ++i) {
+    std::ostringstream s;
+    if (!t[i].data) {
+      s << "tensor " << i << " has no data";
+      raise(SQC_E_ARG, s.str());
+    }
+    if (t[i].layout != layout) {
+      s << "tensor " << i << " has the wrong layout";
+      raise(SQC_E_SHAPE, s.str());
+    }
+    if (t[i].n_labels != (int)g.subs[i].inc.size()) {
+      s << "tensor " << i << " has " << t[i].n_labels << " labels but subcircuit " << i
+        << " has degree " << g.subs[i].inc.size();
+      raise(SQC_E_SHAPE, s.str());
+    }
+    if (t[i].n_bits < 0 || t[i].n_bits > SQC_MAX_DATA_BITS) {
+      s << "tensor " << i << " bit count out of range";
+      raise(SQC_E_SHAPE, s.str());
+    }
+    check_storage_prec(t[i].prec, "tensor precision");
+    check_size(2 * t[i].n_labels, t[i].n_bits);
+    bits[i] = t[i].n_bits;
+  }
+  return bits;
+}
+
+struct RecursePlan {
+  std::vector<sqc_masks> masks;
+  std::vector<int> abits;
+  Contraction con;
+  std::vector<size_t> merged_off;
+  size_t partial_off = 0, con_base = 0, total = 0;
+};
+
+RecursePlan plan_recursion(const Graph &g, const sqc_tensor *att, const sqc_masks *scope,
+                           uint64_t M, int top_r, sqc_prec prec) {
+  RecursePlan rp;
+  std::vector<int> d(g.n_sub);
+  for (int i = 0; i < g.n_sub; ++i) d[i] = att[i].n_bits;
+  rp.masks.resize(g.n_sub);
+  assign_bins(g.n_sub, d.data(), scope, M, rp.masks.data());
+  rp.abits.resize(g.n_sub);
+  for (int i = 0; i < g.n_sub; ++i) rp.abits[i] = __builtin_popcountll(rp.masks[i].active);
+  rp.con = plan_for(g, rp.abits, prec);
+  Bump b;
+  int eb = prec == SQC_F64 ? 8 : 4;
+  size_t part = 0;
+  for (int i = 0; i < g.n_sub; ++i) {
+    rp.merged_off.push_back(b.take(((size_t)1 << (2 * att[i].n_labels + rp.abits[i])) * eb));
+    part = std::max(part, merge_ws(att[i], rp.masks[i]));
+  }
+  rp.partial_off = b.take(part);
+  rp.con_base = b.off;
+  rp.total = b.off + contraction_ws(rp.con, top_r, true, prec);
+  return rp;
+}
+
+void enqueue_recursion(sqc_ctx *ctx, const RecursePlan &rp, const sqc_tensor *att, sqc_prec prec,
+                       void *bins, sqc_prec bins_prec, int top_r, void *top_dev, void *sum_dev) {
+  const int n_sub = (int)rp.masks.size();
+  std::vector<const void *> inputs(n_sub);
+  const int path_f32 = prec != SQC_F64;
+  for (int i = 0; i < n_sub; ++i) {
+    void *out = ctx->ws + rp.merged_off[i];
+    enqueue_merge(ctx, att[i], rp.masks[i], out, path_f32,
+                  reinterpret_cast<double *>(ctx->ws + rp.partial_off));
+    inputs[i] = out;
+  }
+  enqueue_contraction(ctx, rp.con, inputs, rp.con_base, bins, bins_prec == SQC_F32, prec, top_r,
+                      top_dev, sum_dev);
+}
+
+}  // namespace
+
+#define SQC_TRY(ctx)          \
+  try {                       \
+    if (!(ctx)) raise(SQC_E_ARG, "ctx is NULL");
+#define SQC_CATCH(ctx)                              \
+  }                                                 \
+  catch (const Error &e) {                          \
+    if (ctx) (ctx)->err = e.msg;                    \
+    else set_thread_error(e.msg);                   \
+    return e.code;                                  \
+  }                                                 \
+  catch (const std::exception &e) {                 \
+    if (ctx) (ctx)->err = e.what();                 \
+    else set_thread_error(e.what());                \
+    return SQC_E_ARG;                               \
+  }
+
+extern "C" {
+
+const char *sqc_version(void) { return "sqc 0.1.0 (gfx950)"; }
+
+const char *sqc_last_error(const sqc_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : thread_error();
+}
+
+sqc_status sqc_ctx_create(int device, void *hip_stream, sqc_ctx **out) {
+  try {
+    if (!out) raise(SQC_E_ARG, "out is NULL");
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) raise(SQC_E_DEVICE, "no HIP device is available");
+    if (device < 0 || device >= n) raise(SQC_E_ARG, "device index out of range");
+    check_hip(hipSetDevice(device), "hipSetDevice");
+    hipDeviceProp_t prop;
+    check_hip(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+      std::ostringstream s;
+      s << "device " << device << " is " << prop.gcnArchName << "; this build targets gfx950";
+      raise(SQC_E_DEVICE, s.str());
+    }
+    sqc_ctx *c = new sqc_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipHostMalloc(&c->pinned, 64 * 1024, hipHostMallocDefault) != hipSuccess) {
+      delete c;
+      raise(SQC_E_DEVICE, "hipHostMalloc of the staging buffer failed");
+    }
+    *out = c;
+    return SQC_OK;
+  } catch (const Error &e) {
+    set_thread_error(e.msg);
+    return e.code;
+  }
+}
+
+sqc_status sqc_ctx_destroy(sqc_ctx *ctx) {
+  if (!ctx) return SQC_E_ARG;
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  delete ctx;
+  return SQC_OK;
+}
+
+sqc_status sqc_ctx_set_stream(sqc_ctx *ctx, void *hip_stream) {
+  SQC_TRY(ctx)
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_ctx_set_workspace(sqc_ctx *ctx, void *dev, size_t bytes) {
+  SQC_TRY(ctx)
+  if (!dev || bytes < kCtlBytes) raise(SQC_E_ARG, "workspace must be at least 4096 bytes");
+  if (reinterpret_cast<uintptr_t>(dev) % 256) raise(SQC_E_ARG, "workspace must be 256-byte aligned");
+  use_device(ctx);
+  ctx->ws = static_cast<char *>(dev);
+  ctx->ws_bytes = bytes;
+  launch_zero(ctx->ws, kCtlBytes, ctx->stream);
+  after_launch("workspace initialisation");
+  hipLaunchKernelGGL(set_unit, dim3(1), dim3(1), 0, ctx->stream,
+                     reinterpret_cast<double *>(ctx->ws + kOffUnit));
+  after_launch("workspace initialisation");
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+size_t sqc_attribute_bytes(const sqc_sub *subs, int32_t n_sub, int32_t sub_id,
+                           const sqc_cut *cuts, int32_t n_cuts, sqc_prec out_prec) {
+  try {
+    Graph g = build_graph(subs, n_sub, cuts, n_cuts);
+    if (sub_id < 0 || sub_id >= n_sub) return 0;
+    if (out_prec != SQC_F64 && out_prec != SQC_F32) return 0;
+    const SubInfo &s = g.subs[sub_id];
+    if (2 * (int)s.inc.size() + s.d > 40) return 0;
+    return ((size_t)1 << (2 * s.inc.size() + s.d)) * elem_bytes(out_prec);
+  } catch (const Error &e) {
+    set_thread_error(e.msg);
+    return 0;
+  }
+}
+
+sqc_status sqc_attribute(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, int32_t sub_id,
+                         const sqc_cut *cuts, int32_t n_cuts, const void *variants_dev,
+                         sqc_prec in_prec, sqc_tensor *out) {
+  SQC_TRY(ctx)
+  Graph g = build_graph(subs, n_sub, cuts, n_cuts);
+  if (sub_id < 0 || sub_id >= n_sub) raise(SQC_E_ARG, "sub_id out of range");
+  if (!variants_dev) raise(SQC_E_ARG, "variants_dev is NULL");
+  if (!out || !out->data) raise(SQC_E_ARG, "out or out->data is NULL");
+  check_storage_prec(in_prec, "in_prec");
+  check_storage_prec(out->prec, "out->prec");
+  const SubInfo &s = g.subs[sub_id];
+  const int c = (int)s.inc.size();
+  check_size(2 * c, s.d);
+  AttrArgs a{};
+  a.var = variants_dev;
+  a.out = out->data;
+  a.in_f32 = in_prec == SQC_F32;
+  a.out_f32 = out->prec == SQC_F32;
+  a.w = s.w;
+  a.d = s.d;
+  a.c = c;
+  int64_t place = 1;
+  for (int q = 0; q < c; ++q) {
+    a.place[q] = place;
+    if (s.role[q] == 0) {
+      a.in_pos[a.n_in++] = q;
+      place *= 4;
+    } else {
+      a.out_wire[a.n_out] = g.cuts[s.inc[q]].up_wire;
+      a.out_pos[a.n_out++] = q;
+      place *= 3;
+    }
+  }
+  for (int j = 0; j < s.d; ++j) a.data_wire[j] = s.data_wire[j];
+  a.scale = std::ldexp(1.0, -a.n_out);
+  use_device(ctx);
+  launch_attribute(a, ctx->stream);
+  after_launch("attribution kernel launch");
+  out->n_labels = c;
+  out->n_bits = s.d;
+  out->layout = SQC_LAYOUT_ATTRIBUTED;
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+size_t sqc_merge_workspace_bytes(const sqc_tensor *attributed, const sqc_masks *masks) {
+  if (!attributed || !masks) return 0;
+  return kCtlBytes + merge_ws(*attributed, *masks);
+}
+
+sqc_status sqc_merge(sqc_ctx *ctx, const sqc_tensor *attributed, const sqc_masks *masks,
+                     sqc_tensor *out) {
+  SQC_TRY(ctx)
+  if (!attributed || !masks || !out || !out->data || !attributed->data)
+    raise(SQC_E_ARG, "NULL argument");
+  if (attributed->layout != SQC_LAYOUT_ATTRIBUTED) raise(SQC_E_SHAPE, "input is not an attributed tensor");
+  check_storage_prec(attributed->prec, "attributed->prec");
+  check_storage_prec(out->prec, "out->prec");
+  if (attributed->n_labels < 0 || attributed->n_labels > SQC_MAX_DEGREE)
+    raise(SQC_E_SHAPE, "label count out of range");
+  if (attributed->n_bits < 0 || attributed->n_bits > SQC_MAX_DATA_BITS)
+    raise(SQC_E_SHAPE, "bit count out of range");
+  check_size(2 * attributed->n_labels, attributed->n_bits);
+  check_masks(*masks, attributed->n_bits, 0);
+  size_t part = merge_ws(*attributed, *masks);
+  if (part) need_ws(ctx, kCtlBytes + part);
+  use_device(ctx);
+  enqueue_merge(ctx, *attributed, *masks, out->data, out->prec == SQC_F32,
+                part ? reinterpret_cast<double *>(ctx->ws + kCtlBytes) : nullptr);
+  out->n_labels = attributed->n_labels;
+  out->n_bits = __builtin_popcountll(masks->active);
+  out->layout = SQC_LAYOUT_MERGED;
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+size_t sqc_contract_workspace_bytes(const sqc_tensor *merged, int32_t n_sub, const sqc_cut *cuts,
+                                    int32_t n_cuts, sqc_prec prec) {
+  try {
+    Graph g = build_topology(n_sub, cuts, n_cuts);
+    if (!merged) return 0;
+    std::vector<int> bits = degrees_match(g, merged, SQC_LAYOUT_MERGED);
+    Contraction c = plan_for(g, bits, prec);
+    return kCtlBytes + contraction_ws(c, 1, false, prec);
+  } catch (const Error &e) {
+    set_thread_error(e.msg);
+    return 0;
+  }
+}
+
+sqc_status sqc_contract(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n_sub, const sqc_cut *cuts,
+                        int32_t n_cuts, sqc_prec prec, void *bins_dev, sqc_prec bins_prec) {
+  SQC_TRY(ctx)
+  Graph g = build_topology(n_sub, cuts, n_cuts);
+  if (!merged || !bins_dev) raise(SQC_E_ARG, "NULL argument");
+  check_path_prec(prec);
+  check_storage_prec(bins_prec, "bins_prec");
+  std::vector<int> bits = degrees_match(g, merged, SQC_LAYOUT_MERGED);
+  for (int i = 0; i < n_sub; ++i) {
+    bool want_f64 = prec == SQC_F64;
+    if ((merged[i].prec == SQC_F64) != want_f64)
+      raise(SQC_E_ARG, "merged tensors must be FP64 for the FP64 path and FP32 otherwise");
+  }
+  Contraction c = plan_for(g, bits, prec);
+  need_ws(ctx, kCtlBytes + contraction_ws(c, 1, false, prec));
+  use_device(ctx);
+  std::vector<const void *> inputs(n_sub);
+  for (int i = 0; i < n_sub; ++i) inputs[i] = merged[i].data;
+  enqueue_contraction(ctx, c, inputs, kCtlBytes, bins_dev, bins_prec == SQC_F32, prec, 0, nullptr,
+                      nullptr);
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+size_t sqc_recurse_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,
+                                   int32_t n_cuts, const sqc_masks *masks, sqc_prec prec) {
+  try {
+    Graph g = build_topology(n_sub, cuts, n_cuts);
+    if (!attributed || !masks) return 0;
+    degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+    // the masks given fix the bin counts: use them as the scope with M large
+    std::vector<int> abits(n_sub);
+    Bump b;
+    int eb = prec == SQC_F64 ? 8 : 4;
+    size_t part = 0;
+    for (int i = 0; i < n_sub; ++i) {
+      abits[i] = __builtin_popcountll(masks[i].active);
+      b.take(((size_t)1 << (2 * attributed[i].n_labels + abits[i])) * eb);
+      part = std::max(part, merge_ws(attributed[i], masks[i]));
+    }
+    b.take(part);
+    Contraction c = plan_for(g, abits, prec);
+    return b.off + contraction_ws(c, SQC_MAX_TOPR, true, prec);
+  } catch (const Error &e) {
+    set_thread_error(e.msg);
+    return 0;
+  }
+}
+
+sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,
+                       int32_t n_cuts, const sqc_masks *scope, uint64_t max_bins_M, int32_t top_r,
+                       sqc_prec prec, void *bins_dev, sqc_prec bins_prec, sqc_masks *masks_out,
+                       void *topr_dev, void *sum_dev) {
+  SQC_TRY(ctx)
+  Graph g = build_topology(n_sub, cuts, n_cuts);
+  if (!attributed || !bins_dev || !topr_dev || !sum_dev) raise(SQC_E_ARG, "NULL argument");
+  check_path_prec(prec);
+  check_storage_prec(bins_prec, "bins_prec");
+  if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
+  degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+  RecursePlan rp = plan_recursion(g, attributed, scope, max_bins_M, top_r, prec);
+  need_ws(ctx, rp.total);
+  use_device(ctx);
+  enqueue_recursion(ctx, rp, attributed, prec, bins_dev, bins_prec, top_r, topr_dev, sum_dev);
+  if (masks_out) std::copy(rp.masks.begin(), rp.masks.end(), masks_out);
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_search(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,
+                      int32_t n_cuts, uint64_t max_bins_M, int32_t max_recursions, sqc_prec prec,
+                      void *bins_dev, sqc_prec bins_prec, sqc_found *solutions,
+                      uint64_t *solution_states, int32_t max_solutions, int32_t *n_solutions,
+                      sqc_recursion_info *info, int32_t *n_recursions) {
+  SQC_TRY(ctx)
+  Graph g = build_topology(n_sub, cuts, n_cuts);
+  if (!attributed || !bins_dev || !n_solutions || !n_recursions) raise(SQC_E_ARG, "NULL argument");
+  if (max_solutions > 0 && (!solutions || !solution_states)) raise(SQC_E_ARG, "NULL solution buffers");
+  check_path_prec(prec);
+  check_storage_prec(bins_prec, "bins_prec");
+  const int R = max_recursions;
+  if (R < 1 || R > SQC_MAX_TOPR) raise(SQC_E_ARG, "max_recursions must be in [1, 64]");
+  degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+  use_device(ctx);
+
+  struct Entry {
+    double prob;
+    int r;
+    uint64_t bin;
+    std::vector<sqc_masks> masks;
+  };
+  std::vector<Entry> L;
+  std::vector<sqc_masks> scope;
+  bool have_scope = false;
+  double parent_prob = 1.0;
+  int nsol = 0, r = 0;
+  void *top_dev = ctx->ws ? ctx->ws + kOffSearchTop : nullptr;
+  void *sum_dev = ctx->ws ? ctx->ws + kOffSearchSum : nullptr;
+  while (r < R) {
+    if (r > 0 && !have_scope) break;
+    RecursePlan rp = plan_recursion(g, attributed, have_scope ? scope.data() : nullptr, max_bins_M,
+                                    R, prec);
+    need_ws(ctx, rp.total);
+    enqueue_recursion(ctx, rp, attributed, prec, bins_dev, bins_prec, R, top_dev, sum_dev);
+    const size_t nbytes = kOffSearchSum + 8 - kOffSearchTop;
+    check_hip(hipMemcpyAsync(ctx->pinned, top_dev, nbytes, hipMemcpyDeviceToHost, ctx->stream),
+              "hipMemcpyAsync");
+    check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    const double *top = static_cast<const double *>(ctx->pinned);
+    const double bsum = top[(kOffSearchSum - kOffSearchTop) / 8];
+    int a = 0;
+    bool leaf = true;
+    for (int i = 0; i < n_sub; ++i) {
+      a += rp.abits[i];
+      if (rp.masks[i].merged) leaf = false;
+    }
+    const uint64_t nbins = a >= 63 ? ~0ull : (uint64_t(1) << a);
+    const int take = (uint64_t)R < nbins ? R : (int)nbins;
+    if (info) {
+      info[r].bins_sum = bsum;
+      info[r].parent_prob = parent_prob;
+      info[r].top_prob = top[0];
+      info[r].active_bits = a;
+      info[r].leaf = leaf ? 1 : 0;
+    }
+    for (int q = 0; q < take; ++q) {
+      double v = top[2 * q];
+      uint64_t bin;
+      std::memcpy(&bin, &top[2 * q + 1], 8);
+      if (!(v == v) || v == -INFINITY) continue;
+      if (!leaf) {
+        L.push_back(Entry{v, r, bin, rp.masks});
+      } else if (nsol < max_solutions) {
+        solutions[nsol].prob = v;
+        solutions[nsol].recursion = r;
+        solutions[nsol].pad = 0;
+        solutions[nsol].bin = bin;
+        uint64_t rem = bin;
+        for (int i = 0; i < n_sub; ++i) {
+          int ai = rp.abits[i];
+          uint64_t beta = ai >= 64 ? rem : (rem & ((uint64_t(1) << ai) - 1));
+          rem = ai >= 64 ? 0 : (rem >> ai);
+          solution_states[(size_t)nsol * n_sub + i] =
+              rp.masks[i].fixed_val | deposit_bits(beta, rp.masks[i].active);
+        }
+        ++nsol;
+      }
+    }
+    std::stable_sort(L.begin(), L.end(), [](const Entry &x, const Entry &y) {
+      if (x.prob != y.prob) return x.prob > y.prob;
+      if (x.r != y.r) return x.r < y.r;
+      return x.bin < y.bin;
+    });
+    if ((int)L.size() > R) L.resize(R);
+    ++r;
+    if (L.empty()) {
+      have_scope = false;
+      continue;
+    }
+    Entry e = L.front();
+    L.erase(L.begin());
+    scope.resize(n_sub);
+    if (sqc_bin_scope(n_sub, e.masks.data(), e.bin, scope.data()) != SQC_OK)
+      raise(SQC_E_ARG, thread_error());
+    have_scope = true;
+    parent_prob = e.prob;
+  }
+  *n_solutions = nsol;
+  *n_recursions = r;
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+}  // extern "C"

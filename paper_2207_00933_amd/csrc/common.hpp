@@ -1,0 +1,193 @@
+// Internal declarations of libsqc: graph bookkeeping, the contraction planner,
+// kernel argument blocks and launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sqc.h"
+
+namespace sqc {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error {
+  sqc_status code;
+  std::string msg;
+};
+
+// Per-thread message for context-less calls.
+void set_thread_error(const std::string &m);
+const char *thread_error();
+
+// ---------------------------------------------------------------------------
+// compute graph
+// ---------------------------------------------------------------------------
+struct SubInfo {
+  int w = 0;                    // wires
+  int d = 0;                    // data bits
+  std::vector<int> data_wire;   // data bit j -> wire
+  std::vector<int> inc;         // incident cut ids, global order
+  std::vector<int> role;        // per incident cut: 0 = in (down), 1 = out (up)
+  int n_in = 0, n_out = 0;
+  int64_t variants = 1;         // 4^n_in * 3^n_out
+};
+
+struct Graph {
+  int n_sub = 0;
+  int n_cuts = 0;
+  std::vector<sqc_cut> cuts;
+  std::vector<SubInfo> subs;
+};
+
+// Topology only (cut endpoints, incident lists, degree cap).  Throws Error.
+Graph build_topology(int n_sub, const sqc_cut *cuts, int n_cuts);
+// Full validation including wires and data wires.  Throws Error.
+Graph build_graph(const sqc_sub *subs, int n_sub, const sqc_cut *cuts, int n_cuts);
+
+// Algorithm 2 as masks (see sqc_assign_bins).  Throws Error.
+void assign_bins(int n_sub, const int *n_data, const sqc_masks *scope, uint64_t M,
+                 sqc_masks *out);
+uint64_t deposit_bits(uint64_t v, uint64_t mask);
+uint64_t extract_bits(uint64_t x, uint64_t mask);
+
+// ---------------------------------------------------------------------------
+// contraction plan
+// ---------------------------------------------------------------------------
+constexpr int kMaxRuns = 12;
+
+// One index space (m, n or k) split into runs of bits; each run has a stride in
+// two operands (X and Y).  index -> offset_X = sum_r ((idx >> shift_r) &
+// (2^bits_r - 1)) * sx[r], the same with sy for operand Y.
+struct IndexMap {
+  int nruns = 0;
+  int bits[kMaxRuns] = {0};
+  int64_t sx[kMaxRuns] = {0};
+  int64_t sy[kMaxRuns] = {0};
+};
+
+struct Axis {
+  int kind;  // 0 = bins of subcircuit `id`, 1 = label of cut `id`
+  int id;
+  int bits;
+};
+
+struct PTensor {
+  std::vector<Axis> axes;  // memory order, fastest first
+  int input_sub = -1;      // >= 0: merged input tensor of this subcircuit
+  int64_t ws_offset = -1;  // intermediate: byte offset in the workspace
+  int bits() const {
+    int b = 0;
+    for (auto &a : axes) b += a.bits;
+    return b;
+  }
+  // element count (only for tensors that exist: at most 2^40 elements)
+  int64_t elems() const { return int64_t(1) << bits(); }
+  double elems_d() const;
+};
+
+struct Step {
+  int a, b, c;       // tensor table indices; a plays the GEMM "A" role
+  int mbits, nbits, kbits;
+  IndexMap m, n, k;  // m: (A, C), n: (B, C), k: (A, B)
+  double mults;      // product of all dimensions involved (Sec. 6.2)
+};
+
+struct Plan {
+  std::vector<PTensor> tensors;  // inputs first (n_sub), then step results
+  std::vector<Step> steps;
+  int out_bits = 0;
+  double mults = 0, max_intermediate = 0, max_step_operands = 0;
+  int64_t inter_bytes = 0;  // workspace for intermediates at the plan's element size
+};
+
+// Build the greedy pairwise plan for merged tensors with `bits[i]` active bits.
+// If `order` is non-null it gives the pairs to use (positions in a working list).
+// elem_bytes > 0 sizes the workspace for intermediates (and rejects plans whose
+// intermediates exceed 2^40 elements); elem_bytes == 0 only costs the plan.
+Plan make_plan(const Graph &g, const std::vector<int> &bits, const int *order,
+               int elem_bytes);
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+constexpr int kMaxWires = 32;  // outcome indices fit 32 bits
+constexpr int kMaxIncident = SQC_MAX_DEGREE;
+
+struct AttrArgs {
+  const void *var;   // [V][2^w]
+  void *out;         // [2^d][4^c]
+  int in_f32, out_f32;
+  int w, d, c;
+  int n_in, n_out;
+  int xt_bits;                 // log2 of the x-tile
+  int in_pos[kMaxIncident];    // incident position of the j-th in-cut
+  int out_pos[kMaxIncident];   // incident position of the j-th out-cut
+  int64_t place[kMaxIncident]; // variant mixed-radix place value per incident cut
+  int out_wire[kMaxIncident];  // wire of the j-th out-cut
+  int data_wire[64];
+  double scale;                // 2^-n_out
+};
+void launch_attribute(const AttrArgs &a, hipStream_t s);
+
+struct MergeArgs {
+  const void *in;   // attributed [2^d][L]
+  void *out;        // merged [L][2^a] (or partials [P][2^a][L] when P > 1)
+  double *partial;  // workspace for y-split partials
+  int in_f32, out_f32;
+  int d, lbits;     // L = 2^lbits = 4^c
+  int abits, mbits; // active, merged bit counts
+  uint64_t fixed_val, active, merged;
+  int ysplit_bits;  // P = 2^ysplit_bits
+  int tb_bits;      // log2 of the b-tile
+  int ts_bits;      // log2 of the sigma-tile
+};
+void launch_merge(const MergeArgs &a, hipStream_t s);
+// FP64 partial-sum elements the merge of these bit counts needs (0: none).
+int64_t merge_partial_elems(int abits, int lbits, int mbits);
+
+struct GemmArgs {
+  const void *A;
+  const void *B;
+  void *C;
+  int mbits, nbits, kbits;
+  IndexMap m, n, k;
+  int out_f32;           // output element type (intermediates follow the path)
+  int final_step;        // 1: compensated FP64 chunks + block statistics
+  int chunk_bits;        // K chunk for the compensated sum
+  // block statistics (final step with statistics)
+  int stats;
+  double *blk_sum;       // [nblk]
+  double *blk_max;       // [nblk]
+  unsigned int *counter; // zero between launches
+  double *tau_sum;       // [2]: threshold and total sum, written by the last block
+  int top_r;
+};
+int gemm_blocks(const GemmArgs &g, int prec);
+void launch_gemm(const GemmArgs &g, int prec, hipStream_t s);
+
+struct TopRArgs {
+  const void *C;        // final bins (dense, index = offset)
+  int out_f32;
+  int mbits, nbits;
+  IndexMap m, n;        // same geometry as the final GEMM (for tile addressing)
+  int nblk;
+  int prec;             // GEMM precision (tile shape)
+  const double *blk_max;
+  const double *tau_sum;
+  double *cand_val;     // [nblk][top_r]
+  uint64_t *cand_idx;   // [nblk][top_r]
+  unsigned int *counter;
+  int top_r;
+  double *top_out;      // top_r x {double, uint64}
+  double *sum_out;
+};
+void launch_topr(const TopRArgs &t, hipStream_t s);
+
+void launch_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace sqc

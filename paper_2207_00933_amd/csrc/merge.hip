@@ -1,0 +1,243 @@
+// States merging (Sec. 4, Algorithm 2): sum the attributed entries of the data
+// states that share a bin.
+//
+//   out[sigma][b] = sum_y T[x(b, y)][sigma],
+//   x(b, y) = fixed_val | deposit(b, active) | deposit(y, merged)
+//
+// The attributed tensor is stored [x][sigma] (labels fastest), so every state
+// x contributes one contiguous row of 4^c labels: a wave reads 64 consecutive
+// labels of one row and the reduction over y is a walk down rows.  For the
+// masks Algorithm 2 produces (fixed bits lowest, then active, then merged) the
+// rows of consecutive b are consecutive in memory at recursion 0.
+//
+// A work-group owns a tile of TB bins x TS labels.  Each thread accumulates in
+// FP64 in ascending y; thread rows that split y are combined in LDS in a fixed
+// order, and a y range split over work-groups (P > 1) goes through an FP64
+// partial buffer summed in ascending partial order, so results are
+// deterministic.  The tile is written [sigma][b] through LDS so that each
+// label row is written as a run of TB consecutive bins.
+#include "common.hpp"
+
+namespace sqc {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTile = 2048;  // outputs per work-group
+
+__device__ __forceinline__ double ld(const void *p, int64_t i, int f32) {
+  return f32 ? (double)static_cast<const float *>(p)[i] : static_cast<const double *>(p)[i];
+}
+
+__device__ __forceinline__ uint64_t deposit(uint64_t v, uint64_t mask) {
+  uint64_t out = 0;
+  for (int b = 0; mask; ++b) {
+    uint64_t low = mask & (~mask + 1);
+    if ((v >> b) & 1) out |= low;
+    mask ^= low;
+  }
+  return out;
+}
+
+__global__ __launch_bounds__(kThreads) void merge_tiles(MergeArgs a) {
+  __shared__ double tile[kTile + 64];
+  const int TS = 1 << a.ts_bits;
+  const int TB = 1 << a.tb_bits;
+  const int R = kThreads >> a.ts_bits;        // thread rows
+  const int RB = R < TB ? R : TB;             // rows that own distinct bins
+  const int YG = R / RB;                      // rows that split y inside the group
+  const int BPT = TB / RB;                    // bins per thread
+  const int tid = threadIdx.x;
+  const int sl = tid & (TS - 1);
+  const int r = tid >> a.ts_bits;
+  const int brow = r % RB;
+  const int g = r / RB;
+
+  const int64_t L = int64_t(1) << a.lbits;
+  const int nsig_tiles = (int)(L >> a.ts_bits);
+  const int64_t tile_id = blockIdx.x;
+  const int p = blockIdx.y;  // y split
+  const int st = (int)(tile_id % nsig_tiles);
+  const int64_t bt = tile_id / nsig_tiles;
+  const int64_t sigma = (int64_t(st) << a.ts_bits) + sl;
+  const int64_t b0 = bt << a.tb_bits;
+
+  const int64_t ny = int64_t(1) << (a.mbits - a.ysplit_bits);  // y per work-group
+  const int64_t y0 = int64_t(p) * ny;
+  const uint64_t nmerged = ~a.merged;
+
+  for (int i = 0; i < BPT; ++i) {
+    const int bl = brow + RB * i;
+    const int64_t b = b0 + bl;
+    const uint64_t xb = a.fixed_val | deposit((uint64_t)b, a.active);
+    double acc = 0.0;
+    // y = y0 + g, y0 + g + YG, ...: walk the merged bits' subsets in order
+    uint64_t z = deposit((uint64_t)(y0 + g), a.merged);
+    for (int64_t y = g; y < ny; y += YG) {
+      acc += ld(a.in, (int64_t)(xb | z) * L + sigma, a.in_f32);
+      for (int s = 0; s < YG; ++s) z = ((z | nmerged) + 1) & a.merged;
+    }
+    tile[(g * TB + bl) * TS + sl] = acc;
+  }
+  __syncthreads();
+  // combine the y groups in order; result at tile[bl * TS + sl]
+  if (YG > 1) {
+    for (int q = tid; q < TB * TS; q += kThreads) {
+      double s = tile[q];
+      for (int gg = 1; gg < YG; ++gg) s += tile[gg * TB * TS + q];
+      tile[q] = s;
+    }
+    __syncthreads();
+  }
+  // write: [sigma][b] with b fastest, or partial[p][b][sigma] with sigma fastest
+  const int64_t nb = int64_t(1) << a.abits;
+  if (a.ysplit_bits == 0) {
+    for (int q = tid; q < TB * TS; q += kThreads) {
+      int bl = q & (TB - 1);
+      int s = q >> a.tb_bits;
+      double v = tile[bl * TS + s];
+      int64_t o = ((int64_t(st) << a.ts_bits) + s) * nb + b0 + bl;
+      if (a.out_f32) static_cast<float *>(a.out)[o] = (float)v;
+      else static_cast<double *>(a.out)[o] = v;
+    }
+  } else {
+    for (int q = tid; q < TB * TS; q += kThreads) {
+      int s = q & (TS - 1);
+      int bl = q >> a.ts_bits;
+      a.partial[(int64_t(p) * nb + b0 + bl) * L + (int64_t(st) << a.ts_bits) + s] = tile[bl * TS + s];
+    }
+  }
+}
+
+// Large reductions: a thread owns V consecutive output columns c = b * L +
+// sigma (same bin, consecutive labels) and walks its share of the merged
+// states, four rows per iteration so that several loads are in flight.  The
+// work-group's FP64 partial sums go to partial[p][c].
+__global__ __launch_bounds__(kThreads) void merge_rows(MergeArgs a) {
+  const int V = a.lbits >= 2 ? 4 : 1;
+  const int64_t L = int64_t(1) << a.lbits;
+  const int64_t NC = int64_t(1) << (a.abits + a.lbits);
+  const int64_t c0 = (int64_t(blockIdx.x) * kThreads + threadIdx.x) * V;
+  if (c0 >= NC) return;
+  const int p = blockIdx.y;
+  const int64_t b = c0 >> a.lbits;
+  const int64_t sigma = c0 & (L - 1);
+  const uint64_t xb = a.fixed_val | deposit((uint64_t)b, a.active);
+  const int64_t ny = int64_t(1) << (a.mbits - a.ysplit_bits);
+  const uint64_t nmerged = ~a.merged;
+  uint64_t z = deposit((uint64_t)(int64_t(p) * ny), a.merged);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t y = 0;
+  if (a.in_f32) {
+    const float *in = static_cast<const float *>(a.in);
+    for (; y + 4 <= ny; y += 4) {
+      int64_t r[4];
+      for (int u = 0; u < 4; ++u) {
+        r[u] = (int64_t)(xb | z) * L + sigma;
+        z = ((z | nmerged) + 1) & a.merged;
+      }
+      if (V == 4) {
+        float4 v[4];
+        for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const float4 *>(in + r[u]);
+        for (int u = 0; u < 4; ++u) {
+          acc[0] += v[u].x; acc[1] += v[u].y; acc[2] += v[u].z; acc[3] += v[u].w;
+        }
+      } else {
+        float v[4];
+        for (int u = 0; u < 4; ++u) v[u] = in[r[u]];
+        for (int u = 0; u < 4; ++u) acc[0] += v[u];
+      }
+    }
+    for (; y < ny; ++y) {
+      int64_t r0 = (int64_t)(xb | z) * L + sigma;
+      z = ((z | nmerged) + 1) & a.merged;
+      for (int q = 0; q < V; ++q) acc[q] += in[r0 + q];
+    }
+  } else {
+    const double *in = static_cast<const double *>(a.in);
+    for (; y + 4 <= ny; y += 4) {
+      int64_t r[4];
+      for (int u = 0; u < 4; ++u) {
+        r[u] = (int64_t)(xb | z) * L + sigma;
+        z = ((z | nmerged) + 1) & a.merged;
+      }
+      if (V == 4) {
+        double2 v[4][2];
+        for (int u = 0; u < 4; ++u) {
+          v[u][0] = *reinterpret_cast<const double2 *>(in + r[u]);
+          v[u][1] = *reinterpret_cast<const double2 *>(in + r[u] + 2);
+        }
+        for (int u = 0; u < 4; ++u) {
+          acc[0] += v[u][0].x; acc[1] += v[u][0].y; acc[2] += v[u][1].x; acc[3] += v[u][1].y;
+        }
+      } else {
+        double v[4];
+        for (int u = 0; u < 4; ++u) v[u] = in[r[u]];
+        for (int u = 0; u < 4; ++u) acc[0] += v[u];
+      }
+    }
+    for (; y < ny; ++y) {
+      int64_t r0 = (int64_t)(xb | z) * L + sigma;
+      z = ((z | nmerged) + 1) & a.merged;
+      for (int q = 0; q < V; ++q) acc[q] += in[r0 + q];
+    }
+  }
+  double *dst = a.partial + int64_t(p) * NC + c0;
+  for (int q = 0; q < V; ++q) dst[q] = acc[q];
+}
+
+// Sum the partials of every column in ascending partial order and write
+// out[sigma][b] (columns are read contiguously; the output is small).
+__global__ __launch_bounds__(kThreads) void merge_finish(MergeArgs a) {
+  const int64_t NC = int64_t(1) << (a.abits + a.lbits);
+  const int64_t L = int64_t(1) << a.lbits;
+  const int64_t nb = int64_t(1) << a.abits;
+  const int P = 1 << a.ysplit_bits;
+  for (int64_t c = int64_t(blockIdx.x) * kThreads + threadIdx.x; c < NC;
+       c += int64_t(gridDim.x) * kThreads) {
+    double s = 0.0;
+    for (int q = 0; q < P; ++q) s += a.partial[int64_t(q) * NC + c];
+    int64_t o = (c & (L - 1)) * nb + (c >> a.lbits);
+    if (a.out_f32) static_cast<float *>(a.out)[o] = (float)s;
+    else static_cast<double *>(a.out)[o] = s;
+  }
+}
+
+}  // namespace
+
+int64_t merge_partial_elems(int abits, int lbits, int mbits) {
+  if (mbits < 6) return 0;
+  const int V = lbits >= 2 ? 4 : 1;
+  int64_t NC = int64_t(1) << (abits + lbits);
+  int64_t bx = (NC / V + kThreads - 1) / kThreads;
+  int ys = 0;
+  while (bx * (int64_t(2) << ys) <= 1024 && mbits - (ys + 1) >= 4) ++ys;
+  return NC << ys;
+}
+
+void launch_merge(const MergeArgs &a0, hipStream_t s) {
+  MergeArgs a = a0;
+  if (a.mbits >= 6) {
+    // streaming reduction over many merged states
+    const int V = a.lbits >= 2 ? 4 : 1;
+    int64_t NC = int64_t(1) << (a.abits + a.lbits);
+    int64_t bx = (NC / V + kThreads - 1) / kThreads;
+    int ys = 0;
+    while (bx * (int64_t(2) << ys) <= 1024 && a.mbits - (ys + 1) >= 4) ++ys;
+    a.ysplit_bits = ys;
+    hipLaunchKernelGGL(merge_rows, dim3((unsigned)bx, 1u << ys), dim3(kThreads), 0, s, a);
+    int64_t blocks = (NC + kThreads - 1) / kThreads;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(merge_finish, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+    return;
+  }
+  a.ysplit_bits = 0;
+  a.ts_bits = a.lbits < 6 ? a.lbits : 6;
+  int tb = 11 - a.ts_bits;  // kTile = 2^11 outputs
+  if (tb > a.abits) tb = a.abits;
+  a.tb_bits = tb;
+  int64_t tiles = (int64_t(1) << (a.lbits - a.ts_bits)) * (int64_t(1) << (a.abits - tb));
+  hipLaunchKernelGGL(merge_tiles, dim3((unsigned)tiles), dim3(kThreads), 0, s, a);
+}
+
+}  // namespace sqc

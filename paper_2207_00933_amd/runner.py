@@ -1,0 +1,123 @@
+"""Buffer management and call sequencing around libsqc for whole workloads.
+
+Nothing here computes: it allocates device buffers with PyTorch, uploads the
+variant probabilities, and calls the C entry points in order (attribute every
+subcircuit once, then recurse / search / contract).  The product path fails
+loudly when the HIP library or a GPU is missing.
+"""
+from __future__ import annotations
+
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import sqc
+
+_TORCH_DTYPE = {sqc.F64: torch.float64, sqc.F32: torch.float32}
+
+
+def _bytes_tensor(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Session:
+    """One context on one device with a caller-owned workspace."""
+
+    def __init__(self, device: int = 0, workspace_bytes: int = 64 << 20):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the reconstruction runs only on the HIP library")
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = sqc.ctx_create(device, self.stream.cuda_stream)
+        self.ws = None
+        self.ensure_workspace(workspace_bytes)
+
+    def ensure_workspace(self, nbytes: int) -> None:
+        if self.ws is not None and self.ws.numel() >= nbytes:
+            return
+        self.ws = _bytes_tensor(nbytes, self.device)
+        sqc.ctx_set_workspace(self.ctx, self.ws)
+
+    def close(self) -> None:
+        if self.ctx:
+            torch.cuda.synchronize(self.device)
+            sqc.ctx_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Circuit:
+    """A compute graph with its variants resident on the device."""
+
+    def __init__(self, session: Session, graph: sqc.Graph,
+                 variants: Sequence[np.ndarray], var_prec: int = sqc.F64):
+        self.s = session
+        self.g = graph
+        self.var_prec = var_prec
+        dt = _TORCH_DTYPE[var_prec]
+        self.var = [torch.from_numpy(np.ascontiguousarray(v)).to(dt).to(session.device)
+                    for v in variants]
+        self.att: List[sqc.Tensor] = []
+        self.att_buf: List[torch.Tensor] = []
+
+    @classmethod
+    def from_cut_circuit(cls, session: Session, cc, variants, var_prec: int = sqc.F64):
+        return cls(session, sqc.Graph.from_cut_circuit(cc), variants, var_prec)
+
+    def attribute(self, out_prec: int = sqc.F64) -> List[sqc.Tensor]:
+        """Attribute every subcircuit (one kernel launch each)."""
+        if len(self.att_buf) != self.g.n_sub or self.att[0].prec != out_prec:
+            self.att_buf = [_bytes_tensor(sqc.attribute_bytes(self.g, i, out_prec), self.s.device)
+                            for i in range(self.g.n_sub)]
+        self.att = [sqc.attribute(self.s.ctx, self.g, i, self.var[i], self.var_prec,
+                                  self.att_buf[i], out_prec)
+                    for i in range(self.g.n_sub)]
+        return self.att
+
+    def attributed_numpy(self, i: int) -> np.ndarray:
+        """Attributed tensor i as [2^d][4^c] float64 (host copy)."""
+        t = self.att[i]
+        n = (1 << t.n_bits) << (2 * t.n_labels)
+        dt = _TORCH_DTYPE[t.prec]
+        x = self.att_buf[i][: n * (8 if t.prec == sqc.F64 else 4)].view(dt)
+        return x.double().cpu().numpy().reshape(1 << t.n_bits, 1 << (2 * t.n_labels))
+
+
+class Recursion:
+    """Output buffers for sqc_recurse at a given largest bin count."""
+
+    def __init__(self, circ: Circuit, max_bits: int, bins_prec: int, top_r: int):
+        s = circ.s
+        self.c = circ
+        self.bins_prec = bins_prec
+        self.top_r = top_r
+        self.bins = torch.empty(1 << max_bits, dtype=_TORCH_DTYPE[bins_prec], device=s.device)
+        self.top = torch.empty(2 * sqc.MAX_TOPR, dtype=torch.float64, device=s.device)
+        self.sum = torch.empty(1, dtype=torch.float64, device=s.device)
+
+    def run(self, prec: int, M: int, scope=None) -> List[sqc.Masks]:
+        c = self.c
+        # reserve workspace for the masks this call will use
+        masks = sqc.assign_bins(c.g.n_data, scope, M)
+        need = sqc.recurse_workspace_bytes(c.att, c.g, masks, prec)
+        if need == 0:
+            raise RuntimeError(sqc.lib().sqc_last_error(None).decode())
+        c.s.ensure_workspace(need)
+        return sqc.recurse(c.s.ctx, c.att, c.g, scope, M, self.top_r, prec, self.bins,
+                           self.bins_prec, self.top, self.sum)
+
+    def top_list(self):
+        t = self.top.cpu().numpy()
+        vals = t[0:2 * self.top_r:2]
+        idx = t[1:2 * self.top_r:2].view(np.uint64)
+        return vals, idx
+
+
+def active_bits(masks: Sequence[sqc.Masks]) -> int:
+    return sum(bin(m.active).count("1") for m in masks)

@@ -1,0 +1,168 @@
+"""The C library without a GPU: it loads, exports every declared symbol, and
+its host logic (graph validation, Algorithm 2 as masks, bin scopes, the
+Sec. 6.2 cost model, Sec. 6.3 slicing) agrees with the oracle and with the
+paper's worked example."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cost as ocost
+from oracle import states_merging as sm
+from workloads import configs
+
+sqc = pytest.importorskip("paper_2207_00933_amd.sqc")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EX = json.load(open(os.path.join(HERE, "golden", "cost_example.json")))
+
+
+def test_library_exports_every_declared_symbol():
+    L = sqc.lib()
+    names = sqc.declared_symbols()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing
+    assert "gfx950" in sqc.version()
+
+
+def test_no_gpu_is_reported():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(sqc.SqcError) as e:
+        sqc.ctx_create(0)
+    assert e.value.status == sqc.E_DEVICE
+
+
+def test_check_graph_accepts_workloads():
+    for cc in (configs.tiny(), configs.precision(), configs.merging(), configs.large()):
+        sqc.check_graph(sqc.Graph.from_cut_circuit(cc))
+
+
+@pytest.mark.parametrize("bad,status", [
+    ("self_cut", sqc.E_SHAPE), ("wire_range", sqc.E_SHAPE), ("orphan_wire", sqc.E_SHAPE),
+    ("double_measure", sqc.E_SHAPE), ("degree", sqc.E_SHAPE), ("sub_range", sqc.E_SHAPE),
+])
+def test_check_graph_rejects(bad, status):
+    n_wires = [3, 3]
+    data = [[1, 2], [0, 1, 2]]
+    cuts = [(0, 0, 1, 0)]
+    if bad == "self_cut":
+        cuts = [(0, 0, 0, 1)]
+    elif bad == "wire_range":
+        cuts = [(0, 5, 1, 0)]
+    elif bad == "orphan_wire":
+        data = [[2], [0, 1, 2]]
+    elif bad == "double_measure":
+        cuts = [(0, 0, 1, 0), (0, 0, 1, 1)]
+    elif bad == "degree":
+        n_wires = [16, 16]
+        data = [[], list(range(16))]
+        cuts = [(0, k, 1, k) for k in range(16)]
+    elif bad == "sub_range":
+        cuts = [(0, 0, 2, 0)]
+    g = sqc.Graph(n_wires, data, cuts)
+    with pytest.raises(sqc.SqcError) as e:
+        sqc.check_graph(g)
+    assert e.value.status == status
+    assert str(e.value)
+
+
+def _partition_from_masks(m, d):
+    """Bins (as sets) described by one subcircuit's masks over d data bits."""
+    bins = {}
+    for x in range(1 << d):
+        if (x & m.fixed) != m.fixed_val:
+            continue
+        b = 0
+        j = 0
+        for bit in range(d):
+            if (m.active >> bit) & 1:
+                b |= ((x >> bit) & 1) << j
+                j += 1
+        bins.setdefault(b, []).append(x)
+    return [sorted(bins[k]) for k in sorted(bins)]
+
+
+@pytest.mark.parametrize("n_list,M", [([3, 4, 2], 16), ([5, 5], 8), ([1, 6, 3], 1000),
+                                      ([4, 4, 4], 1), ([2, 3], 64), ([6, 2, 5, 1], 37)])
+def test_assign_bins_equals_algorithm2(n_list, M):
+    masks = sqc.assign_bins(n_list, None, M)
+    lit = sm.assign_states(0, None, M, n_list)
+    for i, d in enumerate(n_list):
+        assert _partition_from_masks(masks[i], d) == lit[i]
+    # recursion 1 inside a chosen bin
+    counts = [len(b) for b in lit]
+    for k in (0, int(np.prod(counts)) - 1, int(np.prod(counts)) // 3):
+        ks = sm.split_index(k, counts)
+        states = [lit[i][ks[i]] for i in range(len(n_list))]
+        scope = sqc.bin_scope(masks, k)
+        m1 = sqc.assign_bins(n_list, scope, M)
+        lit1 = sm.assign_states(1, states, M, n_list)
+        for i, d in enumerate(n_list):
+            assert _partition_from_masks(m1[i], d) == lit1[i]
+
+
+def test_assign_bins_workload_shapes():
+    m = sqc.assign_bins([16, 14, 16, 14], None, 1 << 20)
+    assert [bin(x.active).count("1") for x in m] == [5, 5, 5, 5]
+    cc = configs.large()
+    d = [s.n_data for s in cc.subs]
+    m = sqc.assign_bins(d, None, 1 << 24)
+    a = [bin(x.active).count("1") for x in m]
+    assert sorted(a) == [1] * 8 + [2] * 8
+    # same bin counts as the literal algorithm (on the counts alone)
+    lp = [1 << v for v in d]
+    while int(np.prod([float(v) for v in lp])) > (1 << 24):
+        i = int(np.argmax(lp))
+        lp[i] = -(-lp[i] // 2)
+    assert [int(np.log2(v)) for v in lp] == a
+
+
+def test_assign_bins_rejects_bad_scope():
+    with pytest.raises(sqc.SqcError):
+        sqc.assign_bins([3], [(0b1000, 0, 0, 0)], 4)
+    with pytest.raises(sqc.SqcError):
+        sqc.assign_bins([3], [(0b001, 0b010, 0, 0)], 4)
+    with pytest.raises(sqc.SqcError):
+        sqc.assign_bins([3], None, 0)
+
+
+def test_cost_model_paper_example():
+    qubits = EX["graph"]["qubits"]
+    cuts = EX["graph"]["cuts"]
+    order = [v for p in EX["order"] for v in p]
+    c = sqc.plan_cost(qubits, cuts, order)
+    assert c.input_floats == EX["input_floats"]
+    assert c.plan_mults == sum(EX["step_mults"])
+    assert c.naive_mults == EX["naive_mults"]
+    assert round(c.naive_mults / c.plan_mults, 1) == EX["naive_over_plan"]
+    # the library's own planner finds a plan no worse than the paper's
+    c2 = sqc.plan_cost(qubits, cuts, None)
+    assert c2.plan_mults <= c.plan_mults
+
+
+def test_cost_model_matches_oracle_on_workloads():
+    for cc in (configs.precision(), configs.merging(), configs.large()):
+        d = [s.n_data for s in cc.subs]
+        cuts = [(c.up_sub, c.down_sub) for c in cc.cuts]
+        c = sqc.plan_cost(d, cuts, None)
+        ts = [(frozenset(k for k, _ in cc.incident(i)), 1 << d[i]) for i in range(cc.n_sub)]
+        assert c.input_floats == ocost.input_floats(ts)
+        order = [(c.order[2 * s], c.order[2 * s + 1]) for s in range(c.n_steps)]
+        _, total = ocost.plan_cost(ts, order)
+        assert c.plan_mults == pytest.approx(total, rel=1e-12)
+        assert c.naive_mults == pytest.approx(ocost.naive_mults(len(cc.cuts), [t[1] for t in ts]),
+                                              rel=1e-12)
+
+
+def test_slicing_paper_example():
+    qubits = EX["graph"]["qubits"]
+    cuts = EX["graph"]["cuts"]
+    chosen = sqc.slice_plan(qubits, cuts, EX["sliced_input_floats"])
+    assert len(chosen) == 1 and tuple(cuts[chosen[0]]) == (0, 2)
+    ts = [(frozenset(k for k, c in enumerate(cuts) if i in c), 1 << q) for i, q in enumerate(qubits)]
+    assert chosen == ocost.greedy_slices(ts, EX["sliced_input_floats"])
