@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark: reconstructed bins per second on one MI355X.
+
+Workload ("precision"): a seeded 24-qubit random brickwork circuit (5 layers
+of sqrt(X)/sqrt(Y)/sqrt(W) + CZ), cut by 6 wire cuts into a chain of 3
+subcircuits; subcircuit outputs from FP64 statevector simulation, cast to
+FP32.  One step is the whole hot path on those inputs, already resident in
+HBM: attribution of the three subcircuits, bin assignment, merge, the
+pairwise contraction into all 2^24 bins, the top-R bins and the FP64 bin sum.
+
+The step is timed for three contraction precisions (FP64 plain, FP32 MFMA,
+split-BF16x3 with an FP64-compensated final sum); ``value`` is the faster of
+the two fast forms, whose bins are also compared with the FP64 GPU path.
+The final contraction kernel is bracketed by HIP events inside the timed
+loop to report its roofline fraction.  The CPU baseline is the FP64 oracle
+(Eq. 1 evaluated bin by bin) on a bounded sample of bins, timed on the host's
+cores before the GPU is touched.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from workloads import configs, qpu  # noqa: E402
+
+HBM_PEAK = 8.0e12                      # B/s
+PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16x3": 2.5e15}  # dense MFMA flop/s
+PREC_ID = {"f64": 0, "f32": 1, "bf16x3": 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on a bounded sample of bins
+# ---------------------------------------------------------------------------
+
+_CPU = {}
+
+
+def _cpu_worker(chunk):
+    from oracle import reconstruction as rc
+    t0 = time.perf_counter()
+    rc.eval_bins(_CPU["Ts"], _CPU["cc"], chunk)
+    return len(chunk), time.perf_counter() - t0
+
+
+def cpu_baseline(cc, var32, seconds: float):
+    import multiprocessing as mp
+    from oracle import reconstruction as rc
+    Ts = [rc.attribute(cc, i, var32[i].astype(np.float64)) for i in range(cc.n_sub)]
+    _CPU["Ts"], _CPU["cc"] = Ts, cc
+    # calibrate the per-bin cost on one core
+    rng = np.random.default_rng(0)
+    probe = rng.integers(0, 1 << cc.n, size=64)
+    t0 = time.perf_counter()
+    rc.eval_bins(Ts, cc, probe)
+    per_bin = (time.perf_counter() - t0) / len(probe)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    workers = max(1, min(16, cores))
+    per_worker = max(16, int(seconds / per_bin))
+    sample = rng.integers(0, 1 << cc.n, size=per_worker * workers)
+    chunks = [sample[w * per_worker:(w + 1) * per_worker] for w in range(workers)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_cpu_worker, chunks)
+    wall = time.perf_counter() - t0
+    nb = sum(r[0] for r in res)
+    return {"value": nb / wall, "unit": "bins/s", "cores": workers, "kind": "oracle",
+            "sample": f"{nb} bins drawn uniformly from the 2^24 outputs, Eq. 1 evaluated "
+                      f"bin by bin (4^6 label assignments each) in FP64 by {workers} worker "
+                      f"processes; {wall:.1f} s wall; attribution excluded",
+            "wall_s": wall}
+
+
+# ---------------------------------------------------------------------------
+# GPU
+# ---------------------------------------------------------------------------
+
+def run_gpu(cc, var32, steps: int, warmup: int, precs):
+    import torch
+    from paper_2207_00933_amd import runner, sqc
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU (the HIP library is the only compute path)")
+    s = runner.Session(0, 64 << 20)
+    circ = runner.Circuit.from_cut_circuit(s, cc, var32, sqc.F32)
+    nbits = cc.n
+    M = 1 << nbits
+    out = {}
+    ref_bins = None
+    for pname in precs:
+        prec = PREC_ID[pname]
+        att_prec = sqc.F64 if prec == sqc.F64 else sqc.F32
+        bins_prec = sqc.F64 if prec == sqc.F64 else sqc.F32
+        rec = runner.Recursion(circ, nbits, bins_prec, 16)
+
+        def step():
+            circ.attribute(att_prec)
+            rec.run(prec, M)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        sqc.ctx_timing(s.ctx, sqc.STAGE_FINAL, reset=True)
+        sqc.ctx_set_timing(s.ctx, sqc.STAGE_FINAL)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs[0].record()
+        for k in range(steps):
+            step()
+            evs[k + 1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sqc.ctx_set_timing(s.ctx, 0)
+        fin = sqc.ctx_timing(s.ctx, sqc.STAGE_FINAL, reset=True)
+        lat = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(steps))
+        ms = wall * 1e3 / steps
+        res = {
+            "ms_per_step": ms,
+            "bins_per_s": M / (ms * 1e-3),
+            "p50_ms": lat[len(lat) // 2],
+            "p99_ms": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
+            "final_kernel_us": fin.ms * 1e3 / max(1, fin.launches),
+            "final_kernel_bytes": fin.bytes / max(1, fin.launches),
+            "final_kernel_flops": fin.flops / max(1, fin.launches),
+            "bins_sum": rec.sum.item(),
+        }
+        b = rec.bins.double()
+        if prec == sqc.F64:
+            ref_bins = b.clone()
+        elif ref_bins is not None:
+            res["max_abs_vs_fp64_gpu"] = (b - ref_bins).abs().max().item()
+        out[pname] = res
+        log(f"[bench] {pname}: {ms:.4f} ms/step, {res['bins_per_s']:.3e} bins/s, "
+            f"final kernel {res['final_kernel_us']:.2f} us")
+        del rec
+    s.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU work per worker for the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precs", default="f64,f32,bf16x3")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "reconstruction of one circuit is a single-GPU job here", file=sys.stderr)
+        sys.exit(2)
+
+    cc = configs.precision()
+    var64 = qpu.all_variants(cc)
+    var32 = [v.astype(np.float32) for v in var64]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline ...")
+        cpu = cpu_baseline(cc, var32, args.cpu_seconds)
+        log(f"[bench] CPU oracle: {cpu['value']:.3e} bins/s on {cpu['cores']} cores")
+
+    precs = [p for p in args.precs.split(",") if p]
+    gpu = run_gpu(cc, var32, args.steps, args.warmup, precs)
+    fast = [p for p in ("bf16x3", "f32") if p in gpu]
+    head = max(fast, key=lambda p: gpu[p]["bins_per_s"]) if fast else precs[0]
+    h = gpu[head]
+    t_hbm = h["final_kernel_bytes"] / HBM_PEAK
+    t_mfma = h["final_kernel_flops"] / PEAK[head]
+    if t_hbm >= t_mfma:
+        roof = {"bound": "hbm", "achieved": h["final_kernel_bytes"] / (h["final_kernel_us"] * 1e-6) / 1e9,
+                "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": h["final_kernel_flops"] / (h["final_kernel_us"] * 1e-6) / 1e12,
+                "peak": PEAK[head] / 1e12, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"final contraction step ({head})"
+    roof["kernel_us"] = h["final_kernel_us"]
+    line = {
+        "metric": "reconstructed bins/s",
+        "value": h["bins_per_s"],
+        "unit": "bins/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {"workload": "precision: 24-qubit random brickwork (5 layers), chain of 3 "
+                               "subcircuits, 6 cuts, FP32-cast subcircuit outputs, full 2^24 "
+                               "reconstruction (attribution + merge + contraction + top-16 + sum)",
+                   "qubits": cc.n, "subcircuits": cc.n_sub, "cuts": len(cc.cuts),
+                   "bins": 1 << cc.n},
+        "roofline": roof,
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in
+                                                  ("value", "unit", "cores", "kind", "sample")},
+        "paths": gpu,
+        "latency_ms": {"p50": h["p50_ms"], "p99": h["p99_ms"]},
+    }
+    if "f64" in gpu:
+        line["speedup_vs_fp64_gpu"] = h["bins_per_s"] / gpu["f64"]["bins_per_s"]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

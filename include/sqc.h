@@ -136,6 +136,27 @@ sqc_status sqc_ctx_set_stream(sqc_ctx *ctx, void *hip_stream);
  * pointer until it is replaced or the context is destroyed; the caller must
  * keep the buffer alive that long.  The buffer is initialised on the stream. */
 sqc_status sqc_ctx_set_workspace(sqc_ctx *ctx, void *dev, size_t bytes);
+/* Stage timing.  With a non-zero mask, every kernel launch of the selected
+ * stages is bracketed by HIP events on the context's stream, and the library
+ * adds the launch's algorithmic bytes (inputs read once, outputs written once)
+ * and useful flops (2 M N K per GEMM) to the stage's totals. */
+#define SQC_STAGE_ATTRIBUTE 1u
+#define SQC_STAGE_MERGE 2u
+#define SQC_STAGE_CONTRACT 4u    /* contraction steps before the last     */
+#define SQC_STAGE_FINAL 8u       /* last contraction step (bins written)  */
+#define SQC_STAGE_TOPR 16u
+typedef struct {
+  double ms;          /* summed event time of the stage's launches         */
+  int64_t launches;
+  double bytes;       /* summed algorithmic bytes                          */
+  double flops;       /* summed useful floating-point operations           */
+} sqc_stage_time;
+sqc_status sqc_ctx_set_timing(sqc_ctx *ctx, uint32_t stage_mask);
+/* Wait for the recorded events and report the totals of one stage (one bit
+ * of the mask) since the last reset; `reset` clears every stage afterwards. */
+sqc_status sqc_ctx_timing(sqc_ctx *ctx, uint32_t stage, int32_t reset,
+                          sqc_stage_time *out);
+
 /* Message describing the last error of this context (or of the calling
  * thread's last context-less call when ctx is NULL).  Never NULL. */
 const char *sqc_last_error(const sqc_ctx *ctx);

@@ -37,15 +37,25 @@ struct sqc_ctx {
   size_t ws_bytes = 0;
   std::string err;
   void *pinned = nullptr;  // host staging for small device results
+  // stage timing
+  uint32_t timing_mask = 0;
+  struct Mark {
+    int stage;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  struct Tot {
+    double ms = 0, bytes = 0, flops = 0;
+    int64_t n = 0;
+  } tot[5];
 };
 
 namespace {
 
 // Control region at the start of the workspace.
 constexpr size_t kCtlBytes = 4096;
-constexpr size_t kOffGemmCounter = 0;    // uint32
-constexpr size_t kOffTopCounters = 16;   // 2 x uint32
-constexpr size_t kOffTauSum = 64;        // 2 x double
 constexpr size_t kOffUnit = 128;         // double 1.0 then float 1.0
 constexpr size_t kOffSearchTop = 256;    // SQC_MAX_TOPR x 16 bytes
 constexpr size_t kOffSearchSum = 256 + 16 * SQC_MAX_TOPR;
@@ -110,6 +120,62 @@ void check_size(int lbits, int dbits) {
   if (lbits + dbits > 40) raise(SQC_E_UNSUPPORTED, "tensor larger than 2^40 elements");
 }
 
+int stage_index(uint32_t bit) {
+  for (int q = 0; q < 5; ++q)
+    if (bit == (1u << q)) return q;
+  return -1;
+}
+
+hipEvent_t take_event(sqc_ctx *ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  check_hip(hipEventCreate(&e), "hipEventCreate");
+  return e;
+}
+
+// Bracket one launch of `stage` with events when timing is on for it.
+struct StageMark {
+  sqc_ctx *ctx;
+  uint32_t stage;
+  bool on;
+  hipEvent_t a{}, b{};
+  double bytes, flops;
+  StageMark(sqc_ctx *c, uint32_t st, double by, double fl)
+      : ctx(c), stage(st), on((c->timing_mask & st) != 0), bytes(by), flops(fl) {
+    if (on) {
+      a = take_event(ctx);
+      b = take_event(ctx);
+      check_hip(hipEventRecord(a, ctx->stream), "hipEventRecord");
+    }
+  }
+  void done() {
+    if (!on) return;
+    check_hip(hipEventRecord(b, ctx->stream), "hipEventRecord");
+    ctx->marks.push_back(sqc_ctx::Mark{stage_index(stage), a, b, bytes, flops});
+    on = false;
+  }
+};
+
+void settle_timing(sqc_ctx *ctx) {
+  for (auto &m : ctx->marks) {
+    check_hip(hipEventSynchronize(m.b), "hipEventSynchronize");
+    float ms = 0.f;
+    check_hip(hipEventElapsedTime(&ms, m.a, m.b), "hipEventElapsedTime");
+    auto &t = ctx->tot[m.stage];
+    t.ms += ms;
+    t.n += 1;
+    t.bytes += m.bytes;
+    t.flops += m.flops;
+    ctx->pool.push_back(m.a);
+    ctx->pool.push_back(m.b);
+  }
+  ctx->marks.clear();
+}
+
 // ---------------------------------------------------------------------------
 // shared pieces of merge / contract / recurse
 // ---------------------------------------------------------------------------
@@ -129,8 +195,21 @@ void enqueue_merge(sqc_ctx *ctx, const sqc_tensor &at, const sqc_masks &mk, void
   a.fixed_val = mk.fixed_val;
   a.active = mk.active;
   a.merged = mk.merged;
+  auto run_lo = [](uint64_t m) -> int {
+    if (!m) return 0;
+    const int lo = __builtin_ctzll(m);
+    const uint64_t r = m >> lo;
+    return (r & (r + 1)) == 0 ? lo : -1;
+  };
+  a.act_lo = run_lo(mk.active);
+  a.mrg_lo = run_lo(mk.merged);
+  const double in_b = at.prec == SQC_F32 ? 4 : 8, out_b = out_f32 ? 4 : 8;
+  const double nread = std::ldexp(1.0, 2 * at.n_labels + a.abits + a.mbits);
+  const double nout = std::ldexp(1.0, 2 * at.n_labels + a.abits);
+  StageMark mark(ctx, SQC_STAGE_MERGE, nread * in_b + nout * out_b, nread);
   launch_merge(a, ctx->stream);
   after_launch("merge kernel launch");
+  mark.done();
 }
 
 size_t merge_ws(const sqc_tensor &at, const sqc_masks &mk) {
@@ -168,6 +247,8 @@ GemmArgs step_args(const Contraction &c, size_t si, const std::vector<const void
       g.m.bits[0] = g.mbits;
       g.m.sx[0] = 1;
       g.m.sy[0] = 1;
+      g.m.lx[0] = 0;
+      g.m.ly[0] = 0;
     }
     g.out_f32 = bins_f32;
     g.final_step = 1;
@@ -194,10 +275,9 @@ GemmArgs step_args(const Contraction &c, size_t si, const std::vector<const void
   return g;
 }
 
-int chunk_bits_for(sqc_prec prec) { return prec == SQC_BF16X3 ? 5 : 5; }
-
 // Workspace needed after the control region: intermediates + statistics.
 size_t contraction_ws(const Contraction &c, int top_r, bool stats, int prec) {
+  (void)prec;
   size_t b = align256(c.plan.inter_bytes);
   if (stats) {
     GemmArgs dummy{};
@@ -208,12 +288,24 @@ size_t contraction_ws(const Contraction &c, int top_r, bool stats, int prec) {
       dummy.mbits = st.mbits;
       dummy.nbits = st.nbits;
     }
-    size_t nblk = (size_t)gemm_blocks(dummy, prec);
-    b += 2 * align256(nblk * sizeof(double));
-    b += 2 * align256(nblk * (size_t)top_r * 8);
+    const size_t nsub = 4 * (size_t)gemm_tiles(dummy);
+    b += 2 * align256(nsub * sizeof(double));   // sub-tile sums and maxima
+    b += 2 * align256(nsub * sizeof(int));      // candidate list, slot counts
+    b += align256(64);                          // threshold, sum, count
+    b += 2 * align256(nsub * (size_t)top_r * 8);
+
   }
   return b;
 }
+
+// Algorithmic bytes of one GEMM step: each operand element read once, each
+// result written once.
+double gemm_bytes(const GemmArgs &g, int path_f32) {
+  const double eb = path_f32 ? 4 : 8, ob = g.out_f32 ? 4 : 8;
+  return (std::ldexp(1.0, g.mbits + g.kbits) + std::ldexp(1.0, g.nbits + g.kbits)) * eb +
+         std::ldexp(1.0, g.mbits + g.nbits) * ob;
+}
+double gemm_flops(const GemmArgs &g) { return std::ldexp(2.0, g.mbits + g.nbits + g.kbits); }
 
 struct StatsBufs {
   double *blk_sum, *blk_max, *cand_val;
@@ -232,20 +324,22 @@ void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<c
   size_t nsteps = c.unit ? 1 : c.plan.steps.size();
   for (size_t si = 0; si < nsteps; ++si) {
     GemmArgs g = step_args(c, si, inputs, ws, inter_base, bins, bins_f32, unit);
-    g.chunk_bits = chunk_bits_for(prec);
+    if (g.mbits > 31 || g.nbits > 31 || g.kbits > 31)
+      raise(SQC_E_UNSUPPORTED, "a contraction dimension exceeds 2^31");
     bool last = si + 1 == nsteps;
     if (last && top_dev) {
-      size_t nblk = (size_t)gemm_blocks(g, prec);
+      const size_t nsub = 4 * (size_t)gemm_tiles(g);
       Bump bp;
       bp.off = stats_base;
       g.stats = 1;
-      g.blk_sum = reinterpret_cast<double *>(ws + bp.take(nblk * sizeof(double)));
-      g.blk_max = reinterpret_cast<double *>(ws + bp.take(nblk * sizeof(double)));
-      g.counter = reinterpret_cast<unsigned int *>(ws + kOffGemmCounter);
-      g.tau_sum = reinterpret_cast<double *>(ws + kOffTauSum);
-      g.top_r = top_r;
-      launch_gemm(g, prec, ctx->stream);
-      after_launch("contraction kernel launch");
+      g.blk_sum = reinterpret_cast<double *>(ws + bp.take(nsub * sizeof(double)));
+      g.blk_max = reinterpret_cast<double *>(ws + bp.take(nsub * sizeof(double)));
+      {
+        StageMark mark(ctx, SQC_STAGE_FINAL, gemm_bytes(g, c.path_f32), gemm_flops(g));
+        launch_gemm(g, prec, ctx->stream);
+        after_launch("contraction kernel launch");
+        mark.done();
+      }
       TopRArgs t{};
       t.C = bins;
       t.out_f32 = bins_f32;
@@ -253,21 +347,31 @@ void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<c
       t.nbits = g.nbits;
       t.m = g.m;
       t.n = g.n;
-      t.nblk = (int)nblk;
-      t.prec = prec;
+      t.nsub = (int)nsub;
+      t.blk_sum = g.blk_sum;
       t.blk_max = g.blk_max;
-      t.tau_sum = g.tau_sum;
-      t.cand_val = reinterpret_cast<double *>(ws + bp.take(nblk * (size_t)top_r * 8));
-      t.cand_idx = reinterpret_cast<uint64_t *>(ws + bp.take(nblk * (size_t)top_r * 8));
-      t.counter = reinterpret_cast<unsigned int *>(ws + kOffTopCounters);
+      t.cand = reinterpret_cast<int *>(ws + bp.take(nsub * sizeof(int)));
+      t.slot_n = reinterpret_cast<int *>(ws + bp.take(nsub * sizeof(int)));
+      char *misc = ws + bp.take(64);
+      t.tau_sum = reinterpret_cast<double *>(misc);
+      t.cand_count = reinterpret_cast<int *>(misc + 16);
+      t.slot_val = reinterpret_cast<double *>(ws + bp.take(nsub * (size_t)top_r * 8));
+      t.slot_idx = reinterpret_cast<uint64_t *>(ws + bp.take(nsub * (size_t)top_r * 8));
       t.top_r = top_r;
       t.top_out = static_cast<double *>(top_dev);
       t.sum_out = static_cast<double *>(sum_dev);
-      launch_topr(t, ctx->stream);
-      after_launch("top-R kernel launch");
+      {
+        StageMark mark(ctx, SQC_STAGE_TOPR, 0.0, 0.0);
+        launch_topr(t, ctx->stream);
+        after_launch("top-R kernel launch");
+        mark.done();
+      }
     } else {
+      StageMark mark(ctx, last ? SQC_STAGE_FINAL : SQC_STAGE_CONTRACT, gemm_bytes(g, c.path_f32),
+                     gemm_flops(g));
       launch_gemm(g, prec, ctx->stream);
       after_launch("contraction kernel launch");
+      mark.done();
     }
   }
 }
@@ -414,7 +518,14 @@ sqc_status sqc_ctx_create(int device, void *hip_stream, sqc_ctx **out) {
 
 sqc_status sqc_ctx_destroy(sqc_ctx *ctx) {
   if (!ctx) return SQC_E_ARG;
-  if (ctx->pinned) hipHostFree(ctx->pinned);
+  (void)hipSetDevice(ctx->device);
+  for (auto &m : ctx->marks) {
+    (void)hipEventSynchronize(m.b);
+    (void)hipEventDestroy(m.a);
+    (void)hipEventDestroy(m.b);
+  }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return SQC_OK;
 }
@@ -422,6 +533,29 @@ sqc_status sqc_ctx_destroy(sqc_ctx *ctx) {
 sqc_status sqc_ctx_set_stream(sqc_ctx *ctx, void *hip_stream) {
   SQC_TRY(ctx)
   ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_ctx_set_timing(sqc_ctx *ctx, uint32_t stage_mask) {
+  SQC_TRY(ctx)
+  ctx->timing_mask = stage_mask & 31u;
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_ctx_timing(sqc_ctx *ctx, uint32_t stage, int32_t reset, sqc_stage_time *out) {
+  SQC_TRY(ctx)
+  int q = stage_index(stage);
+  if (q < 0 || !out) raise(SQC_E_ARG, "stage must be one SQC_STAGE_* bit and out non-NULL");
+  use_device(ctx);
+  settle_timing(ctx);
+  out->ms = ctx->tot[q].ms;
+  out->launches = ctx->tot[q].n;
+  out->bytes = ctx->tot[q].bytes;
+  out->flops = ctx->tot[q].flops;
+  if (reset)
+    for (auto &t : ctx->tot) t = sqc_ctx::Tot{};
   return SQC_OK;
   SQC_CATCH(ctx)
 }
@@ -493,8 +627,13 @@ sqc_status sqc_attribute(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, int32
   for (int j = 0; j < s.d; ++j) a.data_wire[j] = s.data_wire[j];
   a.scale = std::ldexp(1.0, -a.n_out);
   use_device(ctx);
+  const double nvar = double(s.variants) * std::ldexp(1.0, s.w);
+  const double nout = std::ldexp(1.0, 2 * c + s.d);
+  StageMark mark(ctx, SQC_STAGE_ATTRIBUTE,
+                 nvar * (a.in_f32 ? 4 : 8) + nout * (a.out_f32 ? 4 : 8), nvar);
   launch_attribute(a, ctx->stream);
   after_launch("attribution kernel launch");
+  mark.done();
   out->n_labels = c;
   out->n_bits = s.d;
   out->layout = SQC_LAYOUT_ATTRIBUTED;

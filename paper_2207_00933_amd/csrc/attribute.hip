@@ -21,7 +21,9 @@ namespace sqc {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kLdsElems = 4096;  // doubles staged per work-group
+constexpr int kLdsElems = 2048;  // doubles staged per work-group
+constexpr int kMaxNS = 1024;     // preparation patterns a work-group tabulates
+constexpr int kMaxNB = 1024;     // out-cut outcome patterns
 
 __device__ __forceinline__ double load_prob(const void *p, int64_t i, int f32) {
   return f32 ? (double)static_cast<const float *>(p)[i] : static_cast<const double *>(p)[i];
@@ -29,30 +31,39 @@ __device__ __forceinline__ double load_prob(const void *p, int64_t i, int f32) {
 
 __global__ __launch_bounds__(kThreads) void attribute_lds(AttrArgs a) {
   __shared__ double buf[kLdsElems];
-  // outcome offsets: [0, XT) data-state tile entries, [XT, XT + NB) out-cut
-  // bit patterns (XT * NB <= kLdsElems, so XT + NB <= kLdsElems + 1)
-  __shared__ uint32_t offs[kLdsElems + 1];
+  // per work-group tables (NS * XT * NB <= kLdsElems, NS <= kMaxNS, NB <= kMaxNB):
+  //   vtab[s]   variant row offset of preparation index s (with this beta)
+  //   xoff[xt]  outcome offset of tile entry xt;  boff[b] of out-cut bits b
+  //   sin[s]    label index contributed by the in-cut digits of s
+  //   sout[v]   label index of valid out-cut slot v;  slot[v] its bit pattern
+  __shared__ uint32_t tab[kLdsElems + 2 * kMaxNB + 64];
+  __shared__ int64_t vtab[kMaxNS];
   const int tid = threadIdx.x;
   const int XT = 1 << a.xt_bits;
   const int NB = 1 << a.n_out;
   const int NS = 1 << (2 * a.n_in);
   const int E = NS * XT * NB;
   const int64_t x0 = int64_t(blockIdx.x) << a.xt_bits;
-  uint32_t *xt_off = offs;
-  uint32_t *b_off = offs + XT;
 
   // basis digits of this work-group and the fixed part of the variant index
   int beta[kMaxIncident];
   int64_t vbeta = 0;
+  int nz = 0;
   {
     int rem = blockIdx.y;
     for (int j = 0; j < a.n_out; ++j) {
       beta[j] = rem % 3;
       rem /= 3;
       vbeta += int64_t(beta[j]) * a.place[a.out_pos[j]];
+      nz += beta[j] == 0 ? 1 : 0;
     }
   }
-  // outcome offset of the tile origin and of every tile entry / out-cut pattern
+  const int NV = 1 << nz;  // valid out-cut slots: a Z-basis cut carries I and Z
+  uint32_t *xoff = tab;
+  uint32_t *boff = xoff + XT;
+  uint32_t *sin = boff + NB;
+  uint32_t *sout = sin + NS;
+  uint32_t *slot = sout + NV;
   int64_t base = 0;
   for (int j = 0; j < a.d; ++j)
     if ((x0 >> j) & 1) base |= int64_t(1) << a.data_wire[j];
@@ -60,25 +71,51 @@ __global__ __launch_bounds__(kThreads) void attribute_lds(AttrArgs a) {
     uint32_t o = 0;
     for (int j = 0; j < a.xt_bits; ++j)
       if ((t >> j) & 1) o |= uint32_t(1) << a.data_wire[j];
-    xt_off[t] = o;
+    xoff[t] = o;
   }
   for (int t = tid; t < NB; t += kThreads) {
     uint32_t o = 0;
     for (int j = 0; j < a.n_out; ++j)
       if ((t >> j) & 1) o |= uint32_t(1) << a.out_wire[j];
-    b_off[t] = o;
+    boff[t] = o;
+  }
+  for (int t = tid; t < NS; t += kThreads) {
+    int64_t v = vbeta;
+    uint32_t sg = 0;
+    for (int j = 0; j < a.n_in; ++j) {
+      const int dgt = (t >> (2 * j)) & 3;
+      v += int64_t(dgt) * a.place[a.in_pos[j]];
+      sg |= uint32_t(dgt) << (2 * a.in_pos[j]);
+    }
+    vtab[t] = (v << a.w) + base;
+    sin[t] = sg;
+  }
+  for (int t = tid; t < NV; t += kThreads) {
+    uint32_t sg = 0, sl = 0;
+    int zb = 0;
+    for (int j = 0; j < a.n_out; ++j) {
+      int lab;
+      if (beta[j] == 0) {
+        const int bit = (t >> zb) & 1;
+        ++zb;
+        lab = bit ? 3 : 0;  // slot bit 0 holds I, bit 1 holds Z
+        sl |= uint32_t(bit) << j;
+      } else {
+        lab = beta[j];  // X = 1, Y = 2 coincide with the basis digits
+      }
+      sg |= uint32_t(lab) << (2 * a.out_pos[j]);
+    }
+    sout[t] = sg;
+    slot[t] = sl;
   }
   __syncthreads();
 
   // stage: element e = (s * XT + xt) * NB + b
-  const int64_t row = int64_t(1) << a.w;
   for (int e = tid; e < E; e += kThreads) {
-    int b = e & (NB - 1);
-    int xt = (e >> a.n_out) & (XT - 1);
-    int s = e >> (a.n_out + a.xt_bits);
-    int64_t v = vbeta;
-    for (int j = 0; j < a.n_in; ++j) v += int64_t((s >> (2 * j)) & 3) * a.place[a.in_pos[j]];
-    buf[e] = load_prob(a.var, v * row + base + (int64_t)(xt_off[xt] | b_off[b]), a.in_f32);
+    const int b = e & (NB - 1);
+    const int xt = (e >> a.n_out) & (XT - 1);
+    const int s = e >> (a.n_out + a.xt_bits);
+    buf[e] = load_prob(a.var, vtab[s] + (int64_t)(xoff[xt] | boff[b]), a.in_f32);
   }
   __syncthreads();
 
@@ -111,50 +148,19 @@ __global__ __launch_bounds__(kThreads) void attribute_lds(AttrArgs a) {
     __syncthreads();
   }
 
-  // write every label assignment compatible with beta.  Output slots are
-  // enumerated with the first incident cut fastest, then the tile entry.
-  int rbits[kMaxIncident];  // bits of each incident digit in the slot index
-  int kind[kMaxIncident];   // 0: in-cut j, 1: out-cut with Z basis, 2: fixed X/Y
-  int idx[kMaxIncident];    // in-cut or out-cut ordinal
-  int nslot_bits = 0;
-  for (int q = 0; q < a.c; ++q) rbits[q] = -1;
-  for (int j = 0; j < a.n_in; ++j) {
-    rbits[a.in_pos[j]] = 2;
-    kind[a.in_pos[j]] = 0;
-    idx[a.in_pos[j]] = j;
-  }
-  for (int j = 0; j < a.n_out; ++j) {
-    rbits[a.out_pos[j]] = beta[j] == 0 ? 1 : 0;
-    kind[a.out_pos[j]] = beta[j] == 0 ? 1 : 2;
-    idx[a.out_pos[j]] = j;
-  }
-  for (int q = 0; q < a.c; ++q) nslot_bits += rbits[q];
-  const int nslots = XT << nslot_bits;
+  // write every label assignment compatible with beta: q = (xt, v, s), s fastest
+  const int lNS = 2 * a.n_in;
+  const int nq = (XT * NV) << lNS;
   const int64_t L = int64_t(1) << (2 * a.c);
-  for (int qs = tid; qs < nslots; qs += kThreads) {
-    int rem = qs;
-    int64_t sigma = 0;
-    int s = 0, slot = 0;
-    for (int q = 0; q < a.c; ++q) {
-      int dig = rem & ((1 << rbits[q]) - 1);
-      rem >>= rbits[q];
-      int lab;
-      if (kind[q] == 0) {
-        lab = dig;
-        s |= dig << (2 * idx[q]);
-      } else if (kind[q] == 1) {
-        lab = dig ? 3 : 0;
-        slot |= dig << idx[q];
-      } else {
-        lab = beta[idx[q]];  // X = 1, Y = 2 coincide with the basis digits
-      }
-      sigma += int64_t(lab) << (2 * q);
-    }
-    int xt = rem;
-    double v = buf[(s * XT + xt) * NB + slot] * a.scale;
-    int64_t o = (x0 + xt) * L + sigma;
-    if (a.out_f32) static_cast<float *>(a.out)[o] = (float)v;
-    else static_cast<double *>(a.out)[o] = v;
+  for (int q = tid; q < nq; q += kThreads) {
+    const int s = q & (NS - 1);
+    const int rest = q >> lNS;
+    const int v = rest & (NV - 1);
+    const int xt = rest >> nz;
+    const double val = buf[(s * XT + xt) * NB + slot[v]] * a.scale;
+    const int64_t o = (x0 + xt) * L + (sin[s] | sout[v]);
+    if (a.out_f32) static_cast<float *>(a.out)[o] = (float)val;
+    else static_cast<double *>(a.out)[o] = val;
   }
 }
 
@@ -214,7 +220,8 @@ __global__ __launch_bounds__(kThreads) void attribute_direct(AttrArgs a) {
 void launch_attribute(const AttrArgs &a0, hipStream_t s) {
   AttrArgs a = a0;
   const int64_t per_x = (int64_t(1) << (2 * a.n_in)) << a.n_out;
-  if (per_x <= kLdsElems && a.n_out <= 10) {  // grid.y = 3^n_out <= 59049
+  const int64_t ns = int64_t(1) << (2 * a.n_in), nb = int64_t(1) << a.n_out;
+  if (per_x <= kLdsElems && ns <= kMaxNS && nb <= kMaxNB && a.n_out <= 10) {  // grid.y = 3^n_out
     int xb = 0;
     while ((per_x << (xb + 1)) <= kLdsElems && xb + 1 <= a.d) ++xb;
     int64_t nbeta = 1;

@@ -68,6 +68,9 @@ struct IndexMap {
   int bits[kMaxRuns] = {0};
   int64_t sx[kMaxRuns] = {0};
   int64_t sy[kMaxRuns] = {0};
+  // log2 of sx / sy: every stride is a product of power-of-two dimensions
+  int8_t lx[kMaxRuns] = {0};
+  int8_t ly[kMaxRuns] = {0};
 };
 
 struct Axis {
@@ -142,6 +145,8 @@ struct MergeArgs {
   int d, lbits;     // L = 2^lbits = 4^c
   int abits, mbits; // active, merged bit counts
   uint64_t fixed_val, active, merged;
+  int act_lo;       // active bits form one run starting here (-1: not a run)
+  int mrg_lo;       // merged bits form one run starting here (-1: not a run)
   int ysplit_bits;  // P = 2^ysplit_bits
   int tb_bits;      // log2 of the b-tile
   int ts_bits;      // log2 of the sigma-tile
@@ -157,31 +162,43 @@ struct GemmArgs {
   int mbits, nbits, kbits;
   IndexMap m, n, k;
   int out_f32;           // output element type (intermediates follow the path)
-  int final_step;        // 1: compensated FP64 chunks + block statistics
-  int chunk_bits;        // K chunk for the compensated sum
-  // block statistics (final step with statistics)
+  int final_step;        // 1: compensated FP64 fold of the FP32 sums of K stages
+  // statistics of every 32 x 32 sub-tile (final step of a recursion)
   int stats;
-  double *blk_sum;       // [nblk]
-  double *blk_max;       // [nblk]
-  unsigned int *counter; // zero between launches
-  double *tau_sum;       // [2]: threshold and total sum, written by the last block
-  int top_r;
+  double *blk_sum;       // [4 * tiles] FP64 sum of the sub-tile's bins
+  double *blk_max;       // [4 * tiles] largest stored bin of the sub-tile
+  // filled by launch_gemm: offsets of the low index bits the kernel adds to
+  // a wave's origin (index maps are linear in disjoint bit fields)
+  int64_t koff_a[16];    // A offset of k = 0..15
+  int64_t koff_b[16];    // B offset of k = 0..15
+  int64_t coff_n[16];    // C offset of each accumulator element's n
+  int64_t coff_m16;      // C offset of m = 16
 };
-int gemm_blocks(const GemmArgs &g, int prec);
+// 64 x 64 output tiles of a GEMM (sub-tile statistics: 4 per tile).
+int64_t gemm_tiles(const GemmArgs &g);
 void launch_gemm(const GemmArgs &g, int prec, hipStream_t s);
 
+// Top-R selection over the final bins after a GEMM with statistics:
+//   select:  total sum; threshold tau = the R-th largest sub-tile maximum;
+//            ordered list of the sub-tiles whose maximum reaches tau;
+//   gather:  each listed sub-tile's bins >= tau (its own R best when it holds
+//            more) into a fixed slot of R entries;
+//   rank:    the R best entries (value descending, lower index first).
+// Deterministic, no atomics.
 struct TopRArgs {
   const void *C;        // final bins (dense, index = offset)
   int out_f32;
   int mbits, nbits;
-  IndexMap m, n;        // same geometry as the final GEMM (for tile addressing)
-  int nblk;
-  int prec;             // GEMM precision (tile shape)
+  IndexMap m, n;        // geometry of the final GEMM (sub-tile addressing)
+  int nsub;             // sub-tiles (4 per GEMM tile)
+  const double *blk_sum;
   const double *blk_max;
-  const double *tau_sum;
-  double *cand_val;     // [nblk][top_r]
-  uint64_t *cand_idx;   // [nblk][top_r]
-  unsigned int *counter;
+  double *tau_sum;      // [2]
+  int *cand;            // [nsub] listed sub-tiles
+  int *cand_count;      // [1]
+  int *slot_n;          // [nsub]
+  double *slot_val;     // [nsub][top_r]
+  uint64_t *slot_idx;   // [nsub][top_r]
   int top_r;
   double *top_out;      // top_r x {double, uint64}
   double *sum_out;

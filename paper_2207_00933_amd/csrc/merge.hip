@@ -39,6 +39,11 @@ __device__ __forceinline__ uint64_t deposit(uint64_t v, uint64_t mask) {
   return out;
 }
 
+// deposit() of a value into a mask that is one contiguous run starting at lo
+__device__ __forceinline__ uint64_t deposit_run(uint64_t v, uint64_t mask, int lo) {
+  return lo >= 0 ? (v << lo) : deposit(v, mask);
+}
+
 __global__ __launch_bounds__(kThreads) void merge_tiles(MergeArgs a) {
   __shared__ double tile[kTile + 64];
   const int TS = 1 << a.ts_bits;
@@ -54,11 +59,11 @@ __global__ __launch_bounds__(kThreads) void merge_tiles(MergeArgs a) {
   const int g = r / RB;
 
   const int64_t L = int64_t(1) << a.lbits;
-  const int nsig_tiles = (int)(L >> a.ts_bits);
+  const int lsig_tiles = a.lbits - a.ts_bits;
   const int64_t tile_id = blockIdx.x;
   const int p = blockIdx.y;  // y split
-  const int st = (int)(tile_id % nsig_tiles);
-  const int64_t bt = tile_id / nsig_tiles;
+  const int st = (int)(tile_id & ((int64_t(1) << lsig_tiles) - 1));
+  const int64_t bt = tile_id >> lsig_tiles;
   const int64_t sigma = (int64_t(st) << a.ts_bits) + sl;
   const int64_t b0 = bt << a.tb_bits;
 
@@ -69,10 +74,10 @@ __global__ __launch_bounds__(kThreads) void merge_tiles(MergeArgs a) {
   for (int i = 0; i < BPT; ++i) {
     const int bl = brow + RB * i;
     const int64_t b = b0 + bl;
-    const uint64_t xb = a.fixed_val | deposit((uint64_t)b, a.active);
+    const uint64_t xb = a.fixed_val | deposit_run((uint64_t)b, a.active, a.act_lo);
     double acc = 0.0;
     // y = y0 + g, y0 + g + YG, ...: walk the merged bits' subsets in order
-    uint64_t z = deposit((uint64_t)(y0 + g), a.merged);
+    uint64_t z = deposit_run((uint64_t)(y0 + g), a.merged, a.mrg_lo);
     for (int64_t y = g; y < ny; y += YG) {
       acc += ld(a.in, (int64_t)(xb | z) * L + sigma, a.in_f32);
       for (int s = 0; s < YG; ++s) z = ((z | nmerged) + 1) & a.merged;
@@ -122,10 +127,10 @@ __global__ __launch_bounds__(kThreads) void merge_rows(MergeArgs a) {
   const int p = blockIdx.y;
   const int64_t b = c0 >> a.lbits;
   const int64_t sigma = c0 & (L - 1);
-  const uint64_t xb = a.fixed_val | deposit((uint64_t)b, a.active);
+  const uint64_t xb = a.fixed_val | deposit_run((uint64_t)b, a.active, a.act_lo);
   const int64_t ny = int64_t(1) << (a.mbits - a.ysplit_bits);
   const uint64_t nmerged = ~a.merged;
-  uint64_t z = deposit((uint64_t)(int64_t(p) * ny), a.merged);
+  uint64_t z = deposit_run((uint64_t)(int64_t(p) * ny), a.merged, a.mrg_lo);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   int64_t y = 0;
   if (a.in_f32) {

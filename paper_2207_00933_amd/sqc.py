@@ -67,6 +67,14 @@ class RecursionInfo(ctypes.Structure):
                 ("active_bits", c_int32), ("leaf", c_int32)]
 
 
+class StageTime(ctypes.Structure):
+    _fields_ = [("ms", c_double), ("launches", ctypes.c_int64), ("bytes", c_double),
+                ("flops", c_double)]
+
+
+STAGE_ATTRIBUTE, STAGE_MERGE, STAGE_CONTRACT, STAGE_FINAL, STAGE_TOPR = 1, 2, 4, 8, 16
+
+
 class SqcError(RuntimeError):
     def __init__(self, status: int, msg: str):
         name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
@@ -93,6 +101,8 @@ def lib():
             "sqc_ctx_destroy": (c_int, [P]),
             "sqc_ctx_set_stream": (c_int, [P, P]),
             "sqc_ctx_set_workspace": (c_int, [P, P, c_size_t]),
+            "sqc_ctx_set_timing": (c_int, [P, ctypes.c_uint32]),
+            "sqc_ctx_timing": (c_int, [P, ctypes.c_uint32, c_int32, POINTER(StageTime)]),
             "sqc_check_graph": (c_int, [POINTER(Sub), c_int32, POINTER(Cut), c_int32]),
             "sqc_assign_bins": (c_int, [c_int32, POINTER(c_int32), POINTER(Masks), c_uint64,
                                         POINTER(Masks)]),
@@ -225,6 +235,16 @@ def ctx_set_stream(ctx: int, stream: Optional[int]) -> None:
 
 def ctx_set_workspace(ctx: int, buf) -> None:
     _check(lib().sqc_ctx_set_workspace(ctx, _ptr(buf), buf.numel() * buf.element_size()), ctx)
+
+
+def ctx_set_timing(ctx: int, mask: int) -> None:
+    _check(lib().sqc_ctx_set_timing(ctx, mask), ctx)
+
+
+def ctx_timing(ctx: int, stage: int, reset: bool = False) -> StageTime:
+    out = StageTime()
+    _check(lib().sqc_ctx_timing(ctx, stage, 1 if reset else 0, ctypes.byref(out)), ctx)
+    return out
 
 
 def check_graph(g: Graph) -> None:
