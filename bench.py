@@ -157,6 +157,22 @@ def run_gpu(cc, var32, steps: int, warmup: int, precs):
     return out
 
 
+def calib_copy(mib: int):
+    """A plain device-to-device copy of known size (reads and writes mib MiB),
+    three times; profiler counters of this kernel scale the byte counters of
+    the others."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy of {mib} MiB done")
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +182,9 @@ def main():
                     help="target CPU work per worker for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precs", default="f64,f32,bf16x3")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration "
+                         "for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -183,6 +202,8 @@ def main():
         log(f"[bench] CPU oracle: {cpu['value']:.3e} bins/s on {cpu['cores']} cores")
 
     precs = [p for p in args.precs.split(",") if p]
+    if args.calib_copy_mb > 0:
+        calib_copy(args.calib_copy_mb)
     gpu = run_gpu(cc, var32, args.steps, args.warmup, precs)
     fast = [p for p in ("bf16x3", "f32") if p in gpu]
     head = max(fast, key=lambda p: gpu[p]["bins_per_s"]) if fast else precs[0]

@@ -289,10 +289,8 @@ size_t contraction_ws(const Contraction &c, int top_r, bool stats, int prec) {
       dummy.nbits = st.nbits;
     }
     const size_t nsub = 4 * (size_t)gemm_tiles(dummy);
-    b += 2 * align256(nsub * sizeof(double));   // sub-tile sums and maxima
-    b += 2 * align256(nsub * sizeof(int));      // candidate list, slot counts
-    b += align256(64);                          // threshold, sum, count
-    b += 2 * align256(nsub * (size_t)top_r * 8);
+    b += align256(nsub * sizeof(double));             // sub-tile maxima
+    b += align256(3 * kMaxGemmGroups * sizeof(double));  // work-group statistics
 
   }
   return b;
@@ -306,11 +304,6 @@ double gemm_bytes(const GemmArgs &g, int path_f32) {
          std::ldexp(1.0, g.mbits + g.nbits) * ob;
 }
 double gemm_flops(const GemmArgs &g) { return std::ldexp(2.0, g.mbits + g.nbits + g.kbits); }
-
-struct StatsBufs {
-  double *blk_sum, *blk_max, *cand_val;
-  uint64_t *cand_idx;
-};
 
 // Enqueue every GEMM of a contraction.  With `top_dev` non-null, the final
 // step gathers statistics and the top-R kernel follows.
@@ -332,11 +325,12 @@ void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<c
       Bump bp;
       bp.off = stats_base;
       g.stats = 1;
-      g.blk_sum = reinterpret_cast<double *>(ws + bp.take(nsub * sizeof(double)));
       g.blk_max = reinterpret_cast<double *>(ws + bp.take(nsub * sizeof(double)));
+      g.wg_stats = reinterpret_cast<double *>(ws + bp.take(3 * kMaxGemmGroups * sizeof(double)));
+      int groups = 0;
       {
         StageMark mark(ctx, SQC_STAGE_FINAL, gemm_bytes(g, c.path_f32), gemm_flops(g));
-        launch_gemm(g, prec, ctx->stream);
+        groups = launch_gemm(g, prec, ctx->stream);
         after_launch("contraction kernel launch");
         mark.done();
       }
@@ -348,15 +342,9 @@ void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<c
       t.m = g.m;
       t.n = g.n;
       t.nsub = (int)nsub;
-      t.blk_sum = g.blk_sum;
       t.blk_max = g.blk_max;
-      t.cand = reinterpret_cast<int *>(ws + bp.take(nsub * sizeof(int)));
-      t.slot_n = reinterpret_cast<int *>(ws + bp.take(nsub * sizeof(int)));
-      char *misc = ws + bp.take(64);
-      t.tau_sum = reinterpret_cast<double *>(misc);
-      t.cand_count = reinterpret_cast<int *>(misc + 16);
-      t.slot_val = reinterpret_cast<double *>(ws + bp.take(nsub * (size_t)top_r * 8));
-      t.slot_idx = reinterpret_cast<uint64_t *>(ws + bp.take(nsub * (size_t)top_r * 8));
+      t.wg_stats = g.wg_stats;
+      t.ngroups = groups;
       t.top_r = top_r;
       t.top_out = static_cast<double *>(top_dev);
       t.sum_out = static_cast<double *>(sum_dev);

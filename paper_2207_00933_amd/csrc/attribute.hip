@@ -110,12 +110,32 @@ __global__ __launch_bounds__(kThreads) void attribute_lds(AttrArgs a) {
   }
   __syncthreads();
 
-  // stage: element e = (s * XT + xt) * NB + b
-  for (int e = tid; e < E; e += kThreads) {
-    const int b = e & (NB - 1);
-    const int xt = (e >> a.n_out) & (XT - 1);
-    const int s = e >> (a.n_out + a.xt_bits);
-    buf[e] = load_prob(a.var, vtab[s] + (int64_t)(xoff[xt] | boff[b]), a.in_f32);
+  // stage: element e = (s * XT + xt) * NB + b; all of a thread's loads are
+  // issued before the first is used (clamped offsets, no branches)
+  {
+    constexpr int kPer = kLdsElems / kThreads;
+    int64_t off[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + k * kThreads;
+      const int b = e & (NB - 1);
+      const int xt = (e >> a.n_out) & (XT - 1);
+      const int s = (e >> (a.n_out + a.xt_bits)) & (NS - 1);
+      off[k] = e < E ? vtab[s] + (int64_t)(xoff[xt] | boff[b]) : 0;
+    }
+    double v[kPer];
+    if (a.in_f32) {
+      const float *in = static_cast<const float *>(a.var);
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) v[k] = (double)in[off[k]];
+    } else {
+      const double *in = static_cast<const double *>(a.var);
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) v[k] = in[off[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (tid + k * kThreads < E) buf[tid + k * kThreads] = v[k];
   }
   __syncthreads();
 

@@ -165,8 +165,10 @@ struct GemmArgs {
   int final_step;        // 1: compensated FP64 fold of the FP32 sums of K stages
   // statistics of every 32 x 32 sub-tile (final step of a recursion)
   int stats;
-  double *blk_sum;       // [4 * tiles] FP64 sum of the sub-tile's bins
-  double *blk_max;       // [4 * tiles] largest stored bin of the sub-tile
+  double *blk_max;       // [4 * tiles] largest stored bin of each 32 x 32 sub-tile
+  double *wg_stats;      // [3 * work-groups] per work-group: FP64 sum, its
+                         // compensation, largest stored bin (work-group g owns
+                         // the tiles [g T / G, (g + 1) T / G))
   // filled by launch_gemm: offsets of the low index bits the kernel adds to
   // a wave's origin (index maps are linear in disjoint bit fields)
   int64_t koff_a[16];    // A offset of k = 0..15
@@ -176,30 +178,24 @@ struct GemmArgs {
 };
 // 64 x 64 output tiles of a GEMM (sub-tile statistics: 4 per tile).
 int64_t gemm_tiles(const GemmArgs &g);
-void launch_gemm(const GemmArgs &g, int prec, hipStream_t s);
+// Work-groups launch_gemm uses at most (size of wg_stats).
+constexpr int kMaxGemmGroups = 4096;
+// Enqueue; returns the number of work-groups launched.
+int launch_gemm(const GemmArgs &g, int prec, hipStream_t s);
 
-// Top-R selection over the final bins after a GEMM with statistics:
-//   select:  total sum; threshold tau = the R-th largest sub-tile maximum;
-//            ordered list of the sub-tiles whose maximum reaches tau;
-//   gather:  each listed sub-tile's bins >= tau (its own R best when it holds
-//            more) into a fixed slot of R entries;
-//   rank:    the R best entries (value descending, lower index first).
-// Deterministic, no atomics.
+// Top-R selection over the final bins after a GEMM with statistics: the
+// compensated total sum and the R best bins (value descending, lower index
+// first), in one deterministic work-group without atomics.
 struct TopRArgs {
   const void *C;        // final bins (dense, index = offset)
   int out_f32;
   int mbits, nbits;
   IndexMap m, n;        // geometry of the final GEMM (sub-tile addressing)
   int nsub;             // sub-tiles (4 per GEMM tile)
-  const double *blk_sum;
   const double *blk_max;
-  double *tau_sum;      // [2]
-  int *cand;            // [nsub] listed sub-tiles
-  int *cand_count;      // [1]
-  int *slot_n;          // [nsub]
-  double *slot_val;     // [nsub][top_r]
-  uint64_t *slot_idx;   // [nsub][top_r]
-  int top_r;
+  const double *wg_stats;
+  int ngroups;          // work-groups of the final GEMM
+  int top_r;            // 1 .. SQC_MAX_TOPR
   double *top_out;      // top_r x {double, uint64}
   double *sum_out;
 };

@@ -72,49 +72,8 @@ __device__ __forceinline__ bool better(double v1, uint64_t i1, double v2, uint64
   return v1 > v2 || (v1 == v2 && i1 < i2);
 }
 
-__device__ __forceinline__ void wave_argmax(double &v, uint64_t &i) {
-  for (int off = 32; off >= 1; off >>= 1) {
-    double ov = __shfl_xor(v, off);
-    uint64_t oi = __shfl_xor(i, off);
-    if (better(ov, oi, v, i)) {
-      v = ov;
-      i = oi;
-    }
-  }
-}
 
-// Block-wide argmax (all threads get the result); sv / si hold one entry per wave.
-__device__ __forceinline__ void block_argmax(double &v, uint64_t &i, double *sv, uint64_t *si) {
-  wave_argmax(v, i);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    sv[w] = v;
-    si[w] = i;
-  }
-  __syncthreads();
-  v = sv[0];
-  i = si[0];
-  for (int q = 1; q < (int)(blockDim.x >> 6); ++q)
-    if (better(sv[q], si[q], v, i)) {
-      v = sv[q];
-      i = si[q];
-    }
-}
 
-// Inclusive scan of one int per thread over the block (Hillis-Steele).
-__device__ int block_scan_incl(int v, int *buf) {
-  const int tid = threadIdx.x;
-  buf[tid] = v;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    int add = tid >= off ? buf[tid - off] : 0;
-    __syncthreads();
-    buf[tid] += add;
-    __syncthreads();
-  }
-  return buf[tid];
-}
 
 // Per-wave accumulators.  The MFMA operands are swapped (B feeds the
 // instruction's A side), so result rows run over n and columns over m:
@@ -139,6 +98,7 @@ struct Tr<SQC_F64> {
 
 struct Sched {
   int first, end;  // this work-group's tiles: [first, end)
+  int id;          // its place in tile order
 };
 
 // Contiguous chunks of tiles per work-group; work-groups are dispatched
@@ -148,6 +108,7 @@ __device__ __forceinline__ Sched schedule(int ntiles) {
   const int G = gridDim.x, b = blockIdx.x;
   const int lb = (G & 7) == 0 ? (b & 7) * (G >> 3) + (b >> 3) : b;
   Sched s;
+  s.id = lb;
   s.first = (int)((int64_t)lb * ntiles / G);
   s.end = (int)((int64_t)(lb + 1) * ntiles / G);
   return s;
@@ -186,7 +147,33 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
   const int nks = g.kbits > 6 ? 1 << (g.kbits - 6) : 1;  // K stages of BK
 
   const Sched sc = schedule(1 << (lmt + lnt));
-  if (sc.first >= sc.end) return;
+  // work-group statistics: running compensated sum and maximum of its waves
+  __shared__ double wg_part[3][4];
+  double wsum = 0.0, wcmp = 0.0, wmax = -INFINITY;
+  auto write_wg_stats = [&]() {
+    if (!g.stats) return;
+    if (lane == 0) {
+      wg_part[0][wave] = wsum;
+      wg_part[1][wave] = wcmp;
+      wg_part[2][wave] = wmax;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0, c = 0.0, mx = -INFINITY;
+      for (int w = 0; w < 4; ++w) {
+        neumaier(s, c, wg_part[0][w]);
+        c += wg_part[1][w];
+        mx = fmax(mx, wg_part[2][w]);
+      }
+      g.wg_stats[3 * sc.id] = s;
+      g.wg_stats[3 * sc.id + 1] = c;
+      g.wg_stats[3 * sc.id + 2] = mx;
+    }
+  };
+  if (sc.first >= sc.end) {
+    write_wg_stats();
+    return;
+  }
 
   // staging: the thread holds column `lane` (m of A, n of B) of the tile at
   // the 16 k rows 16 wave + j
@@ -391,276 +378,362 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
           lsum += __shfl_xor(lsum, off);
           lmax = fmax(lmax, __shfl_xor(lmax, off));
         }
-        if (lane == 0) {
-          g.blk_sum[(int64_t)cur_tile * 4 + wave] = lsum;
-          g.blk_max[(int64_t)cur_tile * 4 + wave] = lmax;
-        }
+        if (lane == 0) g.blk_max[(int64_t)cur_tile * 4 + wave] = lmax;
+        neumaier(wsum, wcmp, lsum);
+        wmax = fmax(wmax, lmax);
       }
       reset();
     }
     if (!more) break;
     __syncthreads();  // LDS is rewritten by the next stage
   }
+  write_wg_stats();
 }
 
 // ---------------------------------------------------------------------------
-// top-R selection over the final bins.  The unit is the 32 x 32 sub-tile of
-// one wave (sub-tile s = tile * 4 + wave), whose FP64 sum and maximum the
-// final GEMM wrote.
+// top-R selection over the final bins.  The final GEMM wrote the maximum of
+// every 32 x 32 sub-tile (sub-tile s = tile * 4 + wave) and, per work-group,
+// the compensated sum and maximum of its contiguous range of tiles.  One
+// work-group of 1024 threads:
+//   1. total sum over the work-group sums; threshold tau = the R-th largest
+//      work-group maximum (R groups hold a bin >= tau each, so tau is no
+//      larger than the R-th largest bin); list of the sub-tiles of groups
+//      whose maximum reaches tau, kept where the sub-tile's own maximum does
+//      (every one of the R largest bins lies in one of them);
+//   2. the listed sub-tiles' bins are streamed in batches; bins that can
+//      still enter the top R are buffered in LDS, and a full buffer is cut
+//      back to its R best by ranking (rank = number of better entries under
+//      the strict order: larger value, then lower index);
+//   3. the final ranking writes the R best.
+// Deterministic: the only atomics are integer histogram counts in LDS.  The
+// number of passes grows only when many bins tie at the threshold.
 // ---------------------------------------------------------------------------
 
 constexpr int kSelThreads = 1024;
 constexpr int kSelWaves = kSelThreads / 64;
-constexpr int kRankCap = 2048;   // entries ranked in LDS
+constexpr int kCandCap = 4096;            // listed sub-tiles held in LDS
+constexpr int kBufCap = 2048;             // buffered entries
+constexpr int kBatch = 16;                // sub-tiles per streamed batch
 
-__device__ __forceinline__ void sub_origin(const TopRArgs &t, int64_t s, int64_t &m0, int64_t &n0) {
-  const int64_t N = int64_t(1) << t.nbits;
-  const int64_t nt = N > BN ? N / BN : 1;
-  const int64_t tile = s >> 2;
-  const int w = (int)(s & 3);
-  m0 = (tile / nt) * BM + (w & 1) * 32;
-  n0 = (tile % nt) * BN + (w >> 1) * 32;
+// Exclusive prefix of v over the work-group; `total` gets the sum.
+__device__ __forceinline__ int block_scan_excl(int v, int *wsum, int &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(incl, off);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int before = 0;
+  total = 0;
+  for (int q = 0; q < kSelWaves; ++q) {
+    const int x = wsum[q];
+    before += q < w ? x : 0;
+    total += x;
+  }
+  __syncthreads();  // wsum is reused by the next scan
+  return before + incl - v;
 }
 
-constexpr int kGroups = 256;     // groups of sub-tiles ranked for the threshold
-constexpr int kPerThread = 16;   // sub-tile statistics a thread keeps in registers
+__device__ __forceinline__ void two_sum_merge(double &s, double &c, double s2, double c2) {
+  const double t = s + s2;
+  const double err = fabs(s) >= fabs(s2) ? (s - t) + s2 : (s2 - t) + s;
+  s = t;
+  c += c2 + err;
+}
 
-// Total sum; threshold tau; ordered list of the sub-tiles whose maximum reaches
-// tau.  The sub-tiles are split into G contiguous groups (4 threads each); tau
-// is the R-th largest group maximum.  R groups hold a value >= tau each, so tau
-// is no larger than the R-th largest bin, and every one of the R largest bins
-// lies in a sub-tile whose maximum reaches tau.
-__global__ __launch_bounds__(kSelThreads) void topr_select(TopRArgs t) {
-  __shared__ double ps[kSelThreads], pc[kSelThreads];
-  __shared__ double gmax[kGroups];
-  __shared__ int scan[kSelThreads];
-  __shared__ double s_tau;
+// Order-preserving map of doubles to unsigned keys (NaN lowest).
+__device__ __forceinline__ uint64_t order_key(double v) {
+  if (v != v) return 0;
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double key_value(uint64_t k) {
+  return __longlong_as_double((long long)((k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k));
+}
+
+__global__ __launch_bounds__(kSelThreads) void topr(TopRArgs t) {
+  __shared__ double ps[kSelWaves], pc[kSelWaves];
+  __shared__ int hist[256];
+  __shared__ int s_sel[2];
+  __shared__ int wsum[kSelWaves];
+  __shared__ int cand[kCandCap];
+  __shared__ int64_t boff[kBatch];
+  __shared__ double bval[kBufCap];
+  __shared__ uint64_t bidx[kBufCap];
+  __shared__ double lval[SQC_MAX_TOPR];
+  __shared__ uint64_t lidx[SQC_MAX_TOPR];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int nsub = t.nsub;
   const int R = t.top_r;
-  const int per = (nsub + kSelThreads - 1) / kSelThreads;
-  const int b0 = tid * per < nsub ? tid * per : nsub;
-  const int b1 = (b0 + per < nsub) ? b0 + per : nsub;
-  // statistics of this thread's sub-tiles: the first kPerThread in registers
-  double mx[kPerThread];
-  double s = 0.0, c = 0.0, tmax = -INFINITY;
-#pragma unroll
-  for (int q = 0; q < kPerThread; ++q) mx[q] = (b0 + q < b1) ? t.blk_max[b0 + q] : -INFINITY;
-#pragma unroll
-  for (int q = 0; q < kPerThread; ++q)
-    if (b0 + q < b1) neumaier(s, c, t.blk_sum[b0 + q]);
-  for (int b = b0 + kPerThread; b < b1; ++b) {
-    neumaier(s, c, t.blk_sum[b]);
-    const double v = t.blk_max[b];
-    tmax = v > tmax ? v : tmax;
-  }
-#pragma unroll
-  for (int q = 0; q < kPerThread; ++q) tmax = mx[q] > tmax ? mx[q] : tmax;
-  ps[tid] = s;
-  pc[tid] = c;
-  // group maximum over 4 consecutive threads
-  double gm = tmax;
-  gm = fmax(gm, __shfl_xor(gm, 1));
-  gm = fmax(gm, __shfl_xor(gm, 2));
-  if ((tid & 3) == 0) gmax[tid >> 2] = gm;
-  if (tid == 0) s_tau = -INFINITY;
-  __syncthreads();
-  for (int h = kSelThreads / 2; h >= 1; h >>= 1) {
-    if (tid < h) {
-      const double a = ps[tid], bb = ps[tid + h];
-      const double sum = a + bb;
-      const double err = fabs(a) >= fabs(bb) ? (a - sum) + bb : (bb - sum) + a;
-      ps[tid] = sum;
-      pc[tid] += pc[tid + h] + err;
-    }
-    __syncthreads();
-  }
-  // groups that hold at least one sub-tile
-  const int groups = (nsub + 4 * per - 1) / (4 * per);
-  if (groups >= R && tid < groups) {
-    const double v = gmax[tid];
-    int rank = 0;
-    for (int q = 0; q < groups; ++q) {
-      const double o = gmax[q];
-      rank += (o > v || (o == v && q < tid)) ? 1 : 0;
-    }
-    if (rank == R - 1) s_tau = v;
-  }
-  __syncthreads();
-  const double tau = s_tau;  // -inf with fewer groups than R
-  int cnt = 0;
-#pragma unroll
-  for (int q = 0; q < kPerThread; ++q) cnt += (b0 + q < b1 && mx[q] >= tau) ? 1 : 0;
-  for (int b = b0 + kPerThread; b < b1; ++b) cnt += t.blk_max[b] >= tau ? 1 : 0;
-  const int incl = block_scan_incl(cnt, scan);
-  int pos = incl - cnt;
-#pragma unroll
-  for (int q = 0; q < kPerThread; ++q)
-    if (b0 + q < b1 && mx[q] >= tau) t.cand[pos++] = b0 + q;
-  for (int b = b0 + kPerThread; b < b1; ++b)
-    if (t.blk_max[b] >= tau) t.cand[pos++] = b;
-  if (tid == kSelThreads - 1) *t.cand_count = incl;
-  if (tid == 0) {
-    t.tau_sum[0] = tau;
-    t.tau_sum[1] = ps[0] + pc[0];
-  }
-}
+  const int G = t.ngroups;                 // work-groups of the final GEMM
+  const int ntiles = nsub >> 2;
 
-// Bins >= tau of each listed sub-tile (its R best when it holds more) into
-// the sub-tile's slot of R entries.
-__global__ __launch_bounds__(kThreads) void topr_gather(TopRArgs t) {
-  __shared__ double red_v[4];
-  __shared__ uint64_t red_i[4];
-  __shared__ int s_cnt[4];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const double tau = t.tau_sum[0];
-  const int R = t.top_r;
-  const int ncand = *t.cand_count;
-  const int64_t M = int64_t(1) << t.mbits;
-  const int64_t N = int64_t(1) << t.nbits;
-  for (int c = blockIdx.x; c < ncand; c += gridDim.x) {
-    int64_t m0, n0;
-    sub_origin(t, t.cand[c], m0, n0);
-    double v[4];
-    uint64_t ix[4];
-    int cnt = 0;
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + kThreads * q;  // 1024 bins of the 32 x 32 sub-tile
-      const int64_t m = m0 + (e & 31), n = n0 + (e >> 5);
-      v[q] = -INFINITY;
-      ix[q] = ~uint64_t(0);
-      if (m < M && n < N) {
-        const int64_t o = map_y(t.m, m) + map_y(t.n, n);
-        const double x = t.out_f32 ? (double)static_cast<const float *>(t.C)[o]
-                                   : static_cast<const double *>(t.C)[o];
-        if (x == x && x >= tau) {
-          v[q] = x;
-          ix[q] = (uint64_t)o;
-          ++cnt;
-        }
-      }
+  // ---- 1. work-group statistics; group g belongs to thread g % 1024 ----
+  constexpr int kGPT = kMaxGemmGroups / kSelThreads;
+  double gm[kGPT];
+  double s = 0.0, c = 0.0;
+  {
+    double gs[kGPT], gc[kGPT];
+#pragma unroll
+    for (int q = 0; q < kGPT; ++q) {
+      const int gi = tid + q * kSelThreads;
+      const int gg = gi < G ? gi : 0;
+      gs[q] = t.wg_stats[3 * gg];
+      gc[q] = t.wg_stats[3 * gg + 1];
+      gm[q] = t.wg_stats[3 * gg + 2];
     }
-    int wc = cnt;
-    for (int off = 32; off >= 1; off >>= 1) wc += __shfl_xor(wc, off);
-    __syncthreads();
-    if (lane == 0) s_cnt[wave] = wc;
-    __syncthreads();
-    const int total = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-    double *sv = t.slot_val + int64_t(c) * R;
-    uint64_t *si = t.slot_idx + int64_t(c) * R;
-    if (total <= R) {
-      int incl = cnt;
-      for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(incl, off);
-        if (lane >= off) incl += o;
+#pragma unroll
+    for (int q = 0; q < kGPT; ++q)
+      if (tid + q * kSelThreads < G) {
+        neumaier(s, c, gs[q]);
+        c += gc[q];
       }
-      int pos = incl - cnt;
-      for (int q = 0; q < wave; ++q) pos += s_cnt[q];
-      for (int q = 0; q < 4; ++q)
-        if (ix[q] != ~uint64_t(0)) {
-          sv[pos] = v[q];
-          si[pos] = ix[q];
-          ++pos;
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double s2 = __shfl_xor(s, off), c2 = __shfl_xor(c, off);
+    two_sum_merge(s, c, s2, c2);
+  }
+  if (lane == 0) {
+    ps[wave] = s;
+    pc[wave] = c;
+  }
+
+  // threshold: the R-th largest work-group maximum (radix select on keys,
+  // 8 bits per pass; histogram counts are order independent)
+  double tau = -INFINITY;
+  if (G >= R) {
+    uint64_t prefix = 0, hi = 0;
+    int need = R;
+    for (int pass = 0; pass < 8; ++pass) {
+      const int sh = 56 - 8 * pass;
+      if (tid < 256) hist[tid] = 0;
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kGPT; ++q) {
+        const uint64_t k = order_key(gm[q]);
+        if (tid + q * kSelThreads < G && (k & hi) == prefix) atomicAdd(&hist[(k >> sh) & 255], 1);
+      }
+      __syncthreads();
+      if (wave == 0) {
+        int h[4], tot = 0;
+        for (int j = 0; j < 4; ++j) {
+          h[j] = hist[255 - 4 * lane - j];  // digits in descending order
+          tot += h[j];
         }
-      if (tid == 0) t.slot_n[c] = total;
-    } else {
-      double pv = INFINITY;
-      uint64_t pi = 0;
-      for (int r = 0; r < R; ++r) {
-        double bv = -INFINITY;
-        uint64_t bi = ~uint64_t(0);
-        for (int q = 0; q < 4; ++q) {
-          if (ix[q] == ~uint64_t(0)) continue;
-          const bool below = r == 0 || better(pv, pi, v[q], ix[q]);
-          if (below && better(v[q], ix[q], bv, bi)) {
-            bv = v[q];
-            bi = ix[q];
+        int incl = tot;
+        for (int off = 1; off < 64; off <<= 1) {
+          const int o = __shfl_up(incl, off);
+          if (lane >= off) incl += o;
+        }
+        int cum = incl - tot;
+        for (int j = 0; j < 4; ++j) {
+          if (cum < need && need <= cum + h[j]) {
+            s_sel[0] = 255 - 4 * lane - j;
+            s_sel[1] = need - cum;
           }
+          cum += h[j];
         }
-        block_argmax(bv, bi, red_v, red_i);
-        if (tid == 0) {
-          sv[r] = bv;
-          si[r] = bi;
-        }
-        pv = bv;
-        pi = bi;
       }
-      if (tid == 0) t.slot_n[c] = R;
+      __syncthreads();
+      prefix |= (uint64_t)s_sel[0] << sh;
+      hi |= (uint64_t)255 << sh;
+      need = s_sel[1];
     }
+    tau = key_value(prefix);
+    if (tau != tau) tau = -INFINITY;  // fewer than R groups hold a number
   }
-}
 
-// Rank the gathered entries (an entry's rank is the number of better
-// entries); ranks below R give the output positions.
-__global__ __launch_bounds__(kSelThreads) void topr_rank(TopRArgs t) {
-  __shared__ double sv[kRankCap];
-  __shared__ uint64_t si[kRankCap];
-  __shared__ int scan[kSelThreads];
-  __shared__ double red_v[kSelWaves];
-  __shared__ uint64_t red_i[kSelWaves];
-  const int tid = threadIdx.x;
-  const int R = t.top_r;
-  const int ncand = *t.cand_count;
-  for (int r = tid; r < R; r += kSelThreads) {
-    t.top_out[2 * r] = -INFINITY;
-    reinterpret_cast<uint64_t *>(t.top_out)[2 * r + 1] = ~uint64_t(0);
-  }
-  const int per = (ncand + kSelThreads - 1) / kSelThreads;
-  const int c0 = tid * per < ncand ? tid * per : ncand;
-  const int c1 = (c0 + per < ncand) ? c0 + per : ncand;
+  // ---- sub-tiles of the groups whose maximum reaches tau ----
   int cnt = 0;
-  for (int c = c0; c < c1; ++c) cnt += t.slot_n[c];
-  const int incl = block_scan_incl(cnt, scan);
-  const int n = scan[kSelThreads - 1];
-  __syncthreads();
-  if (n <= kRankCap) {
-    int pos = incl - cnt;
-    for (int c = c0; c < c1; ++c)
-      for (int j = 0; j < t.slot_n[c]; ++j) {
-        sv[pos] = t.slot_val[int64_t(c) * R + j];
-        si[pos] = t.slot_idx[int64_t(c) * R + j];
-        ++pos;
+#pragma unroll
+  for (int q = 0; q < kGPT; ++q) {
+    const int gi = tid + q * kSelThreads;
+    if (gi < G && gm[q] >= tau)
+      cnt += 4 * (int)(((int64_t)(gi + 1) * ntiles / G) - ((int64_t)gi * ntiles / G));
+  }
+  int nlist;
+  int pos = block_scan_excl(cnt, wsum, nlist);
+  bool listed = nlist <= kCandCap;  // else every sub-tile is streamed
+  int ncand = 0;
+  if (listed) {
+#pragma unroll
+    for (int q = 0; q < kGPT; ++q) {
+      const int gi = tid + q * kSelThreads;
+      if (gi < G && gm[q] >= tau) {
+        const int f = (int)((int64_t)gi * ntiles / G), e = (int)((int64_t)(gi + 1) * ntiles / G);
+        for (int sb = 4 * f; sb < 4 * e; ++sb) cand[pos++] = sb;
       }
+    }
     __syncthreads();
-    for (int e = tid; e < n; e += kSelThreads) {
-      const double v = sv[e];
-      const uint64_t i = si[e];
+    // keep the listed sub-tiles whose own maximum reaches tau
+    constexpr int kLPT = kCandCap / kSelThreads;
+    int sbv[kLPT];
+    int keep = 0;
+#pragma unroll
+    for (int q = 0; q < kLPT; ++q) {
+      const int e = tid + q * kSelThreads;
+      sbv[q] = e < nlist ? cand[e] : -1;
+    }
+    double mxv[kLPT];
+#pragma unroll
+    for (int q = 0; q < kLPT; ++q) mxv[q] = t.blk_max[sbv[q] >= 0 ? sbv[q] : 0];
+#pragma unroll
+    for (int q = 0; q < kLPT; ++q) keep += (sbv[q] >= 0 && mxv[q] >= tau) ? 1 : 0;
+    int at = block_scan_excl(keep, wsum, ncand);  // also orders the reads above before the writes
+#pragma unroll
+    for (int q = 0; q < kLPT; ++q)
+      if (sbv[q] >= 0 && mxv[q] >= tau) cand[at++] = sbv[q];
+  }
+  const int nstream = listed ? ncand : nsub;
+  __syncthreads();
+
+  // ---- 2. stream the bins; thread tid reads bin (tid % 32, tid / 32) of each sub-tile ----
+  const uint32_t M = 1u << t.mbits, N = 1u << t.nbits;
+  const int lnt = t.nbits > 6 ? t.nbits - 6 : 0;
+  const uint32_t ml = tid & 31, nl = tid >> 5;
+  const int64_t o_lane = map_y(t.m, ml) + map_y(t.n, nl);
+  int nbuf = 0;
+  bool have_bar = false;  // R entries kept: a new entry must beat the R-th
+  double bar_v = 0.0;
+  uint64_t bar_i = 0;
+
+  // cut the buffer back to its R best (in order, at its front)
+  auto cut = [&]() {
+    for (int e = tid; e < nbuf; e += kSelThreads) {
+      const double v = bval[e];
+      const uint64_t i = bidx[e];
       int rank = 0;
-      for (int q = 0; q < n; ++q) rank += better(sv[q], si[q], v, i) ? 1 : 0;
+#pragma unroll 8
+      for (int q = 0; q < nbuf; ++q) rank += better(bval[q], bidx[q], v, i) ? 1 : 0;
       if (rank < R) {
-        t.top_out[2 * rank] = v;
-        reinterpret_cast<uint64_t *>(t.top_out)[2 * rank + 1] = i;
+        lval[rank] = v;
+        lidx[rank] = i;
       }
     }
-  } else {
-    // many ties at tau: R rounds of block argmax over the slots in memory
-    double pv = INFINITY;
-    uint64_t pi = 0;
-    for (int r = 0; r < R; ++r) {
-      double bv = -INFINITY;
-      uint64_t bi = ~uint64_t(0);
-      for (int c = 0; c < ncand; ++c)
-        for (int j = tid; j < t.slot_n[c]; j += kSelThreads) {
-          const double v = t.slot_val[int64_t(c) * R + j];
-          const uint64_t i = t.slot_idx[int64_t(c) * R + j];
-          const bool below = r == 0 || better(pv, pi, v, i);
-          if (below && better(v, i, bv, bi)) {
-            bv = v;
-            bi = i;
-          }
-        }
-      block_argmax(bv, bi, red_v, red_i);
-      if (tid == 0) {
-        t.top_out[2 * r] = bv;
-        reinterpret_cast<uint64_t *>(t.top_out)[2 * r + 1] = bi;
+    __syncthreads();
+    const int kept = nbuf < R ? nbuf : R;
+    if (tid < kept) {
+      bval[tid] = lval[tid];
+      bidx[tid] = lidx[tid];
+    }
+    __syncthreads();
+    nbuf = kept;
+    if (kept == R) {
+      have_bar = true;
+      bar_v = lval[R - 1];
+      bar_i = lidx[R - 1];
+    }
+  };
+
+  // a sub-tile's bin (ml, nl) exists iff the sub-tile origin and (ml, nl)
+  // both lie inside the M x N result (origins are multiples of 32)
+  const bool lane_ok = ml < M && nl < N;
+  for (int cb = 0; cb < nstream; cb += kBatch) {
+    // origin offsets of the batch's sub-tiles, one thread each (-1: skipped)
+    if (tid < kBatch) {
+      const int ci = cb + tid;
+      int64_t o = -1;
+      if (ci < nstream) {
+        const int sb = listed ? cand[ci] : ci;
+        const int tile = sb >> 2, w = sb & 3;
+        const uint32_t m0 = ((uint32_t)(tile >> lnt) << 6) + (w & 1) * 32;
+        const uint32_t n0 = ((uint32_t)(tile & ((1 << lnt) - 1)) << 6) + (w >> 1) * 32;
+        if (m0 < M && n0 < N && (listed || t.blk_max[sb] >= tau)) o = map_y(t.m, m0) + map_y(t.n, n0);
       }
-      pv = bv;
-      pi = bi;
+      boff[tid] = o;
+    }
+    __syncthreads();
+    double v[kBatch];
+    uint64_t ix[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int64_t o = boff[u];
+      ix[u] = (o >= 0 && lane_ok) ? (uint64_t)(o + o_lane) : ~uint64_t(0);
+    }
+    // loads with a clamped offset, all in flight together
+    if (t.out_f32) {
+      const float *Cf = static_cast<const float *>(t.C);
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) v[u] = (double)Cf[ix[u] == ~uint64_t(0) ? 0 : ix[u]];
+    } else {
+      const double *Cd = static_cast<const double *>(t.C);
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) v[u] = Cd[ix[u] == ~uint64_t(0) ? 0 : ix[u]];
+    }
+    // entries that can still enter the top R
+    auto qualifies = [&](int u) {
+      return ix[u] != ~uint64_t(0) && v[u] == v[u] && v[u] >= tau &&
+             (!have_bar || better(v[u], ix[u], bar_v, bar_i));
+    };
+    int k = 0;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) k += qualifies(u) ? 1 : 0;
+    int total;
+    int at = block_scan_excl(k, wsum, total);
+    if (nbuf + total > kBufCap && nbuf > R) {
+      cut();
+      k = 0;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) k += qualifies(u) ? 1 : 0;
+      at = block_scan_excl(k, wsum, total);
+    }
+    if (nbuf + total <= kBufCap) {
+      at += nbuf;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        if (qualifies(u)) {
+          bval[at] = v[u];
+          bidx[at] = ix[u];
+          ++at;
+        }
+      nbuf += total;
+      __syncthreads();
+    } else {
+      // many ties: one sub-tile at a time (at most 1024 entries each); the
+      // entry is picked from registers by selects (no indexed register array)
+      for (int u = 0; u < kBatch; ++u) {
+        double vu = v[0];
+        uint64_t iu = ix[0];
+#pragma unroll
+        for (int q = 1; q < kBatch; ++q) {
+          vu = u == q ? v[q] : vu;
+          iu = u == q ? ix[q] : iu;
+        }
+        auto qual1 = [&]() {
+          return iu != ~uint64_t(0) && vu == vu && vu >= tau && (!have_bar || better(vu, iu, bar_v, bar_i));
+        };
+        int one = qual1() ? 1 : 0;
+        int tot1;
+        int at1 = block_scan_excl(one, wsum, tot1);
+        if (nbuf + tot1 > kBufCap) {
+          cut();
+          one = qual1() ? 1 : 0;
+          at1 = block_scan_excl(one, wsum, tot1);
+        }
+        if (one) {
+          bval[nbuf + at1] = vu;
+          bidx[nbuf + at1] = iu;
+        }
+        nbuf += tot1;
+        __syncthreads();
+      }
     }
   }
-  if (tid == 0) *t.sum_out = t.tau_sum[1];
+
+  // ---- 3. final ranking ----
+  cut();
+  if (tid < R) {
+    t.top_out[2 * tid] = tid < nbuf ? bval[tid] : -INFINITY;
+    reinterpret_cast<uint64_t *>(t.top_out)[2 * tid + 1] = tid < nbuf ? bidx[tid] : ~uint64_t(0);
+  }
+  if (tid == 0) {
+    double S = ps[0], Cc = pc[0];
+    for (int q = 1; q < kSelWaves; ++q) two_sum_merge(S, Cc, ps[q], pc[q]);
+    *t.sum_out = S + Cc;
+  }
 }
 
 __global__ void zero_bytes(unsigned int *p, size_t nwords) {
@@ -705,14 +778,16 @@ int resident_groups() {
 }
 
 template <int PREC, bool FOLD>
-void launch_gemm_t(const GemmArgs &g, hipStream_t s) {
+int launch_gemm_t(const GemmArgs &g, hipStream_t s) {
   const int64_t tiles = gemm_tiles(g);
-  const int64_t cap = resident_groups<PREC, FOLD>();
-  const dim3 grid((unsigned)(tiles < cap ? tiles : cap));
-  hipLaunchKernelGGL((gemm<PREC, FOLD>), grid, dim3(kThreads), 0, s, g);
+  int64_t cap = resident_groups<PREC, FOLD>();
+  if (cap > kMaxGemmGroups) cap = kMaxGemmGroups;
+  const int G = (int)(tiles < cap ? tiles : cap);
+  hipLaunchKernelGGL((gemm<PREC, FOLD>), dim3((unsigned)G), dim3(kThreads), 0, s, g);
+  return G;
 }
 
-void launch_gemm(const GemmArgs &g_in, int prec, hipStream_t s) {
+int launch_gemm(const GemmArgs &g_in, int prec, hipStream_t s) {
   GemmArgs g = g_in;
   for (int j = 0; j < 16; ++j) {
     g.koff_a[j] = host_map(g.k, j, false);
@@ -727,16 +802,13 @@ void launch_gemm(const GemmArgs &g_in, int prec, hipStream_t s) {
   // fold FP32 chunks into FP64 only when the final K spans several chunks;
   // a chunk is one K stage
   const bool fold = g.final_step && g.kbits > 6;
-  if (prec == SQC_F64) launch_gemm_t<SQC_F64, false>(g, s);
-  else if (prec == SQC_F32) fold ? launch_gemm_t<SQC_F32, true>(g, s) : launch_gemm_t<SQC_F32, false>(g, s);
-  else fold ? launch_gemm_t<SQC_BF16X3, true>(g, s) : launch_gemm_t<SQC_BF16X3, false>(g, s);
+  if (prec == SQC_F64) return launch_gemm_t<SQC_F64, false>(g, s);
+  if (prec == SQC_F32) return fold ? launch_gemm_t<SQC_F32, true>(g, s) : launch_gemm_t<SQC_F32, false>(g, s);
+  return fold ? launch_gemm_t<SQC_BF16X3, true>(g, s) : launch_gemm_t<SQC_BF16X3, false>(g, s);
 }
 
 void launch_topr(const TopRArgs &t, hipStream_t s) {
-  hipLaunchKernelGGL(topr_select, dim3(1), dim3(kSelThreads), 0, s, t);
-  const int g = t.nsub < 128 ? t.nsub : 128;
-  hipLaunchKernelGGL(topr_gather, dim3((unsigned)g), dim3(kThreads), 0, s, t);
-  hipLaunchKernelGGL(topr_rank, dim3(1), dim3(kSelThreads), 0, s, t);
+  hipLaunchKernelGGL(topr, dim3(1), dim3(kSelThreads), 0, s, t);
 }
 
 void launch_zero(void *p, size_t bytes, hipStream_t s) {

@@ -71,19 +71,43 @@ __global__ __launch_bounds__(kThreads) void merge_tiles(MergeArgs a) {
   const int64_t y0 = int64_t(p) * ny;
   const uint64_t nmerged = ~a.merged;
 
-  for (int i = 0; i < BPT; ++i) {
-    const int bl = brow + RB * i;
-    const int64_t b = b0 + bl;
-    const uint64_t xb = a.fixed_val | deposit_run((uint64_t)b, a.active, a.act_lo);
-    double acc = 0.0;
-    // y = y0 + g, y0 + g + YG, ...: walk the merged bits' subsets in order
-    uint64_t z = deposit_run((uint64_t)(y0 + g), a.merged, a.mrg_lo);
-    for (int64_t y = g; y < ny; y += YG) {
-      acc += ld(a.in, (int64_t)(xb | z) * L + sigma, a.in_f32);
-      for (int s = 0; s < YG; ++s) z = ((z | nmerged) + 1) & a.merged;
-    }
-    tile[(g * TB + bl) * TS + sl] = acc;
+  // the thread's BPT <= kMaxBPT bins: states without the merged bits
+  constexpr int kMaxBPT = kTile / kThreads;
+  uint64_t xb[kMaxBPT];
+  double acc[kMaxBPT];
+#pragma unroll
+  for (int i = 0; i < kMaxBPT; ++i) {
+    const int64_t b = b0 + brow + RB * i;
+    xb[i] = i < BPT ? a.fixed_val | deposit_run((uint64_t)b, a.active, a.act_lo) : 0;
+    acc[i] = 0.0;
   }
+  // y = y0 + g, y0 + g + YG, ...: walk the merged bits' subsets in order; the
+  // loads of one y are issued together (clamped offsets, no branches)
+  uint64_t z = deposit_run((uint64_t)(y0 + g), a.merged, a.mrg_lo);
+  for (int64_t y = g; y < ny; y += YG) {
+    int64_t off[kMaxBPT];
+#pragma unroll
+    for (int i = 0; i < kMaxBPT; ++i) off[i] = i < BPT ? (int64_t)(xb[i] | z) * L + sigma : 0;
+    if (a.in_f32) {
+      const float *in = static_cast<const float *>(a.in);
+      float v[kMaxBPT];
+#pragma unroll
+      for (int i = 0; i < kMaxBPT; ++i) v[i] = in[off[i]];
+#pragma unroll
+      for (int i = 0; i < kMaxBPT; ++i) acc[i] += (double)v[i];
+    } else {
+      const double *in = static_cast<const double *>(a.in);
+      double v[kMaxBPT];
+#pragma unroll
+      for (int i = 0; i < kMaxBPT; ++i) v[i] = in[off[i]];
+#pragma unroll
+      for (int i = 0; i < kMaxBPT; ++i) acc[i] += v[i];
+    }
+    for (int s = 0; s < YG; ++s) z = ((z | nmerged) + 1) & a.merged;
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxBPT; ++i)
+    if (i < BPT) tile[(g * TB + brow + RB * i) * TS + sl] = acc[i];
   __syncthreads();
   // combine the y groups in order; result at tile[bl * TS + sl]
   if (YG > 1) {

@@ -1,0 +1,103 @@
+"""GPU top-R selection and bin sum against a sort of the same bins.
+
+One subcircuit with no cuts and every data bit active makes the bins the
+attributed entries themselves (Eq. 1 with an empty label set), so the top-R
+stage can be fed any distribution: heavy ties, all-equal bins, negative values,
+and bin counts large enough to take its fallback passes (more listed
+sub-tiles than fit on chip, a buffer that overflows on ties).
+
+Expected: the R best bins under the strict order "larger value first, lower
+index first" (a stable descending sort), and the compensated FP64 sum of all
+bins."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+sqc = pytest.importorskip("paper_2207_00933_amd.sqc")
+runner = pytest.importorskip("paper_2207_00933_amd.runner")
+
+PRECS = [("f64", 0), ("f32", 1), ("bf16x3", 2)]
+
+
+@pytest.fixture(scope="module")
+def session():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = runner.Session(0, 64 << 20)
+    yield s
+    s.close()
+
+
+def planted(name: str) -> np.ndarray:
+    rng = np.random.default_rng(sum(map(ord, name)))
+    if name == "ties3":
+        return rng.integers(0, 3, 1 << 14).astype(np.float64)
+    if name == "zeros":
+        return np.zeros(1 << 16)
+    if name == "negative":
+        return rng.standard_normal(1 << 12)
+    if name == "smooth":
+        return rng.random(1 << 20)
+    if name == "one_peak":
+        v = rng.random(1 << 18) * 1e-3
+        v[123457] = 5.0
+        return v
+    if name == "flat_big":  # every sub-tile reaches the threshold
+        return np.ones(1 << 23)
+    if name == "ties_big":  # half the bins tie at the threshold
+        return rng.integers(0, 2, 1 << 22).astype(np.float64)
+    if name == "tiny":
+        return np.array([0.5, 2.0, 2.0, -1.0])
+    raise KeyError(name)
+
+
+def run_topr(session, vals: np.ndarray, R: int, prec: int, bins_prec: int):
+    d = int(np.log2(len(vals)))
+    g = sqc.Graph([d], [list(range(d))], [])
+    in_prec = sqc.F64 if prec == sqc.F64 else sqc.F32
+    dt = torch.float64 if in_prec == sqc.F64 else torch.float32
+    buf = torch.from_numpy(vals).to(dt).cuda()
+    att = [sqc.tensor_desc(buf, 0, d, in_prec, sqc.LAYOUT_ATTRIBUTED)]
+    masks = sqc.assign_bins([d], None, 1 << d)
+    session.ensure_workspace(sqc.recurse_workspace_bytes(att, g, masks, prec))
+    bins = torch.empty(1 << d, dtype=torch.float64 if bins_prec == sqc.F64 else torch.float32,
+                       device="cuda")
+    top = torch.full((2 * sqc.MAX_TOPR,), 7.0, dtype=torch.float64, device="cuda")
+    bsum = torch.empty(1, dtype=torch.float64, device="cuda")
+    sqc.recurse(session.ctx, att, g, None, 1 << d, R, prec, bins, bins_prec, top, bsum)
+    torch.cuda.synchronize()
+    t = top.cpu().numpy()
+    return (bins.double().cpu().numpy(), t[0:2 * R:2], t[1:2 * R:2].view(np.uint64),
+            bsum.item())
+
+
+CASES = ["tiny", "ties3", "zeros", "negative", "smooth", "one_peak", "flat_big", "ties_big"]
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("pname,prec", PRECS)
+def test_topr_matches_stable_sort(session, name, pname, prec):
+    vals = planted(name)
+    for R, bins_prec in ((1, sqc.F64), (16, sqc.F32), (64, sqc.F64)):
+        say(f"topr {name} {pname} R={R} bins={bins_prec}")
+        bins, tv, ti, s = run_topr(session, vals, R, prec, bins_prec)
+        if prec == sqc.F64 and bins_prec == sqc.F64:
+            assert np.array_equal(bins, vals)
+        k = min(R, len(bins))
+        order = np.argsort(-bins, kind="stable")[:k]
+        assert np.array_equal(tv[:k], bins[order])
+        assert np.array_equal(ti[:k], order.astype(np.uint64))
+        if k < R:  # fewer bins than R: the rest are empty records
+            assert np.all(tv[k:] == -np.inf)
+            assert np.all(ti[k:] == np.uint64(0xFFFFFFFFFFFFFFFF))
+        # the sum is taken over the accumulated values: the FP64 inputs on the
+        # FP64 path, the stored FP32 accumulators on the others
+        ref = vals if prec == sqc.F64 else bins
+        want = math.fsum(ref.tolist())
+        assert abs(s - want) <= 1e-15 * max(1.0, math.fsum(np.abs(ref).tolist())), (s, want)
