@@ -291,6 +291,8 @@ size_t contraction_ws(const Contraction &c, int top_r, bool stats, int prec) {
     const size_t nsub = 4 * (size_t)gemm_tiles(dummy);
     b += align256(nsub * sizeof(double));             // sub-tile maxima
     b += align256(3 * kMaxGemmGroups * sizeof(double));  // work-group statistics
+    b += align256(kTopRSlots * sizeof(int)) + align256(64);   // slot counts, control
+    b += 2 * align256(kTopRSlots * (size_t)top_r * 8);       // slot values and indices
 
   }
   return b;
@@ -345,6 +347,13 @@ void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<c
       t.blk_max = g.blk_max;
       t.wg_stats = g.wg_stats;
       t.ngroups = groups;
+      t.slot_n = reinterpret_cast<int *>(ws + bp.take(kTopRSlots * sizeof(int)));
+      char *misc = ws + bp.take(64);
+      t.tau_sum = reinterpret_cast<double *>(misc);
+      t.ctl = reinterpret_cast<int *>(misc + 16);
+      t.slot_val = reinterpret_cast<double *>(ws + bp.take(kTopRSlots * (size_t)top_r * 8));
+      t.slot_idx = reinterpret_cast<uint64_t *>(ws + bp.take(kTopRSlots * (size_t)top_r * 8));
+
       t.top_r = top_r;
       t.top_out = static_cast<double *>(top_dev);
       t.sum_out = static_cast<double *>(sum_dev);

@@ -69,8 +69,8 @@ struct IndexMap {
   int64_t sx[kMaxRuns] = {0};
   int64_t sy[kMaxRuns] = {0};
   // log2 of sx / sy: every stride is a product of power-of-two dimensions
-  int8_t lx[kMaxRuns] = {0};
-  int8_t ly[kMaxRuns] = {0};
+  int32_t lx[kMaxRuns] = {0};
+  int32_t ly[kMaxRuns] = {0};
 };
 
 struct Axis {
@@ -185,7 +185,7 @@ int launch_gemm(const GemmArgs &g, int prec, hipStream_t s);
 
 // Top-R selection over the final bins after a GEMM with statistics: the
 // compensated total sum and the R best bins (value descending, lower index
-// first), in one deterministic work-group without atomics.
+// first); deterministic, no atomics.
 struct TopRArgs {
   const void *C;        // final bins (dense, index = offset)
   int out_f32;
@@ -195,10 +195,17 @@ struct TopRArgs {
   const double *blk_max;
   const double *wg_stats;
   int ngroups;          // work-groups of the final GEMM
+  int *ctl;             // [1] listed sub-tiles, -1 when the list did not fit
+  double *tau_sum;      // [2] threshold, total sum
+  int *slot_n;          // [kTopRSlots]
+  double *slot_val;     // [kTopRSlots][top_r]
+  uint64_t *slot_idx;   // [kTopRSlots][top_r]
   int top_r;            // 1 .. SQC_MAX_TOPR
   double *top_out;      // top_r x {double, uint64}
   double *sum_out;
 };
+// Listed sub-tiles (slots) the top-R workspace holds at most.
+constexpr int kTopRSlots = 4096;
 void launch_topr(const TopRArgs &t, hipStream_t s);
 
 void launch_zero(void *p, size_t bytes, hipStream_t s);

@@ -27,6 +27,8 @@
 // result store run along m, the contiguous output axis.
 #include "common.hpp"
 
+#include <type_traits>
+
 namespace sqc {
 
 namespace {
@@ -122,7 +124,10 @@ __device__ __forceinline__ Sched schedule(int ntiles) {
 // FOLD: the final K axis spans several K stages; the FP32 sum of each stage
 // (one chunk of 2^6 labels) is folded into FP64 with Neumaier compensation.
 // Otherwise the FP32 accumulator is the result.
-template <int PREC, bool FOLD>
+// OUTF: FP32 result (else FP64).
+// REG: M, N, K >= 64 and the lowest run of k spans >= 4 bits, so no tile,
+// row or element needs a bound check and k rows are shifts.
+template <int PREC, bool FOLD, bool OUTF, bool REG>
 __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
   typedef typename Tr<PREC>::T T;
   typedef typename Tr<PREC>::Acc Acc;
@@ -182,23 +187,56 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
   const int64_t a_kw = map_x(g.k, 16 * wave);
   const int64_t b_kw = map_y(g.k, 16 * wave);
   T av[NJ], bv[NJ];
+  // k offsets of rows j = 0..15: shifts when the lowest run of k spans >= 4
+  // bits (the usual case), else a table staged in LDS
+  const bool kfast = REG || (g.k.nruns >= 1 && g.k.bits[0] >= 4);
+  const int sa = g.k.lx[0], sb = g.k.ly[0];
+  __shared__ int64_t ktab[2][NJ];
+  if (!kfast) {
+    if (tid < NJ) {
+      ktab[0][tid] = g.koff_a[tid];
+      ktab[1][tid] = g.koff_b[tid];
+    }
+    __syncthreads();
+  }
+  // a full K stage needs no per-row bound; rows past K (K < 64) read offset 0
+  const bool kfull = REG || g.kbits >= 6;
+  auto load_rows = [&](const T *p, T *v, int which, int s_shift, uint32_t k0) {
+    if (kfull && kfast) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) v[j] = p[(int64_t)j << s_shift];
+    } else {
+      const int kr = (int)(k0 + 16 * wave);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const bool in = (uint32_t)(kr + j) < K;
+        const int64_t o = kfast ? ((int64_t)j << s_shift) : ktab[which][j];
+        v[j] = p[in ? o : 0];
+      }
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        if ((uint32_t)(kr + j) >= K) v[j] = T(0);
+    }
+  };
   auto load_a = [&](int tile, int ks) {
     const uint32_t m0 = (uint32_t)(tile >> lnt) << 6;
     const uint32_t k0 = (uint32_t)ks << 6;
-    const T *base = static_cast<const T *>(g.A) + (map_x(g.m, m0) + map_x(g.k, k0) + a_kw);
-    const bool ok = m0 + lane < M;
+    const bool ok = REG || m0 + lane < M;  // columns past M read the column origin
+    const T *p = static_cast<const T *>(g.A) + (map_x(g.m, m0) + map_x(g.k, k0) + a_kw) + (ok ? a_lane : 0);
+    load_rows(p, av, 0, sa, k0);
+    if (!ok)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      av[j] = (ok && k0 + 16 * wave + j < K) ? base[g.koff_a[j] + a_lane] : T(0);
+      for (int j = 0; j < NJ; ++j) av[j] = T(0);
   };
   auto load_b = [&](int tile, int ks) {
     const uint32_t n0 = (uint32_t)(tile & ((1 << lnt) - 1)) << 6;
     const uint32_t k0 = (uint32_t)ks << 6;
-    const T *base = static_cast<const T *>(g.B) + (map_x(g.n, n0) + map_y(g.k, k0) + b_kw);
-    const bool ok = n0 + lane < N;
+    const bool ok = REG || n0 + lane < N;
+    const T *p = static_cast<const T *>(g.B) + (map_x(g.n, n0) + map_y(g.k, k0) + b_kw) + (ok ? b_lane : 0);
+    load_rows(p, bv, 1, sb, k0);
+    if (!ok)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      bv[j] = (ok && k0 + 16 * wave + j < K) ? base[g.koff_b[j] + b_lane] : T(0);
+      for (int j = 0; j < NJ; ++j) bv[j] = T(0);
   };
   auto stage = [&](const T *v, unsigned char *dst, int ld) {
     if constexpr (!SPLIT) {
@@ -321,7 +359,7 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
     }
     // ---- MFMA on the staged stage ----
     const uint32_t k0 = (uint32_t)cur_ks << 6;
-    const int kend = (K - k0) < (uint32_t)BK ? (int)(K - k0) : BK;
+    const int kend = (REG || (K - k0) >= (uint32_t)BK) ? BK : (int)(K - k0);
     if (kend == BK) {
 #pragma unroll
       for (int kk = 0; kk < BK / KSTEP; ++kk) mfma_step(kk);
@@ -334,21 +372,19 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
       const uint32_t mw = ((uint32_t)(cur_tile >> lnt) << 6) + wm * 32;  // wave origin
       const uint32_t nw = ((uint32_t)(cur_tile & ((1 << lnt) - 1)) << 6) + wn * 32;
       double lsum = 0.0, lmax = -INFINITY;
-      if (mw < M && nw < N) {
+      if (REG || (mw < M && nw < N)) {
         const int64_t cw = map_y(g.m, mw) + map_y(g.n, nw);
+        typedef typename std::conditional<OUTF, float, double>::type O;
+        O *C = static_cast<O *>(g.C) + cw + c_lane_m + c_lane_n;
+        // with M, N >= 32 every element of a wave inside the result is inside
+        const bool whole = REG || (g.mbits >= 5 && g.nbits >= 5);
+        O omax = -INFINITY;
         auto put = [&](uint32_t mloc, uint32_t nloc, int64_t o, double v) {
-          if (mw + mloc >= M || nw + nloc >= N) return;
-          double stored;
-          if (g.out_f32) {
-            const float f = (float)v;
-            static_cast<float *>(g.C)[o] = f;
-            stored = (double)f;
-          } else {
-            static_cast<double *>(g.C)[o] = v;
-            stored = v;
-          }
+          if (!whole && (mw + mloc >= M || nw + nloc >= N)) return;
+          const O st = (O)v;
+          C[o] = st;
           lsum += v;
-          lmax = fmax(lmax, stored);
+          omax = fmax(omax, st);
         };
         if constexpr (PREC == SQC_F64) {
 #pragma unroll
@@ -358,20 +394,20 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const uint32_t nl = 16 * jn + 4 * r;
-                const int64_t o = cw + (im ? g.coff_m16 : 0) + g.coff_n[4 * jn + r] + c_lane_m + c_lane_n;
-                put(16 * im + (lane & 15), nl + (lane >> 4), o, acc[2 * jn + im][r]);
+                put(16 * im + (lane & 15), nl + (lane >> 4), (im ? g.coff_m16 : 0) + g.coff_n[4 * jn + r],
+                    acc[2 * jn + im][r]);
               }
         } else {
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const uint32_t nl = 8 * (r >> 2) + (r & 3);
-            const int64_t o = cw + g.coff_n[r] + c_lane_m + c_lane_n;
             double v;
             if constexpr (FOLD) v = S[r] + Cc[r];
             else v = (double)acc[0][r];
-            put(lane & 31, nl + 4 * (lane >> 5), o, v);
+            put(lane & 31, nl + 4 * (lane >> 5), g.coff_n[r], v);
           }
         }
+        lmax = (double)omax;
       }
       if (g.stats) {
         for (int off = 32; off >= 1; off >>= 1) {
@@ -393,30 +429,35 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
 // ---------------------------------------------------------------------------
 // top-R selection over the final bins.  The final GEMM wrote the maximum of
 // every 32 x 32 sub-tile (sub-tile s = tile * 4 + wave) and, per work-group,
-// the compensated sum and maximum of its contiguous range of tiles.  One
-// work-group of 1024 threads:
-//   1. total sum over the work-group sums; threshold tau = the R-th largest
-//      work-group maximum (R groups hold a bin >= tau each, so tau is no
-//      larger than the R-th largest bin); list of the sub-tiles of groups
-//      whose maximum reaches tau, kept where the sub-tile's own maximum does
-//      (every one of the R largest bins lies in one of them);
-//   2. the listed sub-tiles' bins are streamed in batches; bins that can
-//      still enter the top R are buffered in LDS, and a full buffer is cut
-//      back to its R best by ranking (rank = number of better entries under
-//      the strict order: larger value, then lower index);
-//   3. the final ranking writes the R best.
-// Deterministic: the only atomics are integer histogram counts in LDS.  The
-// number of passes grows only when many bins tie at the threshold.
+// the compensated sum and maximum of its contiguous range of tiles.
+//   gather (a few work-groups, each repeating the selection): the GEMM's
+//     work-groups are joined into at most 256 groups of consecutive
+//     work-groups; threshold tau = the R-th largest group maximum (R groups
+//     hold a bin >= tau each, so tau is no larger than the R-th largest
+//     bin), found by sorting each wave's maxima and ranking every maximum
+//     against the other waves' sorted lists; the sub-tiles of groups whose
+//     maximum reaches tau are listed where the sub-tile's own maximum does
+//     (every one of the R largest bins lies in one of them); each work-group
+//     then takes its share of the listed sub-tiles and writes their bins
+//     >= tau into a slot of R entries (a sub-tile's R best when it holds more);
+//   rank (one work-group): the slot entries are streamed through an LDS
+//     buffer that is cut back to its R best by ranking (rank = number of
+//     better entries under the strict order: larger value, then lower index).
+// When the list does not fit, rank streams every sub-tile whose maximum
+// reaches tau instead.  Deterministic, no atomics.  The code is kept compact
+// (loops, not unrolled copies): a single work-group runs it once per call,
+// so its instruction fetch is not amortised.
 // ---------------------------------------------------------------------------
 
-constexpr int kSelThreads = 1024;
-constexpr int kSelWaves = kSelThreads / 64;
-constexpr int kCandCap = 4096;            // listed sub-tiles held in LDS
-constexpr int kBufCap = 2048;             // buffered entries
-constexpr int kBatch = 16;                // sub-tiles per streamed batch
+constexpr int kTW = 4;                    // waves of the top-R work-groups
+constexpr int kTThreads = 64 * kTW;
+constexpr int kNG = kTThreads;            // groups of GEMM work-groups
+constexpr int kListCap = 4096;            // sub-tiles of candidate groups examined
+constexpr int kBufCap = 2048;             // buffered entries in rank
+constexpr int kGatherGroups = 32;
 
 // Exclusive prefix of v over the work-group; `total` gets the sum.
-__device__ __forceinline__ int block_scan_excl(int v, int *wsum, int &total) {
+__device__ int block_scan_excl(int v, int *wsum, int &total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int incl = v;
   for (int off = 1; off < 64; off <<= 1) {
@@ -427,7 +468,7 @@ __device__ __forceinline__ int block_scan_excl(int v, int *wsum, int &total) {
   __syncthreads();
   int before = 0;
   total = 0;
-  for (int q = 0; q < kSelWaves; ++q) {
+  for (int q = 0; q < kTW; ++q) {
     const int x = wsum[q];
     before += q < w ? x : 0;
     total += x;
@@ -443,297 +484,368 @@ __device__ __forceinline__ void two_sum_merge(double &s, double &c, double s2, d
   c += c2 + err;
 }
 
-// Order-preserving map of doubles to unsigned keys (NaN lowest).
-__device__ __forceinline__ uint64_t order_key(double v) {
-  if (v != v) return 0;
-  const uint64_t b = (uint64_t)__double_as_longlong(v);
-  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double key_value(uint64_t k) {
-  return __longlong_as_double((long long)((k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k));
+// origin (m0, n0) of sub-tile sb of a GEMM with 2^lnt n tiles
+__device__ __forceinline__ void sub_origin(int sb, int lnt, uint32_t &m0, uint32_t &n0) {
+  const int tile = sb >> 2, w = sb & 3;
+  m0 = ((uint32_t)(tile >> lnt) << 6) + (w & 1) * 32;
+  n0 = ((uint32_t)(tile & ((1 << lnt) - 1)) << 6) + (w >> 1) * 32;
 }
 
-__global__ __launch_bounds__(kSelThreads) void topr(TopRArgs t) {
-  __shared__ double ps[kSelWaves], pc[kSelWaves];
-  __shared__ int hist[256];
-  __shared__ int s_sel[2];
-  __shared__ int wsum[kSelWaves];
-  __shared__ int cand[kCandCap];
-  __shared__ int64_t boff[kBatch];
-  __shared__ double bval[kBufCap];
-  __shared__ uint64_t bidx[kBufCap];
-  __shared__ double lval[SQC_MAX_TOPR];
-  __shared__ uint64_t lidx[SQC_MAX_TOPR];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int nsub = t.nsub;
+// Offset of bin (ml, nl) of a sub-tile, or ~0 when it lies outside the result.
+struct SubTileBins {
+  uint32_t M, N;
+  int lnt;
+  int64_t o_lane[4];  // thread's bins e = tid + 256 q: (e % 32, e / 32)
+  bool ok[4];
+  __device__ void init(const TopRArgs &t) {
+    M = 1u << t.mbits;
+    N = 1u << t.nbits;
+    lnt = t.nbits > 6 ? t.nbits - 6 : 0;
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t e = threadIdx.x + kTThreads * q, ml = e & 31, nl = e >> 5;
+      o_lane[q] = map_y(t.m, ml) + map_y(t.n, nl);
+      ok[q] = ml < M && nl < N;
+    }
+  }
+  // origins are multiples of 32: a bin exists iff the origin and (ml, nl) do
+  __device__ void load(const TopRArgs &t, int sb, double v[4], uint64_t ix[4]) const {
+    uint32_t m0, n0;
+    sub_origin(sb, lnt, m0, n0);
+    const bool sub_ok = m0 < M && n0 < N;
+    const int64_t o0 = sub_ok ? map_y(t.m, m0) + map_y(t.n, n0) : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ix[q] = (sub_ok && ok[q]) ? (uint64_t)(o0 + o_lane[q]) : ~uint64_t(0);
+    if (t.out_f32) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        v[q] = (double)static_cast<const float *>(t.C)[ix[q] == ~uint64_t(0) ? 0 : ix[q]];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = static_cast<const double *>(t.C)[ix[q] == ~uint64_t(0) ? 0 : ix[q]];
+    }
+  }
+};
+
+__global__ __launch_bounds__(kTThreads) void topr_gather(TopRArgs t) {
+  __shared__ double sv[kNG];
+  __shared__ int si[kNG];
+  __shared__ int wsum[kTW];
+  __shared__ int gbase[kNG], gfirst[kNG];
+  __shared__ int cand[kListCap];
+  __shared__ double red_v[kTW];
+  __shared__ uint64_t red_i[kTW];
+  __shared__ double ps[kTW], pc[kTW];
+  __shared__ double s_tau;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = t.top_r;
-  const int G = t.ngroups;                 // work-groups of the final GEMM
-  const int ntiles = nsub >> 2;
+  const int G = t.ngroups;
+  const int ntiles = t.nsub >> 2;
+  const int ng = G < kNG ? G : kNG;  // group t: GEMM work-groups [t G / ng, (t+1) G / ng)
 
-  // ---- 1. work-group statistics; group g belongs to thread g % 1024 ----
-  constexpr int kGPT = kMaxGemmGroups / kSelThreads;
-  double gm[kGPT];
-  double s = 0.0, c = 0.0;
-  {
-    double gs[kGPT], gc[kGPT];
+  // ---- group maxima (and, in work-group 0, the total sum) ----
+  double s = 0.0, c = 0.0, gm = -INFINITY;
+  if (tid < ng) {
+    const int w0 = tid * G / ng, w1 = (tid + 1) * G / ng;
+    for (int w = w0; w < w1; w += 4) {
+      double x[4][3];
 #pragma unroll
-    for (int q = 0; q < kGPT; ++q) {
-      const int gi = tid + q * kSelThreads;
-      const int gg = gi < G ? gi : 0;
-      gs[q] = t.wg_stats[3 * gg];
-      gc[q] = t.wg_stats[3 * gg + 1];
-      gm[q] = t.wg_stats[3 * gg + 2];
+      for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 3; ++k) x[j][k] = t.wg_stats[3 * (w + j < w1 ? w + j : w0) + k];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (w + j < w1) {
+          neumaier(s, c, x[j][0]);
+          c += x[j][1];
+          gm = fmax(gm, x[j][2]);
+        }
     }
-#pragma unroll
-    for (int q = 0; q < kGPT; ++q)
-      if (tid + q * kSelThreads < G) {
-        neumaier(s, c, gs[q]);
-        c += gc[q];
-      }
   }
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double s2 = __shfl_xor(s, off), c2 = __shfl_xor(c, off);
-    two_sum_merge(s, c, s2, c2);
-  }
-  if (lane == 0) {
-    ps[wave] = s;
-    pc[wave] = c;
-  }
-
-  // threshold: the R-th largest work-group maximum (radix select on keys,
-  // 8 bits per pass; histogram counts are order independent)
-  double tau = -INFINITY;
-  if (G >= R) {
-    uint64_t prefix = 0, hi = 0;
-    int need = R;
-    for (int pass = 0; pass < 8; ++pass) {
-      const int sh = 56 - 8 * pass;
-      if (tid < 256) hist[tid] = 0;
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < kGPT; ++q) {
-        const uint64_t k = order_key(gm[q]);
-        if (tid + q * kSelThreads < G && (k & hi) == prefix) atomicAdd(&hist[(k >> sh) & 255], 1);
-      }
-      __syncthreads();
-      if (wave == 0) {
-        int h[4], tot = 0;
-        for (int j = 0; j < 4; ++j) {
-          h[j] = hist[255 - 4 * lane - j];  // digits in descending order
-          tot += h[j];
-        }
-        int incl = tot;
-        for (int off = 1; off < 64; off <<= 1) {
-          const int o = __shfl_up(incl, off);
-          if (lane >= off) incl += o;
-        }
-        int cum = incl - tot;
-        for (int j = 0; j < 4; ++j) {
-          if (cum < need && need <= cum + h[j]) {
-            s_sel[0] = 255 - 4 * lane - j;
-            s_sel[1] = need - cum;
-          }
-          cum += h[j];
-        }
-      }
-      __syncthreads();
-      prefix |= (uint64_t)s_sel[0] << sh;
-      hi |= (uint64_t)255 << sh;
-      need = s_sel[1];
+  if (blockIdx.x == 0) {
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double s2 = __shfl_xor(s, off), c2 = __shfl_xor(c, off);
+      two_sum_merge(s, c, s2, c2);
     }
-    tau = key_value(prefix);
-    if (tau != tau) tau = -INFINITY;  // fewer than R groups hold a number
+    if (lane == 0) {
+      ps[wave] = s;
+      pc[wave] = c;
+    }
   }
 
-  // ---- sub-tiles of the groups whose maximum reaches tau ----
-  int cnt = 0;
-#pragma unroll
-  for (int q = 0; q < kGPT; ++q) {
-    const int gi = tid + q * kSelThreads;
-    if (gi < G && gm[q] >= tau)
-      cnt += 4 * (int)(((int64_t)(gi + 1) * ntiles / G) - ((int64_t)gi * ntiles / G));
+  // ---- threshold: bitonic sort of each wave's maxima (value descending,
+  // group ascending), then every maximum's rank by binary search ----
+  double kv = gm;
+  int ki = tid;
+  for (int k = 2; k <= 64; k <<= 1)
+    for (int j = k >> 1; j >= 1; j >>= 1) {
+      const double ov = __shfl_xor(kv, j);
+      const int oi = __shfl_xor(ki, j);
+      const bool ob = better(ov, (uint64_t)oi, kv, (uint64_t)ki);
+      if (((lane & j) == 0) == ((lane & k) == 0) ? ob : !ob) {
+        kv = ov;
+        ki = oi;
+      }
+    }
+  sv[tid] = kv;
+  si[tid] = ki;
+  if (tid == 0) s_tau = -INFINITY;
+  __syncthreads();
+  if (ng >= R && ki < ng) {
+    int rank = lane;  // better entries of this wave
+    for (int w = 0; w < kTW; ++w) {
+      if (w == wave) continue;
+      int lo = 0, hi = 64;  // first entry of wave w that is not better
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (better(sv[64 * w + mid], (uint64_t)si[64 * w + mid], kv, (uint64_t)ki)) lo = mid + 1;
+        else hi = mid;
+      }
+      rank += lo;
+    }
+    if (rank == R - 1) s_tau = kv;
+  }
+  __syncthreads();
+  const double tau = s_tau;  // -inf with fewer groups than R
+
+  // ---- list: sub-tiles of the groups reaching tau, kept where their own
+  // maximum reaches tau ----
+  int cnt = 0, first = 0;
+  if (tid < ng && gm >= tau) {
+    const int w0 = tid * G / ng, w1 = (tid + 1) * G / ng;
+    first = 4 * (int)((int64_t)w0 * ntiles / G);
+    cnt = 4 * (int)((int64_t)w1 * ntiles / G) - first;
   }
   int nlist;
-  int pos = block_scan_excl(cnt, wsum, nlist);
-  bool listed = nlist <= kCandCap;  // else every sub-tile is streamed
-  int ncand = 0;
-  if (listed) {
+  const int base = block_scan_excl(cnt, wsum, nlist);
+  gbase[tid] = tid < ng ? base : nlist;
+  gfirst[tid] = first;
+  __syncthreads();
+  int ncand = -1;  // -1: the list does not fit; rank streams every sub-tile
+  if (nlist <= kListCap) {
+    ncand = 0;
+    for (int e0 = 0; e0 < nlist; e0 += 4 * kTThreads) {
+      int sb[4];
+      double mx[4];
 #pragma unroll
-    for (int q = 0; q < kGPT; ++q) {
-      const int gi = tid + q * kSelThreads;
-      if (gi < G && gm[q] >= tau) {
-        const int f = (int)((int64_t)gi * ntiles / G), e = (int)((int64_t)(gi + 1) * ntiles / G);
-        for (int sb = 4 * f; sb < 4 * e; ++sb) cand[pos++] = sb;
+      for (int j = 0; j < 4; ++j) {
+        const int e = e0 + j * kTThreads + tid;
+        sb[j] = -1;
+        if (e < nlist) {
+          int lo = 0, hi = ng - 1;  // the last group whose offset is <= e
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (gbase[mid] <= e) lo = mid;
+            else hi = mid - 1;
+          }
+          sb[j] = gfirst[lo] + (e - gbase[lo]);
+        }
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) mx[j] = t.blk_max[sb[j] >= 0 ? sb[j] : 0];
+      int keep = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) keep += (sb[j] >= 0 && mx[j] >= tau) ? 1 : 0;
+      int total;
+      int at = ncand + block_scan_excl(keep, wsum, total);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (sb[j] >= 0 && mx[j] >= tau) cand[at++] = sb[j];
+      ncand += total;
     }
     __syncthreads();
-    // keep the listed sub-tiles whose own maximum reaches tau
-    constexpr int kLPT = kCandCap / kSelThreads;
-    int sbv[kLPT];
-    int keep = 0;
-#pragma unroll
-    for (int q = 0; q < kLPT; ++q) {
-      const int e = tid + q * kSelThreads;
-      sbv[q] = e < nlist ? cand[e] : -1;
-    }
-    double mxv[kLPT];
-#pragma unroll
-    for (int q = 0; q < kLPT; ++q) mxv[q] = t.blk_max[sbv[q] >= 0 ? sbv[q] : 0];
-#pragma unroll
-    for (int q = 0; q < kLPT; ++q) keep += (sbv[q] >= 0 && mxv[q] >= tau) ? 1 : 0;
-    int at = block_scan_excl(keep, wsum, ncand);  // also orders the reads above before the writes
-#pragma unroll
-    for (int q = 0; q < kLPT; ++q)
-      if (sbv[q] >= 0 && mxv[q] >= tau) cand[at++] = sbv[q];
   }
-  const int nstream = listed ? ncand : nsub;
-  __syncthreads();
+  if (blockIdx.x == 0 && tid == 0) {
+    double S = ps[0], Cc = pc[0];
+    for (int q = 1; q < kTW; ++q) two_sum_merge(S, Cc, ps[q], pc[q]);
+    t.tau_sum[0] = tau;
+    t.tau_sum[1] = S + Cc;
+    t.ctl[0] = ncand;
+  }
 
-  // ---- 2. stream the bins; thread tid reads bin (tid % 32, tid / 32) of each sub-tile ----
-  const uint32_t M = 1u << t.mbits, N = 1u << t.nbits;
-  const int lnt = t.nbits > 6 ? t.nbits - 6 : 0;
-  const uint32_t ml = tid & 31, nl = tid >> 5;
-  const int64_t o_lane = map_y(t.m, ml) + map_y(t.n, nl);
-  int nbuf = 0;
+  // ---- gather this work-group's share of the listed sub-tiles ----
+  SubTileBins stb;
+  stb.init(t);
+  for (int ci = blockIdx.x; ci < ncand; ci += gridDim.x) {
+    double v[4];
+    uint64_t ix[4];
+    stb.load(t, cand[ci], v, ix);
+    int k = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!(ix[q] != ~uint64_t(0) && v[q] == v[q] && v[q] >= tau)) ix[q] = ~uint64_t(0);
+      k += ix[q] != ~uint64_t(0) ? 1 : 0;
+    }
+    int total;
+    int at = block_scan_excl(k, wsum, total);
+    double *slv = t.slot_val + (int64_t)ci * R;
+    uint64_t *sli = t.slot_idx + (int64_t)ci * R;
+    if (total <= R) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (ix[q] != ~uint64_t(0)) {
+          slv[at] = v[q];
+          sli[at] = ix[q];
+          ++at;
+        }
+      if (tid == 0) t.slot_n[ci] = total;
+    } else {
+      // R rounds of a work-group argmax below the previous pick
+      double pv = INFINITY;
+      uint64_t pi = 0;
+      for (int r = 0; r < R; ++r) {
+        double bv = -INFINITY;
+        uint64_t bi = ~uint64_t(0);
+        for (int q = 0; q < 4; ++q)
+          if (ix[q] != ~uint64_t(0) && (r == 0 || better(pv, pi, v[q], ix[q])) && better(v[q], ix[q], bv, bi)) {
+            bv = v[q];
+            bi = ix[q];
+          }
+        for (int off = 32; off >= 1; off >>= 1) {
+          const double ov = __shfl_xor(bv, off);
+          const uint64_t oi = __shfl_xor(bi, off);
+          if (better(ov, oi, bv, bi)) {
+            bv = ov;
+            bi = oi;
+          }
+        }
+        if (lane == 0) {
+          red_v[wave] = bv;
+          red_i[wave] = bi;
+        }
+        __syncthreads();
+        bv = red_v[0];
+        bi = red_i[0];
+        for (int w = 1; w < kTW; ++w)
+          if (better(red_v[w], red_i[w], bv, bi)) {
+            bv = red_v[w];
+            bi = red_i[w];
+          }
+        __syncthreads();
+        if (tid == 0) {
+          slv[r] = bv;
+          sli[r] = bi;
+        }
+        pv = bv;
+        pi = bi;
+      }
+      if (tid == 0) t.slot_n[ci] = R;
+    }
+  }
+}
+
+// LDS buffer of entries cut back to the R best.
+struct TopBuf {
+  double *val;
+  uint64_t *idx;
+  double *lval;
+  uint64_t *lidx;
+  int n = 0;
   bool have_bar = false;  // R entries kept: a new entry must beat the R-th
   double bar_v = 0.0;
   uint64_t bar_i = 0;
-
-  // cut the buffer back to its R best (in order, at its front)
-  auto cut = [&]() {
-    for (int e = tid; e < nbuf; e += kSelThreads) {
-      const double v = bval[e];
-      const uint64_t i = bidx[e];
+  __device__ bool wants(double v, uint64_t i, double tau) const {
+    return i != ~uint64_t(0) && v == v && v >= tau && (!have_bar || better(v, i, bar_v, bar_i));
+  }
+  // keep the R best, in order, at the front
+  __device__ void cut(int R) {
+    for (int e = threadIdx.x; e < n; e += kTThreads) {
+      const double v = val[e];
+      const uint64_t i = idx[e];
       int rank = 0;
-#pragma unroll 8
-      for (int q = 0; q < nbuf; ++q) rank += better(bval[q], bidx[q], v, i) ? 1 : 0;
+      for (int q = 0; q < n; ++q) rank += better(val[q], idx[q], v, i) ? 1 : 0;
       if (rank < R) {
         lval[rank] = v;
         lidx[rank] = i;
       }
     }
     __syncthreads();
-    const int kept = nbuf < R ? nbuf : R;
-    if (tid < kept) {
-      bval[tid] = lval[tid];
-      bidx[tid] = lidx[tid];
+    const int kept = n < R ? n : R;
+    if ((int)threadIdx.x < kept) {
+      val[threadIdx.x] = lval[threadIdx.x];
+      idx[threadIdx.x] = lidx[threadIdx.x];
     }
     __syncthreads();
-    nbuf = kept;
+    n = kept;
     if (kept == R) {
       have_bar = true;
       bar_v = lval[R - 1];
       bar_i = lidx[R - 1];
     }
-  };
-
-  // a sub-tile's bin (ml, nl) exists iff the sub-tile origin and (ml, nl)
-  // both lie inside the M x N result (origins are multiples of 32)
-  const bool lane_ok = ml < M && nl < N;
-  for (int cb = 0; cb < nstream; cb += kBatch) {
-    // origin offsets of the batch's sub-tiles, one thread each (-1: skipped)
-    if (tid < kBatch) {
-      const int ci = cb + tid;
-      int64_t o = -1;
-      if (ci < nstream) {
-        const int sb = listed ? cand[ci] : ci;
-        const int tile = sb >> 2, w = sb & 3;
-        const uint32_t m0 = ((uint32_t)(tile >> lnt) << 6) + (w & 1) * 32;
-        const uint32_t n0 = ((uint32_t)(tile & ((1 << lnt) - 1)) << 6) + (w >> 1) * 32;
-        if (m0 < M && n0 < N && (listed || t.blk_max[sb] >= tau)) o = map_y(t.m, m0) + map_y(t.n, n0);
-      }
-      boff[tid] = o;
-    }
-    __syncthreads();
-    double v[kBatch];
-    uint64_t ix[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int64_t o = boff[u];
-      ix[u] = (o >= 0 && lane_ok) ? (uint64_t)(o + o_lane) : ~uint64_t(0);
-    }
-    // loads with a clamped offset, all in flight together
-    if (t.out_f32) {
-      const float *Cf = static_cast<const float *>(t.C);
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) v[u] = (double)Cf[ix[u] == ~uint64_t(0) ? 0 : ix[u]];
-    } else {
-      const double *Cd = static_cast<const double *>(t.C);
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) v[u] = Cd[ix[u] == ~uint64_t(0) ? 0 : ix[u]];
-    }
-    // entries that can still enter the top R
-    auto qualifies = [&](int u) {
-      return ix[u] != ~uint64_t(0) && v[u] == v[u] && v[u] >= tau &&
-             (!have_bar || better(v[u], ix[u], bar_v, bar_i));
-    };
+  }
+  // add the thread's up to 4 entries (at most 4 * kTThreads <= kBufCap - R
+  // in all, so one cut always makes room)
+  __device__ void add(const double v[4], const uint64_t ix[4], double tau, int R, int *wsum) {
     int k = 0;
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) k += qualifies(u) ? 1 : 0;
+    for (int q = 0; q < 4; ++q) k += wants(v[q], ix[q], tau) ? 1 : 0;
     int total;
     int at = block_scan_excl(k, wsum, total);
-    if (nbuf + total > kBufCap && nbuf > R) {
-      cut();
+    if (n + total > kBufCap) {
+      cut(R);
       k = 0;
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) k += qualifies(u) ? 1 : 0;
+      for (int q = 0; q < 4; ++q) k += wants(v[q], ix[q], tau) ? 1 : 0;
       at = block_scan_excl(k, wsum, total);
     }
-    if (nbuf + total <= kBufCap) {
-      at += nbuf;
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u)
-        if (qualifies(u)) {
-          bval[at] = v[u];
-          bidx[at] = ix[u];
-          ++at;
-        }
-      nbuf += total;
-      __syncthreads();
-    } else {
-      // many ties: one sub-tile at a time (at most 1024 entries each); the
-      // entry is picked from registers by selects (no indexed register array)
-      for (int u = 0; u < kBatch; ++u) {
-        double vu = v[0];
-        uint64_t iu = ix[0];
-#pragma unroll
-        for (int q = 1; q < kBatch; ++q) {
-          vu = u == q ? v[q] : vu;
-          iu = u == q ? ix[q] : iu;
-        }
-        auto qual1 = [&]() {
-          return iu != ~uint64_t(0) && vu == vu && vu >= tau && (!have_bar || better(vu, iu, bar_v, bar_i));
-        };
-        int one = qual1() ? 1 : 0;
-        int tot1;
-        int at1 = block_scan_excl(one, wsum, tot1);
-        if (nbuf + tot1 > kBufCap) {
-          cut();
-          one = qual1() ? 1 : 0;
-          at1 = block_scan_excl(one, wsum, tot1);
-        }
-        if (one) {
-          bval[nbuf + at1] = vu;
-          bidx[nbuf + at1] = iu;
-        }
-        nbuf += tot1;
-        __syncthreads();
+    at += n;
+    for (int q = 0; q < 4; ++q)
+      if (wants(v[q], ix[q], tau)) {
+        val[at] = v[q];
+        idx[at] = ix[q];
+        ++at;
       }
+    n += total;
+    __syncthreads();
+  }
+};
+
+__global__ __launch_bounds__(kTThreads) void topr_rank(TopRArgs t) {
+  __shared__ int wsum[kTW];
+  __shared__ double bval[kBufCap];
+  __shared__ uint64_t bidx[kBufCap];
+  __shared__ double lval[SQC_MAX_TOPR];
+  __shared__ uint64_t lidx[SQC_MAX_TOPR];
+  const int tid = threadIdx.x;
+  const int R = t.top_r;
+  const int ncand = t.ctl[0];
+  const double tau = t.tau_sum[0];
+  TopBuf buf;
+  buf.val = bval;
+  buf.idx = bidx;
+  buf.lval = lval;
+  buf.lidx = lidx;
+  if (ncand >= 0) {
+    // slot entries f = c R + j, j < slot_n[c]
+    const int npos = ncand * R;
+    for (int f0 = 0; f0 < npos; f0 += 4 * kTThreads) {
+      double v[4];
+      uint64_t ix[4];
+      int cn[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = f0 + q * kTThreads + tid, ff = f < npos ? f : 0;
+        cn[q] = t.slot_n[ff / R];
+        v[q] = t.slot_val[ff];
+        ix[q] = t.slot_idx[ff];
+        if (!(f < npos && ff % R < cn[q])) ix[q] = ~uint64_t(0);
+      }
+      buf.add(v, ix, tau, R, wsum);
+    }
+  } else {
+    // every sub-tile whose maximum reaches tau
+    SubTileBins stb;
+    stb.init(t);
+    for (int sb = 0; sb < t.nsub; ++sb) {
+      if (!(t.blk_max[sb] >= tau)) continue;
+      double v[4];
+      uint64_t ix[4];
+      stb.load(t, sb, v, ix);
+      buf.add(v, ix, tau, R, wsum);
     }
   }
-
-  // ---- 3. final ranking ----
-  cut();
+  buf.cut(R);
   if (tid < R) {
-    t.top_out[2 * tid] = tid < nbuf ? bval[tid] : -INFINITY;
-    reinterpret_cast<uint64_t *>(t.top_out)[2 * tid + 1] = tid < nbuf ? bidx[tid] : ~uint64_t(0);
+    t.top_out[2 * tid] = tid < buf.n ? bval[tid] : -INFINITY;
+    reinterpret_cast<uint64_t *>(t.top_out)[2 * tid + 1] = tid < buf.n ? bidx[tid] : ~uint64_t(0);
   }
-  if (tid == 0) {
-    double S = ps[0], Cc = pc[0];
-    for (int q = 1; q < kSelWaves; ++q) two_sum_merge(S, Cc, ps[q], pc[q]);
-    *t.sum_out = S + Cc;
-  }
+  if (tid == 0) *t.sum_out = t.tau_sum[1];
 }
 
 __global__ void zero_bytes(unsigned int *p, size_t nwords) {
@@ -760,14 +872,14 @@ int64_t host_map(const IndexMap &m, uint32_t idx, bool y) {
 }
 
 // Work-groups of one kernel resident on the device at once.
-template <int PREC, bool FOLD>
+template <int PREC, bool FOLD, bool OUTF, bool REG>
 int resident_groups() {
   static int cached[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
   if (!cached[dev]) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gemm<PREC, FOLD>, kThreads, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gemm<PREC, FOLD, OUTF, REG>, kThreads, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 2;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
@@ -777,14 +889,21 @@ int resident_groups() {
   return cached[dev];
 }
 
-template <int PREC, bool FOLD>
+template <int PREC, bool FOLD, bool OUTF, bool REG>
 int launch_gemm_t(const GemmArgs &g, hipStream_t s) {
   const int64_t tiles = gemm_tiles(g);
-  int64_t cap = resident_groups<PREC, FOLD>();
+  int64_t cap = resident_groups<PREC, FOLD, OUTF, REG>();
   if (cap > kMaxGemmGroups) cap = kMaxGemmGroups;
   const int G = (int)(tiles < cap ? tiles : cap);
-  hipLaunchKernelGGL((gemm<PREC, FOLD>), dim3((unsigned)G), dim3(kThreads), 0, s, g);
+  hipLaunchKernelGGL((gemm<PREC, FOLD, OUTF, REG>), dim3((unsigned)G), dim3(kThreads), 0, s, g);
   return G;
+}
+
+template <int PREC, bool FOLD>
+int launch_gemm_o(const GemmArgs &g, bool reg, hipStream_t s) {
+  if (g.out_f32)
+    return reg ? launch_gemm_t<PREC, FOLD, true, true>(g, s) : launch_gemm_t<PREC, FOLD, true, false>(g, s);
+  return reg ? launch_gemm_t<PREC, FOLD, false, true>(g, s) : launch_gemm_t<PREC, FOLD, false, false>(g, s);
 }
 
 int launch_gemm(const GemmArgs &g_in, int prec, hipStream_t s) {
@@ -802,13 +921,16 @@ int launch_gemm(const GemmArgs &g_in, int prec, hipStream_t s) {
   // fold FP32 chunks into FP64 only when the final K spans several chunks;
   // a chunk is one K stage
   const bool fold = g.final_step && g.kbits > 6;
-  if (prec == SQC_F64) return launch_gemm_t<SQC_F64, false>(g, s);
-  if (prec == SQC_F32) return fold ? launch_gemm_t<SQC_F32, true>(g, s) : launch_gemm_t<SQC_F32, false>(g, s);
-  return fold ? launch_gemm_t<SQC_BF16X3, true>(g, s) : launch_gemm_t<SQC_BF16X3, false>(g, s);
+  const bool reg = g.mbits >= 6 && g.nbits >= 6 && g.kbits >= 6 && g.k.nruns >= 1 && g.k.bits[0] >= 4;
+  if (prec == SQC_F64) return launch_gemm_o<SQC_F64, false>(g, reg, s);
+  if (prec == SQC_F32)
+    return fold ? launch_gemm_o<SQC_F32, true>(g, reg, s) : launch_gemm_o<SQC_F32, false>(g, reg, s);
+  return fold ? launch_gemm_o<SQC_BF16X3, true>(g, reg, s) : launch_gemm_o<SQC_BF16X3, false>(g, reg, s);
 }
 
 void launch_topr(const TopRArgs &t, hipStream_t s) {
-  hipLaunchKernelGGL(topr, dim3(1), dim3(kSelThreads), 0, s, t);
+  hipLaunchKernelGGL(topr_gather, dim3(kGatherGroups), dim3(kTThreads), 0, s, t);
+  hipLaunchKernelGGL(topr_rank, dim3(1), dim3(kTThreads), 0, s, t);
 }
 
 void launch_zero(void *p, size_t bytes, hipStream_t s) {

@@ -239,8 +239,8 @@ static void push_run(IndexMap &m, int bits, int64_t sx, int64_t sy) {
   m.bits[m.nruns] = bits;
   m.sx[m.nruns] = sx;
   m.sy[m.nruns] = sy;
-  m.lx[m.nruns] = (int8_t)(63 - __builtin_clzll((unsigned long long)sx));
-  m.ly[m.nruns] = (int8_t)(63 - __builtin_clzll((unsigned long long)sy));
+  m.lx[m.nruns] = (int32_t)(63 - __builtin_clzll((unsigned long long)sx));
+  m.ly[m.nruns] = (int32_t)(63 - __builtin_clzll((unsigned long long)sy));
   m.nruns++;
 }
 
