@@ -3,12 +3,14 @@
 // sigma of its cuts, with the factor 1/2 per out-cut folded in.  FP64.
 //
 // Structure: the map from (preparation s, basis beta, outcome b) to sigma is a
-// tensor product of one small map per cut.  A work-group owns one combination
-// of measurement bases beta (a label Z, X or Y per out-cut) and a tile of XT
-// consecutive data states.  It stages p[(s, beta)][x, b] for all
-// preparations s and out-cut outcomes b of its tile in LDS, applies the
-// per-cut maps in place, one pass per cut, and writes every label assignment
-// compatible with beta (beta(I) = beta(Z) = Z, so a Z basis serves I and Z).
+// tensor product of one small map per cut.  A work item is one combination of
+// measurement bases beta (a label Z, X or Y per out-cut) and a tile of XT
+// consecutive data states.  Its entries p[(s, beta)][x, b] for all
+// preparations s and out-cut outcomes b are staged in LDS, the per-cut maps
+// are applied in place, one pass per cut, and every label assignment
+// compatible with beta is written (beta(I) = beta(Z) = Z, so a Z basis serves
+// I and Z).  The code is kept in loops: a kernel's first pass over
+// straight-line code is bound by instruction fetch.
 //
 //   in-cut  (digit of s -> digit of sigma):  I = p0 + p1,  Z = p0 - p1,
 //            X = 2 p+ - p0 - p1,  Y = 2 p+i - p0 - p1
@@ -21,57 +23,72 @@ namespace sqc {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kLdsElems = 2048;  // doubles staged per work-group
-constexpr int kMaxNS = 1024;     // preparation patterns a work-group tabulates
-constexpr int kMaxNB = 1024;     // out-cut outcome patterns
+constexpr int kLdsElems = 2048;   // doubles staged per work-group
+constexpr int kPer = kLdsElems / kThreads;
+constexpr int kMaxNS = 1024;
+constexpr int kMaxNB = 1024;
 
 __device__ __forceinline__ double load_prob(const void *p, int64_t i, int f32) {
   return f32 ? (double)static_cast<const float *>(p)[i] : static_cast<const double *>(p)[i];
 }
 
+// Bytes of dynamic LDS a work-group uses.
+size_t attribute_lds_bytes(int xt_bits, int n_in, int n_out) {
+  const size_t E = (size_t(1) << (2 * n_in)) << (n_out + xt_bits);
+  const size_t NS = size_t(1) << (2 * n_in), NB = size_t(1) << n_out, XT = size_t(1) << xt_bits;
+  return E * 8 + NS * 8 + NS * 4 + 3 * NB * 4 + XT * 4;
+}
+
+// One work-group = (basis combination beta, tile of XT consecutive data
+// states).  The threads first tabulate the offsets and label bits of the
+// preparations, outcome bits and tile states (one entry each), then issue all
+// variant loads at once.  LDS is sized to the subcircuit (dynamic), so small
+// stages leave room for many work-groups per CU.
 __global__ __launch_bounds__(kThreads) void attribute_lds(AttrArgs a) {
-  __shared__ double buf[kLdsElems];
-  // per work-group tables (NS * XT * NB <= kLdsElems, NS <= kMaxNS, NB <= kMaxNB):
-  //   vtab[s]   variant row offset of preparation index s (with this beta)
-  //   xoff[xt]  outcome offset of tile entry xt;  boff[b] of out-cut bits b
-  //   sin[s]    label index contributed by the in-cut digits of s
-  //   sout[v]   label index of valid out-cut slot v;  slot[v] its bit pattern
-  __shared__ uint32_t tab[kLdsElems + 2 * kMaxNB + 64];
-  __shared__ int64_t vtab[kMaxNS];
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
   const int tid = threadIdx.x;
   const int XT = 1 << a.xt_bits;
   const int NB = 1 << a.n_out;
   const int NS = 1 << (2 * a.n_in);
   const int E = NS * XT * NB;
-  const int64_t x0 = int64_t(blockIdx.x) << a.xt_bits;
+  double *buf = reinterpret_cast<double *>(dyn);            // [E]
+  int64_t *vin = reinterpret_cast<int64_t *>(buf + E);      // [NS] variant index of the in-cut digits of s
+  uint32_t *sinl = reinterpret_cast<uint32_t *>(vin + NS);  // [NS] their label bits
+  uint32_t *boff = sinl + NS;                               // [NB] wire offset of outcome bits b
+  uint32_t *sout = boff + NB;                               // [NV] label bits of valid out-cut slot v
+  uint32_t *slot = sout + NB;                               // [NV] its outcome bits
+  uint32_t *xoff = slot + NB;                               // [XT] wire offset of tile state xt
+  const int lnxt = a.d - a.xt_bits;
+  const int bidx = blockIdx.x >> lnxt;
+  const int64_t x0 = int64_t(blockIdx.x & ((1 << lnxt) - 1)) << a.xt_bits;
 
-  // basis digits of this work-group and the fixed part of the variant index
-  int beta[kMaxIncident];
+  // basis digits of this work-group
+  int zmask = 0;  // bit j: out-cut j measured in the Z basis
   int64_t vbeta = 0;
-  int nz = 0;
   {
-    int rem = blockIdx.y;
+    int rem = bidx;
     for (int j = 0; j < a.n_out; ++j) {
-      beta[j] = rem % 3;
+      const int bj = rem % 3;
       rem /= 3;
-      vbeta += int64_t(beta[j]) * a.place[a.out_pos[j]];
-      nz += beta[j] == 0 ? 1 : 0;
+      vbeta += int64_t(bj) * a.place[a.out_pos[j]];
+      zmask |= (bj == 0 ? 1 : 0) << j;
     }
   }
-  const int NV = 1 << nz;  // valid out-cut slots: a Z-basis cut carries I and Z
-  uint32_t *xoff = tab;
-  uint32_t *boff = xoff + XT;
-  uint32_t *sin = boff + NB;
-  uint32_t *sout = sin + NS;
-  uint32_t *slot = sout + NV;
+  const int nz = __builtin_popcount(zmask);
+  const int NV = 1 << nz;  // a Z-basis cut carries both I and Z
   int64_t base = 0;
-  for (int j = 0; j < a.d; ++j)
+  for (int j = a.xt_bits; j < a.d; ++j)
     if ((x0 >> j) & 1) base |= int64_t(1) << a.data_wire[j];
-  for (int t = tid; t < XT; t += kThreads) {
-    uint32_t o = 0;
-    for (int j = 0; j < a.xt_bits; ++j)
-      if ((t >> j) & 1) o |= uint32_t(1) << a.data_wire[j];
-    xoff[t] = o;
+  for (int t = tid; t < NS; t += kThreads) {
+    int64_t vr = 0;
+    uint32_t sg = 0;
+    for (int j = 0; j < a.n_in; ++j) {
+      const int dgt = (t >> (2 * j)) & 3;
+      vr += int64_t(dgt) * a.place[a.in_pos[j]];
+      sg |= uint32_t(dgt) << (2 * a.in_pos[j]);
+    }
+    vin[t] = vr;
+    sinl[t] = sg;
   }
   for (int t = tid; t < NB; t += kThreads) {
     uint32_t o = 0;
@@ -79,29 +96,24 @@ __global__ __launch_bounds__(kThreads) void attribute_lds(AttrArgs a) {
       if ((t >> j) & 1) o |= uint32_t(1) << a.out_wire[j];
     boff[t] = o;
   }
-  for (int t = tid; t < NS; t += kThreads) {
-    int64_t v = vbeta;
-    uint32_t sg = 0;
-    for (int j = 0; j < a.n_in; ++j) {
-      const int dgt = (t >> (2 * j)) & 3;
-      v += int64_t(dgt) * a.place[a.in_pos[j]];
-      sg |= uint32_t(dgt) << (2 * a.in_pos[j]);
-    }
-    vtab[t] = (v << a.w) + base;
-    sin[t] = sg;
+  for (int t = tid; t < XT; t += kThreads) {
+    uint32_t o = 0;
+    for (int j = 0; j < a.xt_bits; ++j)
+      if ((t >> j) & 1) o |= uint32_t(1) << a.data_wire[j];
+    xoff[t] = o;
   }
   for (int t = tid; t < NV; t += kThreads) {
     uint32_t sg = 0, sl = 0;
-    int zb = 0;
+    int zb = 0, rem = bidx;
     for (int j = 0; j < a.n_out; ++j) {
-      int lab;
-      if (beta[j] == 0) {
+      const int bj = rem % 3;  // basis digit j
+      rem /= 3;
+      int lab = bj;            // X = 1, Y = 2 coincide with the basis digits
+      if (bj == 0) {
         const int bit = (t >> zb) & 1;
         ++zb;
         lab = bit ? 3 : 0;  // slot bit 0 holds I, bit 1 holds Z
         sl |= uint32_t(bit) << j;
-      } else {
-        lab = beta[j];  // X = 1, Y = 2 coincide with the basis digits
       }
       sg |= uint32_t(lab) << (2 * a.out_pos[j]);
     }
@@ -110,18 +122,16 @@ __global__ __launch_bounds__(kThreads) void attribute_lds(AttrArgs a) {
   }
   __syncthreads();
 
-  // stage: element e = (s * XT + xt) * NB + b; all of a thread's loads are
-  // issued before the first is used (clamped offsets, no branches)
+  // stage: element e = (s XT + xt) NB + b; all loads in flight together
   {
-    constexpr int kPer = kLdsElems / kThreads;
     int64_t off[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int e = tid + k * kThreads;
       const int b = e & (NB - 1);
       const int xt = (e >> a.n_out) & (XT - 1);
-      const int s = (e >> (a.n_out + a.xt_bits)) & (NS - 1);
-      off[k] = e < E ? vtab[s] + (int64_t)(xoff[xt] | boff[b]) : 0;
+      const int sdx = (e >> (a.n_out + a.xt_bits)) & (NS - 1);
+      off[k] = e < E ? ((vbeta + vin[sdx]) << a.w) + base + (int64_t)(xoff[xt] | boff[b]) : 0;
     }
     double v[kPer];
     if (a.in_f32) {
@@ -139,46 +149,67 @@ __global__ __launch_bounds__(kThreads) void attribute_lds(AttrArgs a) {
   }
   __syncthreads();
 
-  // out-cut maps: pair (b_j = 0, b_j = 1) -> slot 0 / 1
+  // out-cut maps: pair (b_j = 0, b_j = 1) -> slot 0 / 1.  A thread's pairs
+  // of one pass are read together, then written (one LDS round trip).
   for (int j = 0; j < a.n_out; ++j) {
-    const bool zb = beta[j] == 0;
-    for (int p = tid; p < E / 2; p += kThreads) {
-      int e0 = ((p >> j) << (j + 1)) | (p & ((1 << j) - 1));
-      int e1 = e0 | (1 << j);
-      double q0 = buf[e0], q1 = buf[e1];
-      buf[e0] = zb ? q0 + q1 : q0 - q1;
-      buf[e1] = zb ? q0 - q1 : 0.0;
+    const bool zb = (zmask >> j) & 1;
+    for (int p0 = 0; p0 < E / 2; p0 += 4 * kThreads) {
+      double q0[4], q1[4];
+      int e0[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = p0 + u * kThreads + tid;
+        e0[u] = p < E / 2 ? ((p >> j) << (j + 1)) | (p & ((1 << j) - 1)) : -1;
+        q0[u] = e0[u] >= 0 ? buf[e0[u]] : 0.0;
+        q1[u] = e0[u] >= 0 ? buf[e0[u] | (1 << j)] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0[u] >= 0) {
+          buf[e0[u]] = zb ? q0[u] + q1[u] : q0[u] - q1[u];
+          buf[e0[u] | (1 << j)] = zb ? q0[u] - q1[u] : 0.0;
+        }
     }
     __syncthreads();
   }
   // in-cut maps: digit j of s, 4 entries -> labels I, X, Y, Z
   for (int j = 0; j < a.n_in; ++j) {
     const int sh = 2 * j + a.xt_bits + a.n_out;
-    for (int p = tid; p < E / 4; p += kThreads) {
-      int lo = p & ((1 << sh) - 1);
-      int e0 = ((p >> sh) << (sh + 2)) | lo;
-      int st = 1 << sh;
-      double p0 = buf[e0], p1 = buf[e0 + st], pp = buf[e0 + 2 * st], pi = buf[e0 + 3 * st];
-      double s01 = p0 + p1;
-      buf[e0] = s01;
-      buf[e0 + st] = 2.0 * pp - s01;
-      buf[e0 + 2 * st] = 2.0 * pi - s01;
-      buf[e0 + 3 * st] = p0 - p1;
+    const int st = 1 << sh;
+    for (int p0 = 0; p0 < E / 4; p0 += 2 * kThreads) {
+      double q[2][4];
+      int e0[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int p = p0 + u * kThreads + tid;
+        e0[u] = p < E / 4 ? ((p >> sh) << (sh + 2)) | (p & (st - 1)) : -1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) q[u][r] = e0[u] >= 0 ? buf[e0[u] + r * st] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        if (e0[u] >= 0) {
+          const double s01 = q[u][0] + q[u][1];
+          buf[e0[u]] = s01;
+          buf[e0[u] + st] = 2.0 * q[u][2] - s01;
+          buf[e0[u] + 2 * st] = 2.0 * q[u][3] - s01;
+          buf[e0[u] + 3 * st] = q[u][0] - q[u][1];
+        }
     }
     __syncthreads();
   }
 
-  // write every label assignment compatible with beta: q = (xt, v, s), s fastest
+  // every label assignment compatible with beta: q = (xt, v, s), s fastest
   const int lNS = 2 * a.n_in;
-  const int nq = (XT * NV) << lNS;
   const int64_t L = int64_t(1) << (2 * a.c);
+  const int nq = (XT * NV) << lNS;
   for (int q = tid; q < nq; q += kThreads) {
-    const int s = q & (NS - 1);
+    const int sdx = q & (NS - 1);
     const int rest = q >> lNS;
-    const int v = rest & (NV - 1);
+    const int vv = rest & (NV - 1);
     const int xt = rest >> nz;
-    const double val = buf[(s * XT + xt) * NB + slot[v]] * a.scale;
-    const int64_t o = (x0 + xt) * L + (sin[s] | sout[v]);
+    const double val = buf[(sdx * XT + xt) * NB + slot[vv]] * a.scale;
+    const int64_t o = (x0 + xt) * L + (sinl[sdx] | sout[vv]);
     if (a.out_f32) static_cast<float *>(a.out)[o] = (float)val;
     else static_cast<double *>(a.out)[o] = val;
   }
@@ -240,18 +271,18 @@ __global__ __launch_bounds__(kThreads) void attribute_direct(AttrArgs a) {
 void launch_attribute(const AttrArgs &a0, hipStream_t s) {
   AttrArgs a = a0;
   const int64_t per_x = (int64_t(1) << (2 * a.n_in)) << a.n_out;
-  const int64_t ns = int64_t(1) << (2 * a.n_in), nb = int64_t(1) << a.n_out;
-  if (per_x <= kLdsElems && ns <= kMaxNS && nb <= kMaxNB && a.n_out <= 10) {  // grid.y = 3^n_out
+  const int64_t ns = int64_t(1) << (2 * a.n_in);
+  if (per_x <= kLdsElems && ns <= kMaxNS && (int64_t(1) << a.n_out) <= kMaxNB) {
+    // x-tile: as many data states as fill the stage, then halved while that
+    // gives too few work-groups to fill the device and keeps >= 256 entries
     int xb = 0;
     while ((per_x << (xb + 1)) <= kLdsElems && xb + 1 <= a.d) ++xb;
     int64_t nbeta = 1;
     for (int j = 0; j < a.n_out; ++j) nbeta *= 3;
-    // shrink the tile while that gives more work-groups and keeps >= 1024 entries
-    while (xb > 0 && (((int64_t(1) << a.d) >> xb) * nbeta) < 1024 && (per_x << (xb - 1)) >= 1024)
-      --xb;
+    while (xb > 0 && (nbeta << (a.d - xb)) < 1024 && (per_x << (xb - 1)) >= 256) --xb;
     a.xt_bits = xb;
-    dim3 grid((unsigned)((int64_t(1) << a.d) >> xb), (unsigned)nbeta);
-    hipLaunchKernelGGL(attribute_lds, grid, dim3(kThreads), 0, s, a);
+    const dim3 grid((unsigned)(nbeta << (a.d - xb)));
+    hipLaunchKernelGGL(attribute_lds, grid, dim3(kThreads), attribute_lds_bytes(xb, a.n_in, a.n_out), s, a);
   } else {
     int64_t total = (int64_t(1) << a.d) << (2 * a.c);
     int64_t blocks = (total + kThreads - 1) / kThreads;

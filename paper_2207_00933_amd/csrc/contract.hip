@@ -501,11 +501,17 @@ struct SubTileBins {
     M = 1u << t.mbits;
     N = 1u << t.nbits;
     lnt = t.nbits > 6 ? t.nbits - 6 : 0;
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t e = threadIdx.x + kTThreads * q, ml = e & 31, nl = e >> 5;
-      o_lane[q] = map_y(t.m, ml) + map_y(t.n, nl);
-      ok[q] = ml < M && nl < N;
-    }
+    // bins q and q + 1 differ by 8 rows: o_lane[q] = o(ml, nl0) + o(8 q)
+    // (nl0 = tid / 32 < 8 for 256 threads, disjoint bits)
+    const uint32_t ml = threadIdx.x & 31, nl0 = threadIdx.x >> 5;
+    const int64_t o0 = map_y(t.m, ml) + map_y(t.n, nl0);
+    const int64_t r8 = map_y(t.n, 8), r16 = map_y(t.n, 16);
+    o_lane[0] = o0;
+    o_lane[1] = o0 + r8;
+    o_lane[2] = o0 + r16;
+    o_lane[3] = o0 + r8 + r16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ok[q] = ml < M && nl0 + 8 * q < N;
   }
   // origins are multiples of 32: a bin exists iff the origin and (ml, nl) do
   __device__ void load(const TopRArgs &t, int sb, double v[4], uint64_t ix[4]) const {
@@ -575,7 +581,9 @@ __global__ __launch_bounds__(kTThreads) void topr_gather(TopRArgs t) {
   // group ascending), then every maximum's rank by binary search ----
   double kv = gm;
   int ki = tid;
+#pragma unroll 1
   for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll 1
     for (int j = k >> 1; j >= 1; j >>= 1) {
       const double ov = __shfl_xor(kv, j);
       const int oi = __shfl_xor(ki, j);

@@ -93,6 +93,71 @@ def test_attribute_direct_path(session):
     assert np.abs(got[:, sig] - want.T).max() <= 1e-12
 
 
+def _hub_graph(n_in, n_out, d_extra, interleave, seed):
+    """Subcircuit 0 with n_in in-cuts and n_out out-cuts to single-wire
+    partners.  Wires of sub 0: out-cut wires (measured), in-cut wires
+    (initialised from a cut, read out as data) and d_extra plain data wires;
+    with ``interleave`` the wire order, the data order and the incident cut
+    order are shuffled."""
+    rng = np.random.default_rng(seed)
+    w = n_out + n_in + d_extra
+    wires = list(range(w))
+    if interleave:
+        rng.shuffle(wires)
+    out_w, in_w, extra_w = wires[:n_out], wires[n_out:n_out + n_in], wires[n_out + n_in:]
+    data0 = in_w + extra_w
+    if interleave:
+        rng.shuffle(data0)
+    n_wires = [w] + [1] * (n_in + n_out)
+    data = [data0] + [[] for _ in range(n_in)] + [[0] for _ in range(n_out)]
+    cuts = [(1 + k, 0, 0, in_w[k]) for k in range(n_in)] + \
+           [(0, out_w[j], 1 + n_in + j, 0) for j in range(n_out)]
+    if interleave:
+        order = rng.permutation(len(cuts))
+        cuts = [cuts[q] for q in order]
+    return n_wires, data, cuts
+
+
+ATTR_GRAPHS = {
+    # name: (n_in, n_out, d_extra, interleave)
+    "lds_in4": (4, 1, 2, False),       # 4^4 preparations: LDS stage
+    "lds_out7": (0, 7, 3, True),       # 2^7 outcomes: LDS stage
+    "reg_2_6": (2, 6, 1, False),       # register form, most out-cuts
+    "reg_mixed": (2, 2, 3, True),      # register form, scattered wires and labels
+    "reg_in3": (3, 0, 4, True),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ATTR_GRAPHS))
+@pytest.mark.parametrize("in_prec,out_prec", [(0, 0), (1, 1)])
+def test_attribute_graph_paths(session, name, in_prec, out_prec):
+    """Random variants on hub graphs that steer attribution through its LDS
+    and register forms; all label rows (or 256 sampled) against the oracle."""
+    n_in, n_out, d_extra, inter = ATTR_GRAPHS[name]
+    n_wires, data, cuts = _hub_graph(n_in, n_out, d_extra, inter, seed=len(name))
+    g = sqc.Graph(n_wires, data, cuts)
+    sqc.check_graph(g)
+    cc = _GraphView(n_wires, data, cuts)
+    rng = np.random.default_rng(11)
+    var0 = rng.random((4 ** n_in * 3 ** n_out, 1 << n_wires[0]))
+    if in_prec == sqc.F32:
+        var0 = var0.astype(np.float32).astype(np.float64)
+    c = n_in + n_out
+    sig = list(range(4 ** c)) if 4 ** c <= 256 else \
+        sorted(rng.choice(4 ** c, size=256, replace=False).tolist())
+    want = rc.fold_half(rc.attribute(cc, 0, var0, sigmas=sig), n_out)
+    say(f"attribute graph {name} in={in_prec} out={out_prec}")
+    dt = torch.float64 if in_prec == sqc.F64 else torch.float32
+    vt = torch.from_numpy(var0).to(dt).cuda()
+    out = torch.empty(sqc.attribute_bytes(g, 0, out_prec), dtype=torch.uint8, device="cuda")
+    d = sqc.attribute(session.ctx, g, 0, vt, in_prec, out, out_prec)
+    torch.cuda.synchronize()
+    odt = torch.float64 if out_prec == sqc.F64 else torch.float32
+    got = out.view(odt).double().cpu().numpy().reshape(1 << d.n_bits, 1 << (2 * d.n_labels))
+    tol = 1e-12 if out_prec == sqc.F64 else 1e-6 * max(1.0, np.abs(want).max())
+    assert np.abs(got[:, sig] - want.T).max() <= tol
+
+
 class _GraphView:
     """Minimal cut-circuit view for the oracle from plain graph arrays."""
 
