@@ -319,6 +319,7 @@ void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<c
   size_t nsteps = c.unit ? 1 : c.plan.steps.size();
   for (size_t si = 0; si < nsteps; ++si) {
     GemmArgs g = step_args(c, si, inputs, ws, inter_base, bins, bins_f32, unit);
+    g.nmajor = gemm_nmajor(g);
     if (g.mbits > 31 || g.nbits > 31 || g.kbits > 31)
       raise(SQC_E_UNSUPPORTED, "a contraction dimension exceeds 2^31");
     bool last = si + 1 == nsteps;
@@ -347,6 +348,7 @@ void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<c
       t.blk_max = g.blk_max;
       t.wg_stats = g.wg_stats;
       t.ngroups = groups;
+      t.nmajor = g.nmajor;
       t.slot_n = reinterpret_cast<int *>(ws + bp.take(kTopRSlots * sizeof(int)));
       char *misc = ws + bp.take(64);
       t.tau_sum = reinterpret_cast<double *>(misc);

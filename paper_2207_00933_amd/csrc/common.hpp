@@ -163,6 +163,7 @@ struct GemmArgs {
   IndexMap m, n, k;
   int out_f32;           // output element type (intermediates follow the path)
   int final_step;        // 1: compensated FP64 fold of the FP32 sums of K stages
+  int nmajor;            // tile order: 0 = m panels outer (A panel read once), 1 = n panels outer
   // statistics of every 32 x 32 sub-tile (final step of a recursion)
   int stats;
   double *blk_max;       // [4 * tiles] largest stored bin of each 32 x 32 sub-tile
@@ -178,6 +179,9 @@ struct GemmArgs {
 };
 // 64 x 64 output tiles of a GEMM (sub-tile statistics: 4 per tile).
 int64_t gemm_tiles(const GemmArgs &g);
+// Tile order reading the larger operand once (the other one's panels are
+// re-read, from L2 when small).
+int gemm_nmajor(const GemmArgs &g);
 // Work-groups launch_gemm uses at most (size of wg_stats).
 constexpr int kMaxGemmGroups = 4096;
 // Enqueue; returns the number of work-groups launched.
@@ -195,6 +199,7 @@ struct TopRArgs {
   const double *blk_max;
   const double *wg_stats;
   int ngroups;          // work-groups of the final GEMM
+  int nmajor;           // its tile order
   int *ctl;             // [1] listed sub-tiles, -1 when the list did not fit
   double *tau_sum;      // [2] threshold, total sum
   int *slot_n;          // [kTopRSlots]

@@ -151,6 +151,10 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
   const int lmt = g.mbits > 6 ? g.mbits - 6 : 0;
   const int nks = g.kbits > 6 ? 1 << (g.kbits - 6) : 1;  // K stages of BK
 
+  // tile -> (m panel, n panel)
+  const int nmaj = g.nmajor;
+  auto tile_m = [&](int t) -> uint32_t { return nmaj ? (uint32_t)(t & ((1 << lmt) - 1)) : (uint32_t)(t >> lnt); };
+  auto tile_n = [&](int t) -> uint32_t { return nmaj ? (uint32_t)(t >> lmt) : (uint32_t)(t & ((1 << lnt) - 1)); };
   const Sched sc = schedule(1 << (lmt + lnt));
   // work-group statistics: running compensated sum and maximum of its waves
   __shared__ double wg_part[3][4];
@@ -219,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
     }
   };
   auto load_a = [&](int tile, int ks) {
-    const uint32_t m0 = (uint32_t)(tile >> lnt) << 6;
+    const uint32_t m0 = tile_m(tile) << 6;
     const uint32_t k0 = (uint32_t)ks << 6;
     const bool ok = REG || m0 + lane < M;  // columns past M read the column origin
     const T *p = static_cast<const T *>(g.A) + (map_x(g.m, m0) + map_x(g.k, k0) + a_kw) + (ok ? a_lane : 0);
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
       for (int j = 0; j < NJ; ++j) av[j] = T(0);
   };
   auto load_b = [&](int tile, int ks) {
-    const uint32_t n0 = (uint32_t)(tile & ((1 << lnt) - 1)) << 6;
+    const uint32_t n0 = tile_n(tile) << 6;
     const uint32_t k0 = (uint32_t)ks << 6;
     const bool ok = REG || n0 + lane < N;
     const T *p = static_cast<const T *>(g.B) + (map_x(g.n, n0) + map_y(g.k, k0) + b_kw) + (ok ? b_lane : 0);
@@ -328,10 +332,8 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
   }
   reset();
 
-  // A stays staged while consecutive tiles share the m panel (single stage);
-  // B stays staged when there is a single n tile and a single stage.
-  const bool reuse_a = nks == 1;
-  const bool reuse_b = nks == 1 && lnt == 0;
+  // with a single K stage an operand panel stays staged while consecutive
+  // tiles share it
   int tile = sc.first, ks = 0;
   bool need_a = true, need_b = true;
   load_a(tile, ks);
@@ -351,8 +353,8 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
       ++tile;
       more = tile < sc.end;
     }
-    need_a = !(reuse_a && (tile >> lnt) == (cur_tile >> lnt));
-    need_b = !reuse_b;
+    need_a = !(nks == 1 && tile_m(tile) == tile_m(cur_tile));
+    need_b = !(nks == 1 && tile_n(tile) == tile_n(cur_tile));
     if (more) {
       if (need_a) load_a(tile, ks);
       if (need_b) load_b(tile, ks);
@@ -369,8 +371,8 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
     fold();  // one FP32 chunk per K stage
     // ---- epilogue after the tile's last stage ----
     if (cur_ks == nks - 1) {
-      const uint32_t mw = ((uint32_t)(cur_tile >> lnt) << 6) + wm * 32;  // wave origin
-      const uint32_t nw = ((uint32_t)(cur_tile & ((1 << lnt) - 1)) << 6) + wn * 32;
+      const uint32_t mw = (tile_m(cur_tile) << 6) + wm * 32;  // wave origin
+      const uint32_t nw = (tile_n(cur_tile) << 6) + wn * 32;
       double lsum = 0.0, lmax = -INFINITY;
       if (REG || (mw < M && nw < N)) {
         const int64_t cw = map_y(g.m, mw) + map_y(g.n, nw);
@@ -484,23 +486,28 @@ __device__ __forceinline__ void two_sum_merge(double &s, double &c, double s2, d
   c += c2 + err;
 }
 
-// origin (m0, n0) of sub-tile sb of a GEMM with 2^lnt n tiles
-__device__ __forceinline__ void sub_origin(int sb, int lnt, uint32_t &m0, uint32_t &n0) {
+// origin (m0, n0) of sub-tile sb of a GEMM with 2^lmt m tiles and 2^lnt n
+// tiles in the given tile order
+__device__ __forceinline__ void sub_origin(int sb, int lmt, int lnt, int nmaj, uint32_t &m0, uint32_t &n0) {
   const int tile = sb >> 2, w = sb & 3;
-  m0 = ((uint32_t)(tile >> lnt) << 6) + (w & 1) * 32;
-  n0 = ((uint32_t)(tile & ((1 << lnt) - 1)) << 6) + (w >> 1) * 32;
+  const uint32_t mt = nmaj ? (uint32_t)(tile & ((1 << lmt) - 1)) : (uint32_t)(tile >> lnt);
+  const uint32_t nt = nmaj ? (uint32_t)(tile >> lmt) : (uint32_t)(tile & ((1 << lnt) - 1));
+  m0 = (mt << 6) + (w & 1) * 32;
+  n0 = (nt << 6) + (w >> 1) * 32;
 }
 
 // Offset of bin (ml, nl) of a sub-tile, or ~0 when it lies outside the result.
 struct SubTileBins {
   uint32_t M, N;
-  int lnt;
+  int lmt, lnt, nmaj;
   int64_t o_lane[4];  // thread's bins e = tid + 256 q: (e % 32, e / 32)
   bool ok[4];
   __device__ void init(const TopRArgs &t) {
     M = 1u << t.mbits;
     N = 1u << t.nbits;
     lnt = t.nbits > 6 ? t.nbits - 6 : 0;
+    lmt = t.mbits > 6 ? t.mbits - 6 : 0;
+    nmaj = t.nmajor;
     // bins q and q + 1 differ by 8 rows: o_lane[q] = o(ml, nl0) + o(8 q)
     // (nl0 = tid / 32 < 8 for 256 threads, disjoint bits)
     const uint32_t ml = threadIdx.x & 31, nl0 = threadIdx.x >> 5;
@@ -516,7 +523,7 @@ struct SubTileBins {
   // origins are multiples of 32: a bin exists iff the origin and (ml, nl) do
   __device__ void load(const TopRArgs &t, int sb, double v[4], uint64_t ix[4]) const {
     uint32_t m0, n0;
-    sub_origin(sb, lnt, m0, n0);
+    sub_origin(sb, lmt, lnt, nmaj, m0, n0);
     const bool sub_ok = m0 < M && n0 < N;
     const int64_t o0 = sub_ok ? map_y(t.m, m0) + map_y(t.n, n0) : 0;
 #pragma unroll
@@ -863,6 +870,11 @@ __global__ void zero_bytes(unsigned int *p, size_t nwords) {
 }
 
 }  // namespace
+
+int gemm_nmajor(const GemmArgs &g) {
+  // n panels outer when B is the larger operand (and there are several m panels)
+  return g.mbits > 6 && g.nbits > g.mbits ? 1 : 0;
+}
 
 int64_t gemm_tiles(const GemmArgs &g) {
   const int64_t mt = g.mbits > 6 ? (int64_t(1) << (g.mbits - 6)) : 1;

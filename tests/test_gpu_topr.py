@@ -101,3 +101,31 @@ def test_topr_matches_stable_sort(session, name, pname, prec):
         ref = vals if prec == sqc.F64 else bins
         want = math.fsum(ref.tolist())
         assert abs(s - want) <= 1e-15 * max(1.0, math.fsum(np.abs(ref).tolist())), (s, want)
+
+
+def test_topr_two_subcircuits_n_panel_order(session):
+    """Two subcircuits (7 and 10 data bits, one cut): the final contraction
+    has more n than m panels and runs with n panels outermost; the top-R stage
+    must address its sub-tiles in that order.  Random attributed entries."""
+    rng = np.random.default_rng(21)
+    g = sqc.Graph([8, 10], [list(range(7)), list(range(10))], [(0, 7, 1, 0)])
+    bufs = [torch.from_numpy(rng.random((1 << 7) * 4)).cuda(),
+            torch.from_numpy(rng.random((1 << 10) * 4)).cuda()]
+    att = [sqc.tensor_desc(bufs[0], 1, 7, sqc.F64, sqc.LAYOUT_ATTRIBUTED),
+           sqc.tensor_desc(bufs[1], 1, 10, sqc.F64, sqc.LAYOUT_ATTRIBUTED)]
+    M = 1 << 17
+    for pname, prec in PRECS:
+        say(f"topr two subs {pname}")
+        masks = sqc.assign_bins([7, 10], None, M)
+        session.ensure_workspace(sqc.recurse_workspace_bytes(att, g, masks, prec))
+        bins = torch.empty(M, dtype=torch.float64, device="cuda")
+        top = torch.empty(2 * sqc.MAX_TOPR, dtype=torch.float64, device="cuda")
+        bsum = torch.empty(1, dtype=torch.float64, device="cuda")
+        sqc.recurse(session.ctx, att, g, None, M, 32, prec, bins, sqc.F64, top, bsum)
+        torch.cuda.synchronize()
+        b = bins.cpu().numpy()
+        t = top.cpu().numpy()
+        order = np.argsort(-b, kind="stable")[:32]
+        assert np.array_equal(t[0:64:2], b[order])
+        assert np.array_equal(t[1:64:2].view(np.uint64), order.astype(np.uint64))
+        assert abs(bsum.item() - math.fsum(b.tolist())) <= 1e-12 * math.fsum(np.abs(b).tolist())
