@@ -339,6 +339,68 @@ sqc_status sqc_search(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
                       int32_t *n_solutions, sqc_recursion_info *info,
                       int32_t *n_recursions);
 
+/* ---- serving (an engine around sqc_recurse; not part of the paper) -------------
+ *
+ * A server keeps registered circuits' attributed tensors resident (the caller
+ * keeps the buffers alive until sqc_serve_destroy) and runs requests, each one
+ * states-merging recursion exactly as sqc_recurse computes it.  It owns
+ * n_slots HIP streams (default priority), one context each, and the caller's
+ * workspace buffer.  A request is admitted when a slot is idle and a free
+ * block of the workspace holds its footprint (sqc_serve_footprint); the others
+ * wait in arrival order, and a later request that fits may be admitted before
+ * an earlier one that does not.  Admitted requests run concurrently on their
+ * slots' streams, so requests that arrive while others are on the device
+ * overlap with them as slots and memory free up.  Each result is bitwise the
+ * same as the same sqc_recurse call made alone.  The engine advances (retires
+ * finished requests, admits waiting ones) inside sqc_serve_submit,
+ * sqc_serve_poll and sqc_serve_wait; it is not thread-safe. */
+typedef struct sqc_server sqc_server;
+
+typedef struct {
+  int32_t circuit;            /* id from sqc_serve_register                  */
+  int32_t top_r;              /* 1 .. SQC_MAX_TOPR                           */
+  uint64_t max_bins_M;        /* M of Algorithm 2                            */
+  const sqc_masks *scope;     /* n_sub masks of the expanded bin, or NULL at
+                                 recursion 0; copied by sqc_serve_submit     */
+  sqc_prec prec;              /* contraction path                            */
+  sqc_prec bins_prec;         /* storage of bins_dev                         */
+  void *bins_dev;             /* 2^a elements, caller-owned                  */
+  void *topr_dev;             /* top_r {double, uint64} records              */
+  void *sum_dev;              /* one double                                  */
+  sqc_masks *masks_out;       /* optional, n_sub entries, written at admission */
+} sqc_request;
+
+typedef struct {
+  uint64_t submitted, admitted, completed;
+  int32_t running, queued;
+  int32_t max_running;        /* most requests on the device at once         */
+  int32_t pad;
+  uint64_t workspace_bytes, workspace_peak;  /* bytes in use at most         */
+} sqc_serve_stats;
+
+/* Create a server on `device` with n_slots (1..64) streams using the caller's
+ * workspace (256-byte aligned device buffer; it is split among the running
+ * requests). */
+sqc_status sqc_serve_create(int device, int32_t n_slots, void *workspace_dev,
+                            size_t workspace_bytes, sqc_server **out);
+/* Wait for running requests, then release the streams and contexts. */
+sqc_status sqc_serve_destroy(sqc_server *srv);
+/* Register a circuit: its attributed tensors and cut list (copied; the tensor
+ * buffers stay the caller's). */
+sqc_status sqc_serve_register(sqc_server *srv, const sqc_tensor *attributed, int32_t n_sub,
+                              const sqc_cut *cuts, int32_t n_cuts, int32_t *circuit_id);
+/* Workspace bytes the request needs (0 on invalid input). */
+size_t sqc_serve_footprint(sqc_server *srv, const sqc_request *req);
+/* Validate and queue a request; SQC_E_NOMEM when its footprint exceeds the
+ * whole workspace.  `ticket` identifies it in sqc_serve_poll / _wait. */
+sqc_status sqc_serve_submit(sqc_server *srv, const sqc_request *req, uint64_t *ticket);
+/* state: 0 waiting, 1 running, 2 done; an admission error is returned here. */
+sqc_status sqc_serve_poll(sqc_server *srv, uint64_t ticket, int32_t *state);
+/* Block until the request is done. */
+sqc_status sqc_serve_wait(sqc_server *srv, uint64_t ticket);
+sqc_status sqc_serve_get_stats(sqc_server *srv, sqc_serve_stats *out);
+const char *sqc_serve_last_error(const sqc_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -121,3 +121,66 @@ class Recursion:
 
 def active_bits(masks: Sequence[sqc.Masks]) -> int:
     return sum(bin(m.active).count("1") for m in masks)
+
+
+class Server:
+    """The serving engine with a device workspace of its own.  Output buffers
+    of a request are the caller's and must stay alive until it is done; the
+    request structs (with their scope arrays) are kept here until then."""
+
+    def __init__(self, device: int = 0, n_slots: int = 4, workspace_bytes: int = 256 << 20):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the serving engine runs only on the HIP library")
+        self.device = torch.device("cuda", device)
+        self.ws = _bytes_tensor(workspace_bytes, self.device)
+        self.srv = sqc.serve_create(device, n_slots, self.ws)
+        self.graphs = {}
+        self._live = {}
+
+    def register(self, circ: Circuit) -> int:
+        # the attributed tensors were written on the session's stream
+        torch.cuda.synchronize(self.device)
+        cid = sqc.serve_register(self.srv, circ.att, circ.g)
+        self.graphs[cid] = circ.g
+        return cid
+
+    def request(self, cid: int, scope, M: int, top_r: int, prec: int, bins, bins_prec: int,
+                topr, bsum, masks_out: bool = False) -> sqc.Request:
+        n_sub = self.graphs[cid].n_sub
+        mo = (sqc.Masks * n_sub)() if masks_out else None
+        r = sqc.make_request(cid, n_sub, scope, M, top_r, prec, bins, bins_prec, topr, bsum, mo)
+        r._masks = mo
+        return r
+
+    def footprint(self, req: sqc.Request) -> int:
+        return sqc.serve_footprint(self.srv, req)
+
+    def submit(self, req: sqc.Request) -> int:
+        t = sqc.serve_submit(self.srv, req)
+        self._live[t] = req
+        return t
+
+    def poll(self, ticket: int) -> int:
+        st = sqc.serve_poll(self.srv, ticket)
+        if st == sqc.DONE:
+            self._live.pop(ticket, None)
+        return st
+
+    def wait(self, ticket: int) -> None:
+        sqc.serve_wait(self.srv, ticket)
+        self._live.pop(ticket, None)
+
+    def stats(self) -> sqc.ServeStats:
+        return sqc.serve_get_stats(self.srv)
+
+    def close(self) -> None:
+        if self.srv:
+            sqc.serve_destroy(self.srv)
+            self.srv = 0
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -72,6 +72,21 @@ class StageTime(ctypes.Structure):
                 ("flops", c_double)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("circuit", c_int32), ("top_r", c_int32), ("max_bins_M", c_uint64),
+                ("scope", POINTER(Masks)), ("prec", c_int), ("bins_prec", c_int),
+                ("bins_dev", c_void_p), ("topr_dev", c_void_p), ("sum_dev", c_void_p),
+                ("masks_out", POINTER(Masks))]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", c_uint64), ("admitted", c_uint64), ("completed", c_uint64),
+                ("running", c_int32), ("queued", c_int32), ("max_running", c_int32),
+                ("pad", c_int32), ("workspace_bytes", c_uint64), ("workspace_peak", c_uint64)]
+
+
+WAITING, RUNNING, DONE = 0, 1, 2
+
 STAGE_ATTRIBUTE, STAGE_MERGE, STAGE_CONTRACT, STAGE_FINAL, STAGE_TOPR = 1, 2, 4, 8, 16
 
 
@@ -130,6 +145,16 @@ def lib():
                                    c_int32, c_int, P, c_int, POINTER(Found), POINTER(c_uint64),
                                    c_int32, POINTER(c_int32), POINTER(RecursionInfo),
                                    POINTER(c_int32)]),
+            "sqc_serve_create": (c_int, [c_int, c_int32, P, c_size_t, POINTER(P)]),
+            "sqc_serve_destroy": (c_int, [P]),
+            "sqc_serve_register": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
+                                           POINTER(c_int32)]),
+            "sqc_serve_footprint": (c_size_t, [P, POINTER(Request)]),
+            "sqc_serve_submit": (c_int, [P, POINTER(Request), POINTER(c_uint64)]),
+            "sqc_serve_poll": (c_int, [P, c_uint64, POINTER(c_int32)]),
+            "sqc_serve_wait": (c_int, [P, c_uint64]),
+            "sqc_serve_get_stats": (c_int, [P, POINTER(ServeStats)]),
+            "sqc_serve_last_error": (c_char_p, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -363,3 +388,75 @@ def search(ctx: int, att: Sequence[Tensor], g: Graph, M: int, R: int, prec: int,
     infos = [(info[r].bins_sum, info[r].parent_prob, info[r].top_prob, info[r].active_bits,
               bool(info[r].leaf)) for r in range(nrec.value)]
     return sols, infos
+
+
+# ---------------------------------------------------------------------------
+# serving engine
+# ---------------------------------------------------------------------------
+
+def _check_srv(status: int, srv):
+    if status != OK:
+        raise SqcError(status, lib().sqc_serve_last_error(srv).decode())
+
+
+def serve_create(device: int, n_slots: int, workspace) -> int:
+    h = c_void_p()
+    _check(lib().sqc_serve_create(device, n_slots, _ptr(workspace),
+                                  workspace.numel() * workspace.element_size(), ctypes.byref(h)))
+    return h.value
+
+
+def serve_destroy(srv: int) -> None:
+    _check(lib().sqc_serve_destroy(srv))
+
+
+def serve_register(srv: int, att: Sequence[Tensor], g: Graph) -> int:
+    cid = c_int32()
+    _check_srv(lib().sqc_serve_register(srv, tensor_array(att), g.n_sub, g.cuts, g.n_cuts,
+                                        ctypes.byref(cid)), srv)
+    return cid.value
+
+
+def make_request(circuit: int, n_sub: int, scope, M: int, top_r: int, prec: int, bins,
+                 bins_prec: int, topr, bsum, masks_out=None) -> Request:
+    """A request struct; the scope and masks arrays it points to are kept on
+    the struct (``_keep``) so they outlive the call."""
+    r = Request()
+    r.circuit, r.top_r, r.max_bins_M, r.prec, r.bins_prec = circuit, top_r, M, prec, bins_prec
+    keep = []
+    if scope is not None:
+        sc = masks_array(scope)
+        keep.append(sc)
+        r.scope = ctypes.cast(sc, POINTER(Masks))
+    if masks_out is not None:
+        keep.append(masks_out)
+        r.masks_out = ctypes.cast(masks_out, POINTER(Masks))
+    r.bins_dev, r.topr_dev, r.sum_dev = _ptr(bins), _ptr(topr), _ptr(bsum)
+    r._keep = keep
+    return r
+
+
+def serve_footprint(srv: int, req: Request) -> int:
+    return int(lib().sqc_serve_footprint(srv, ctypes.byref(req)))
+
+
+def serve_submit(srv: int, req: Request) -> int:
+    t = c_uint64()
+    _check_srv(lib().sqc_serve_submit(srv, ctypes.byref(req), ctypes.byref(t)), srv)
+    return t.value
+
+
+def serve_poll(srv: int, ticket: int) -> int:
+    st = c_int32()
+    _check_srv(lib().sqc_serve_poll(srv, ticket, ctypes.byref(st)), srv)
+    return st.value
+
+
+def serve_wait(srv: int, ticket: int) -> None:
+    _check_srv(lib().sqc_serve_wait(srv, ticket), srv)
+
+
+def serve_get_stats(srv: int) -> ServeStats:
+    out = ServeStats()
+    _check(lib().sqc_serve_get_stats(srv, ctypes.byref(out)))
+    return out
