@@ -197,6 +197,169 @@ def measured_traffic():
         return None
 
 
+# ---------------------------------------------------------------------------
+# serving: Poisson arrivals of mixed recursions over a resident circuit pool
+# ---------------------------------------------------------------------------
+
+def serve_requests(sqc, pool, n_req: int, seed: int):
+    """Seeded request mix: a circuit of the pool, a = log2 M in [12, 24]
+    (capped by the circuit's unfixed data bits), and for 30% of requests a
+    recursion step on a bin of a coarse recursion-0 assignment (the scope of
+    a popped bin).  Returns (circuit index, scope, M, active bits)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_req):
+        ci = int(rng.integers(len(pool)))
+        nd = [s.n_data for s in pool[ci].subs]
+        scope, free = None, sum(nd)
+        if rng.random() < 0.3:
+            m0 = sqc.assign_bins(nd, None, 1 << int(rng.integers(1, 9)))
+            a0 = sum(bin(m.active).count("1") for m in m0)
+            scope = sqc.bin_scope(m0, int(rng.integers(1 << a0)))
+            free -= a0
+        a = min(int(rng.integers(12, 25)), free)
+        masks = sqc.assign_bins(nd, scope, 1 << a)
+        out.append((ci, scope, 1 << a, sum(bin(m.active).count("1") for m in masks)))
+    return out
+
+
+def replay(srv, reqs, arrivals):
+    """Submit each request at its arrival time (seconds from the start) and
+    record its completion; returns (wall seconds, latencies in ms)."""
+    n = len(reqs)
+    lat = [0.0] * n
+    owner = {}
+    i = done = 0
+    host = 0.0
+    t0 = time.perf_counter()
+    while done < n:
+        now = time.perf_counter() - t0
+        while i < n and arrivals[i] <= now:
+            h0 = time.perf_counter()
+            owner[srv.submit(reqs[i])] = i
+            host += time.perf_counter() - h0
+            i += 1
+        for t in srv.completed():
+            k = owner.pop(t)
+            lat[k] = (time.perf_counter() - t0 - arrivals[k]) * 1e3
+            done += 1
+    replay.host_submit_s = host
+    return time.perf_counter() - t0, lat
+
+
+def pct(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
+
+
+def run_serving(n_req: int, slots: int, seed: int = 4, load: float = 0.7):
+    import torch
+    from paper_2207_00933_amd import runner, sqc
+
+    pool = configs.serving_pool(seed=seed, count=32)
+    log(f"[serve] simulating the subcircuit variants of {len(pool)} circuits ...")
+    variants = [qpu.all_variants(cc) for cc in pool]
+    s = runner.Session(0, 64 << 20)
+    circ = {}
+    for k, (cc, var) in enumerate(zip(pool, variants)):
+        c64 = runner.Circuit.from_cut_circuit(s, cc, var, sqc.F64)
+        c64.attribute(sqc.F64)
+        c32 = runner.Circuit.from_cut_circuit(s, cc, var, sqc.F64)
+        c32.attribute(sqc.F32)
+        circ[k] = (c64, c32)
+    torch.cuda.synchronize()
+    spec = serve_requests(sqc, pool, n_req, seed)
+    total_bins = float(sum(1 << a for _, _, _, a in spec))
+    fast, plain = sqc.BF16X3, sqc.F64
+
+    def outputs(prec):
+        dt = torch.float64 if prec == sqc.F64 else torch.float32
+        return [(torch.empty(1 << a, dtype=dt, device="cuda"),
+                 torch.empty(2 * sqc.MAX_TOPR, dtype=torch.float64, device="cuda"),
+                 torch.empty(1, dtype=torch.float64, device="cuda")) for _, _, _, a in spec]
+
+    # alone: every request through sqc_recurse one by one, with the per-stage
+    # algorithmic byte counts (the ideal time of a request at HBM peak)
+    alone = outputs(fast)
+    all_stages = (sqc.STAGE_ATTRIBUTE | sqc.STAGE_MERGE | sqc.STAGE_CONTRACT | sqc.STAGE_FINAL
+                  | sqc.STAGE_TOPR)
+    sqc.ctx_set_timing(s.ctx, all_stages)
+    for (ci, scope, M, a), (b, t, bs) in zip(spec, alone):
+        c = circ[ci][1]
+        s.ensure_workspace(sqc.recurse_workspace_bytes(c.att, c.g, sqc.assign_bins(c.g.n_data, scope, M), fast))
+        sqc.recurse(s.ctx, c.att, c.g, scope, M, 16, fast, b, sqc.F32, t, bs)
+    torch.cuda.synchronize()
+    sqc.ctx_set_timing(s.ctx, 0)
+    ideal_bytes = sum(sqc.ctx_timing(s.ctx, 1 << q).bytes for q in range(5))
+    sqc.ctx_timing(s.ctx, 1, reset=True)
+
+    def engine(prec, n_slots, outs):
+        srv = runner.Server(0, n_slots=n_slots, workspace_bytes=8 << 30)
+        ids = {k: srv.register(circ[k][0 if prec == sqc.F64 else 1]) for k in circ}
+        bprec = sqc.F64 if prec == sqc.F64 else sqc.F32
+        reqs = [srv.request(ids[ci], scope, M, 16, prec, b, bprec, t, bs)
+                for (ci, scope, M, a), (b, t, bs) in zip(spec, outs)]
+        torch.cuda.synchronize()
+        return srv, reqs
+
+    res = {}
+    rng = np.random.default_rng(seed + 1)
+    gaps = rng.exponential(1.0, n_req)
+    lam = None
+    for name, prec, n_slots in (("engine", fast, slots), ("serial_fp64", plain, 1)):
+        outs = outputs(prec)
+        srv, reqs = engine(prec, n_slots, outs)
+        replay(srv, reqs[: min(32, n_req)], [0.0] * min(32, n_req))  # warm-up
+        wall_sat, lat_sat = replay(srv, reqs, [0.0] * n_req)
+        host_sat = replay.host_submit_s
+        if lam is None:
+            lam = load * n_req / wall_sat
+        arrivals = np.cumsum(gaps) / lam
+        arrivals -= arrivals[0]
+        wall, lat = replay(srv, reqs, arrivals.tolist())
+        st = srv.stats()
+        res[name] = {
+            "prec": {sqc.F64: "f64", sqc.F32: "f32", sqc.BF16X3: "bf16x3"}[prec],
+            "slots": n_slots,
+            "saturation": {"wall_s": wall_sat, "req_per_s": n_req / wall_sat,
+                           "bins_per_s": total_bins / wall_sat,
+                           "host_submit_s": host_sat},
+            "poisson": {"lambda_req_per_s": lam, "wall_s": wall, "bins_per_s": total_bins / wall,
+                        "p50_ms": pct(lat, 0.50), "p99_ms": pct(lat, 0.99)},
+            "max_running": st.max_running, "workspace_peak_bytes": st.workspace_peak,
+        }
+        log(f"[serve] {name}: saturation {n_req / wall_sat:.0f} req/s "
+            f"({total_bins / wall_sat:.3e} bins/s, {host_sat * 1e3:.1f} ms of {wall_sat * 1e3:.1f} "
+            f"in submit); Poisson {lam:.0f} req/s: "
+            f"p50 {pct(lat, 0.5):.3f} ms p99 {pct(lat, 0.99):.3f} ms; max running {st.max_running}")
+        srv.close()
+        if prec == fast:
+            same = all(torch.equal(b0, b1) and torch.equal(s0, s1)
+                       for (b0, _, s0), (b1, _, s1) in zip(alone, outs))
+            fast_outs = outs
+        else:
+            err = max((b32.double() - b64).abs().max().item()
+                      for (b32, _, _), (b64, _, _) in zip(fast_outs, outs))
+    s.close()
+    e = res["engine"]
+    return {
+        "workload": f"{n_req} requests, Poisson arrivals at {load} x the engine's saturation rate, "
+                    "pool of 32 seeded brickwork chains / planted QAOA rings (16-80 qubits, 2-5 "
+                    "subcircuits, 2-10 cuts) resident on the device, a = 12..24 active bits, 30% "
+                    "recursion steps on a popped bin, top-16",
+        "requests": n_req,
+        "total_bins": total_bins,
+        "engine": e,
+        "serial_fp64": res["serial_fp64"],
+        "speedup_bins_per_s_saturation": e["saturation"]["bins_per_s"]
+        / res["serial_fp64"]["saturation"]["bins_per_s"],
+        "hbm_roofline_frac_saturation": ideal_bytes / HBM_PEAK / e["saturation"]["wall_s"],
+        "algorithmic_bytes": ideal_bytes,
+        "bitwise_equal_alone": bool(same),
+        "max_abs_vs_fp64": err,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +369,9 @@ def main():
                     help="target CPU work per worker for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precs", default="f64,f32,bf16x3")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration "
                          "for profiler runs)")
@@ -229,6 +395,7 @@ def main():
     if args.calib_copy_mb > 0:
         calib_copy(args.calib_copy_mb)
     gpu = run_gpu(cc, var32, args.steps, args.warmup, precs)
+    serving = run_serving(args.serve_requests, args.serve_slots) if args.serve_requests > 0 else None
     fast = [p for p in ("bf16x3", "f32") if p in gpu]
     head = max(fast, key=lambda p: gpu[p]["bins_per_s"]) if fast else precs[0]
     h = gpu[head]
@@ -267,6 +434,7 @@ def main():
                                                   ("value", "unit", "cores", "kind", "sample")},
         "paths": gpu,
         "latency_ms": {"p50": h["p50_ms"], "p99": h["p99_ms"]},
+        "serving": serving,
     }
     if "f64" in gpu:
         line["speedup_vs_fp64_gpu"] = h["bins_per_s"] / gpu["f64"]["bins_per_s"]

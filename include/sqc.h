@@ -134,7 +134,8 @@ sqc_status sqc_ctx_set_stream(sqc_ctx *ctx, void *hip_stream);
 /* Give the context a caller-owned device workspace used by merge, contract,
  * recurse and search for intermediates and scratch.  The context keeps the
  * pointer until it is replaced or the context is destroyed; the caller must
- * keep the buffer alive that long.  The buffer is initialised on the stream. */
+ * keep the buffer alive that long.  Nothing is launched: the buffer needs no
+ * initialisation, and the call is cheap enough to make before every request. */
 sqc_status sqc_ctx_set_workspace(sqc_ctx *ctx, void *dev, size_t bytes);
 /* Stage timing.  With a non-zero mask, every kernel launch of the selected
  * stages is bracketed by HIP events on the context's stream, and the library
@@ -398,6 +399,11 @@ sqc_status sqc_serve_submit(sqc_server *srv, const sqc_request *req, uint64_t *t
 sqc_status sqc_serve_poll(sqc_server *srv, uint64_t ticket, int32_t *state);
 /* Block until the request is done. */
 sqc_status sqc_serve_wait(sqc_server *srv, uint64_t ticket);
+/* Advance the engine, then hand out the tickets of requests that finished
+ * since the last call (a completion queue, oldest first): up to `cap` go to
+ * `tickets`, their count to `n`; the rest stay queued for the next call.
+ * A ticket handed out here is forgotten: later polls of it fail. */
+sqc_status sqc_serve_completed(sqc_server *srv, uint64_t *tickets, int32_t cap, int32_t *n);
 sqc_status sqc_serve_get_stats(sqc_server *srv, sqc_serve_stats *out);
 const char *sqc_serve_last_error(const sqc_server *srv);
 

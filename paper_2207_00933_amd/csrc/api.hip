@@ -19,11 +19,6 @@ __global__ void cast_copy(const void *src, int src_f32, void *dst, int dst_f32, 
   }
 }
 
-__global__ void set_unit(double *p) {
-  p[0] = 1.0;
-  reinterpret_cast<float *>(p + 1)[0] = 1.0f;
-}
-
 }  // namespace
 
 }  // namespace sqc
@@ -37,6 +32,7 @@ struct sqc_ctx {
   size_t ws_bytes = 0;
   std::string err;
   void *pinned = nullptr;  // host staging for small device results
+  double *unit = nullptr;  // device: double 1.0 then float 1.0 (one-element tensor)
   // stage timing
   uint32_t timing_mask = 0;
   struct Mark {
@@ -56,7 +52,6 @@ namespace {
 
 // Control region at the start of the workspace.
 constexpr size_t kCtlBytes = 4096;
-constexpr size_t kOffUnit = 128;         // double 1.0 then float 1.0
 constexpr size_t kOffSearchTop = 256;    // SQC_MAX_TOPR x 16 bytes
 constexpr size_t kOffSearchSum = 256 + 16 * SQC_MAX_TOPR;
 
@@ -180,8 +175,8 @@ void settle_timing(sqc_ctx *ctx) {
 // shared pieces of merge / contract / recurse
 // ---------------------------------------------------------------------------
 
-void enqueue_merge(sqc_ctx *ctx, const sqc_tensor &at, const sqc_masks &mk, void *out,
-                   int out_f32, double *partial) {
+MergeArgs merge_args(const sqc_tensor &at, const sqc_masks &mk, void *out, int out_f32,
+                     double *partial) {
   MergeArgs a{};
   a.in = at.data;
   a.out = out;
@@ -203,11 +198,25 @@ void enqueue_merge(sqc_ctx *ctx, const sqc_tensor &at, const sqc_masks &mk, void
   };
   a.act_lo = run_lo(mk.active);
   a.mrg_lo = run_lo(mk.merged);
-  const double in_b = at.prec == SQC_F32 ? 4 : 8, out_b = out_f32 ? 4 : 8;
-  const double nread = std::ldexp(1.0, 2 * at.n_labels + a.abits + a.mbits);
-  const double nout = std::ldexp(1.0, 2 * at.n_labels + a.abits);
-  StageMark mark(ctx, SQC_STAGE_MERGE, nread * in_b + nout * out_b, nread);
-  launch_merge(a, ctx->stream);
+  return a;
+}
+
+// Algorithmic bytes of one merge: every attributed entry in scope read once,
+// every merged entry written once.
+double merge_bytes(const MergeArgs &a) {
+  const double in_b = a.in_f32 ? 4 : 8, out_b = a.out_f32 ? 4 : 8;
+  return std::ldexp(1.0, a.lbits + a.abits + a.mbits) * in_b + std::ldexp(1.0, a.lbits + a.abits) * out_b;
+}
+
+// Enqueue merges (one launch per pass for all of them).
+void enqueue_merges(sqc_ctx *ctx, const std::vector<MergeArgs> &jobs) {
+  double bytes = 0, reads = 0;
+  for (const MergeArgs &a : jobs) {
+    bytes += merge_bytes(a);
+    reads += std::ldexp(1.0, a.lbits + a.abits + a.mbits);
+  }
+  StageMark mark(ctx, SQC_STAGE_MERGE, bytes, reads);
+  launch_merges(jobs.data(), (int)jobs.size(), ctx->stream);
   after_launch("merge kernel launch");
   mark.done();
 }
@@ -216,6 +225,22 @@ size_t merge_ws(const sqc_tensor &at, const sqc_masks &mk) {
   int64_t e = merge_partial_elems(__builtin_popcountll(mk.active), 2 * at.n_labels,
                                   __builtin_popcountll(mk.merged));
   return (size_t)e * sizeof(double);
+}
+
+// Merged tensors then one partial buffer per merge (the merges run together).
+struct MergeLayout {
+  std::vector<size_t> merged_off, partial_off;
+};
+MergeLayout layout_merges(Bump &b, const sqc_tensor *att, const sqc_masks *masks, int n_sub, int eb) {
+  MergeLayout L;
+  for (int i = 0; i < n_sub; ++i)
+    L.merged_off.push_back(
+        b.take(((size_t)1 << (2 * att[i].n_labels + __builtin_popcountll(masks[i].active))) * eb));
+  for (int i = 0; i < n_sub; ++i) {
+    const size_t part = merge_ws(att[i], masks[i]);
+    L.partial_off.push_back(part ? b.take(part) : 0);
+  }
+  return L;
 }
 
 struct Contraction {
@@ -313,7 +338,7 @@ void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<c
                          size_t base, void *bins, int bins_f32, sqc_prec prec, int top_r,
                          void *top_dev, void *sum_dev) {
   char *ws = ctx->ws;
-  const void *unit = ws + kOffUnit + (c.path_f32 ? 8 : 0);
+  const void *unit = reinterpret_cast<const char *>(ctx->unit) + (c.path_f32 ? 8 : 0);
   size_t inter_base = base;
   size_t stats_base = base + align256(c.plan.inter_bytes);
   size_t nsteps = c.unit ? 1 : c.plan.steps.size();
@@ -417,8 +442,8 @@ struct RecursePlan {
   std::vector<sqc_masks> masks;
   std::vector<int> abits;
   Contraction con;
-  std::vector<size_t> merged_off;
-  size_t partial_off = 0, con_base = 0, total = 0;
+  MergeLayout ml;
+  size_t con_base = 0, total = 0;
 };
 
 RecursePlan plan_recursion(const Graph &g, const sqc_tensor *att, const sqc_masks *scope,
@@ -432,13 +457,7 @@ RecursePlan plan_recursion(const Graph &g, const sqc_tensor *att, const sqc_mask
   for (int i = 0; i < g.n_sub; ++i) rp.abits[i] = __builtin_popcountll(rp.masks[i].active);
   rp.con = plan_for(g, rp.abits, prec);
   Bump b;
-  int eb = prec == SQC_F64 ? 8 : 4;
-  size_t part = 0;
-  for (int i = 0; i < g.n_sub; ++i) {
-    rp.merged_off.push_back(b.take(((size_t)1 << (2 * att[i].n_labels + rp.abits[i])) * eb));
-    part = std::max(part, merge_ws(att[i], rp.masks[i]));
-  }
-  rp.partial_off = b.take(part);
+  rp.ml = layout_merges(b, att, rp.masks.data(), g.n_sub, prec == SQC_F64 ? 8 : 4);
   rp.con_base = b.off;
   rp.total = b.off + contraction_ws(rp.con, top_r, true, prec);
   return rp;
@@ -449,12 +468,14 @@ void enqueue_recursion(sqc_ctx *ctx, const RecursePlan &rp, const sqc_tensor *at
   const int n_sub = (int)rp.masks.size();
   std::vector<const void *> inputs(n_sub);
   const int path_f32 = prec != SQC_F64;
+  std::vector<MergeArgs> jobs(n_sub);
   for (int i = 0; i < n_sub; ++i) {
-    void *out = ctx->ws + rp.merged_off[i];
-    enqueue_merge(ctx, att[i], rp.masks[i], out, path_f32,
-                  reinterpret_cast<double *>(ctx->ws + rp.partial_off));
+    void *out = ctx->ws + rp.ml.merged_off[i];
+    jobs[i] = merge_args(att[i], rp.masks[i], out, path_f32,
+                         reinterpret_cast<double *>(ctx->ws + rp.ml.partial_off[i]));
     inputs[i] = out;
   }
+  enqueue_merges(ctx, jobs);
   enqueue_contraction(ctx, rp.con, inputs, rp.con_base, bins, bins_prec == SQC_F32, prec, top_r,
                       top_dev, sum_dev);
 }
@@ -507,6 +528,16 @@ sqc_status sqc_ctx_create(int device, void *hip_stream, sqc_ctx **out) {
       delete c;
       raise(SQC_E_DEVICE, "hipHostMalloc of the staging buffer failed");
     }
+    double unit[2] = {1.0, 0.0};
+    const float one = 1.0f;
+    std::memcpy(&unit[1], &one, sizeof(one));
+    if (hipMalloc(reinterpret_cast<void **>(&c->unit), sizeof(unit)) != hipSuccess ||
+        hipMemcpy(c->unit, unit, sizeof(unit), hipMemcpyHostToDevice) != hipSuccess) {
+      if (c->unit) (void)hipFree(c->unit);
+      (void)hipHostFree(c->pinned);
+      delete c;
+      raise(SQC_E_DEVICE, "allocation of the context's constants failed");
+    }
     *out = c;
     return SQC_OK;
   } catch (const Error &e) {
@@ -525,6 +556,7 @@ sqc_status sqc_ctx_destroy(sqc_ctx *ctx) {
   }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->unit) (void)hipFree(ctx->unit);
   delete ctx;
   return SQC_OK;
 }
@@ -563,14 +595,8 @@ sqc_status sqc_ctx_set_workspace(sqc_ctx *ctx, void *dev, size_t bytes) {
   SQC_TRY(ctx)
   if (!dev || bytes < kCtlBytes) raise(SQC_E_ARG, "workspace must be at least 4096 bytes");
   if (reinterpret_cast<uintptr_t>(dev) % 256) raise(SQC_E_ARG, "workspace must be 256-byte aligned");
-  use_device(ctx);
   ctx->ws = static_cast<char *>(dev);
   ctx->ws_bytes = bytes;
-  launch_zero(ctx->ws, kCtlBytes, ctx->stream);
-  after_launch("workspace initialisation");
-  hipLaunchKernelGGL(set_unit, dim3(1), dim3(1), 0, ctx->stream,
-                     reinterpret_cast<double *>(ctx->ws + kOffUnit));
-  after_launch("workspace initialisation");
   return SQC_OK;
   SQC_CATCH(ctx)
 }
@@ -662,8 +688,8 @@ sqc_status sqc_merge(sqc_ctx *ctx, const sqc_tensor *attributed, const sqc_masks
   size_t part = merge_ws(*attributed, *masks);
   if (part) need_ws(ctx, kCtlBytes + part);
   use_device(ctx);
-  enqueue_merge(ctx, *attributed, *masks, out->data, out->prec == SQC_F32,
-                part ? reinterpret_cast<double *>(ctx->ws + kCtlBytes) : nullptr);
+  enqueue_merges(ctx, {merge_args(*attributed, *masks, out->data, out->prec == SQC_F32,
+                                  part ? reinterpret_cast<double *>(ctx->ws + kCtlBytes) : nullptr)});
   out->n_labels = attributed->n_labels;
   out->n_bits = __builtin_popcountll(masks->active);
   out->layout = SQC_LAYOUT_MERGED;
@@ -717,15 +743,9 @@ size_t sqc_recurse_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub, 
     degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
     // the masks given fix the bin counts: use them as the scope with M large
     std::vector<int> abits(n_sub);
+    for (int i = 0; i < n_sub; ++i) abits[i] = __builtin_popcountll(masks[i].active);
     Bump b;
-    int eb = prec == SQC_F64 ? 8 : 4;
-    size_t part = 0;
-    for (int i = 0; i < n_sub; ++i) {
-      abits[i] = __builtin_popcountll(masks[i].active);
-      b.take(((size_t)1 << (2 * attributed[i].n_labels + abits[i])) * eb);
-      part = std::max(part, merge_ws(attributed[i], masks[i]));
-    }
-    b.take(part);
+    layout_merges(b, attributed, masks, n_sub, prec == SQC_F64 ? 8 : 4);
     Contraction c = plan_for(g, abits, prec);
     return b.off + contraction_ws(c, SQC_MAX_TOPR, true, prec);
   } catch (const Error &e) {

@@ -150,8 +150,14 @@ struct MergeArgs {
   int ysplit_bits;  // P = 2^ysplit_bits
   int tb_bits;      // log2 of the b-tile
   int ts_bits;      // log2 of the sigma-tile
+  int64_t grid_x;   // work-groups along the outputs (set by the launcher)
+  int64_t blocks;   // work-groups of the main pass
+  int64_t fin_blocks;  // work-groups of the partial-sum pass (0: none)
 };
-void launch_merge(const MergeArgs &a, hipStream_t s);
+// Merges launched together (at most this many per launch; more are split).
+constexpr int kMergeJobs = 8;
+// Enqueue n merges; jobs with merged bits >= 6 need their own partial buffer.
+void launch_merges(const MergeArgs *jobs, int n, hipStream_t s);
 // FP64 partial-sum elements the merge of these bit counts needs (0: none).
 int64_t merge_partial_elems(int abits, int lbits, int mbits);
 

@@ -18,6 +18,8 @@
 // label row is written as a run of TB consecutive bins.
 #include "common.hpp"
 
+#include <vector>
+
 namespace sqc {
 
 namespace {
@@ -44,8 +46,8 @@ __device__ __forceinline__ uint64_t deposit_run(uint64_t v, uint64_t mask, int l
   return lo >= 0 ? (v << lo) : deposit(v, mask);
 }
 
-__global__ __launch_bounds__(kThreads) void merge_tiles(MergeArgs a) {
-  __shared__ double tile[kTile + 64];
+__device__ __forceinline__ void merge_tiles_body(const MergeArgs &a, int64_t tile_id, int p,
+                                                 double *tile) {
   const int TS = 1 << a.ts_bits;
   const int TB = 1 << a.tb_bits;
   const int R = kThreads >> a.ts_bits;        // thread rows
@@ -60,8 +62,6 @@ __global__ __launch_bounds__(kThreads) void merge_tiles(MergeArgs a) {
 
   const int64_t L = int64_t(1) << a.lbits;
   const int lsig_tiles = a.lbits - a.ts_bits;
-  const int64_t tile_id = blockIdx.x;
-  const int p = blockIdx.y;  // y split
   const int st = (int)(tile_id & ((int64_t(1) << lsig_tiles) - 1));
   const int64_t bt = tile_id >> lsig_tiles;
   const int64_t sigma = (int64_t(st) << a.ts_bits) + sl;
@@ -142,13 +142,12 @@ __global__ __launch_bounds__(kThreads) void merge_tiles(MergeArgs a) {
 // sigma (same bin, consecutive labels) and walks its share of the merged
 // states, four rows per iteration so that several loads are in flight.  The
 // work-group's FP64 partial sums go to partial[p][c].
-__global__ __launch_bounds__(kThreads) void merge_rows(MergeArgs a) {
+__device__ __forceinline__ void merge_rows_body(const MergeArgs &a, int64_t bx, int p) {
   const int V = a.lbits >= 2 ? 4 : 1;
   const int64_t L = int64_t(1) << a.lbits;
   const int64_t NC = int64_t(1) << (a.abits + a.lbits);
-  const int64_t c0 = (int64_t(blockIdx.x) * kThreads + threadIdx.x) * V;
+  const int64_t c0 = (bx * kThreads + threadIdx.x) * V;
   if (c0 >= NC) return;
-  const int p = blockIdx.y;
   const int64_t b = c0 >> a.lbits;
   const int64_t sigma = c0 & (L - 1);
   const uint64_t xb = a.fixed_val | deposit_run((uint64_t)b, a.active, a.act_lo);
@@ -217,13 +216,12 @@ __global__ __launch_bounds__(kThreads) void merge_rows(MergeArgs a) {
 
 // Sum the partials of every column in ascending partial order and write
 // out[sigma][b] (columns are read contiguously; the output is small).
-__global__ __launch_bounds__(kThreads) void merge_finish(MergeArgs a) {
+__device__ __forceinline__ void merge_finish_body(const MergeArgs &a, int64_t blk, int64_t nblk) {
   const int64_t NC = int64_t(1) << (a.abits + a.lbits);
   const int64_t L = int64_t(1) << a.lbits;
   const int64_t nb = int64_t(1) << a.abits;
   const int P = 1 << a.ysplit_bits;
-  for (int64_t c = int64_t(blockIdx.x) * kThreads + threadIdx.x; c < NC;
-       c += int64_t(gridDim.x) * kThreads) {
+  for (int64_t c = blk * kThreads + threadIdx.x; c < NC; c += nblk * kThreads) {
     double s = 0.0;
     for (int q = 0; q < P; ++q) s += a.partial[int64_t(q) * NC + c];
     int64_t o = (c & (L - 1)) * nb + (c >> a.lbits);
@@ -232,32 +230,20 @@ __global__ __launch_bounds__(kThreads) void merge_finish(MergeArgs a) {
   }
 }
 
-}  // namespace
-
-int64_t merge_partial_elems(int abits, int lbits, int mbits) {
-  if (mbits < 6) return 0;
-  const int V = lbits >= 2 ? 4 : 1;
-  int64_t NC = int64_t(1) << (abits + lbits);
-  int64_t bx = (NC / V + kThreads - 1) / kThreads;
-  int ys = 0;
-  while (bx * (int64_t(2) << ys) <= 1024 && mbits - (ys + 1) >= 4) ++ys;
-  return NC << ys;
-}
-
-void launch_merge(const MergeArgs &a0, hipStream_t s) {
-  MergeArgs a = a0;
+// Grid shape of one merge (work-groups of each pass) and its y split.
+void shape_merge(MergeArgs &a) {
   if (a.mbits >= 6) {
-    // streaming reduction over many merged states
+    // streaming reduction over many merged states, then the partial sums
     const int V = a.lbits >= 2 ? 4 : 1;
     int64_t NC = int64_t(1) << (a.abits + a.lbits);
     int64_t bx = (NC / V + kThreads - 1) / kThreads;
     int ys = 0;
     while (bx * (int64_t(2) << ys) <= 1024 && a.mbits - (ys + 1) >= 4) ++ys;
     a.ysplit_bits = ys;
-    hipLaunchKernelGGL(merge_rows, dim3((unsigned)bx, 1u << ys), dim3(kThreads), 0, s, a);
-    int64_t blocks = (NC + kThreads - 1) / kThreads;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(merge_finish, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+    a.grid_x = bx;
+    a.blocks = bx << ys;
+    int64_t fin = (NC + kThreads - 1) / kThreads;
+    a.fin_blocks = fin > 65536 ? 65536 : fin;
     return;
   }
   a.ysplit_bits = 0;
@@ -265,8 +251,92 @@ void launch_merge(const MergeArgs &a0, hipStream_t s) {
   int tb = 11 - a.ts_bits;  // kTile = 2^11 outputs
   if (tb > a.abits) tb = a.abits;
   a.tb_bits = tb;
-  int64_t tiles = (int64_t(1) << (a.lbits - a.ts_bits)) * (int64_t(1) << (a.abits - tb));
-  hipLaunchKernelGGL(merge_tiles, dim3((unsigned)tiles), dim3(kThreads), 0, s, a);
+  a.blocks = (int64_t(1) << (a.lbits - a.ts_bits)) * (int64_t(1) << (a.abits - tb));
+  a.grid_x = a.blocks;
+  a.fin_blocks = 0;
+}
+
+// Several merges in one launch: work-group w belongs to the job j with
+// start[j] <= w < start[j + 1] (a uniform scan over at most kMergeJobs
+// entries), and runs that job's pass with its local index.
+struct MergeBatch {
+  int n;
+  int64_t start[kMergeJobs + 1];
+  MergeArgs job[kMergeJobs];
+};
+
+__device__ __forceinline__ int batch_job(const MergeBatch &b, int64_t w) {
+  int j = 0;
+  while (j + 1 < b.n && w >= b.start[j + 1]) ++j;
+  return j;
+}
+
+__global__ __launch_bounds__(kThreads) void merge_tiles(MergeBatch b) {
+  __shared__ double tile[kTile + 64];
+  const int j = batch_job(b, blockIdx.x);
+  merge_tiles_body(b.job[j], int64_t(blockIdx.x) - b.start[j], 0, tile);
+}
+
+__global__ __launch_bounds__(kThreads) void merge_rows(MergeBatch b) {
+  const int j = batch_job(b, blockIdx.x);
+  const MergeArgs &a = b.job[j];
+  const int64_t w = int64_t(blockIdx.x) - b.start[j];
+  merge_rows_body(a, w % a.grid_x, (int)(w / a.grid_x));
+}
+
+__global__ __launch_bounds__(kThreads) void merge_finish(MergeBatch b) {
+  const int j = batch_job(b, blockIdx.x);
+  merge_finish_body(b.job[j], int64_t(blockIdx.x) - b.start[j], b.job[j].fin_blocks);
+}
+
+enum Pass { kTiles, kRows, kFinish };
+
+int64_t pass_blocks(const MergeArgs &a, Pass p) { return p == kFinish ? a.fin_blocks : a.blocks; }
+
+void launch_pass(const std::vector<MergeArgs> &jobs, Pass p, hipStream_t s) {
+  MergeBatch b{};
+  auto flush = [&]() {
+    if (!b.n) return;
+    const unsigned grid = (unsigned)b.start[b.n];
+    if (p == kTiles) hipLaunchKernelGGL(merge_tiles, dim3(grid), dim3(kThreads), 0, s, b);
+    else if (p == kRows) hipLaunchKernelGGL(merge_rows, dim3(grid), dim3(kThreads), 0, s, b);
+    else hipLaunchKernelGGL(merge_finish, dim3(grid), dim3(kThreads), 0, s, b);
+    b = MergeBatch{};
+  };
+  for (const MergeArgs &a : jobs) {
+    const int64_t nb = pass_blocks(a, p);
+    if (b.n == kMergeJobs || b.start[b.n] + nb > (int64_t(1) << 31) - 1) flush();
+    b.job[b.n] = a;
+    b.start[b.n + 1] = b.start[b.n] + nb;
+    ++b.n;
+  }
+  flush();
+}
+
+}  // namespace
+
+int64_t merge_partial_elems(int abits, int lbits, int mbits) {
+  if (mbits < 6) return 0;
+  MergeArgs a{};
+  a.abits = abits;
+  a.lbits = lbits;
+  a.mbits = mbits;
+  shape_merge(a);
+  return (int64_t(1) << (abits + lbits)) << a.ysplit_bits;
+}
+
+void launch_merges(const MergeArgs *jobs, int n, hipStream_t s) {
+  std::vector<MergeArgs> tiles, rows;
+  for (int i = 0; i < n; ++i) {
+    MergeArgs a = jobs[i];
+    shape_merge(a);
+    (a.mbits >= 6 ? rows : tiles).push_back(a);
+  }
+  if (!tiles.empty()) launch_pass(tiles, kTiles, s);
+  if (!rows.empty()) {
+    launch_pass(rows, kRows, s);
+    launch_pass(rows, kFinish, s);
+  }
 }
 
 }  // namespace sqc

@@ -60,6 +60,7 @@ struct sqc_server {
   std::vector<Slot> slots;
   std::vector<Circuit> circuits;
   std::deque<Pending> waiting;
+  std::deque<uint64_t> finished;  // completion queue
   std::unordered_map<uint64_t, int> state;
   std::unordered_map<uint64_t, std::string> failure;
   uint64_t next_ticket = 1;
@@ -125,6 +126,7 @@ sqc_status pump(sqc_server *s) {
     if (q != hipSuccess) return fail(s, SQC_E_DEVICE, std::string("request failed on the device: ") +
                                                           hipGetErrorString(q));
     s->state[sl.ticket] = kDone;
+    s->finished.push_back(sl.ticket);
     give_block(s, sl.off, sl.len);
     s->st.workspace_bytes -= sl.len;
     sl.busy = false;
@@ -145,8 +147,7 @@ sqc_status pump(sqc_server *s) {
       continue;
     }
     const Circuit &c = s->circuits[it->req.circuit];
-    // The block's control region may have been overwritten by another
-    // request since this context last used it: always re-initialise it.
+    // point the slot's context at the block (a host-side pointer update)
     sqc_status rc = sqc_ctx_set_workspace(idle->ctx, s->ws + off, it->footprint);
     if (rc == SQC_OK) {
       const sqc_masks *scope = it->scope.empty() ? nullptr : it->scope.data();
@@ -296,6 +297,20 @@ sqc_status sqc_serve_wait(sqc_server *s, uint64_t ticket) {
     if (!ev) return fail(s, SQC_E_ARG, "request can never be admitted");
     if (hipEventSynchronize(ev) != hipSuccess) return fail(s, SQC_E_DEVICE, "hipEventSynchronize failed");
   }
+}
+
+sqc_status sqc_serve_completed(sqc_server *s, uint64_t *tickets, int32_t cap, int32_t *n) {
+  if (!s || !n || cap < 0 || (cap > 0 && !tickets)) return fail(s, SQC_E_ARG, "invalid argument to sqc_serve_completed");
+  const sqc_status rc = pump(s);
+  if (rc != SQC_OK) return rc;
+  int32_t k = 0;
+  while (k < cap && !s->finished.empty()) {
+    tickets[k++] = s->finished.front();
+    s->state.erase(s->finished.front());
+    s->finished.pop_front();
+  }
+  *n = k;
+  return SQC_OK;
 }
 
 sqc_status sqc_serve_get_stats(sqc_server *s, sqc_serve_stats *out) {

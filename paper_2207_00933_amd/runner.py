@@ -170,6 +170,12 @@ class Server:
         sqc.serve_wait(self.srv, ticket)
         self._live.pop(ticket, None)
 
+    def completed(self, cap: int = 256) -> List[int]:
+        done = sqc.serve_completed(self.srv, cap)
+        for t in done:
+            self._live.pop(t, None)
+        return done
+
     def stats(self) -> sqc.ServeStats:
         return sqc.serve_get_stats(self.srv)
 

@@ -154,6 +154,7 @@ def lib():
             "sqc_serve_poll": (c_int, [P, c_uint64, POINTER(c_int32)]),
             "sqc_serve_wait": (c_int, [P, c_uint64]),
             "sqc_serve_get_stats": (c_int, [P, POINTER(ServeStats)]),
+            "sqc_serve_completed": (c_int, [P, POINTER(c_uint64), c_int32, POINTER(c_int32)]),
             "sqc_serve_last_error": (c_char_p, [P]),
         }
         for name, (res, args) in sig.items():
@@ -454,6 +455,13 @@ def serve_poll(srv: int, ticket: int) -> int:
 
 def serve_wait(srv: int, ticket: int) -> None:
     _check_srv(lib().sqc_serve_wait(srv, ticket), srv)
+
+
+def serve_completed(srv: int, cap: int = 256) -> List[int]:
+    buf = (c_uint64 * max(1, cap))()
+    n = c_int32()
+    _check_srv(lib().sqc_serve_completed(srv, buf, cap, ctypes.byref(n)), srv)
+    return [buf[k] for k in range(n.value)]
 
 
 def serve_get_stats(srv: int) -> ServeStats:
