@@ -293,8 +293,8 @@ def run_serving(n_req: int, slots: int, seed: int = 4, load: float = 0.7):
     ideal_bytes = sum(sqc.ctx_timing(s.ctx, 1 << q).bytes for q in range(5))
     sqc.ctx_timing(s.ctx, 1, reset=True)
 
-    def engine(prec, n_slots, outs):
-        srv = runner.Server(0, n_slots=n_slots, workspace_bytes=8 << 30)
+    def engine(prec, n_slots, max_batch, outs):
+        srv = runner.Server(0, n_slots=n_slots, workspace_bytes=8 << 30, max_batch=max_batch)
         ids = {k: srv.register(circ[k][0 if prec == sqc.F64 else 1]) for k in circ}
         bprec = sqc.F64 if prec == sqc.F64 else sqc.F32
         reqs = [srv.request(ids[ci], scope, M, 16, prec, b, bprec, t, bs)
@@ -306,9 +306,12 @@ def run_serving(n_req: int, slots: int, seed: int = 4, load: float = 0.7):
     rng = np.random.default_rng(seed + 1)
     gaps = rng.exponential(1.0, n_req)
     lam = None
-    for name, prec, n_slots in (("engine", fast, slots), ("serial_fp64", plain, 1)):
+    # the engine (split-BF16x3, batched), the same engine on the FP64 path,
+    # and plain FP64 served one request at a time on one stream
+    for name, prec, n_slots, mb in (("engine", fast, slots, 128), ("batched_fp64", plain, slots, 128),
+                                    ("serial_fp64", plain, 1, 1)):
         outs = outputs(prec)
-        srv, reqs = engine(prec, n_slots, outs)
+        srv, reqs = engine(prec, n_slots, mb, outs)
         replay(srv, reqs[: min(32, n_req)], [0.0] * min(32, n_req))  # warm-up
         wall_sat, lat_sat = replay(srv, reqs, [0.0] * n_req)
         host_sat = replay.host_submit_s
@@ -320,18 +323,20 @@ def run_serving(n_req: int, slots: int, seed: int = 4, load: float = 0.7):
         st = srv.stats()
         res[name] = {
             "prec": {sqc.F64: "f64", sqc.F32: "f32", sqc.BF16X3: "bf16x3"}[prec],
-            "slots": n_slots,
+            "slots": n_slots, "max_batch": mb,
             "saturation": {"wall_s": wall_sat, "req_per_s": n_req / wall_sat,
                            "bins_per_s": total_bins / wall_sat,
                            "host_submit_s": host_sat},
             "poisson": {"lambda_req_per_s": lam, "wall_s": wall, "bins_per_s": total_bins / wall,
                         "p50_ms": pct(lat, 0.50), "p99_ms": pct(lat, 0.99)},
             "max_running": st.max_running, "workspace_peak_bytes": st.workspace_peak,
+            "batches": st.batches, "max_batch": st.max_batch,
         }
         log(f"[serve] {name}: saturation {n_req / wall_sat:.0f} req/s "
             f"({total_bins / wall_sat:.3e} bins/s, {host_sat * 1e3:.1f} ms of {wall_sat * 1e3:.1f} "
             f"in submit); Poisson {lam:.0f} req/s: "
-            f"p50 {pct(lat, 0.5):.3f} ms p99 {pct(lat, 0.99):.3f} ms; max running {st.max_running}")
+            f"p50 {pct(lat, 0.5):.3f} ms p99 {pct(lat, 0.99):.3f} ms; max running {st.max_running}, "
+            f"{st.batches} batches (largest {st.max_batch})")
         srv.close()
         if prec == fast:
             same = all(torch.equal(b0, b1) and torch.equal(s0, s1)
@@ -340,6 +345,7 @@ def run_serving(n_req: int, slots: int, seed: int = 4, load: float = 0.7):
         else:
             err = max((b32.double() - b64).abs().max().item()
                       for (b32, _, _), (b64, _, _) in zip(fast_outs, outs))
+        del outs
     s.close()
     e = res["engine"]
     return {
@@ -350,6 +356,7 @@ def run_serving(n_req: int, slots: int, seed: int = 4, load: float = 0.7):
         "requests": n_req,
         "total_bins": total_bins,
         "engine": e,
+        "batched_fp64": res["batched_fp64"],
         "serial_fp64": res["serial_fp64"],
         "speedup_bins_per_s_saturation": e["saturation"]["bins_per_s"]
         / res["serial_fp64"]["saturation"]["bins_per_s"],
@@ -371,7 +378,7 @@ def main():
     ap.add_argument("--precs", default="f64,f32,bf16x3")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving leg (0 skips it)")
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration "
                          "for profiler runs)")

@@ -346,15 +346,20 @@ sqc_status sqc_search(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
  * keeps the buffers alive until sqc_serve_destroy) and runs requests, each one
  * states-merging recursion exactly as sqc_recurse computes it.  It owns
  * n_slots HIP streams (default priority), one context each, and the caller's
- * workspace buffer.  A request is admitted when a slot is idle and a free
- * block of the workspace holds its footprint (sqc_serve_footprint); the others
- * wait in arrival order, and a later request that fits may be admitted before
- * an earlier one that does not.  Admitted requests run concurrently on their
- * slots' streams, so requests that arrive while others are on the device
- * overlap with them as slots and memory free up.  Each result is bitwise the
- * same as the same sqc_recurse call made alone.  The engine advances (retires
- * finished requests, admits waiting ones) inside sqc_serve_submit,
- * sqc_serve_poll and sqc_serve_wait; it is not thread-safe. */
+ * workspace buffer.  Requests are validated and planned by sqc_serve_submit.
+ * Whenever a slot is idle, the waiting requests (in arrival order; a later
+ * request that fits may pass an earlier one that does not) are shared among
+ * the idle slots as batches, each limited by the largest free block of the
+ * workspace; a batch runs as one set of launches whose kernels read the
+ * requests' jobs from a table in device memory (merges, each GEMM level per
+ * kernel specialisation, top-R), so a batch costs a few launches however many
+ * requests it holds.  Batches on different slots overlap on the device, and
+ * requests that arrive while others run are admitted as slots and memory free
+ * up.  Each result is bitwise the same as the same sqc_recurse call made
+ * alone.  The engine advances (retires finished batches, admits waiting
+ * requests) inside sqc_serve_submit, _poll, _wait and _completed; it is not
+ * thread-safe.  Output buffers must not be touched by other streams while a
+ * request runs: the engine's streams do not wait for other work. */
 typedef struct sqc_server sqc_server;
 
 typedef struct {
@@ -368,15 +373,16 @@ typedef struct {
   void *bins_dev;             /* 2^a elements, caller-owned                  */
   void *topr_dev;             /* top_r {double, uint64} records              */
   void *sum_dev;              /* one double                                  */
-  sqc_masks *masks_out;       /* optional, n_sub entries, written at admission */
+  sqc_masks *masks_out;       /* optional, n_sub entries, written by submit  */
 } sqc_request;
 
 typedef struct {
   uint64_t submitted, admitted, completed;
   int32_t running, queued;
   int32_t max_running;        /* most requests on the device at once         */
-  int32_t pad;
-  uint64_t workspace_bytes, workspace_peak;  /* bytes in use at most         */
+  int32_t max_batch;          /* most requests in one batch                  */
+  uint64_t workspace_bytes, workspace_peak;  /* bytes in use, at most        */
+  uint64_t batches;           /* batches launched                            */
 } sqc_serve_stats;
 
 /* Create a server on `device` with n_slots (1..64) streams using the caller's
@@ -384,16 +390,20 @@ typedef struct {
  * requests). */
 sqc_status sqc_serve_create(int device, int32_t n_slots, void *workspace_dev,
                             size_t workspace_bytes, sqc_server **out);
+/* Largest batch (1 .. 128, default 128); 1 runs every request on its own
+ * launches, as sqc_recurse does. */
+sqc_status sqc_serve_set_max_batch(sqc_server *srv, int32_t max_batch);
 /* Wait for running requests, then release the streams and contexts. */
 sqc_status sqc_serve_destroy(sqc_server *srv);
 /* Register a circuit: its attributed tensors and cut list (copied; the tensor
  * buffers stay the caller's). */
 sqc_status sqc_serve_register(sqc_server *srv, const sqc_tensor *attributed, int32_t n_sub,
                               const sqc_cut *cuts, int32_t n_cuts, int32_t *circuit_id);
-/* Workspace bytes the request needs (0 on invalid input). */
+/* Workspace bytes the request needs, its share of a batch's job table
+ * included (0 on invalid input). */
 size_t sqc_serve_footprint(sqc_server *srv, const sqc_request *req);
-/* Validate and queue a request; SQC_E_NOMEM when its footprint exceeds the
- * whole workspace.  `ticket` identifies it in sqc_serve_poll / _wait. */
+/* Validate, plan and queue a request; SQC_E_NOMEM when its footprint exceeds
+ * the whole workspace.  `ticket` identifies it in sqc_serve_poll / _wait. */
 sqc_status sqc_serve_submit(sqc_server *srv, const sqc_request *req, uint64_t *ticket);
 /* state: 0 waiting, 1 running, 2 done; an admission error is returned here. */
 sqc_status sqc_serve_poll(sqc_server *srv, uint64_t ticket, int32_t *state);

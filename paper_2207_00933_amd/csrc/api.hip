@@ -4,7 +4,11 @@
 #include <cstring>
 #include <sstream>
 
+#include "batch.hpp"
 #include "common.hpp"
+
+#include <climits>
+#include <map>
 
 namespace sqc {
 
@@ -316,7 +320,7 @@ size_t contraction_ws(const Contraction &c, int top_r, bool stats, int prec) {
     const size_t nsub = 4 * (size_t)gemm_tiles(dummy);
     b += align256(nsub * sizeof(double));             // sub-tile maxima
     b += align256(3 * kMaxGemmGroups * sizeof(double));  // work-group statistics
-    b += align256(kTopRSlots * sizeof(int)) + align256(64);   // slot counts, control
+    b += align256(kTopRSlots * sizeof(int)) + align256(64);   // slot counts, threshold and sum
     b += 2 * align256(kTopRSlots * (size_t)top_r * 8);       // slot values and indices
 
   }
@@ -332,13 +336,27 @@ double gemm_bytes(const GemmArgs &g, int path_f32) {
 }
 double gemm_flops(const GemmArgs &g) { return std::ldexp(2.0, g.mbits + g.nbits + g.kbits); }
 
-// Enqueue every GEMM of a contraction.  With `top_dev` non-null, the final
-// step gathers statistics and the top-R kernel follows.
-void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<const void *> &inputs,
-                         size_t base, void *bins, int bins_f32, sqc_prec prec, int top_r,
-                         void *top_dev, void *sum_dev) {
-  char *ws = ctx->ws;
-  const void *unit = reinterpret_cast<const char *>(ctx->unit) + (c.path_f32 ? 8 : 0);
+// Every launch of a contraction (or of a whole recursion): the merges, the
+// GEMM steps with their kernel specialisations and work-group counts, and the
+// top-R selection after the final step.  Built once, then enqueued either
+// directly or as part of a batch of recursions; both give the same results.
+struct Launches {
+  std::vector<MergeArgs> merges;
+  std::vector<GemmArgs> steps;
+  std::vector<GemmSpec> specs;
+  std::vector<int> groups;
+  bool topr = false;
+  TopRArgs t{};
+  int path_f32 = 1;
+};
+
+// GEMM steps of a contraction whose intermediates start at ws + base.  With
+// `top_dev` non-null, the final step gathers statistics for the top-R stage.
+void describe_contraction(Launches &L, const Contraction &c, const std::vector<const void *> &inputs,
+                          char *ws, const double *unit2, size_t base, void *bins, int bins_f32,
+                          sqc_prec prec, int top_r, void *top_dev, void *sum_dev) {
+  const void *unit = reinterpret_cast<const char *>(unit2) + (c.path_f32 ? 8 : 0);
+  L.path_f32 = c.path_f32;
   size_t inter_base = base;
   size_t stats_base = base + align256(c.plan.inter_bytes);
   size_t nsteps = c.unit ? 1 : c.plan.steps.size();
@@ -347,22 +365,24 @@ void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<c
     g.nmajor = gemm_nmajor(g);
     if (g.mbits > 31 || g.nbits > 31 || g.kbits > 31)
       raise(SQC_E_UNSUPPORTED, "a contraction dimension exceeds 2^31");
-    bool last = si + 1 == nsteps;
+    const bool last = si + 1 == nsteps;
+    Bump bp;
+    bp.off = stats_base;
+    size_t nsub = 0;
     if (last && top_dev) {
-      const size_t nsub = 4 * (size_t)gemm_tiles(g);
-      Bump bp;
-      bp.off = stats_base;
+      nsub = 4 * (size_t)gemm_tiles(g);
       g.stats = 1;
       g.blk_max = reinterpret_cast<double *>(ws + bp.take(nsub * sizeof(double)));
       g.wg_stats = reinterpret_cast<double *>(ws + bp.take(3 * kMaxGemmGroups * sizeof(double)));
-      int groups = 0;
-      {
-        StageMark mark(ctx, SQC_STAGE_FINAL, gemm_bytes(g, c.path_f32), gemm_flops(g));
-        groups = launch_gemm(g, prec, ctx->stream);
-        after_launch("contraction kernel launch");
-        mark.done();
-      }
-      TopRArgs t{};
+    }
+    const GemmSpec sp = prepare_gemm(g, prec);
+    const int groups = gemm_groups(g, sp);
+    L.steps.push_back(g);
+    L.specs.push_back(sp);
+    L.groups.push_back(groups);
+    if (last && top_dev) {
+      TopRArgs &t = L.t;
+      L.topr = true;
       t.C = bins;
       t.out_f32 = bins_f32;
       t.mbits = g.mbits;
@@ -377,27 +397,42 @@ void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<c
       t.slot_n = reinterpret_cast<int *>(ws + bp.take(kTopRSlots * sizeof(int)));
       char *misc = ws + bp.take(64);
       t.tau_sum = reinterpret_cast<double *>(misc);
-      t.ctl = reinterpret_cast<int *>(misc + 16);
       t.slot_val = reinterpret_cast<double *>(ws + bp.take(kTopRSlots * (size_t)top_r * 8));
       t.slot_idx = reinterpret_cast<uint64_t *>(ws + bp.take(kTopRSlots * (size_t)top_r * 8));
-
       t.top_r = top_r;
       t.top_out = static_cast<double *>(top_dev);
       t.sum_out = static_cast<double *>(sum_dev);
-      {
-        StageMark mark(ctx, SQC_STAGE_TOPR, 0.0, 0.0);
-        launch_topr(t, ctx->stream);
-        after_launch("top-R kernel launch");
-        mark.done();
-      }
-    } else {
-      StageMark mark(ctx, last ? SQC_STAGE_FINAL : SQC_STAGE_CONTRACT, gemm_bytes(g, c.path_f32),
-                     gemm_flops(g));
-      launch_gemm(g, prec, ctx->stream);
-      after_launch("contraction kernel launch");
-      mark.done();
     }
   }
+}
+
+// Enqueue the launches one by one on the context's stream (with stage timing).
+void run_direct(sqc_ctx *ctx, const Launches &L) {
+  if (!L.merges.empty()) enqueue_merges(ctx, L.merges);
+  const size_t n = L.steps.size();
+  for (size_t si = 0; si < n; ++si) {
+    const GemmArgs &g = L.steps[si];
+    StageMark mark(ctx, si + 1 == n ? SQC_STAGE_FINAL : SQC_STAGE_CONTRACT, gemm_bytes(g, L.path_f32),
+                   gemm_flops(g));
+    launch_gemm_spec(g, L.specs[si], L.groups[si], ctx->stream);
+    after_launch("contraction kernel launch");
+    mark.done();
+  }
+  if (L.topr) {
+    StageMark mark(ctx, SQC_STAGE_TOPR, 0.0, 0.0);
+    launch_topr(L.t, ctx->stream);
+    after_launch("top-R kernel launch");
+    mark.done();
+  }
+}
+
+void enqueue_contraction(sqc_ctx *ctx, const Contraction &c, const std::vector<const void *> &inputs,
+                         size_t base, void *bins, int bins_f32, sqc_prec prec, int top_r,
+                         void *top_dev, void *sum_dev) {
+  Launches L;
+  describe_contraction(L, c, inputs, ctx->ws, ctx->unit, base, bins, bins_f32, prec, top_r, top_dev,
+                       sum_dev);
+  run_direct(ctx, L);
 }
 
 void need_ws(sqc_ctx *ctx, size_t bytes) {
@@ -463,24 +498,222 @@ RecursePlan plan_recursion(const Graph &g, const sqc_tensor *att, const sqc_mask
   return rp;
 }
 
-void enqueue_recursion(sqc_ctx *ctx, const RecursePlan &rp, const sqc_tensor *att, sqc_prec prec,
-                       void *bins, sqc_prec bins_prec, int top_r, void *top_dev, void *sum_dev) {
+// The launches of one recursion whose workspace starts at ws.
+Launches describe_recursion(const RecursePlan &rp, const sqc_tensor *att, sqc_prec prec, char *ws,
+                            const double *unit2, void *bins, sqc_prec bins_prec, int top_r,
+                            void *top_dev, void *sum_dev) {
   const int n_sub = (int)rp.masks.size();
   std::vector<const void *> inputs(n_sub);
   const int path_f32 = prec != SQC_F64;
-  std::vector<MergeArgs> jobs(n_sub);
+  Launches L;
+  L.merges.resize(n_sub);
   for (int i = 0; i < n_sub; ++i) {
-    void *out = ctx->ws + rp.ml.merged_off[i];
-    jobs[i] = merge_args(att[i], rp.masks[i], out, path_f32,
-                         reinterpret_cast<double *>(ctx->ws + rp.ml.partial_off[i]));
+    void *out = ws + rp.ml.merged_off[i];
+    L.merges[i] = merge_args(att[i], rp.masks[i], out, path_f32,
+                             reinterpret_cast<double *>(ws + rp.ml.partial_off[i]));
     inputs[i] = out;
   }
-  enqueue_merges(ctx, jobs);
-  enqueue_contraction(ctx, rp.con, inputs, rp.con_base, bins, bins_prec == SQC_F32, prec, top_r,
-                      top_dev, sum_dev);
+  describe_contraction(L, rp.con, inputs, ws, unit2, rp.con_base, bins, bins_prec == SQC_F32, prec,
+                       top_r, top_dev, sum_dev);
+  return L;
+}
+
+void enqueue_recursion(sqc_ctx *ctx, const RecursePlan &rp, const sqc_tensor *att, sqc_prec prec,
+                       void *bins, sqc_prec bins_prec, int top_r, void *top_dev, void *sum_dev) {
+  run_direct(ctx, describe_recursion(rp, att, prec, ctx->ws, ctx->unit, bins, bins_prec, top_r, top_dev,
+                                     sum_dev));
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// requests planned ahead and batched launches (used by the serving engine)
+// ---------------------------------------------------------------------------
+
+namespace sqc {
+
+struct CircuitTopo {
+  Graph g;
+  std::vector<sqc_tensor> att;
+};
+
+struct PreparedRecursion {
+  std::shared_ptr<const CircuitTopo> c;
+  RecursePlan rp;
+  sqc_prec prec, bins_prec;
+  void *bins, *top, *sum;
+  int top_r;
+};
+
+void PreparedDeleter::operator()(PreparedRecursion *p) const { delete p; }
+
+std::shared_ptr<const CircuitTopo> make_circuit(const sqc_tensor *att, int n_sub, const sqc_cut *cuts,
+                                                int n_cuts) {
+  auto c = std::make_shared<CircuitTopo>();
+  c->g = build_topology(n_sub, cuts, n_cuts);
+  if (!att) raise(SQC_E_ARG, "NULL argument");
+  degrees_match(c->g, att, SQC_LAYOUT_ATTRIBUTED);
+  c->att.assign(att, att + n_sub);
+  return c;
+}
+
+int circuit_n_sub(const CircuitTopo &c) { return c.g.n_sub; }
+
+PreparedPtr prepare_recursion(std::shared_ptr<const CircuitTopo> c, const sqc_masks *scope, uint64_t M,
+                              int top_r, sqc_prec prec, void *bins, sqc_prec bins_prec, void *top_dev,
+                              void *sum_dev) {
+  if (!bins || !top_dev || !sum_dev) raise(SQC_E_ARG, "request output buffers must be set");
+  check_path_prec(prec);
+  check_storage_prec(bins_prec, "bins_prec");
+  if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
+  PreparedPtr p(new PreparedRecursion());
+  p->rp = plan_recursion(c->g, c->att.data(), scope, M, top_r, prec);
+  p->c = std::move(c);
+  p->prec = prec;
+  p->bins_prec = bins_prec;
+  p->bins = bins;
+  p->top = top_dev;
+  p->sum = sum_dev;
+  p->top_r = top_r;
+  return p;
+}
+
+size_t prepared_workspace(const PreparedRecursion &p) { return align256(p.rp.total); }
+
+size_t prepared_table_bytes(const PreparedRecursion &p) {
+  const size_t n_sub = p.rp.masks.size();
+  const size_t steps = p.rp.con.unit ? 1 : p.rp.con.plan.steps.size();
+  return n_sub * sizeof(MergeArgs) + steps * sizeof(GemmArgs) + sizeof(TopRArgs) +
+         sizeof(int) * (3 * n_sub + 2 * steps + 8) + 256 * (2 * steps + 8);
+}
+
+const sqc_masks *prepared_masks(const PreparedRecursion &p) { return p.rp.masks.data(); }
+
+namespace {
+
+Launches describe_prepared(sqc_ctx *ctx, const PreparedRecursion &p, char *ws) {
+  return describe_recursion(p.rp, p.c->att.data(), p.prec, ws, ctx->unit, p.bins, p.bins_prec, p.top_r,
+                            p.top, p.sum);
+}
+
+// Host image of a batch's job tables (arrays 256-byte aligned).
+struct TableImage {
+  char *host;
+  size_t cap, off = 0;
+  template <class T>
+  size_t put(const T *v, size_t n) {
+    const size_t at = align256(off);
+    const size_t bytes = n * sizeof(T);
+    if (at + bytes > cap) raise(SQC_E_NOMEM, "batch job table exceeds its staging buffer");
+    std::memcpy(host + at, v, bytes);
+    off = at + bytes;
+    return at;
+  }
+};
+
+// One grouped launch: kind 0 merge pass `code`, 1 GEMM of spec `spec`, 2 top-R.
+struct GroupedDesc {
+  int kind, code;
+  GemmSpec spec;
+  size_t jobs, start;
+  int n, total;
+};
+
+// Work-group prefix of jobs in one pass; fails when it does not fit a grid.
+std::vector<int> block_prefix(const std::vector<int64_t> &blocks) {
+  std::vector<int> start(blocks.size() + 1, 0);
+  int64_t acc = 0;
+  for (size_t k = 0; k < blocks.size(); ++k) {
+    start[k] = (int)acc;
+    acc += blocks[k];
+    if (acc > INT_MAX) raise(SQC_E_UNSUPPORTED, "a batched launch exceeds 2^31 work-groups");
+  }
+  start[blocks.size()] = (int)acc;
+  return start;
+}
+
+}  // namespace
+
+void enqueue_prepared(sqc_ctx *ctx, const PreparedRecursion &p, char *ws) {
+  use_device(ctx);
+  run_direct(ctx, describe_prepared(ctx, p, ws));
+}
+
+void enqueue_batch(sqc_ctx *ctx, PreparedRecursion *const *p, int n, char *const *ws, char *table_dev,
+                   size_t table_bytes, void *staging, size_t staging_bytes) {
+  use_device(ctx);
+  std::vector<Launches> Ls;
+  Ls.reserve(n);
+  for (int i = 0; i < n; ++i) Ls.push_back(describe_prepared(ctx, *p[i], ws[i]));
+  TableImage tab{static_cast<char *>(staging), std::min(table_bytes, staging_bytes)};
+  std::vector<GroupedDesc> descs;
+
+  // merges: every subcircuit of every request, one launch per pass
+  std::vector<MergeArgs> tiles, rows;
+  for (auto &L : Ls)
+    for (MergeArgs a : L.merges) {
+      merge_shape(a);
+      (merge_pass_blocks(a, 0) ? tiles : rows).push_back(a);
+    }
+  auto merge_pass = [&](const std::vector<MergeArgs> &jobs, int pass, size_t at) {
+    std::vector<int64_t> nb(jobs.size());
+    for (size_t k = 0; k < jobs.size(); ++k) nb[k] = merge_pass_blocks(jobs[k], pass);
+    const std::vector<int> start = block_prefix(nb);
+    descs.push_back(GroupedDesc{0, pass, GemmSpec{}, at, tab.put(start.data(), start.size()),
+                                (int)jobs.size(), start.back()});
+  };
+  if (!tiles.empty()) merge_pass(tiles, 0, tab.put(tiles.data(), tiles.size()));
+  if (!rows.empty()) {
+    const size_t at = tab.put(rows.data(), rows.size());
+    merge_pass(rows, 1, at);
+    merge_pass(rows, 2, at);
+  }
+
+  // GEMM steps level by level (a request's step s + 1 reads its step s), one
+  // launch per kernel specialisation within a level
+  size_t levels = 0;
+  for (auto &L : Ls) levels = std::max(levels, L.steps.size());
+  for (size_t lv = 0; lv < levels; ++lv) {
+    std::map<int, std::vector<int>> by_spec;  // spec id -> requests
+    for (int i = 0; i < n; ++i)
+      if (lv < Ls[i].steps.size()) by_spec[gemm_spec_id(Ls[i].specs[lv])].push_back(i);
+    for (auto &kv : by_spec) {
+      std::vector<GemmArgs> jobs;
+      std::vector<int64_t> nb;
+      for (int i : kv.second) {
+        jobs.push_back(Ls[i].steps[lv]);
+        nb.push_back(Ls[i].groups[lv]);
+      }
+      const std::vector<int> start = block_prefix(nb);
+      const size_t at = tab.put(jobs.data(), jobs.size());
+      descs.push_back(GroupedDesc{1, kv.first, Ls[kv.second[0]].specs[lv], at,
+                                  tab.put(start.data(), start.size()), (int)jobs.size(), start.back()});
+    }
+  }
+
+  // top-R of every request
+  std::vector<TopRArgs> tops;
+  for (auto &L : Ls)
+    if (L.topr) tops.push_back(L.t);
+  if (!tops.empty())
+    descs.push_back(GroupedDesc{2, 0, GemmSpec{}, tab.put(tops.data(), tops.size()), 0, (int)tops.size(), 0});
+
+  check_hip(hipMemcpyAsync(table_dev, staging, tab.off, hipMemcpyHostToDevice, ctx->stream),
+            "hipMemcpyAsync of the batch job table");
+  for (const GroupedDesc &d : descs) {
+    if (d.kind == 0)
+      launch_merge_grouped(d.code, reinterpret_cast<const MergeArgs *>(table_dev + d.jobs),
+                           reinterpret_cast<const int *>(table_dev + d.start), d.n, d.total, ctx->stream);
+    else if (d.kind == 1)
+      launch_gemm_grouped(d.spec, reinterpret_cast<const GemmArgs *>(table_dev + d.jobs),
+                          reinterpret_cast<const int *>(table_dev + d.start), d.n, d.total, ctx->stream);
+    else
+      launch_topr_grouped(reinterpret_cast<const TopRArgs *>(table_dev + d.jobs), d.n, ctx->stream);
+    after_launch("batched kernel launch");
+  }
+}
+
+}  // namespace sqc
 
 #define SQC_TRY(ctx)          \
   try {                       \

@@ -158,6 +158,14 @@ struct MergeArgs {
 constexpr int kMergeJobs = 8;
 // Enqueue n merges; jobs with merged bits >= 6 need their own partial buffer.
 void launch_merges(const MergeArgs *jobs, int n, hipStream_t s);
+// For batched launches from a device table: set a job's grid shape (as
+// launch_merges does), its work-groups in pass 0 (merged bits < 6), 1 (the
+// streaming reduction, merged bits >= 6) or 2 (its partial sums), and launch
+// one pass over n shaped jobs, job j taking work-groups [start[j], start[j + 1]).
+void merge_shape(MergeArgs &a);
+int64_t merge_pass_blocks(const MergeArgs &a, int pass);
+void launch_merge_grouped(int pass, const MergeArgs *jobs_dev, const int *start_dev, int n, int total,
+                          hipStream_t s);
 // FP64 partial-sum elements the merge of these bit counts needs (0: none).
 int64_t merge_partial_elems(int abits, int lbits, int mbits);
 
@@ -192,6 +200,25 @@ int gemm_nmajor(const GemmArgs &g);
 constexpr int kMaxGemmGroups = 4096;
 // Enqueue; returns the number of work-groups launched.
 int launch_gemm(const GemmArgs &g, int prec, hipStream_t s);
+// The same in parts, for callers that batch GEMMs: the kernel specialisation
+// (precision path, FP64 fold of K stages, FP32 output, regular shape)...
+struct GemmSpec {
+  int prec;
+  bool fold, outf, reg;
+};
+// ...chosen after filling g's offset tables,
+GemmSpec prepare_gemm(GemmArgs &g, int prec);
+// a dense id of it (0 .. 23),
+int gemm_spec_id(const GemmSpec &sp);
+// the work-groups launch_gemm would use (results, including the work-group
+// statistics, depend on this count),
+int gemm_groups(const GemmArgs &g, const GemmSpec &sp);
+// one launch,
+void launch_gemm_spec(const GemmArgs &g, const GemmSpec &sp, int groups, hipStream_t s);
+// and n GEMMs of one specialisation in one launch from a device table: job j
+// takes work-groups [start[j], start[j + 1]) of `total` = start[n].
+void launch_gemm_grouped(const GemmSpec &sp, const GemmArgs *jobs_dev, const int *start_dev, int n,
+                         int total, hipStream_t s);
 
 // Top-R selection over the final bins after a GEMM with statistics: the
 // compensated total sum and the R best bins (value descending, lower index
@@ -206,7 +233,6 @@ struct TopRArgs {
   const double *wg_stats;
   int ngroups;          // work-groups of the final GEMM
   int nmajor;           // its tile order
-  int *ctl;             // [1] listed sub-tiles, -1 when the list did not fit
   double *tau_sum;      // [2] threshold, total sum
   int *slot_n;          // [kTopRSlots]
   double *slot_val;     // [kTopRSlots][top_r]
@@ -215,9 +241,11 @@ struct TopRArgs {
   double *top_out;      // top_r x {double, uint64}
   double *sum_out;
 };
-// Listed sub-tiles (slots) the top-R workspace holds at most.
-constexpr int kTopRSlots = 4096;
+// Work-groups of the gather stage; each leaves its R best in a slot.
+constexpr int kTopRSlots = 64;
 void launch_topr(const TopRArgs &t, hipStream_t s);
+// n top-R selections from a device table of n TopRArgs, in two launches.
+void launch_topr_grouped(const TopRArgs *jobs_dev, int n, hipStream_t s);
 
 void launch_zero(void *p, size_t bytes, hipStream_t s);
 

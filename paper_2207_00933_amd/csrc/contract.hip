@@ -106,8 +106,7 @@ struct Sched {
 // Contiguous chunks of tiles per work-group; work-groups are dispatched
 // round-robin over 8 XCDs, so chunk order follows (XCD, work-group within the
 // XCD) and the chunks of one XCD are adjacent (shared A panels stay in its L2).
-__device__ __forceinline__ Sched schedule(int ntiles) {
-  const int G = gridDim.x, b = blockIdx.x;
+__device__ __forceinline__ Sched schedule(int ntiles, int b, int G) {
   const int lb = (G & 7) == 0 ? (b & 7) * (G >> 3) + (b >> 3) : b;
   Sched s;
   s.id = lb;
@@ -127,8 +126,9 @@ __device__ __forceinline__ Sched schedule(int ntiles) {
 // OUTF: FP32 result (else FP64).
 // REG: M, N, K >= 64 and the lowest run of k spans >= 4 bits, so no tile,
 // row or element needs a bound check and k rows are shifts.
+// One work-group `blk` of G working on the GEMM `g`.
 template <int PREC, bool FOLD, bool OUTF, bool REG>
-__global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
+__device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   typedef typename Tr<PREC>::T T;
   typedef typename Tr<PREC>::Acc Acc;
   constexpr int NACC = Tr<PREC>::NACC;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
   const int nmaj = g.nmajor;
   auto tile_m = [&](int t) -> uint32_t { return nmaj ? (uint32_t)(t & ((1 << lmt) - 1)) : (uint32_t)(t >> lnt); };
   auto tile_n = [&](int t) -> uint32_t { return nmaj ? (uint32_t)(t >> lmt) : (uint32_t)(t & ((1 << lnt) - 1)); };
-  const Sched sc = schedule(1 << (lmt + lnt));
+  const Sched sc = schedule(1 << (lmt + lnt), blk, G);
   // work-group statistics: running compensated sum and maximum of its waves
   __shared__ double wg_part[3][4];
   double wsum = 0.0, wcmp = 0.0, wmax = -INFINITY;
@@ -428,35 +428,62 @@ __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
   write_wg_stats();
 }
 
+template <int PREC, bool FOLD, bool OUTF, bool REG>
+__global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
+  gemm_body<PREC, FOLD, OUTF, REG>(g, blockIdx.x, gridDim.x);
+}
+
+// Job j of a table with work-group prefix `start` (start[0] = 0, n + 1
+// entries): the largest j with start[j] <= w (a uniform binary search).
+__device__ __forceinline__ int find_job(const int *__restrict__ start, int n, int w) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Several GEMMs of one specialisation in one launch (requests batched by the
+// serving engine): job j owns work-groups [start[j], start[j + 1]) and runs
+// exactly as the single launch with start[j + 1] - start[j] work-groups.
+template <int PREC, bool FOLD, bool OUTF, bool REG>
+__global__ __launch_bounds__(kThreads) void gemm_grouped(const GemmArgs *__restrict__ jobs,
+                                                          const int *__restrict__ start, int n) {
+  const int j = find_job(start, n, blockIdx.x);
+  const int s0 = start[j];
+  gemm_body<PREC, FOLD, OUTF, REG>(jobs[j], (int)blockIdx.x - s0, start[j + 1] - s0);
+}
+
 // ---------------------------------------------------------------------------
 // top-R selection over the final bins.  The final GEMM wrote the maximum of
 // every 32 x 32 sub-tile (sub-tile s = tile * 4 + wave) and, per work-group,
 // the compensated sum and maximum of its contiguous range of tiles.
-//   gather (a few work-groups, each repeating the selection): the GEMM's
-//     work-groups are joined into at most 256 groups of consecutive
-//     work-groups; threshold tau = the R-th largest group maximum (R groups
-//     hold a bin >= tau each, so tau is no larger than the R-th largest
-//     bin), found by sorting each wave's maxima and ranking every maximum
-//     against the other waves' sorted lists; the sub-tiles of groups whose
-//     maximum reaches tau are listed where the sub-tile's own maximum does
-//     (every one of the R largest bins lies in one of them); each work-group
-//     then takes its share of the listed sub-tiles and writes their bins
-//     >= tau into a slot of R entries (a sub-tile's R best when it holds more);
-//   rank (one work-group): the slot entries are streamed through an LDS
-//     buffer that is cut back to its R best by ranking (rank = number of
-//     better entries under the strict order: larger value, then lower index).
-// When the list does not fit, rank streams every sub-tile whose maximum
-// reaches tau instead.  Deterministic, no atomics.  The code is kept compact
-// (loops, not unrolled copies): a single work-group runs it once per call,
-// so its instruction fetch is not amortised.
+//   gather (kGatherGroups work-groups): the GEMM's work-groups are joined
+//     into at most 256 groups of consecutive work-groups; threshold tau = the
+//     R-th largest group maximum (R groups hold a bin >= tau each, so tau is
+//     no larger than the R-th largest bin), found by sorting each wave's
+//     maxima and ranking every maximum against the other waves' sorted lists.
+//     Work-group w then visits the sub-tiles of its runs of 256 (runs w,
+//     w + kGatherGroups, ...) whose maximum reaches tau (and the running R-th
+//     best) and keeps its R best bins in an LDS buffer: a bin
+//     enters when it reaches tau and beats the buffer's R-th best so far; a
+//     full buffer is cut back to its R best by a bitonic sort.  Its R best go
+//     to slot w.
+//   rank (one work-group): the slots are merged the same way.
+// The order is strict (larger value, then lower index), so the result is
+// unique: deterministic, no atomics.  Ties at the top cost no more than
+// distinct values: tied bins beyond the R lowest indices are dropped at once.
+// The code is kept compact (loops, not unrolled copies): these are small
+// grids whose instruction fetch is not amortised.
 // ---------------------------------------------------------------------------
 
 constexpr int kTW = 4;                    // waves of the top-R work-groups
 constexpr int kTThreads = 64 * kTW;
 constexpr int kNG = kTThreads;            // groups of GEMM work-groups
-constexpr int kListCap = 4096;            // sub-tiles of candidate groups examined
-constexpr int kBufCap = 2048;             // buffered entries in rank
-constexpr int kGatherGroups = 32;
+constexpr int kBufCap = 2048;             // buffered entries per work-group
+constexpr int kGatherGroups = kTopRSlots;
 
 // Exclusive prefix of v over the work-group; `total` gets the sum.
 __device__ int block_scan_excl(int v, int *wsum, int &total) {
@@ -539,21 +566,119 @@ struct SubTileBins {
   }
 };
 
-__global__ __launch_bounds__(kTThreads) void topr_gather(TopRArgs t) {
+// A work-group's running R best: entries [0, n) of val / idx in LDS.
+struct TopBuf {
+  double *val;
+  uint64_t *idx;
+  int n = 0;
+  bool have_bar = false;  // R entries kept: a new entry must beat the R-th
+  double bar_v = 0.0;
+  uint64_t bar_i = 0;
+  __device__ bool wants(double v, uint64_t i, double tau) const {
+    return i != ~uint64_t(0) && v == v && v >= tau && (!have_bar || better(v, i, bar_v, bar_i));
+  }
+  double *tv;      // [SQC_MAX_TOPR] staging of a small selection
+  uint64_t *ti;
+  // keep the R best, in order (better first): few entries are ranked by
+  // counting the better ones, more are sorted by a bitonic network (padded
+  // to a power of two with entries worse than any bin)
+  __device__ void cut(int R) {
+    if (n <= kTThreads) {
+      const int e = threadIdx.x;
+      double v = 0.0;
+      uint64_t i = 0;
+      int rank = R;
+      if (e < n) {
+        v = val[e];
+        i = idx[e];
+        rank = 0;
+        for (int q = 0; q < n; ++q) rank += better(val[q], idx[q], v, i) ? 1 : 0;
+      }
+      if (rank < R) {
+        tv[rank] = v;
+        ti[rank] = i;
+      }
+      __syncthreads();
+      const int kept = n < R ? n : R;
+      if (e < kept) {
+        val[e] = tv[e];
+        idx[e] = ti[e];
+      }
+      __syncthreads();
+    } else {
+      int P = 2;
+      while (P < n) P <<= 1;
+      for (int e = n + (int)threadIdx.x; e < P; e += kTThreads) {
+        val[e] = -INFINITY;
+        idx[e] = ~uint64_t(0);
+      }
+      __syncthreads();
+      for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j >= 1; j >>= 1) {
+          for (int p = threadIdx.x; p < (P >> 1); p += kTThreads) {
+            const int lo = ((p / j) * 2 * j) + (p % j), hi = lo + j;
+            const double vl = val[lo], vh = val[hi];
+            const uint64_t il = idx[lo], ih = idx[hi];
+            // better entry first in blocks with (lo & k) == 0, last in the others
+            const bool swap = ((lo & k) == 0) ? better(vh, ih, vl, il) : better(vl, il, vh, ih);
+            if (swap) {
+              val[lo] = vh;
+              val[hi] = vl;
+              idx[lo] = ih;
+              idx[hi] = il;
+            }
+          }
+          __syncthreads();
+        }
+    }
+    n = n < R ? n : R;
+    if (n == R) {
+      have_bar = true;
+      bar_v = val[R - 1];
+      bar_i = idx[R - 1];
+    }
+    __syncthreads();
+  }
+  // add the thread's up to 4 entries (at most 4 * kTThreads <= kBufCap - R
+  // in all, so one cut always makes room)
+  __device__ void add(const double v[4], const uint64_t ix[4], double tau, int R, int *wsum) {
+    int k = 0;
+    for (int q = 0; q < 4; ++q) k += wants(v[q], ix[q], tau) ? 1 : 0;
+    int total;
+    int at = block_scan_excl(k, wsum, total);
+    if (n + total > kBufCap) {
+      cut(R);
+      k = 0;
+      for (int q = 0; q < 4; ++q) k += wants(v[q], ix[q], tau) ? 1 : 0;
+      at = block_scan_excl(k, wsum, total);
+    }
+    at += n;
+    for (int q = 0; q < 4; ++q)
+      if (wants(v[q], ix[q], tau)) {
+        val[at] = v[q];
+        idx[at] = ix[q];
+        ++at;
+      }
+    n += total;
+    __syncthreads();
+  }
+};
+
+__device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int nb) {
   __shared__ double sv[kNG];
   __shared__ int si[kNG];
   __shared__ int wsum[kTW];
-  __shared__ int gbase[kNG], gfirst[kNG];
-  __shared__ int cand[kListCap];
-  __shared__ double red_v[kTW];
-  __shared__ uint64_t red_i[kTW];
   __shared__ double ps[kTW], pc[kTW];
   __shared__ double s_tau;
+  __shared__ double bval[kBufCap];
+  __shared__ uint64_t bidx[kBufCap];
+  __shared__ double tval[SQC_MAX_TOPR];
+  __shared__ uint64_t tidx[SQC_MAX_TOPR];
+  __shared__ int list[kTThreads];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = t.top_r;
   const int G = t.ngroups;
-  const int ntiles = t.nsub >> 2;
-  const int ng = G < kNG ? G : kNG;  // group t: GEMM work-groups [t G / ng, (t+1) G / ng)
+  const int ng = G < kNG ? G : kNG;  // group g: GEMM work-groups [g G / ng, (g+1) G / ng)
 
   // ---- group maxima (and, in work-group 0, the total sum) ----
   double s = 0.0, c = 0.0, gm = -INFINITY;
@@ -573,7 +698,7 @@ __global__ __launch_bounds__(kTThreads) void topr_gather(TopRArgs t) {
         }
     }
   }
-  if (blockIdx.x == 0) {
+  if (bid == 0) {
     for (int off = 32; off >= 1; off >>= 1) {
       const double s2 = __shfl_xor(s, off), c2 = __shfl_xor(c, off);
       two_sum_merge(s, c, s2, c2);
@@ -620,240 +745,86 @@ __global__ __launch_bounds__(kTThreads) void topr_gather(TopRArgs t) {
   }
   __syncthreads();
   const double tau = s_tau;  // -inf with fewer groups than R
-
-  // ---- list: sub-tiles of the groups reaching tau, kept where their own
-  // maximum reaches tau ----
-  int cnt = 0, first = 0;
-  if (tid < ng && gm >= tau) {
-    const int w0 = tid * G / ng, w1 = (tid + 1) * G / ng;
-    first = 4 * (int)((int64_t)w0 * ntiles / G);
-    cnt = 4 * (int)((int64_t)w1 * ntiles / G) - first;
-  }
-  int nlist;
-  const int base = block_scan_excl(cnt, wsum, nlist);
-  gbase[tid] = tid < ng ? base : nlist;
-  gfirst[tid] = first;
-  __syncthreads();
-  int ncand = -1;  // -1: the list does not fit; rank streams every sub-tile
-  if (nlist <= kListCap) {
-    ncand = 0;
-    for (int e0 = 0; e0 < nlist; e0 += 4 * kTThreads) {
-      int sb[4];
-      double mx[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int e = e0 + j * kTThreads + tid;
-        sb[j] = -1;
-        if (e < nlist) {
-          int lo = 0, hi = ng - 1;  // the last group whose offset is <= e
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (gbase[mid] <= e) lo = mid;
-            else hi = mid - 1;
-          }
-          sb[j] = gfirst[lo] + (e - gbase[lo]);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) mx[j] = t.blk_max[sb[j] >= 0 ? sb[j] : 0];
-      int keep = 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) keep += (sb[j] >= 0 && mx[j] >= tau) ? 1 : 0;
-      int total;
-      int at = ncand + block_scan_excl(keep, wsum, total);
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (sb[j] >= 0 && mx[j] >= tau) cand[at++] = sb[j];
-      ncand += total;
-    }
-    __syncthreads();
-  }
-  if (blockIdx.x == 0 && tid == 0) {
+  if (bid == 0 && tid == 0) {
     double S = ps[0], Cc = pc[0];
     for (int q = 1; q < kTW; ++q) two_sum_merge(S, Cc, ps[q], pc[q]);
     t.tau_sum[0] = tau;
     t.tau_sum[1] = S + Cc;
-    t.ctl[0] = ncand;
   }
 
-  // ---- gather this work-group's share of the listed sub-tiles ----
+  // ---- this work-group's sub-tiles whose maximum reaches tau (and the
+  // running R-th best): listed kTThreads at a time, then visited ----
+  TopBuf buf;
+  buf.val = bval;
+  buf.idx = bidx;
+  buf.tv = tval;
+  buf.ti = tidx;
   SubTileBins stb;
   stb.init(t);
-  for (int ci = blockIdx.x; ci < ncand; ci += gridDim.x) {
-    double v[4];
-    uint64_t ix[4];
-    stb.load(t, cand[ci], v, ix);
-    int k = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (!(ix[q] != ~uint64_t(0) && v[q] == v[q] && v[q] >= tau)) ix[q] = ~uint64_t(0);
-      k += ix[q] != ~uint64_t(0) ? 1 : 0;
-    }
+  for (int base = bid * kTThreads; base < t.nsub; base += nb * kTThreads) {
+    const int sb = base + tid;
+    const double mx = sb < t.nsub ? t.blk_max[sb] : -INFINITY;
+    const int keep = (sb < t.nsub && mx >= tau && (!buf.have_bar || mx >= buf.bar_v)) ? 1 : 0;
     int total;
-    int at = block_scan_excl(k, wsum, total);
-    double *slv = t.slot_val + (int64_t)ci * R;
-    uint64_t *sli = t.slot_idx + (int64_t)ci * R;
-    if (total <= R) {
+    const int at = block_scan_excl(keep, wsum, total);
+    if (keep) list[at] = sb;
+    __syncthreads();
+    // four sub-tiles' loads in flight at a time
+    for (int q = 0; q < total; q += 4) {
+      double v[4][4];
+      uint64_t ix[4][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (ix[q] != ~uint64_t(0)) {
-          slv[at] = v[q];
-          sli[at] = ix[q];
-          ++at;
-        }
-      if (tid == 0) t.slot_n[ci] = total;
-    } else {
-      // R rounds of a work-group argmax below the previous pick
-      double pv = INFINITY;
-      uint64_t pi = 0;
-      for (int r = 0; r < R; ++r) {
-        double bv = -INFINITY;
-        uint64_t bi = ~uint64_t(0);
-        for (int q = 0; q < 4; ++q)
-          if (ix[q] != ~uint64_t(0) && (r == 0 || better(pv, pi, v[q], ix[q])) && better(v[q], ix[q], bv, bi)) {
-            bv = v[q];
-            bi = ix[q];
-          }
-        for (int off = 32; off >= 1; off >>= 1) {
-          const double ov = __shfl_xor(bv, off);
-          const uint64_t oi = __shfl_xor(bi, off);
-          if (better(ov, oi, bv, bi)) {
-            bv = ov;
-            bi = oi;
+      for (int u = 0; u < 4; ++u) {
+        if (q + u < total) {
+          stb.load(t, list[q + u], v[u], ix[u]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            v[u][e] = 0.0;
+            ix[u][e] = ~uint64_t(0);
           }
         }
-        if (lane == 0) {
-          red_v[wave] = bv;
-          red_i[wave] = bi;
-        }
-        __syncthreads();
-        bv = red_v[0];
-        bi = red_i[0];
-        for (int w = 1; w < kTW; ++w)
-          if (better(red_v[w], red_i[w], bv, bi)) {
-            bv = red_v[w];
-            bi = red_i[w];
-          }
-        __syncthreads();
-        if (tid == 0) {
-          slv[r] = bv;
-          sli[r] = bi;
-        }
-        pv = bv;
-        pi = bi;
       }
-      if (tid == 0) t.slot_n[ci] = R;
+      for (int u = 0; u < 4; ++u) buf.add(v[u], ix[u], tau, R, wsum);
     }
+    __syncthreads();  // list is rewritten by the next round
   }
+  if (buf.n > R) buf.cut(R);  // the slot need not be sorted
+  if (tid < R) {
+    t.slot_val[(int64_t)bid * R + tid] = tid < buf.n ? bval[tid] : -INFINITY;
+    t.slot_idx[(int64_t)bid * R + tid] = tid < buf.n ? bidx[tid] : ~uint64_t(0);
+  }
+  if (tid == 0) t.slot_n[bid] = buf.n;
 }
 
-// LDS buffer of entries cut back to the R best.
-struct TopBuf {
-  double *val;
-  uint64_t *idx;
-  double *lval;
-  uint64_t *lidx;
-  int n = 0;
-  bool have_bar = false;  // R entries kept: a new entry must beat the R-th
-  double bar_v = 0.0;
-  uint64_t bar_i = 0;
-  __device__ bool wants(double v, uint64_t i, double tau) const {
-    return i != ~uint64_t(0) && v == v && v >= tau && (!have_bar || better(v, i, bar_v, bar_i));
-  }
-  // keep the R best, in order, at the front
-  __device__ void cut(int R) {
-    for (int e = threadIdx.x; e < n; e += kTThreads) {
-      const double v = val[e];
-      const uint64_t i = idx[e];
-      int rank = 0;
-      for (int q = 0; q < n; ++q) rank += better(val[q], idx[q], v, i) ? 1 : 0;
-      if (rank < R) {
-        lval[rank] = v;
-        lidx[rank] = i;
-      }
-    }
-    __syncthreads();
-    const int kept = n < R ? n : R;
-    if ((int)threadIdx.x < kept) {
-      val[threadIdx.x] = lval[threadIdx.x];
-      idx[threadIdx.x] = lidx[threadIdx.x];
-    }
-    __syncthreads();
-    n = kept;
-    if (kept == R) {
-      have_bar = true;
-      bar_v = lval[R - 1];
-      bar_i = lidx[R - 1];
-    }
-  }
-  // add the thread's up to 4 entries (at most 4 * kTThreads <= kBufCap - R
-  // in all, so one cut always makes room)
-  __device__ void add(const double v[4], const uint64_t ix[4], double tau, int R, int *wsum) {
-    int k = 0;
-    for (int q = 0; q < 4; ++q) k += wants(v[q], ix[q], tau) ? 1 : 0;
-    int total;
-    int at = block_scan_excl(k, wsum, total);
-    if (n + total > kBufCap) {
-      cut(R);
-      k = 0;
-      for (int q = 0; q < 4; ++q) k += wants(v[q], ix[q], tau) ? 1 : 0;
-      at = block_scan_excl(k, wsum, total);
-    }
-    at += n;
-    for (int q = 0; q < 4; ++q)
-      if (wants(v[q], ix[q], tau)) {
-        val[at] = v[q];
-        idx[at] = ix[q];
-        ++at;
-      }
-    n += total;
-    __syncthreads();
-  }
-};
-
-__global__ __launch_bounds__(kTThreads) void topr_rank(TopRArgs t) {
+__device__ __forceinline__ void topr_rank_body(const TopRArgs &t) {
   __shared__ int wsum[kTW];
   __shared__ double bval[kBufCap];
   __shared__ uint64_t bidx[kBufCap];
-  __shared__ double lval[SQC_MAX_TOPR];
-  __shared__ uint64_t lidx[SQC_MAX_TOPR];
+  __shared__ double tval[SQC_MAX_TOPR];
+  __shared__ uint64_t tidx[SQC_MAX_TOPR];
   const int tid = threadIdx.x;
   const int R = t.top_r;
-  const int ncand = t.ctl[0];
   const double tau = t.tau_sum[0];
   TopBuf buf;
   buf.val = bval;
   buf.idx = bidx;
-  buf.lval = lval;
-  buf.lidx = lidx;
-  if (ncand >= 0) {
-    // slot entries f = c R + j, j < slot_n[c]
-    const int npos = ncand * R;
-    for (int f0 = 0; f0 < npos; f0 += 4 * kTThreads) {
-      double v[4];
-      uint64_t ix[4];
-      int cn[4];
+  buf.tv = tval;
+  buf.ti = tidx;
+  // slot entries f = w R + j, j < slot_n[w]
+  const int npos = kGatherGroups * R;
+  for (int f0 = 0; f0 < npos; f0 += 4 * kTThreads) {
+    double v[4];
+    uint64_t ix[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int f = f0 + q * kTThreads + tid, ff = f < npos ? f : 0;
-        cn[q] = t.slot_n[ff / R];
-        v[q] = t.slot_val[ff];
-        ix[q] = t.slot_idx[ff];
-        if (!(f < npos && ff % R < cn[q])) ix[q] = ~uint64_t(0);
-      }
-      buf.add(v, ix, tau, R, wsum);
+    for (int q = 0; q < 4; ++q) {
+      const int f = f0 + q * kTThreads + tid, ff = f < npos ? f : 0;
+      const int cn = t.slot_n[ff / R];
+      v[q] = t.slot_val[ff];
+      ix[q] = t.slot_idx[ff];
+      if (!(f < npos && ff % R < cn)) ix[q] = ~uint64_t(0);
     }
-  } else {
-    // every sub-tile whose maximum reaches tau
-    SubTileBins stb;
-    stb.init(t);
-    for (int sb = 0; sb < t.nsub; ++sb) {
-      if (!(t.blk_max[sb] >= tau)) continue;
-      double v[4];
-      uint64_t ix[4];
-      stb.load(t, sb, v, ix);
-      buf.add(v, ix, tau, R, wsum);
-    }
+    buf.add(v, ix, tau, R, wsum);
   }
   buf.cut(R);
   if (tid < R) {
@@ -861,6 +832,19 @@ __global__ __launch_bounds__(kTThreads) void topr_rank(TopRArgs t) {
     reinterpret_cast<uint64_t *>(t.top_out)[2 * tid + 1] = tid < buf.n ? bidx[tid] : ~uint64_t(0);
   }
   if (tid == 0) *t.sum_out = t.tau_sum[1];
+}
+
+__global__ __launch_bounds__(kTThreads) void topr_gather(TopRArgs t) {
+  topr_gather_body(t, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kTThreads) void topr_rank(TopRArgs t) { topr_rank_body(t); }
+
+// Batched top-R: kGatherGroups work-groups per job, then one per job.
+__global__ __launch_bounds__(kTThreads) void topr_gather_grouped(const TopRArgs *__restrict__ jobs) {
+  topr_gather_body(jobs[blockIdx.x / kGatherGroups], blockIdx.x % kGatherGroups, kGatherGroups);
+}
+__global__ __launch_bounds__(kTThreads) void topr_rank_grouped(const TopRArgs *__restrict__ jobs) {
+  topr_rank_body(jobs[blockIdx.x]);
 }
 
 __global__ void zero_bytes(unsigned int *p, size_t nwords) {
@@ -909,25 +893,54 @@ int resident_groups() {
   return cached[dev];
 }
 
-template <int PREC, bool FOLD, bool OUTF, bool REG>
-int launch_gemm_t(const GemmArgs &g, hipStream_t s) {
-  const int64_t tiles = gemm_tiles(g);
-  int64_t cap = resident_groups<PREC, FOLD, OUTF, REG>();
-  if (cap > kMaxGemmGroups) cap = kMaxGemmGroups;
-  const int G = (int)(tiles < cap ? tiles : cap);
-  hipLaunchKernelGGL((gemm<PREC, FOLD, OUTF, REG>), dim3((unsigned)G), dim3(kThreads), 0, s, g);
-  return G;
+// Calls L::run<PREC, FOLD, OUTF, REG>() for the specialisation `sp`.
+template <int PREC, bool FOLD, class L>
+int dispatch_o(const GemmSpec &sp, const L &l) {
+  if (sp.outf) return sp.reg ? l.template run<PREC, FOLD, true, true>() : l.template run<PREC, FOLD, true, false>();
+  return sp.reg ? l.template run<PREC, FOLD, false, true>() : l.template run<PREC, FOLD, false, false>();
+}
+template <class L>
+int dispatch(const GemmSpec &sp, const L &l) {
+  if (sp.prec == SQC_F64) return dispatch_o<SQC_F64, false>(sp, l);
+  if (sp.prec == SQC_F32) return sp.fold ? dispatch_o<SQC_F32, true>(sp, l) : dispatch_o<SQC_F32, false>(sp, l);
+  return sp.fold ? dispatch_o<SQC_BF16X3, true>(sp, l) : dispatch_o<SQC_BF16X3, false>(sp, l);
 }
 
-template <int PREC, bool FOLD>
-int launch_gemm_o(const GemmArgs &g, bool reg, hipStream_t s) {
-  if (g.out_f32)
-    return reg ? launch_gemm_t<PREC, FOLD, true, true>(g, s) : launch_gemm_t<PREC, FOLD, true, false>(g, s);
-  return reg ? launch_gemm_t<PREC, FOLD, false, true>(g, s) : launch_gemm_t<PREC, FOLD, false, false>(g, s);
-}
+struct GroupsQuery {
+  int64_t tiles;
+  template <int PREC, bool FOLD, bool OUTF, bool REG>
+  int run() const {
+    int64_t cap = resident_groups<PREC, FOLD, OUTF, REG>();
+    if (cap > kMaxGemmGroups) cap = kMaxGemmGroups;
+    return (int)(tiles < cap ? tiles : cap);
+  }
+};
 
-int launch_gemm(const GemmArgs &g_in, int prec, hipStream_t s) {
-  GemmArgs g = g_in;
+struct DirectLaunch {
+  const GemmArgs &g;
+  int groups;
+  hipStream_t s;
+  template <int PREC, bool FOLD, bool OUTF, bool REG>
+  int run() const {
+    hipLaunchKernelGGL((gemm<PREC, FOLD, OUTF, REG>), dim3((unsigned)groups), dim3(kThreads), 0, s, g);
+    return groups;
+  }
+};
+
+struct GroupedLaunch {
+  const GemmArgs *jobs;
+  const int *start;
+  int n, total;
+  hipStream_t s;
+  template <int PREC, bool FOLD, bool OUTF, bool REG>
+  int run() const {
+    hipLaunchKernelGGL((gemm_grouped<PREC, FOLD, OUTF, REG>), dim3((unsigned)total), dim3(kThreads), 0, s,
+                       jobs, start, n);
+    return total;
+  }
+};
+
+GemmSpec prepare_gemm(GemmArgs &g, int prec) {
   for (int j = 0; j < 16; ++j) {
     g.koff_a[j] = host_map(g.k, j, false);
     g.koff_b[j] = host_map(g.k, j, true);
@@ -938,19 +951,47 @@ int launch_gemm(const GemmArgs &g_in, int prec, hipStream_t s) {
     g.coff_n[r] = host_map(g.n, nl, true);
   }
   g.coff_m16 = host_map(g.m, 16, true);
+  GemmSpec sp;
+  sp.prec = prec;
   // fold FP32 chunks into FP64 only when the final K spans several chunks;
   // a chunk is one K stage
-  const bool fold = g.final_step && g.kbits > 6;
-  const bool reg = g.mbits >= 6 && g.nbits >= 6 && g.kbits >= 6 && g.k.nruns >= 1 && g.k.bits[0] >= 4;
-  if (prec == SQC_F64) return launch_gemm_o<SQC_F64, false>(g, reg, s);
-  if (prec == SQC_F32)
-    return fold ? launch_gemm_o<SQC_F32, true>(g, reg, s) : launch_gemm_o<SQC_F32, false>(g, reg, s);
-  return fold ? launch_gemm_o<SQC_BF16X3, true>(g, reg, s) : launch_gemm_o<SQC_BF16X3, false>(g, reg, s);
+  sp.fold = prec != SQC_F64 && g.final_step && g.kbits > 6;
+  sp.outf = g.out_f32 != 0;
+  sp.reg = g.mbits >= 6 && g.nbits >= 6 && g.kbits >= 6 && g.k.nruns >= 1 && g.k.bits[0] >= 4;
+  return sp;
+}
+
+int gemm_spec_id(const GemmSpec &sp) {
+  return ((sp.prec * 2 + (sp.fold ? 1 : 0)) * 2 + (sp.outf ? 1 : 0)) * 2 + (sp.reg ? 1 : 0);
+}
+
+int gemm_groups(const GemmArgs &g, const GemmSpec &sp) { return dispatch(sp, GroupsQuery{gemm_tiles(g)}); }
+
+void launch_gemm_spec(const GemmArgs &g, const GemmSpec &sp, int groups, hipStream_t s) {
+  dispatch(sp, DirectLaunch{g, groups, s});
+}
+
+void launch_gemm_grouped(const GemmSpec &sp, const GemmArgs *jobs, const int *start, int n, int total,
+                         hipStream_t s) {
+  dispatch(sp, GroupedLaunch{jobs, start, n, total, s});
+}
+
+int launch_gemm(const GemmArgs &g_in, int prec, hipStream_t s) {
+  GemmArgs g = g_in;
+  const GemmSpec sp = prepare_gemm(g, prec);
+  const int groups = gemm_groups(g, sp);
+  launch_gemm_spec(g, sp, groups, s);
+  return groups;
 }
 
 void launch_topr(const TopRArgs &t, hipStream_t s) {
   hipLaunchKernelGGL(topr_gather, dim3(kGatherGroups), dim3(kTThreads), 0, s, t);
   hipLaunchKernelGGL(topr_rank, dim3(1), dim3(kTThreads), 0, s, t);
+}
+
+void launch_topr_grouped(const TopRArgs *jobs, int n, hipStream_t s) {
+  hipLaunchKernelGGL(topr_gather_grouped, dim3((unsigned)(n * kGatherGroups)), dim3(kTThreads), 0, s, jobs);
+  hipLaunchKernelGGL(topr_rank_grouped, dim3((unsigned)n), dim3(kTThreads), 0, s, jobs);
 }
 
 void launch_zero(void *p, size_t bytes, hipStream_t s) {

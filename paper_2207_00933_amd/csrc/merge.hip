@@ -289,6 +289,41 @@ __global__ __launch_bounds__(kThreads) void merge_finish(MergeBatch b) {
   merge_finish_body(b.job[j], int64_t(blockIdx.x) - b.start[j], b.job[j].fin_blocks);
 }
 
+// Job j of a device table with work-group prefix `start` (n + 1 entries,
+// start[0] = 0): the largest j with start[j] <= w (a uniform binary search).
+__device__ __forceinline__ int find_job(const int *__restrict__ start, int n, int w) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// The same passes over a device table of shaped jobs (requests batched by the
+// serving engine).
+__global__ __launch_bounds__(kThreads) void merge_tiles_grouped(const MergeArgs *__restrict__ jobs,
+                                                                 const int *__restrict__ start, int n) {
+  __shared__ double tile[kTile + 64];
+  const int j = find_job(start, n, blockIdx.x);
+  merge_tiles_body(jobs[j], int64_t(blockIdx.x) - start[j], 0, tile);
+}
+
+__global__ __launch_bounds__(kThreads) void merge_rows_grouped(const MergeArgs *__restrict__ jobs,
+                                                                const int *__restrict__ start, int n) {
+  const int j = find_job(start, n, blockIdx.x);
+  const MergeArgs &a = jobs[j];
+  const int64_t w = int64_t(blockIdx.x) - start[j];
+  merge_rows_body(a, w % a.grid_x, (int)(w / a.grid_x));
+}
+
+__global__ __launch_bounds__(kThreads) void merge_finish_grouped(const MergeArgs *__restrict__ jobs,
+                                                                  const int *__restrict__ start, int n) {
+  const int j = find_job(start, n, blockIdx.x);
+  merge_finish_body(jobs[j], int64_t(blockIdx.x) - start[j], jobs[j].fin_blocks);
+}
+
 enum Pass { kTiles, kRows, kFinish };
 
 int64_t pass_blocks(const MergeArgs &a, Pass p) { return p == kFinish ? a.fin_blocks : a.blocks; }
@@ -323,6 +358,25 @@ int64_t merge_partial_elems(int abits, int lbits, int mbits) {
   a.mbits = mbits;
   shape_merge(a);
   return (int64_t(1) << (abits + lbits)) << a.ysplit_bits;
+}
+
+void merge_shape(MergeArgs &a) { shape_merge(a); }
+
+int64_t merge_pass_blocks(const MergeArgs &a, int pass) {
+  const bool rows = a.mbits >= 6;
+  if (pass == kTiles) return rows ? 0 : a.blocks;
+  if (pass == kRows) return rows ? a.blocks : 0;
+  return rows ? a.fin_blocks : 0;
+}
+
+void launch_merge_grouped(int pass, const MergeArgs *jobs, const int *start, int n, int total,
+                          hipStream_t s) {
+  if (pass == kTiles)
+    hipLaunchKernelGGL(merge_tiles_grouped, dim3((unsigned)total), dim3(kThreads), 0, s, jobs, start, n);
+  else if (pass == kRows)
+    hipLaunchKernelGGL(merge_rows_grouped, dim3((unsigned)total), dim3(kThreads), 0, s, jobs, start, n);
+  else
+    hipLaunchKernelGGL(merge_finish_grouped, dim3((unsigned)total), dim3(kThreads), 0, s, jobs, start, n);
 }
 
 void launch_merges(const MergeArgs *jobs, int n, hipStream_t s) {

@@ -1,51 +1,55 @@
-// Serving engine: continuous admission of states-merging recursions
-// (Algorithm 1 body, one sqc_recurse each) onto concurrent HIP streams.
+// Serving engine: continuous batching of states-merging recursions (one
+// Algorithm 1 body each) onto concurrent HIP streams.
 //
-// The engine is host code layered on the public interface: each slot is a
-// stream with its own context; a request gets a block of the engine's
-// workspace of its footprint (first fit over a free list), its context is
-// pointed at that block, sqc_recurse enqueues the recursion on the slot's
-// stream and an event marks its end.  Retiring a finished request frees its
-// slot and block; waiting requests are then admitted in arrival order,
-// skipping those that do not fit yet.
+// A request is validated and planned when it is submitted (bin masks,
+// contraction plan, workspace footprint).  Whenever a slot (a stream with its
+// own context) is idle, the engine forms a batch from the waiting requests in
+// arrival order (skipping those that do not fit yet), takes one block of the
+// workspace for the batch's job table and the requests' workspaces (first fit
+// over a free list), and enqueues the batch: its job table is copied to the
+// device and every request's merges, GEMM steps and top-R selection run in
+// shared launches (one per pass, per GEMM level and kernel specialisation).
+// An event marks the batch's end; retiring it frees the slot and the block.
+// Batches on different slots overlap on the device, so requests that arrive
+// while others run are admitted as slots and memory free up.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <string>
 #include <unordered_map>
 #include <vector>
 
 #include "../../include/sqc.h"
+#include "batch.hpp"
+#include "common.hpp"
 
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kMinBlock = 4096;  // a context's control region
+constexpr size_t kMinWorkspace = 4096;
+constexpr size_t kStagingBytes = size_t(2) << 20;  // pinned job-table image per slot
+constexpr int kMaxBatch = 128;                      // requests per batch
 
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-struct Circuit {
-  std::vector<sqc_tensor> att;
-  std::vector<sqc_cut> cuts;
-  std::vector<int32_t> n_bits;
-};
-
 struct Pending {
-  uint64_t ticket;
-  sqc_request req;
-  std::vector<sqc_masks> scope;
-  size_t footprint;
+  uint64_t ticket = 0;
+  sqc::PreparedPtr prep;
+  size_t ws = 0, table = 0;  // workspace and job-table bytes (rounded)
 };
 
 struct Slot {
   hipStream_t stream = nullptr;
   sqc_ctx *ctx = nullptr;
   hipEvent_t done = nullptr;
+  void *staging = nullptr;  // pinned host image of the batch's job table
   bool busy = false;
-  uint64_t ticket = 0;
-  size_t off = 0, len = 0;  // workspace block of the running request
+  std::vector<Pending> batch;
+  size_t off = 0, len = 0;  // workspace block of the running batch
 };
 
 enum State { kWaiting = 0, kRunning = 1, kDone = 2, kFailed = 3 };
@@ -58,12 +62,13 @@ struct sqc_server {
   size_t ws_bytes = 0;
   std::map<size_t, size_t> free_blocks;  // offset -> length
   std::vector<Slot> slots;
-  std::vector<Circuit> circuits;
+  std::vector<std::shared_ptr<const sqc::CircuitTopo>> circuits;
   std::deque<Pending> waiting;
   std::deque<uint64_t> finished;  // completion queue
   std::unordered_map<uint64_t, int> state;
   std::unordered_map<uint64_t, std::string> failure;
   uint64_t next_ticket = 1;
+  int max_batch = kMaxBatch;
   sqc_serve_stats st{};
   std::string err;
 };
@@ -73,6 +78,12 @@ namespace {
 sqc_status fail(sqc_server *s, sqc_status code, const std::string &msg) {
   if (s) s->err = msg;
   return code;
+}
+
+size_t largest_free(const sqc_server *s) {
+  size_t m = 0;
+  for (auto &kv : s->free_blocks) m = std::max(m, kv.second);
+  return m;
 }
 
 bool take_block(sqc_server *s, size_t need, size_t &off) {
@@ -90,7 +101,6 @@ bool take_block(sqc_server *s, size_t need, size_t &off) {
 
 void give_block(sqc_server *s, size_t off, size_t len) {
   auto it = s->free_blocks.emplace(off, len).first;
-  // merge with the next and the previous free block
   auto nx = std::next(it);
   if (nx != s->free_blocks.end() && it->first + it->second == nx->first) {
     it->second += nx->second;
@@ -105,77 +115,120 @@ void give_block(sqc_server *s, size_t off, size_t len) {
   }
 }
 
-size_t footprint_of(sqc_server *s, const sqc_request &r, const sqc_masks *scope) {
-  if (r.circuit < 0 || r.circuit >= (int)s->circuits.size()) return 0;
-  const Circuit &c = s->circuits[r.circuit];
-  const int n_sub = (int)c.att.size();
-  std::vector<sqc_masks> m(n_sub);
-  if (sqc_assign_bins(n_sub, c.n_bits.data(), scope, r.max_bins_M, m.data()) != SQC_OK) return 0;
-  const size_t b = sqc_recurse_workspace_bytes(c.att.data(), n_sub, c.cuts.data(), (int32_t)c.cuts.size(),
-                                               m.data(), r.prec);
-  if (!b) return 0;
-  return round_up(b < kMinBlock ? kMinBlock : b);
+// Workspace block of a batch: the job table (when it holds more than one
+// request), then each request's workspace.
+size_t batch_bytes(size_t table, size_t ws_sum, int count) { return (count > 1 ? table : 0) + ws_sum; }
+
+// Enqueue the slot's batch into the block at `off`.
+void launch_batch(sqc_server *s, Slot &sl, size_t off) {
+  char *base = s->ws + off;
+  const int n = (int)sl.batch.size();
+  if (n == 1) {
+    sqc::enqueue_prepared(sl.ctx, *sl.batch[0].prep, base);
+  } else {
+    size_t table = 0;
+    for (auto &p : sl.batch) table += p.table;
+    std::vector<sqc::PreparedRecursion *> ps;
+    std::vector<char *> wss;
+    size_t at = table;
+    for (auto &p : sl.batch) {
+      ps.push_back(p.prep.get());
+      wss.push_back(base + at);
+      at += p.ws;
+    }
+    sqc::enqueue_batch(sl.ctx, ps.data(), n, wss.data(), base, table, sl.staging, kStagingBytes);
+  }
+  if (hipEventRecord(sl.done, sl.stream) != hipSuccess)
+    throw sqc::Error{SQC_E_DEVICE, "hipEventRecord failed"};
 }
 
-// Retire finished requests; admit waiting ones that fit.
+// Retire finished batches; admit waiting requests in batches.
 sqc_status pump(sqc_server *s) {
   for (auto &sl : s->slots) {
     if (!sl.busy) continue;
     const hipError_t q = hipEventQuery(sl.done);
     if (q == hipErrorNotReady) continue;
-    if (q != hipSuccess) return fail(s, SQC_E_DEVICE, std::string("request failed on the device: ") +
-                                                          hipGetErrorString(q));
-    s->state[sl.ticket] = kDone;
-    s->finished.push_back(sl.ticket);
+    if (q != hipSuccess)
+      return fail(s, SQC_E_DEVICE, std::string("request failed on the device: ") + hipGetErrorString(q));
+    for (auto &p : sl.batch) {
+      s->state[p.ticket] = kDone;
+      s->finished.push_back(p.ticket);
+    }
     give_block(s, sl.off, sl.len);
     s->st.workspace_bytes -= sl.len;
+    s->st.running -= (int32_t)sl.batch.size();
+    s->st.completed += sl.batch.size();
+    sl.batch.clear();
     sl.busy = false;
-    s->st.running -= 1;
-    s->st.completed += 1;
   }
-  for (auto it = s->waiting.begin(); it != s->waiting.end();) {
-    Slot *idle = nullptr;
+  while (!s->waiting.empty()) {
+    int idle = 0;
+    Slot *slot = nullptr;
     for (auto &sl : s->slots)
       if (!sl.busy) {
-        idle = &sl;
-        break;
+        ++idle;
+        if (!slot) slot = &sl;
       }
-    if (!idle) break;
+    if (!slot) break;
+    // share the waiting requests among the idle slots
+    const int target = std::min<int>(s->max_batch, (int)((s->waiting.size() + idle - 1) / idle));
+    const size_t room = largest_free(s);
+    size_t table = 0, ws_sum = 0;
+    int count = 0;
+    for (auto it = s->waiting.begin(); it != s->waiting.end() && count < target;) {
+      const size_t t2 = table + it->table, w2 = ws_sum + it->ws;
+      if (batch_bytes(t2, w2, count + 1) <= room && t2 <= kStagingBytes) {
+        table = t2;
+        ws_sum = w2;
+        ++count;
+        slot->batch.push_back(std::move(*it));
+        it = s->waiting.erase(it);
+      } else {
+        ++it;  // a later, smaller request may fit
+      }
+    }
+    if (!count) break;
+    const size_t len = batch_bytes(table, ws_sum, count);
     size_t off = 0;
-    if (!take_block(s, it->footprint, off)) {
-      ++it;  // a later, smaller request may fit
+    take_block(s, len, off);  // fits: len <= the largest free block
+    try {
+      launch_batch(s, *slot, off);
+    } catch (const sqc::Error &e) {
+      give_block(s, off, len);
+      for (auto &p : slot->batch) {
+        s->state[p.ticket] = kFailed;
+        s->failure[p.ticket] = e.msg;
+      }
+      slot->batch.clear();
       continue;
     }
-    const Circuit &c = s->circuits[it->req.circuit];
-    // point the slot's context at the block (a host-side pointer update)
-    sqc_status rc = sqc_ctx_set_workspace(idle->ctx, s->ws + off, it->footprint);
-    if (rc == SQC_OK) {
-      const sqc_masks *scope = it->scope.empty() ? nullptr : it->scope.data();
-      rc = sqc_recurse(idle->ctx, c.att.data(), (int32_t)c.att.size(), c.cuts.data(),
-                       (int32_t)c.cuts.size(), scope, it->req.max_bins_M, it->req.top_r, it->req.prec,
-                       it->req.bins_dev, it->req.bins_prec, it->req.masks_out, it->req.topr_dev,
-                       it->req.sum_dev);
-    }
-    if (rc == SQC_OK && hipEventRecord(idle->done, idle->stream) != hipSuccess) rc = SQC_E_DEVICE;
-    if (rc != SQC_OK) {
-      give_block(s, off, it->footprint);
-      s->state[it->ticket] = kFailed;
-      s->failure[it->ticket] = sqc_last_error(idle->ctx);
-    } else {
-      idle->busy = true;
-      idle->ticket = it->ticket;
-      idle->off = off;
-      idle->len = it->footprint;
-      s->state[it->ticket] = kRunning;
-      s->st.admitted += 1;
-      s->st.running += 1;
-      s->st.workspace_bytes += it->footprint;
-      if (s->st.workspace_bytes > s->st.workspace_peak) s->st.workspace_peak = s->st.workspace_bytes;
-      if (s->st.running > s->st.max_running) s->st.max_running = s->st.running;
-    }
-    it = s->waiting.erase(it);
+    slot->busy = true;
+    slot->off = off;
+    slot->len = len;
+    for (auto &p : slot->batch) s->state[p.ticket] = kRunning;
+    s->st.admitted += count;
+    s->st.batches += 1;
+    s->st.running += count;
+    s->st.max_running = std::max(s->st.max_running, s->st.running);
+    s->st.max_batch = std::max(s->st.max_batch, (int32_t)count);
+    s->st.workspace_bytes += len;
+    s->st.workspace_peak = std::max(s->st.workspace_peak, s->st.workspace_bytes);
   }
   s->st.queued = (int32_t)s->waiting.size();
+  return SQC_OK;
+}
+
+sqc_status prepare(sqc_server *s, const sqc_request *req, Pending &p) {
+  if (req->circuit < 0 || req->circuit >= (int)s->circuits.size())
+    return fail(s, SQC_E_ARG, "unknown circuit id");
+  try {
+    p.prep = sqc::prepare_recursion(s->circuits[req->circuit], req->scope, req->max_bins_M, req->top_r,
+                                    req->prec, req->bins_dev, req->bins_prec, req->topr_dev, req->sum_dev);
+  } catch (const sqc::Error &e) {
+    return fail(s, e.code, e.msg);
+  }
+  p.ws = round_up(sqc::prepared_workspace(*p.prep));
+  p.table = round_up(sqc::prepared_table_bytes(*p.prep));
   return SQC_OK;
 }
 
@@ -186,7 +239,7 @@ extern "C" {
 sqc_status sqc_serve_create(int device, int32_t n_slots, void *workspace_dev, size_t workspace_bytes,
                             sqc_server **out) {
   if (!out || !workspace_dev || n_slots < 1 || n_slots > 64) return SQC_E_ARG;
-  if (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign || workspace_bytes < kMinBlock) return SQC_E_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign || workspace_bytes < kMinWorkspace) return SQC_E_ARG;
   if (hipSetDevice(device) != hipSuccess) return SQC_E_DEVICE;
   sqc_server *s = new sqc_server();
   s->device = device;
@@ -197,6 +250,7 @@ sqc_status sqc_serve_create(int device, int32_t n_slots, void *workspace_dev, si
   for (auto &sl : s->slots) {
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc(&sl.staging, kStagingBytes, hipHostMallocDefault) != hipSuccess ||
         sqc_ctx_create(device, sl.stream, &sl.ctx) != SQC_OK) {
       sqc_serve_destroy(s);
       return SQC_E_DEVICE;
@@ -206,12 +260,19 @@ sqc_status sqc_serve_create(int device, int32_t n_slots, void *workspace_dev, si
   return SQC_OK;
 }
 
+sqc_status sqc_serve_set_max_batch(sqc_server *s, int32_t max_batch) {
+  if (!s || max_batch < 1 || max_batch > kMaxBatch) return fail(s, SQC_E_ARG, "max_batch must be in [1, 128]");
+  s->max_batch = max_batch;
+  return SQC_OK;
+}
+
 sqc_status sqc_serve_destroy(sqc_server *s) {
   if (!s) return SQC_E_ARG;
   for (auto &sl : s->slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
     if (sl.ctx) sqc_ctx_destroy(sl.ctx);
     if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.staging) (void)hipHostFree(sl.staging);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   delete s;
@@ -220,55 +281,39 @@ sqc_status sqc_serve_destroy(sqc_server *s) {
 
 sqc_status sqc_serve_register(sqc_server *s, const sqc_tensor *attributed, int32_t n_sub,
                               const sqc_cut *cuts, int32_t n_cuts, int32_t *circuit_id) {
-  if (!s || !attributed || !circuit_id || n_sub < 1 || (n_cuts > 0 && !cuts) || n_cuts < 0)
-    return fail(s, SQC_E_ARG, "invalid argument to sqc_serve_register");
-  Circuit c;
-  c.att.assign(attributed, attributed + n_sub);
-  c.cuts.assign(cuts, cuts + n_cuts);
-  for (int i = 0; i < n_sub; ++i) {
-    if (attributed[i].layout != SQC_LAYOUT_ATTRIBUTED || !attributed[i].data)
-      return fail(s, SQC_E_SHAPE, "registered tensors must be attributed tensors with data");
-    c.n_bits.push_back(attributed[i].n_bits);
+  if (!s || !circuit_id) return fail(s, SQC_E_ARG, "invalid argument to sqc_serve_register");
+  try {
+    s->circuits.push_back(sqc::make_circuit(attributed, n_sub, cuts, n_cuts));
+  } catch (const sqc::Error &e) {
+    return fail(s, e.code, e.msg);
   }
-  // the full-state footprint validates the graph and the tensors
-  sqc_request probe{};
-  probe.max_bins_M = 1;
-  probe.prec = SQC_F64;
-  s->circuits.push_back(c);
-  probe.circuit = (int32_t)s->circuits.size() - 1;
-  if (!footprint_of(s, probe, nullptr)) {
-    s->circuits.pop_back();
-    return fail(s, SQC_E_SHAPE, "the circuit's tensors and cuts do not form a valid compute graph");
-  }
-  *circuit_id = probe.circuit;
+  *circuit_id = (int32_t)s->circuits.size() - 1;
   return SQC_OK;
 }
 
 size_t sqc_serve_footprint(sqc_server *s, const sqc_request *req) {
   if (!s || !req) return 0;
-  return footprint_of(s, *req, req->scope);
+  Pending p;
+  if (prepare(s, req, p) != SQC_OK) return 0;
+  return p.ws + p.table;
 }
 
 sqc_status sqc_serve_submit(sqc_server *s, const sqc_request *req, uint64_t *ticket) {
   if (!s || !req || !ticket) return fail(s, SQC_E_ARG, "invalid argument to sqc_serve_submit");
-  if (req->circuit < 0 || req->circuit >= (int)s->circuits.size())
-    return fail(s, SQC_E_ARG, "unknown circuit id");
-  if (!req->bins_dev || !req->topr_dev || !req->sum_dev)
-    return fail(s, SQC_E_ARG, "request output buffers must be set");
-  if (req->top_r < 1 || req->top_r > SQC_MAX_TOPR) return fail(s, SQC_E_ARG, "top_r must be in [1, 64]");
-  const size_t need = footprint_of(s, *req, req->scope);
-  if (!need) return fail(s, SQC_E_ARG, "the request is not valid for its circuit");
-  if (need > s->ws_bytes) return fail(s, SQC_E_NOMEM, "the request's footprint exceeds the server workspace");
   Pending p;
+  const sqc_status rc = prepare(s, req, p);
+  if (rc != SQC_OK) return rc;
+  if (p.ws + p.table > s->ws_bytes || p.table > kStagingBytes)
+    return fail(s, SQC_E_NOMEM, "the request's footprint exceeds the server workspace");
+  if (req->masks_out) {
+    const int n = sqc::circuit_n_sub(*s->circuits[req->circuit]);
+    std::copy(sqc::prepared_masks(*p.prep), sqc::prepared_masks(*p.prep) + n, req->masks_out);
+  }
   p.ticket = s->next_ticket++;
-  p.req = *req;
-  if (req->scope) p.scope.assign(req->scope, req->scope + s->circuits[req->circuit].att.size());
-  p.req.scope = nullptr;
-  p.footprint = need;
   s->state[p.ticket] = kWaiting;
+  *ticket = p.ticket;
   s->waiting.push_back(std::move(p));
   s->st.submitted += 1;
-  *ticket = s->next_ticket - 1;
   return pump(s);
 }
 
@@ -278,7 +323,7 @@ sqc_status sqc_serve_poll(sqc_server *s, uint64_t ticket, int32_t *state) {
   if (rc != SQC_OK) return rc;
   auto it = s->state.find(ticket);
   if (it == s->state.end()) return fail(s, SQC_E_ARG, "unknown ticket");
-  if (it->second == kFailed) return fail(s, SQC_E_ARG, s->failure[ticket]);
+  if (it->second == kFailed) return fail(s, SQC_E_DEVICE, s->failure[ticket]);
   *state = it->second;
   return SQC_OK;
 }
@@ -290,17 +335,22 @@ sqc_status sqc_serve_wait(sqc_server *s, uint64_t ticket) {
     const sqc_status rc = sqc_serve_poll(s, ticket, &st);
     if (rc != SQC_OK) return rc;
     if (st == kDone) return SQC_OK;
-    // block on the running request that holds the ticket, else on any slot
+    // block on the batch that holds the ticket, else on any running batch
     hipEvent_t ev = nullptr;
-    for (auto &sl : s->slots)
-      if (sl.busy && (sl.ticket == ticket || !ev)) ev = sl.done;
+    for (auto &sl : s->slots) {
+      if (!sl.busy) continue;
+      bool mine = false;
+      for (auto &p : sl.batch) mine = mine || p.ticket == ticket;
+      if (mine || !ev) ev = sl.done;
+    }
     if (!ev) return fail(s, SQC_E_ARG, "request can never be admitted");
     if (hipEventSynchronize(ev) != hipSuccess) return fail(s, SQC_E_DEVICE, "hipEventSynchronize failed");
   }
 }
 
 sqc_status sqc_serve_completed(sqc_server *s, uint64_t *tickets, int32_t cap, int32_t *n) {
-  if (!s || !n || cap < 0 || (cap > 0 && !tickets)) return fail(s, SQC_E_ARG, "invalid argument to sqc_serve_completed");
+  if (!s || !n || cap < 0 || (cap > 0 && !tickets))
+    return fail(s, SQC_E_ARG, "invalid argument to sqc_serve_completed");
   const sqc_status rc = pump(s);
   if (rc != SQC_OK) return rc;
   int32_t k = 0;

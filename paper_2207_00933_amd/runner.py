@@ -128,12 +128,14 @@ class Server:
     of a request are the caller's and must stay alive until it is done; the
     request structs (with their scope arrays) are kept here until then."""
 
-    def __init__(self, device: int = 0, n_slots: int = 4, workspace_bytes: int = 256 << 20):
+    def __init__(self, device: int = 0, n_slots: int = 4, workspace_bytes: int = 256 << 20,
+                 max_batch: int = 128):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the serving engine runs only on the HIP library")
         self.device = torch.device("cuda", device)
         self.ws = _bytes_tensor(workspace_bytes, self.device)
         self.srv = sqc.serve_create(device, n_slots, self.ws)
+        sqc.serve_set_max_batch(self.srv, max_batch)
         self.graphs = {}
         self._live = {}
 

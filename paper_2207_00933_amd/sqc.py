@@ -82,7 +82,8 @@ class Request(ctypes.Structure):
 class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", c_uint64), ("admitted", c_uint64), ("completed", c_uint64),
                 ("running", c_int32), ("queued", c_int32), ("max_running", c_int32),
-                ("pad", c_int32), ("workspace_bytes", c_uint64), ("workspace_peak", c_uint64)]
+                ("max_batch", c_int32), ("workspace_bytes", c_uint64), ("workspace_peak", c_uint64),
+                ("batches", c_uint64)]
 
 
 WAITING, RUNNING, DONE = 0, 1, 2
@@ -147,6 +148,7 @@ def lib():
                                    POINTER(c_int32)]),
             "sqc_serve_create": (c_int, [c_int, c_int32, P, c_size_t, POINTER(P)]),
             "sqc_serve_destroy": (c_int, [P]),
+            "sqc_serve_set_max_batch": (c_int, [P, c_int32]),
             "sqc_serve_register": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
                                            POINTER(c_int32)]),
             "sqc_serve_footprint": (c_size_t, [P, POINTER(Request)]),
@@ -405,6 +407,10 @@ def serve_create(device: int, n_slots: int, workspace) -> int:
     _check(lib().sqc_serve_create(device, n_slots, _ptr(workspace),
                                   workspace.numel() * workspace.element_size(), ctypes.byref(h)))
     return h.value
+
+
+def serve_set_max_batch(srv: int, max_batch: int) -> None:
+    _check_srv(lib().sqc_serve_set_max_batch(srv, max_batch), srv)
 
 
 def serve_destroy(srv: int) -> None:

@@ -157,6 +157,7 @@ def test_alone_equals_burst(setup):
     assert st.submitted == st.completed == len(reqs)
     assert st.running == 0 and st.queued == 0 and st.workspace_bytes == 0
     assert st.max_running > 1  # requests overlapped on the device
+    assert st.max_batch > 1 and st.batches < len(reqs)  # requests shared launches
     check_same(alone, served, reqs)
     srv.close()
 
@@ -249,4 +250,60 @@ def test_footprint_limits(setup):
     assert e.value.status == sqc.E_ARG
     st = srv.stats()
     assert st.submitted == 0
+    srv.close()
+
+
+def test_batch_single_subcircuit_and_unit_path(setup):
+    """Circuits of one subcircuit and no cuts (the bins are the attributed
+    entries summed over merged states; the contraction is against a unit
+    tensor), mixed into batches with a multi-subcircuit circuit."""
+    s, circ = setup
+    rng = np.random.default_rng(31)
+    srv = runner.Server(0, n_slots=2, workspace_bytes=256 << 20)
+    ids = register_all(srv, circ)
+    single = {}
+    keep = []
+    for d, prec in ((9, sqc.F64), (12, sqc.F32)):
+        dt = torch.float64 if prec == sqc.F64 else torch.float32
+        buf = torch.from_numpy(rng.random(1 << d)).to(dt).cuda()
+        keep.append(buf)
+        g = sqc.Graph([d], [list(range(d))], [])
+        att = [sqc.tensor_desc(buf, 0, d, prec, sqc.LAYOUT_ATTRIBUTED)]
+        torch.cuda.synchronize()
+        single[d] = (g, att, sqc.serve_register(srv.srv, att, g))
+    work = []
+    for k in range(24):
+        d = 9 if k % 2 else 12
+        g, att, cid = single[d]
+        prec = sqc.F64 if d == 9 else (sqc.F32 if k % 4 == 0 else sqc.BF16X3)
+        a = int(rng.integers(0, d + 1))
+        top_r = int(rng.integers(1, 65))
+        bprec = sqc.F64 if prec == sqc.F64 else sqc.F32
+        dt = torch.float64 if bprec == sqc.F64 else torch.float32
+        masks = sqc.assign_bins([d], None, 1 << a)
+        nb = 1 << bin(masks[0].active).count("1")
+        outs = [torch.full((nb,), float("nan"), dtype=dt, device="cuda") for _ in range(2)]
+        tops = [torch.zeros(2 * sqc.MAX_TOPR, dtype=torch.float64, device="cuda") for _ in range(2)]
+        sums = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(2)]
+        s.ensure_workspace(sqc.recurse_workspace_bytes(att, g, masks, prec))
+        sqc.recurse(s.ctx, att, g, None, 1 << a, top_r, prec, outs[0], bprec, tops[0], sums[0])
+        srv.graphs[cid] = g
+        r = srv.request(cid, None, 1 << a, top_r, prec, outs[1], bprec, tops[1], sums[1])
+        work.append((r, outs, tops, sums, top_r))
+    # and a few requests of a multi-subcircuit circuit in the same batches
+    reqs = request_list(circ, 9, 8)
+    alone = run_alone(s, circ, reqs)
+    served = make_server_requests(srv, ids, circ, reqs)
+    torch.cuda.synchronize()
+    tickets = [srv.submit(w[0]) for w in work] + [srv.submit(r[0]) for r in served]
+    for t in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    say(f"  single-subcircuit batches: {st.batches} for {st.submitted} requests, max batch {st.max_batch}")
+    assert st.max_batch > 1
+    for r, outs, tops, sums, top_r in work:
+        assert torch.equal(outs[0], outs[1])
+        assert torch.equal(tops[0][:2 * top_r].view(torch.int64), tops[1][:2 * top_r].view(torch.int64))
+        assert torch.equal(sums[0], sums[1])
+    check_same(alone, served, reqs)
     srv.close()
