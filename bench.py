@@ -95,7 +95,7 @@ def cpu_baseline(cc, var32, seconds: float):
 # GPU
 # ---------------------------------------------------------------------------
 
-def run_gpu(cc, var32, steps: int, warmup: int, precs):
+def run_gpu(cc, var32, steps: int, warmup: int, precs, autotune: bool = True):
     import torch
     from paper_2207_00933_amd import runner, sqc
 
@@ -117,6 +117,18 @@ def run_gpu(cc, var32, steps: int, warmup: int, precs):
             circ.attribute(att_prec)
             rec.run(prec, M)
 
+        tune = None
+        if autotune:
+            # launch choices of this workload's contraction steps (one-time,
+            # like a library's tuning cache)
+            circ.attribute(att_prec)
+            masks = sqc.assign_bins(circ.g.n_data, None, M)
+            s.ensure_workspace(sqc.recurse_workspace_bytes(circ.att, circ.g, masks, prec))
+            rep = sqc.autotune(s.ctx, circ.att, circ.g, None, M, prec, rec.bins, bins_prec, reps=5)
+            tune = {"steps": rep.steps, "candidates": rep.candidates,
+                    "default_us": rep.default_us, "tuned_us": rep.tuned_us}
+            log(f"[bench] {pname}: autotune {rep.steps} steps, {rep.default_us:.1f} -> "
+                f"{rep.tuned_us:.1f} us")
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -144,6 +156,7 @@ def run_gpu(cc, var32, steps: int, warmup: int, precs):
             "final_kernel_bytes": fin.bytes / max(1, fin.launches),
             "final_kernel_flops": fin.flops / max(1, fin.launches),
             "bins_sum": rec.sum.item(),
+            "autotune": tune,
         }
         b = rec.bins.double()
         if prec == sqc.F64:
@@ -376,6 +389,8 @@ def main():
                     help="target CPU work per worker for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precs", default="f64,f32,bf16x3")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="launch the contraction steps with the default launch choices")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving leg (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -401,7 +416,7 @@ def main():
     precs = [p for p in args.precs.split(",") if p]
     if args.calib_copy_mb > 0:
         calib_copy(args.calib_copy_mb)
-    gpu = run_gpu(cc, var32, args.steps, args.warmup, precs)
+    gpu = run_gpu(cc, var32, args.steps, args.warmup, precs, autotune=not args.no_autotune)
     serving = run_serving(args.serve_requests, args.serve_slots) if args.serve_requests > 0 else None
     fast = [p for p in ("bf16x3", "f32") if p in gpu]
     head = max(fast, key=lambda p: gpu[p]["bins_per_s"]) if fast else precs[0]

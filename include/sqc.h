@@ -247,6 +247,14 @@ sqc_status sqc_attribute(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub,
                          int32_t sub_id, const sqc_cut *cuts, int32_t n_cuts,
                          const void *variants_dev, sqc_prec in_prec,
                          sqc_tensor *out);
+/* All subcircuits at once: variants_dev[i] holds subcircuit i's variants,
+ * outs[i] its output (data and prec set by the caller; the other fields are
+ * filled as by sqc_attribute).  Subcircuits that fit the on-chip stage share
+ * one launch, so the small ones overlap the large ones. */
+sqc_status sqc_attribute_all(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub,
+                             const sqc_cut *cuts, int32_t n_cuts,
+                             const void *const *variants_dev, sqc_prec in_prec,
+                             sqc_tensor *outs);
 
 /* ---- merging (Sec. 4) ------------------------------------------------------ */
 
@@ -302,6 +310,37 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
                        int32_t top_r, sqc_prec prec, void *bins_dev,
                        sqc_prec bins_prec, sqc_masks *masks_out,
                        void *topr_dev, void *sum_dev);
+
+/* ---- launch tuning (not part of the paper) ------------------------------------ */
+
+/* A project-side autotuner of the contraction launches.  For the recursion
+ * described as in sqc_recurse (its workspace from sqc_recurse_workspace_bytes),
+ * it runs the recursion once, then times every GEMM step of it (`reps`
+ * launches each, HIP events on the context's stream, waiting for the device)
+ * over candidate launch choices: work-group counts of 1/4, 1/2, 1 and 2 times
+ * the resident capacity and one per tile, and both tile orders when the step
+ * has several m and n panels.  The fastest choice of each step is stored in a
+ * process-wide table keyed by the step's kernel specialisation, dimensions
+ * and index maps, and every later launch of the same shape (sqc_contract,
+ * sqc_recurse, sqc_search, the serving engine) uses it.  Tile order changes
+ * no result; the work-group count changes how the bin sum is split, so sums
+ * may differ in the last bits from an untuned run (every run with the same
+ * table gives the same bits).  The recursion is run once more at the end, so
+ * `bins_dev` holds its bins.  Blocks the calling thread.  `report` (optional)
+ * receives the steps tuned, candidates timed and the summed step times with
+ * the default and the chosen launches. */
+typedef struct {
+  int32_t steps, candidates;
+  double default_us, tuned_us;
+} sqc_tune_report;
+sqc_status sqc_autotune(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
+                        const sqc_cut *cuts, int32_t n_cuts, const sqc_masks *scope,
+                        uint64_t max_bins_M, sqc_prec prec, void *bins_dev,
+                        sqc_prec bins_prec, int32_t reps, sqc_tune_report *report);
+/* Forget every tuned choice (launches return to the default heuristics). */
+sqc_status sqc_autotune_reset(void);
+/* Number of tuned shapes in the table. */
+int32_t sqc_autotune_entries(void);
 
 /* ---- the search loop (Algorithm 1) ------------------------------------------- */
 

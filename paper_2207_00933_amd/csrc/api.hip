@@ -376,7 +376,12 @@ void describe_contraction(Launches &L, const Contraction &c, const std::vector<c
       g.wg_stats = reinterpret_cast<double *>(ws + bp.take(3 * kMaxGemmGroups * sizeof(double)));
     }
     const GemmSpec sp = prepare_gemm(g, prec);
-    const int groups = gemm_groups(g, sp);
+    int groups = gemm_groups(g, sp);
+    GemmTuning tu;
+    if (gemm_tuned(g, sp, tu)) {
+      groups = (int)std::min<int64_t>(std::min<int64_t>(tu.groups, gemm_tiles(g)), kMaxGemmGroups);
+      g.nmajor = (g.mbits > 6 && g.nbits > 6) ? tu.nmajor : 0;
+    }
     L.steps.push_back(g);
     L.specs.push_back(sp);
     L.groups.push_back(groups);
@@ -849,12 +854,11 @@ size_t sqc_attribute_bytes(const sqc_sub *subs, int32_t n_sub, int32_t sub_id,
   }
 }
 
-sqc_status sqc_attribute(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, int32_t sub_id,
-                         const sqc_cut *cuts, int32_t n_cuts, const void *variants_dev,
-                         sqc_prec in_prec, sqc_tensor *out) {
-  SQC_TRY(ctx)
-  Graph g = build_graph(subs, n_sub, cuts, n_cuts);
-  if (sub_id < 0 || sub_id >= n_sub) raise(SQC_E_ARG, "sub_id out of range");
+namespace {
+
+// Arguments of one subcircuit's attribution (validates the output tensor).
+AttrArgs attr_args(const Graph &g, int sub_id, const void *variants_dev, sqc_prec in_prec,
+                   const sqc_tensor *out) {
   if (!variants_dev) raise(SQC_E_ARG, "variants_dev is NULL");
   if (!out || !out->data) raise(SQC_E_ARG, "out or out->data is NULL");
   check_storage_prec(in_prec, "in_prec");
@@ -884,17 +888,64 @@ sqc_status sqc_attribute(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, int32
   }
   for (int j = 0; j < s.d; ++j) a.data_wire[j] = s.data_wire[j];
   a.scale = std::ldexp(1.0, -a.n_out);
-  use_device(ctx);
+  return a;
+}
+
+// Algorithmic bytes of one attribution: every variant entry read once, every
+// attributed entry written once.
+double attr_bytes(const Graph &g, int sub_id, const AttrArgs &a, double *reads) {
+  const SubInfo &s = g.subs[sub_id];
   const double nvar = double(s.variants) * std::ldexp(1.0, s.w);
-  const double nout = std::ldexp(1.0, 2 * c + s.d);
-  StageMark mark(ctx, SQC_STAGE_ATTRIBUTE,
-                 nvar * (a.in_f32 ? 4 : 8) + nout * (a.out_f32 ? 4 : 8), nvar);
-  launch_attribute(a, ctx->stream);
+  const double nout = std::ldexp(1.0, 2 * a.c + s.d);
+  *reads += nvar;
+  return nvar * (a.in_f32 ? 4 : 8) + nout * (a.out_f32 ? 4 : 8);
+}
+
+void finish_attr_out(const AttrArgs &a, sqc_tensor *out) {
+  out->n_labels = a.c;
+  out->n_bits = a.d;
+  out->layout = SQC_LAYOUT_ATTRIBUTED;
+}
+
+}  // namespace
+
+sqc_status sqc_attribute(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, int32_t sub_id,
+                         const sqc_cut *cuts, int32_t n_cuts, const void *variants_dev,
+                         sqc_prec in_prec, sqc_tensor *out) {
+  SQC_TRY(ctx)
+  Graph g = build_graph(subs, n_sub, cuts, n_cuts);
+  if (sub_id < 0 || sub_id >= n_sub) raise(SQC_E_ARG, "sub_id out of range");
+  const AttrArgs a = attr_args(g, sub_id, variants_dev, in_prec, out);
+  use_device(ctx);
+  double reads = 0;
+  const double bytes = attr_bytes(g, sub_id, a, &reads);
+  StageMark mark(ctx, SQC_STAGE_ATTRIBUTE, bytes, reads);
+  launch_attributes(&a, 1, ctx->stream);
   after_launch("attribution kernel launch");
   mark.done();
-  out->n_labels = c;
-  out->n_bits = s.d;
-  out->layout = SQC_LAYOUT_ATTRIBUTED;
+  finish_attr_out(a, out);
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_attribute_all(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, const sqc_cut *cuts,
+                             int32_t n_cuts, const void *const *variants_dev, sqc_prec in_prec,
+                             sqc_tensor *outs) {
+  SQC_TRY(ctx)
+  Graph g = build_graph(subs, n_sub, cuts, n_cuts);
+  if (!variants_dev || !outs) raise(SQC_E_ARG, "NULL argument");
+  std::vector<AttrArgs> jobs;
+  double bytes = 0, reads = 0;
+  for (int i = 0; i < n_sub; ++i) {
+    jobs.push_back(attr_args(g, i, variants_dev[i], in_prec, &outs[i]));
+    bytes += attr_bytes(g, i, jobs.back(), &reads);
+  }
+  use_device(ctx);
+  StageMark mark(ctx, SQC_STAGE_ATTRIBUTE, bytes, reads);
+  launch_attributes(jobs.data(), n_sub, ctx->stream);
+  after_launch("attribution kernel launch");
+  mark.done();
+  for (int i = 0; i < n_sub; ++i) finish_attr_out(jobs[i], &outs[i]);
   return SQC_OK;
   SQC_CATCH(ctx)
 }
@@ -1006,6 +1057,92 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
   return SQC_OK;
   SQC_CATCH(ctx)
 }
+
+sqc_status sqc_autotune(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,
+                        int32_t n_cuts, const sqc_masks *scope, uint64_t max_bins_M, sqc_prec prec,
+                        void *bins_dev, sqc_prec bins_prec, int32_t reps, sqc_tune_report *report) {
+  SQC_TRY(ctx)
+  Graph g = build_topology(n_sub, cuts, n_cuts);
+  if (!attributed || !bins_dev) raise(SQC_E_ARG, "NULL argument");
+  if (reps < 1 || reps > 100) raise(SQC_E_ARG, "reps must be in [1, 100]");
+  check_path_prec(prec);
+  check_storage_prec(bins_prec, "bins_prec");
+  degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+  RecursePlan rp = plan_recursion(g, attributed, scope, max_bins_M, 1, prec);
+  need_ws(ctx, rp.total);
+  use_device(ctx);
+  void *top_dev = ctx->ws + kOffSearchTop;
+  void *sum_dev = ctx->ws + kOffSearchSum;
+  // one full recursion leaves every step's inputs in place
+  Launches L = describe_recursion(rp, attributed, prec, ctx->ws, ctx->unit, bins_dev, bins_prec, 1, top_dev,
+                                  sum_dev);
+  run_direct(ctx, L);
+  struct Events {  // returned to the pool on every exit
+    sqc_ctx *c;
+    hipEvent_t a, b;
+    ~Events() {
+      c->pool.push_back(a);
+      c->pool.push_back(b);
+    }
+  } ev{ctx, take_event(ctx), take_event(ctx)};
+  hipEvent_t e0 = ev.a, e1 = ev.b;
+  sqc_tune_report rep{};
+  for (size_t si = 0; si < L.steps.size(); ++si) {
+    const GemmArgs base = L.steps[si];
+    const GemmSpec &sp = L.specs[si];
+    const int64_t tiles = gemm_tiles(base);
+    const int cap = gemm_resident_cap(sp);
+    // candidates: work-group counts around the resident capacity, both tile
+    // orders when there are several m and n panels
+    std::vector<int> counts;
+    for (int64_t c : {int64_t(cap) / 4, int64_t(cap) / 2, int64_t(cap), int64_t(cap) * 2, tiles}) {
+      const int v = (int)std::max<int64_t>(1, std::min<int64_t>({c, tiles, int64_t(kMaxGemmGroups)}));
+      if (std::find(counts.begin(), counts.end(), v) == counts.end()) counts.push_back(v);
+    }
+    std::vector<int> orders{base.nmajor};
+    if (base.mbits > 6 && base.nbits > 6) orders.push_back(1 - base.nmajor);
+    double best = 0.0, dflt = 0.0;
+    GemmTuning pick{L.groups[si], base.nmajor};
+    for (int nm : orders)
+      for (int cnt : counts) {
+        GemmArgs gg = base;
+        gg.nmajor = nm;
+        launch_gemm_spec(gg, sp, cnt, ctx->stream);  // warm
+        check_hip(hipEventRecord(e0, ctx->stream), "hipEventRecord");
+        for (int r = 0; r < reps; ++r) launch_gemm_spec(gg, sp, cnt, ctx->stream);
+        check_hip(hipEventRecord(e1, ctx->stream), "hipEventRecord");
+        after_launch("tuning launch");
+        check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.f;
+        check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        const double us = 1e3 * ms / reps;
+        const bool is_default = nm == base.nmajor && cnt == L.groups[si];
+        if (is_default) dflt = us;
+        ++rep.candidates;
+        if (best == 0.0 || us < best) {
+          best = us;
+          pick = GemmTuning{cnt, nm};
+        }
+      }
+    gemm_tune_store(base, sp, pick);
+    rep.default_us += dflt;
+    rep.tuned_us += best;
+    ++rep.steps;
+  }
+  // leave the outputs of the tuned launches
+  run_direct(ctx, describe_recursion(rp, attributed, prec, ctx->ws, ctx->unit, bins_dev, bins_prec, 1, top_dev,
+                                     sum_dev));
+  if (report) *report = rep;
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_autotune_reset(void) {
+  gemm_tune_reset();
+  return SQC_OK;
+}
+
+int32_t sqc_autotune_entries(void) { return (int32_t)gemm_tune_size(); }
 
 sqc_status sqc_search(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,
                       int32_t n_cuts, uint64_t max_bins_M, int32_t max_recursions, sqc_prec prec,

@@ -18,6 +18,8 @@
 //            Z|X|Y = q0 - q1 (in that basis)
 #include "common.hpp"
 
+#include <algorithm>
+
 namespace sqc {
 
 namespace {
@@ -44,8 +46,7 @@ size_t attribute_lds_bytes(int xt_bits, int n_in, int n_out) {
 // preparations, outcome bits and tile states (one entry each), then issue all
 // variant loads at once.  LDS is sized to the subcircuit (dynamic), so small
 // stages leave room for many work-groups per CU.
-__global__ __launch_bounds__(kThreads) void attribute_lds(AttrArgs a) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+__device__ __forceinline__ void attribute_lds_body(const AttrArgs &a, int blk, unsigned char *dyn) {
   const int tid = threadIdx.x;
   const int XT = 1 << a.xt_bits;
   const int NB = 1 << a.n_out;
@@ -59,8 +60,8 @@ __global__ __launch_bounds__(kThreads) void attribute_lds(AttrArgs a) {
   uint32_t *slot = sout + NB;                               // [NV] its outcome bits
   uint32_t *xoff = slot + NB;                               // [XT] wire offset of tile state xt
   const int lnxt = a.d - a.xt_bits;
-  const int bidx = blockIdx.x >> lnxt;
-  const int64_t x0 = int64_t(blockIdx.x & ((1 << lnxt) - 1)) << a.xt_bits;
+  const int bidx = blk >> lnxt;
+  const int64_t x0 = int64_t(blk & ((1 << lnxt) - 1)) << a.xt_bits;
 
   // basis digits of this work-group
   int zmask = 0;  // bit j: out-cut j measured in the Z basis
@@ -215,6 +216,21 @@ __global__ __launch_bounds__(kThreads) void attribute_lds(AttrArgs a) {
   }
 }
 
+// Several subcircuits in one launch: work-group w belongs to the job j with
+// start[j] <= w < start[j + 1]; dynamic LDS is the largest job's.
+struct AttrBatch {
+  int n;
+  int start[kAttrJobs + 1];
+  AttrArgs job[kAttrJobs];
+};
+
+__global__ __launch_bounds__(kThreads) void attribute_lds(AttrBatch b) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+  int j = 0;
+  while (j + 1 < b.n && (int)blockIdx.x >= b.start[j + 1]) ++j;
+  attribute_lds_body(b.job[j], (int)blockIdx.x - b.start[j], dyn);
+}
+
 // Direct evaluation for subcircuits whose per-state slice does not fit the LDS
 // stage: one thread per output element, reading the variants from memory.
 __global__ __launch_bounds__(kThreads) void attribute_direct(AttrArgs a) {
@@ -268,27 +284,42 @@ __global__ __launch_bounds__(kThreads) void attribute_direct(AttrArgs a) {
 
 }  // namespace
 
-void launch_attribute(const AttrArgs &a0, hipStream_t s) {
-  AttrArgs a = a0;
-  const int64_t per_x = (int64_t(1) << (2 * a.n_in)) << a.n_out;
-  const int64_t ns = int64_t(1) << (2 * a.n_in);
-  if (per_x <= kLdsElems && ns <= kMaxNS && (int64_t(1) << a.n_out) <= kMaxNB) {
-    // x-tile: as many data states as fill the stage, then halved while that
-    // gives too few work-groups to fill the device and keeps >= 256 entries
-    int xb = 0;
-    while ((per_x << (xb + 1)) <= kLdsElems && xb + 1 <= a.d) ++xb;
-    int64_t nbeta = 1;
-    for (int j = 0; j < a.n_out; ++j) nbeta *= 3;
-    while (xb > 0 && (nbeta << (a.d - xb)) < 1024 && (per_x << (xb - 1)) >= 256) --xb;
-    a.xt_bits = xb;
-    const dim3 grid((unsigned)(nbeta << (a.d - xb)));
-    hipLaunchKernelGGL(attribute_lds, grid, dim3(kThreads), attribute_lds_bytes(xb, a.n_in, a.n_out), s, a);
-  } else {
-    int64_t total = (int64_t(1) << a.d) << (2 * a.c);
-    int64_t blocks = (total + kThreads - 1) / kThreads;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(attribute_direct, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+void launch_attributes(const AttrArgs *jobs, int n, hipStream_t s) {
+  AttrBatch b{};
+  size_t lds = 0;
+  auto flush = [&]() {
+    if (!b.n) return;
+    hipLaunchKernelGGL(attribute_lds, dim3((unsigned)b.start[b.n]), dim3(kThreads), lds, s, b);
+    b = AttrBatch{};
+    lds = 0;
+  };
+  for (int i = 0; i < n; ++i) {
+    AttrArgs a = jobs[i];
+    const int64_t per_x = (int64_t(1) << (2 * a.n_in)) << a.n_out;
+    const int64_t ns = int64_t(1) << (2 * a.n_in);
+    if (per_x <= kLdsElems && ns <= kMaxNS && (int64_t(1) << a.n_out) <= kMaxNB) {
+      // x-tile: as many data states as fill the stage, then halved while that
+      // gives too few work-groups to fill the device and keeps >= 256 entries
+      int xb = 0;
+      while ((per_x << (xb + 1)) <= kLdsElems && xb + 1 <= a.d) ++xb;
+      int64_t nbeta = 1;
+      for (int j = 0; j < a.n_out; ++j) nbeta *= 3;
+      while (xb > 0 && (nbeta << (a.d - xb)) < 1024 && (per_x << (xb - 1)) >= 256) --xb;
+      a.xt_bits = xb;
+      const int64_t blocks = nbeta << (a.d - xb);
+      if (b.n == kAttrJobs || b.start[b.n] + blocks > (int64_t(1) << 31) - 1) flush();
+      b.job[b.n] = a;
+      b.start[b.n + 1] = (int)(b.start[b.n] + blocks);
+      ++b.n;
+      lds = std::max(lds, attribute_lds_bytes(xb, a.n_in, a.n_out));
+    } else {
+      int64_t total = (int64_t(1) << a.d) << (2 * a.c);
+      int64_t blocks = (total + kThreads - 1) / kThreads;
+      if (blocks > 65536) blocks = 65536;
+      hipLaunchKernelGGL(attribute_direct, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+    }
   }
+  flush();
 }
 
 }  // namespace sqc

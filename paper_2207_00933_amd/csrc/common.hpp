@@ -135,7 +135,10 @@ struct AttrArgs {
   int data_wire[64];
   double scale;                // 2^-n_out
 };
-void launch_attribute(const AttrArgs &a, hipStream_t s);
+// Enqueue the attribution of n subcircuits (those that fit the LDS stage
+// share launches of up to kAttrJobs jobs).
+constexpr int kAttrJobs = 4;
+void launch_attributes(const AttrArgs *jobs, int n, hipStream_t s);
 
 struct MergeArgs {
   const void *in;   // attributed [2^d][L]
@@ -213,12 +216,28 @@ int gemm_spec_id(const GemmSpec &sp);
 // the work-groups launch_gemm would use (results, including the work-group
 // statistics, depend on this count),
 int gemm_groups(const GemmArgs &g, const GemmSpec &sp);
+// the resident work-group capacity of the specialisation (at most
+// kMaxGemmGroups),
+int gemm_resident_cap(const GemmSpec &sp);
 // one launch,
 void launch_gemm_spec(const GemmArgs &g, const GemmSpec &sp, int groups, hipStream_t s);
 // and n GEMMs of one specialisation in one launch from a device table: job j
 // takes work-groups [start[j], start[j + 1]) of `total` = start[n].
 void launch_gemm_grouped(const GemmSpec &sp, const GemmArgs *jobs_dev, const int *start_dev, int n,
                          int total, hipStream_t s);
+
+// Launch choices of a GEMM shape found by the tuner (process-wide table keyed
+// by specialisation, dimensions and index maps; pointers are not part of the
+// key): work-group count and tile order.
+struct GemmTuning {
+  int groups;
+  int nmajor;
+};
+uint64_t gemm_tune_key(const GemmArgs &g, const GemmSpec &sp);
+bool gemm_tuned(const GemmArgs &g, const GemmSpec &sp, GemmTuning &out);
+void gemm_tune_store(const GemmArgs &g, const GemmSpec &sp, const GemmTuning &t);
+void gemm_tune_reset();
+size_t gemm_tune_size();
 
 // Top-R selection over the final bins after a GEMM with statistics: the
 // compensated total sum and the R best bins (value descending, lower index

@@ -27,7 +27,9 @@
 // result store run along m, the contiguous output axis.
 #include "common.hpp"
 
+#include <mutex>
 #include <type_traits>
+#include <unordered_map>
 
 namespace sqc {
 
@@ -966,6 +968,68 @@ int gemm_spec_id(const GemmSpec &sp) {
 }
 
 int gemm_groups(const GemmArgs &g, const GemmSpec &sp) { return dispatch(sp, GroupsQuery{gemm_tiles(g)}); }
+
+int gemm_resident_cap(const GemmSpec &sp) { return dispatch(sp, GroupsQuery{int64_t(kMaxGemmGroups)}); }
+
+// ---- launch choices found by the tuner, per GEMM shape ----
+namespace {
+std::mutex tune_mu;
+std::unordered_map<uint64_t, GemmTuning> tune_table;
+
+void mix(uint64_t &h, int64_t v) {
+  h ^= (uint64_t)v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+}
+void mix_map(uint64_t &h, const IndexMap &m) {
+  mix(h, m.nruns);
+  for (int r = 0; r < m.nruns; ++r) {
+    mix(h, m.bits[r]);
+    mix(h, m.sx[r]);
+    mix(h, m.sy[r]);
+    mix(h, m.lx[r]);
+    mix(h, m.ly[r]);
+  }
+}
+}  // namespace
+
+uint64_t gemm_tune_key(const GemmArgs &g, const GemmSpec &sp) {
+  uint64_t h = 0x2207009330000001ull;
+  mix(h, gemm_spec_id(sp));
+  mix(h, g.mbits);
+  mix(h, g.nbits);
+  mix(h, g.kbits);
+  mix(h, g.out_f32);
+  mix(h, g.final_step);
+  mix(h, g.stats);
+  mix_map(h, g.m);
+  mix_map(h, g.n);
+  mix_map(h, g.k);
+  return h;
+}
+
+bool gemm_tuned(const GemmArgs &g, const GemmSpec &sp, GemmTuning &out) {
+  const uint64_t k = gemm_tune_key(g, sp);
+  std::lock_guard<std::mutex> lk(tune_mu);
+  auto it = tune_table.find(k);
+  if (it == tune_table.end()) return false;
+  out = it->second;
+  return true;
+}
+
+void gemm_tune_store(const GemmArgs &g, const GemmSpec &sp, const GemmTuning &t) {
+  const uint64_t k = gemm_tune_key(g, sp);
+  std::lock_guard<std::mutex> lk(tune_mu);
+  tune_table[k] = t;
+}
+
+void gemm_tune_reset() {
+  std::lock_guard<std::mutex> lk(tune_mu);
+  tune_table.clear();
+}
+
+size_t gemm_tune_size() {
+  std::lock_guard<std::mutex> lk(tune_mu);
+  return tune_table.size();
+}
 
 void launch_gemm_spec(const GemmArgs &g, const GemmSpec &sp, int groups, hipStream_t s) {
   dispatch(sp, DirectLaunch{g, groups, s});

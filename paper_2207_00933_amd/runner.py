@@ -71,13 +71,13 @@ class Circuit:
         return cls(session, sqc.Graph.from_cut_circuit(cc), variants, var_prec)
 
     def attribute(self, out_prec: int = sqc.F64) -> List[sqc.Tensor]:
-        """Attribute every subcircuit (one kernel launch each)."""
+        """Attribute every subcircuit (subcircuits that fit the on-chip stage
+        share one launch)."""
         if len(self.att_buf) != self.g.n_sub or self.att[0].prec != out_prec:
             self.att_buf = [_bytes_tensor(sqc.attribute_bytes(self.g, i, out_prec), self.s.device)
                             for i in range(self.g.n_sub)]
-        self.att = [sqc.attribute(self.s.ctx, self.g, i, self.var[i], self.var_prec,
-                                  self.att_buf[i], out_prec)
-                    for i in range(self.g.n_sub)]
+        self.att = sqc.attribute_all(self.s.ctx, self.g, self.var, self.var_prec, self.att_buf,
+                                     out_prec)
         return self.att
 
     def attributed_numpy(self, i: int) -> np.ndarray:

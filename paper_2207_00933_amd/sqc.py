@@ -72,6 +72,11 @@ class StageTime(ctypes.Structure):
                 ("flops", c_double)]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("steps", c_int32), ("candidates", c_int32), ("default_us", c_double),
+                ("tuned_us", c_double)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [("circuit", c_int32), ("top_r", c_int32), ("max_bins_M", c_uint64),
                 ("scope", POINTER(Masks)), ("prec", c_int), ("bins_prec", c_int),
@@ -131,6 +136,8 @@ def lib():
                                                c_int32, c_int]),
             "sqc_attribute": (c_int, [P, POINTER(Sub), c_int32, c_int32, POINTER(Cut), c_int32,
                                       P, c_int, POINTER(Tensor)]),
+            "sqc_attribute_all": (c_int, [P, POINTER(Sub), c_int32, POINTER(Cut), c_int32,
+                                          POINTER(c_void_p), c_int, POINTER(Tensor)]),
             "sqc_merge_workspace_bytes": (c_size_t, [POINTER(Tensor), POINTER(Masks)]),
             "sqc_merge": (c_int, [P, POINTER(Tensor), POINTER(Masks), POINTER(Tensor)]),
             "sqc_contract_workspace_bytes": (c_size_t, [POINTER(Tensor), c_int32, POINTER(Cut),
@@ -146,6 +153,10 @@ def lib():
                                    c_int32, c_int, P, c_int, POINTER(Found), POINTER(c_uint64),
                                    c_int32, POINTER(c_int32), POINTER(RecursionInfo),
                                    POINTER(c_int32)]),
+            "sqc_autotune": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32, POINTER(Masks),
+                                     c_uint64, c_int, P, c_int, c_int32, POINTER(TuneReport)]),
+            "sqc_autotune_reset": (c_int, []),
+            "sqc_autotune_entries": (c_int32, []),
             "sqc_serve_create": (c_int, [c_int, c_int32, P, c_size_t, POINTER(P)]),
             "sqc_serve_destroy": (c_int, [P]),
             "sqc_serve_set_max_batch": (c_int, [P, c_int32]),
@@ -333,6 +344,17 @@ def attribute(ctx: int, g: Graph, sub_id: int, variants, in_prec: int, out, out_
     return d
 
 
+def attribute_all(ctx: int, g: Graph, variants, in_prec: int, outs, out_prec: int) -> List[Tensor]:
+    n = g.n_sub
+    vp = (c_void_p * n)(*[_ptr(v) for v in variants])
+    arr = (Tensor * n)()
+    for i in range(n):
+        arr[i].data = _ptr(outs[i])
+        arr[i].prec = out_prec
+    _check(lib().sqc_attribute_all(ctx, g.subs, n, g.cuts, g.n_cuts, vp, in_prec, arr), ctx)
+    return list(arr)
+
+
 def merge_workspace_bytes(att: Tensor, masks) -> int:
     m = masks_array([masks])
     return int(lib().sqc_merge_workspace_bytes(ctypes.byref(att), m))
@@ -371,6 +393,24 @@ def recurse(ctx: int, att: Sequence[Tensor], g: Graph, scope, M: int, top_r: int
     _check(lib().sqc_recurse(ctx, arr, g.n_sub, g.cuts, g.n_cuts, sc, M, top_r, prec, _ptr(bins),
                              bins_prec, out, _ptr(topr), _ptr(bsum)), ctx)
     return list(out)
+
+
+def autotune(ctx: int, att: Sequence[Tensor], g: Graph, scope, M: int, prec: int, bins,
+             bins_prec: int, reps: int = 5) -> TuneReport:
+    arr = tensor_array(att)
+    sc = masks_array(scope) if scope is not None else None
+    rep = TuneReport()
+    _check(lib().sqc_autotune(ctx, arr, g.n_sub, g.cuts, g.n_cuts, sc, M, prec, _ptr(bins), bins_prec,
+                              reps, ctypes.byref(rep)), ctx)
+    return rep
+
+
+def autotune_reset() -> None:
+    _check(lib().sqc_autotune_reset())
+
+
+def autotune_entries() -> int:
+    return int(lib().sqc_autotune_entries())
 
 
 def search(ctx: int, att: Sequence[Tensor], g: Graph, M: int, R: int, prec: int, bins,
