@@ -9,6 +9,7 @@
 
 #include <climits>
 #include <map>
+#include <mutex>
 
 namespace sqc {
 
@@ -405,6 +406,7 @@ void describe_contraction(Launches &L, const Contraction &c, const std::vector<c
       t.slot_val = reinterpret_cast<double *>(ws + bp.take(kTopRSlots * (size_t)top_r * 8));
       t.slot_idx = reinterpret_cast<uint64_t *>(ws + bp.take(kTopRSlots * (size_t)top_r * 8));
       t.top_r = top_r;
+      t.gather_groups = topr_gather_groups(t.nsub);
       t.top_out = static_cast<double *>(top_dev);
       t.sum_out = static_cast<double *>(sum_dev);
     }
@@ -486,8 +488,16 @@ struct RecursePlan {
   size_t con_base = 0, total = 0;
 };
 
+// Contraction plans of one compute graph by active-bit counts and precision
+// (a recursion's plan depends on nothing else), for callers that plan many
+// recursions of the same graph.
+struct PlanCache {
+  std::mutex mu;
+  std::map<std::pair<std::vector<int>, int>, Contraction> plans;
+};
+
 RecursePlan plan_recursion(const Graph &g, const sqc_tensor *att, const sqc_masks *scope,
-                           uint64_t M, int top_r, sqc_prec prec) {
+                           uint64_t M, int top_r, sqc_prec prec, PlanCache *cache = nullptr) {
   RecursePlan rp;
   std::vector<int> d(g.n_sub);
   for (int i = 0; i < g.n_sub; ++i) d[i] = att[i].n_bits;
@@ -495,7 +505,15 @@ RecursePlan plan_recursion(const Graph &g, const sqc_tensor *att, const sqc_mask
   assign_bins(g.n_sub, d.data(), scope, M, rp.masks.data());
   rp.abits.resize(g.n_sub);
   for (int i = 0; i < g.n_sub; ++i) rp.abits[i] = __builtin_popcountll(rp.masks[i].active);
-  rp.con = plan_for(g, rp.abits, prec);
+  if (cache) {
+    std::lock_guard<std::mutex> lk(cache->mu);
+    auto key = std::make_pair(rp.abits, (int)prec);
+    auto it = cache->plans.find(key);
+    if (it == cache->plans.end()) it = cache->plans.emplace(key, plan_for(g, rp.abits, prec)).first;
+    rp.con = it->second;
+  } else {
+    rp.con = plan_for(g, rp.abits, prec);
+  }
   Bump b;
   rp.ml = layout_merges(b, att, rp.masks.data(), g.n_sub, prec == SQC_F64 ? 8 : 4);
   rp.con_base = b.off;
@@ -540,6 +558,7 @@ namespace sqc {
 struct CircuitTopo {
   Graph g;
   std::vector<sqc_tensor> att;
+  mutable PlanCache plans;
 };
 
 struct PreparedRecursion {
@@ -572,7 +591,7 @@ PreparedPtr prepare_recursion(std::shared_ptr<const CircuitTopo> c, const sqc_ma
   check_storage_prec(bins_prec, "bins_prec");
   if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
   PreparedPtr p(new PreparedRecursion());
-  p->rp = plan_recursion(c->g, c->att.data(), scope, M, top_r, prec);
+  p->rp = plan_recursion(c->g, c->att.data(), scope, M, top_r, prec, &c->plans);
   p->c = std::move(c);
   p->prec = prec;
   p->bins_prec = bins_prec;
@@ -667,6 +686,14 @@ void enqueue_batch(sqc_ctx *ctx, PreparedRecursion *const *p, int n, char *const
     descs.push_back(GroupedDesc{0, pass, GemmSpec{}, at, tab.put(start.data(), start.size()),
                                 (int)jobs.size(), start.back()});
   };
+  // larger jobs first: their work-groups start first and the launch ends sooner
+  auto by_blocks = [](int pass) {
+    return [pass](const MergeArgs &a, const MergeArgs &b) {
+      return merge_pass_blocks(a, pass) > merge_pass_blocks(b, pass);
+    };
+  };
+  std::stable_sort(tiles.begin(), tiles.end(), by_blocks(0));
+  std::stable_sort(rows.begin(), rows.end(), by_blocks(1));
   if (!tiles.empty()) merge_pass(tiles, 0, tab.put(tiles.data(), tiles.size()));
   if (!rows.empty()) {
     const size_t at = tab.put(rows.data(), rows.size());
@@ -683,6 +710,8 @@ void enqueue_batch(sqc_ctx *ctx, PreparedRecursion *const *p, int n, char *const
     for (int i = 0; i < n; ++i)
       if (lv < Ls[i].steps.size()) by_spec[gemm_spec_id(Ls[i].specs[lv])].push_back(i);
     for (auto &kv : by_spec) {
+      std::stable_sort(kv.second.begin(), kv.second.end(),
+                       [&](int a, int b) { return Ls[a].groups[lv] > Ls[b].groups[lv]; });
       std::vector<GemmArgs> jobs;
       std::vector<int64_t> nb;
       for (int i : kv.second) {
@@ -700,8 +729,16 @@ void enqueue_batch(sqc_ctx *ctx, PreparedRecursion *const *p, int n, char *const
   std::vector<TopRArgs> tops;
   for (auto &L : Ls)
     if (L.topr) tops.push_back(L.t);
-  if (!tops.empty())
-    descs.push_back(GroupedDesc{2, 0, GemmSpec{}, tab.put(tops.data(), tops.size()), 0, (int)tops.size(), 0});
+  if (!tops.empty()) {
+    std::stable_sort(tops.begin(), tops.end(),
+                     [](const TopRArgs &a, const TopRArgs &b) { return a.nsub > b.nsub; });
+    std::vector<int64_t> nb;
+    for (auto &t : tops) nb.push_back(t.gather_groups);
+    const std::vector<int> start = block_prefix(nb);
+    const size_t at = tab.put(tops.data(), tops.size());
+    descs.push_back(GroupedDesc{2, 0, GemmSpec{}, at, tab.put(start.data(), start.size()), (int)tops.size(),
+                                start.back()});
+  }
 
   check_hip(hipMemcpyAsync(table_dev, staging, tab.off, hipMemcpyHostToDevice, ctx->stream),
             "hipMemcpyAsync of the batch job table");
@@ -713,7 +750,8 @@ void enqueue_batch(sqc_ctx *ctx, PreparedRecursion *const *p, int n, char *const
       launch_gemm_grouped(d.spec, reinterpret_cast<const GemmArgs *>(table_dev + d.jobs),
                           reinterpret_cast<const int *>(table_dev + d.start), d.n, d.total, ctx->stream);
     else
-      launch_topr_grouped(reinterpret_cast<const TopRArgs *>(table_dev + d.jobs), d.n, ctx->stream);
+      launch_topr_grouped(reinterpret_cast<const TopRArgs *>(table_dev + d.jobs),
+                          reinterpret_cast<const int *>(table_dev + d.start), d.n, d.total, ctx->stream);
     after_launch("batched kernel launch");
   }
 }

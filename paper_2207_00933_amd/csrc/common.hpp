@@ -257,14 +257,18 @@ struct TopRArgs {
   double *slot_val;     // [kTopRSlots][top_r]
   uint64_t *slot_idx;   // [kTopRSlots][top_r]
   int top_r;            // 1 .. SQC_MAX_TOPR
+  int gather_groups;    // work-groups of the gather stage (topr_gather_groups)
   double *top_out;      // top_r x {double, uint64}
   double *sum_out;
 };
-// Work-groups of the gather stage; each leaves its R best in a slot.
+// Work-groups of the gather stage at most; each leaves its R best in a slot.
 constexpr int kTopRSlots = 64;
+// Gather work-groups for a GEMM with nsub sub-tiles (about one per 64).
+int topr_gather_groups(int64_t nsub);
 void launch_topr(const TopRArgs &t, hipStream_t s);
-// n top-R selections from a device table of n TopRArgs, in two launches.
-void launch_topr_grouped(const TopRArgs *jobs_dev, int n, hipStream_t s);
+// n top-R selections from a device table of n TopRArgs, in two launches;
+// job j's gather takes work-groups [start[j], start[j + 1]) of total.
+void launch_topr_grouped(const TopRArgs *jobs_dev, const int *start_dev, int n, int total, hipStream_t s);
 
 void launch_zero(void *p, size_t bytes, hipStream_t s);
 

@@ -462,13 +462,14 @@ __global__ __launch_bounds__(kThreads) void gemm_grouped(const GemmArgs *__restr
 // top-R selection over the final bins.  The final GEMM wrote the maximum of
 // every 32 x 32 sub-tile (sub-tile s = tile * 4 + wave) and, per work-group,
 // the compensated sum and maximum of its contiguous range of tiles.
-//   gather (kGatherGroups work-groups): the GEMM's work-groups are joined
+//   gather (t.gather_groups <= kTopRSlots work-groups, about one per 64
+//     sub-tiles): the GEMM's work-groups are joined
 //     into at most 256 groups of consecutive work-groups; threshold tau = the
 //     R-th largest group maximum (R groups hold a bin >= tau each, so tau is
 //     no larger than the R-th largest bin), found by sorting each wave's
 //     maxima and ranking every maximum against the other waves' sorted lists.
 //     Work-group w then visits the sub-tiles of its runs of 256 (runs w,
-//     w + kGatherGroups, ...) whose maximum reaches tau (and the running R-th
+//     w + gather_groups, ...) whose maximum reaches tau (and the running R-th
 //     best) and keeps its R best bins in an LDS buffer: a bin
 //     enters when it reaches tau and beats the buffer's R-th best so far; a
 //     full buffer is cut back to its R best by a bitonic sort.  Its R best go
@@ -485,7 +486,6 @@ constexpr int kTW = 4;                    // waves of the top-R work-groups
 constexpr int kTThreads = 64 * kTW;
 constexpr int kNG = kTThreads;            // groups of GEMM work-groups
 constexpr int kBufCap = 2048;             // buffered entries per work-group
-constexpr int kGatherGroups = kTopRSlots;
 
 // Exclusive prefix of v over the work-group; `total` gets the sum.
 __device__ int block_scan_excl(int v, int *wsum, int &total) {
@@ -814,7 +814,7 @@ __device__ __forceinline__ void topr_rank_body(const TopRArgs &t) {
   buf.tv = tval;
   buf.ti = tidx;
   // slot entries f = w R + j, j < slot_n[w]
-  const int npos = kGatherGroups * R;
+  const int npos = t.gather_groups * R;
   for (int f0 = 0; f0 < npos; f0 += 4 * kTThreads) {
     double v[4];
     uint64_t ix[4];
@@ -841,9 +841,13 @@ __global__ __launch_bounds__(kTThreads) void topr_gather(TopRArgs t) {
 }
 __global__ __launch_bounds__(kTThreads) void topr_rank(TopRArgs t) { topr_rank_body(t); }
 
-// Batched top-R: kGatherGroups work-groups per job, then one per job.
-__global__ __launch_bounds__(kTThreads) void topr_gather_grouped(const TopRArgs *__restrict__ jobs) {
-  topr_gather_body(jobs[blockIdx.x / kGatherGroups], blockIdx.x % kGatherGroups, kGatherGroups);
+// Batched top-R: job j's gather takes work-groups [start[j], start[j + 1]),
+// then one rank work-group per job.
+__global__ __launch_bounds__(kTThreads) void topr_gather_grouped(const TopRArgs *__restrict__ jobs,
+                                                                 const int *__restrict__ start, int n) {
+  const int j = find_job(start, n, blockIdx.x);
+  const int s0 = start[j];
+  topr_gather_body(jobs[j], (int)blockIdx.x - s0, start[j + 1] - s0);
 }
 __global__ __launch_bounds__(kTThreads) void topr_rank_grouped(const TopRArgs *__restrict__ jobs) {
   topr_rank_body(jobs[blockIdx.x]);
@@ -1049,12 +1053,17 @@ int launch_gemm(const GemmArgs &g_in, int prec, hipStream_t s) {
 }
 
 void launch_topr(const TopRArgs &t, hipStream_t s) {
-  hipLaunchKernelGGL(topr_gather, dim3(kGatherGroups), dim3(kTThreads), 0, s, t);
+  hipLaunchKernelGGL(topr_gather, dim3((unsigned)t.gather_groups), dim3(kTThreads), 0, s, t);
   hipLaunchKernelGGL(topr_rank, dim3(1), dim3(kTThreads), 0, s, t);
 }
 
-void launch_topr_grouped(const TopRArgs *jobs, int n, hipStream_t s) {
-  hipLaunchKernelGGL(topr_gather_grouped, dim3((unsigned)(n * kGatherGroups)), dim3(kTThreads), 0, s, jobs);
+int topr_gather_groups(int64_t nsub) {
+  const int64_t g = (nsub + 63) / 64;
+  return (int)(g < 1 ? 1 : (g > kTopRSlots ? kTopRSlots : g));
+}
+
+void launch_topr_grouped(const TopRArgs *jobs, const int *start, int n, int total, hipStream_t s) {
+  hipLaunchKernelGGL(topr_gather_grouped, dim3((unsigned)total), dim3(kTThreads), 0, s, jobs, start, n);
   hipLaunchKernelGGL(topr_rank_grouped, dim3((unsigned)n), dim3(kTThreads), 0, s, jobs);
 }
 

@@ -222,8 +222,17 @@ __device__ __forceinline__ void merge_finish_body(const MergeArgs &a, int64_t bl
   const int64_t nb = int64_t(1) << a.abits;
   const int P = 1 << a.ysplit_bits;
   for (int64_t c = blk * kThreads + threadIdx.x; c < NC; c += nblk * kThreads) {
+    // partials added in ascending order; eight loads in flight at a time
     double s = 0.0;
-    for (int q = 0; q < P; ++q) s += a.partial[int64_t(q) * NC + c];
+    int q = 0;
+    for (; q + 8 <= P; q += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = a.partial[int64_t(q + u) * NC + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; q < P; ++q) s += a.partial[int64_t(q) * NC + c];
     int64_t o = (c & (L - 1)) * nb + (c >> a.lbits);
     if (a.out_f32) static_cast<float *>(a.out)[o] = (float)s;
     else static_cast<double *>(a.out)[o] = s;
