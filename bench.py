@@ -389,8 +389,9 @@ def main():
                     help="target CPU work per worker for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precs", default="f64,f32,bf16x3")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="launch the contraction steps with the default launch choices")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the contraction launches (sqc_autotune) before timing; off by default "
+                         "so that a kernel trace of the command holds only the timed launches")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving leg (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -416,7 +417,7 @@ def main():
     precs = [p for p in args.precs.split(",") if p]
     if args.calib_copy_mb > 0:
         calib_copy(args.calib_copy_mb)
-    gpu = run_gpu(cc, var32, args.steps, args.warmup, precs, autotune=not args.no_autotune)
+    gpu = run_gpu(cc, var32, args.steps, args.warmup, precs, autotune=args.autotune)
     serving = run_serving(args.serve_requests, args.serve_slots) if args.serve_requests > 0 else None
     fast = [p for p in ("bf16x3", "f32") if p in gpu]
     head = max(fast, key=lambda p: gpu[p]["bins_per_s"]) if fast else precs[0]
