@@ -95,18 +95,32 @@ def cpu_baseline(cc, var32, seconds: float):
 # GPU
 # ---------------------------------------------------------------------------
 
-def run_gpu(cc, var32, steps: int, warmup: int, precs, autotune: bool = True):
+def run_gpu(cc, var32, steps: int, warmup: int, precs, autotune: bool = True, graph: bool = True):
     import torch
-    from paper_2207_00933_amd import runner, sqc
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU (the HIP library is the only compute path)")
+    # a created stream: the steps can then also be recorded into a HIP graph
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        return _run_gpu(cc, var32, steps, warmup, precs, autotune, graph)
+
+
+def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph):
+    import torch
+    from paper_2207_00933_amd import runner, sqc
+
     s = runner.Session(0, 64 << 20)
     circ = runner.Circuit.from_cut_circuit(s, cc, var32, sqc.F32)
     nbits = cc.n
     M = 1 << nbits
     out = {}
     ref_bins = None
+    # bring the device to steady clocks (and every lazy initialisation) before
+    # the first timed loop
+    for _ in range(20):
+        circ.attribute(sqc.F32)
+    torch.cuda.synchronize()
     for pname in precs:
         prec = PREC_ID[pname]
         att_prec = sqc.F64 if prec == sqc.F64 else sqc.F32
@@ -158,6 +172,24 @@ def run_gpu(cc, var32, steps: int, warmup: int, precs, autotune: bool = True):
             "bins_sum": rec.sum.item(),
             "autotune": tune,
         }
+        if graph:
+            # the same step recorded once into a HIP graph and replayed: one
+            # launch per step instead of one per kernel
+            torch.cuda.synchronize()
+            sqc.graph_begin(s.ctx)
+            step()
+            g = sqc.graph_end(s.ctx)
+            for _ in range(warmup):
+                sqc.graph_launch(s.ctx, g)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                sqc.graph_launch(s.ctx, g)
+            torch.cuda.synchronize()
+            gms = (time.perf_counter() - t0) * 1e3 / steps
+            sqc.graph_destroy(g)
+            res["graph"] = {"ms_per_step": gms, "bins_per_s": M / (gms * 1e-3)}
+            log(f"[bench] {pname}: graph replay {gms:.4f} ms/step, {M / (gms * 1e-3):.3e} bins/s")
         b = rec.bins.double()
         if prec == sqc.F64:
             ref_bins = b.clone()
@@ -392,6 +424,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="tune the contraction launches (sqc_autotune) before timing; off by default "
                          "so that a kernel trace of the command holds only the timed launches")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the HIP-graph replay measurement of the step")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving leg (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -417,7 +451,8 @@ def main():
     precs = [p for p in args.precs.split(",") if p]
     if args.calib_copy_mb > 0:
         calib_copy(args.calib_copy_mb)
-    gpu = run_gpu(cc, var32, args.steps, args.warmup, precs, autotune=args.autotune)
+    gpu = run_gpu(cc, var32, args.steps, args.warmup, precs, autotune=args.autotune,
+                  graph=not args.no_graph)
     serving = run_serving(args.serve_requests, args.serve_slots) if args.serve_requests > 0 else None
     fast = [p for p in ("bf16x3", "f32") if p in gpu]
     head = max(fast, key=lambda p: gpu[p]["bins_per_s"]) if fast else precs[0]

@@ -311,6 +311,27 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
                        sqc_prec bins_prec, sqc_masks *masks_out,
                        void *topr_dev, void *sum_dev);
 
+/* ---- HIP graphs of enqueued work (not part of the paper) ----------------------- */
+
+/* Record the work later calls enqueue on the context's stream (sqc_attribute,
+ * sqc_attribute_all, sqc_merge, sqc_contract, sqc_recurse) into a HIP graph
+ * instead of running it, then replay it with one launch.  For repeated
+ * queries whose buffers do not change (the graph keeps every pointer and
+ * argument of the recorded calls, including the workspace, so the caller
+ * keeps them alive and unchanged in size until sqc_graph_destroy).  The
+ * context must use a created stream (stream capture is not allowed on the
+ * default stream).  Stage timing is suspended while recording; calls that
+ * wait for the device (sqc_search, sqc_autotune, sqc_ctx_timing) and
+ * sqc_ctx_set_stream fail with SQC_E_ARG while recording.  The recorded work
+ * contains no memset nodes.  A failed call while recording leaves the capture
+ * invalid: sqc_graph_end then fails. */
+typedef struct sqc_graph sqc_graph;
+sqc_status sqc_graph_begin(sqc_ctx *ctx);
+sqc_status sqc_graph_end(sqc_ctx *ctx, sqc_graph **out);
+/* Enqueue one replay on the context's stream. */
+sqc_status sqc_graph_launch(sqc_ctx *ctx, const sqc_graph *graph);
+sqc_status sqc_graph_destroy(sqc_graph *graph);
+
 /* ---- launch tuning (not part of the paper) ------------------------------------ */
 
 /* A project-side autotuner of the contraction launches.  For the recursion

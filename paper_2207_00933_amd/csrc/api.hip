@@ -40,6 +40,8 @@ struct sqc_ctx {
   double *unit = nullptr;  // device: double 1.0 then float 1.0 (one-element tensor)
   // stage timing
   uint32_t timing_mask = 0;
+  uint32_t saved_mask = 0;  // timing mask suspended while a graph is recorded
+  bool recording = false;
   struct Mark {
     int stage;
     hipEvent_t a, b;
@@ -839,9 +841,74 @@ sqc_status sqc_ctx_destroy(sqc_ctx *ctx) {
 
 sqc_status sqc_ctx_set_stream(sqc_ctx *ctx, void *hip_stream) {
   SQC_TRY(ctx)
+  if (ctx->recording) raise(SQC_E_ARG, "the stream cannot change while a graph is recorded");
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   return SQC_OK;
   SQC_CATCH(ctx)
+}
+
+// ---- HIP graphs of enqueued work ----
+
+struct sqc_graph {
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+sqc_status sqc_graph_begin(sqc_ctx *ctx) {
+  SQC_TRY(ctx)
+  if (!ctx->stream) raise(SQC_E_ARG, "graph recording needs a created stream (not the default stream)");
+  if (ctx->recording) raise(SQC_E_ARG, "a graph is already being recorded on this context");
+  use_device(ctx);
+  check_hip(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+  ctx->saved_mask = ctx->timing_mask;
+  ctx->timing_mask = 0;
+  ctx->recording = true;
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_graph_end(sqc_ctx *ctx, sqc_graph **out) {
+  SQC_TRY(ctx)
+  if (!ctx->recording) raise(SQC_E_ARG, "no graph is being recorded on this context");
+  use_device(ctx);
+  ctx->recording = false;
+  ctx->timing_mask = ctx->saved_mask;
+  hipGraph_t graph = nullptr;
+  check_hip(hipStreamEndCapture(ctx->stream, &graph), "hipStreamEndCapture");
+  if (!out) {
+    (void)hipGraphDestroy(graph);
+    raise(SQC_E_ARG, "out is NULL");
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  check_hip(e, "hipGraphInstantiate");
+  sqc_graph *g = new sqc_graph();
+  g->exec = exec;
+  g->device = ctx->device;
+  *out = g;
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_graph_launch(sqc_ctx *ctx, const sqc_graph *g) {
+  SQC_TRY(ctx)
+  if (!g || !g->exec) raise(SQC_E_ARG, "graph is NULL");
+  if (g->device != ctx->device) raise(SQC_E_ARG, "graph was recorded on another device");
+  use_device(ctx);
+  check_hip(hipGraphLaunch(g->exec, ctx->stream), "hipGraphLaunch");
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_graph_destroy(sqc_graph *g) {
+  if (!g) return SQC_E_ARG;
+  if (g->exec) {
+    (void)hipSetDevice(g->device);
+    (void)hipGraphExecDestroy(g->exec);
+  }
+  delete g;
+  return SQC_OK;
 }
 
 sqc_status sqc_ctx_set_timing(sqc_ctx *ctx, uint32_t stage_mask) {
@@ -853,6 +920,7 @@ sqc_status sqc_ctx_set_timing(sqc_ctx *ctx, uint32_t stage_mask) {
 
 sqc_status sqc_ctx_timing(sqc_ctx *ctx, uint32_t stage, int32_t reset, sqc_stage_time *out) {
   SQC_TRY(ctx)
+  if (ctx->recording) raise(SQC_E_ARG, "stage timing cannot be read while a graph is recorded");
   int q = stage_index(stage);
   if (q < 0 || !out) raise(SQC_E_ARG, "stage must be one SQC_STAGE_* bit and out non-NULL");
   use_device(ctx);
@@ -1100,6 +1168,7 @@ sqc_status sqc_autotune(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_su
                         int32_t n_cuts, const sqc_masks *scope, uint64_t max_bins_M, sqc_prec prec,
                         void *bins_dev, sqc_prec bins_prec, int32_t reps, sqc_tune_report *report) {
   SQC_TRY(ctx)
+  if (ctx->recording) raise(SQC_E_ARG, "sqc_autotune waits for the device and cannot be recorded");
   Graph g = build_topology(n_sub, cuts, n_cuts);
   if (!attributed || !bins_dev) raise(SQC_E_ARG, "NULL argument");
   if (reps < 1 || reps > 100) raise(SQC_E_ARG, "reps must be in [1, 100]");
@@ -1188,6 +1257,7 @@ sqc_status sqc_search(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
                       uint64_t *solution_states, int32_t max_solutions, int32_t *n_solutions,
                       sqc_recursion_info *info, int32_t *n_recursions) {
   SQC_TRY(ctx)
+  if (ctx->recording) raise(SQC_E_ARG, "sqc_search waits for the device and cannot be recorded");
   Graph g = build_topology(n_sub, cuts, n_cuts);
   if (!attributed || !bins_dev || !n_solutions || !n_recursions) raise(SQC_E_ARG, "NULL argument");
   if (max_solutions > 0 && (!solutions || !solution_states)) raise(SQC_E_ARG, "NULL solution buffers");

@@ -156,6 +156,10 @@ def lib():
             "sqc_autotune": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32, POINTER(Masks),
                                      c_uint64, c_int, P, c_int, c_int32, POINTER(TuneReport)]),
             "sqc_autotune_reset": (c_int, []),
+            "sqc_graph_begin": (c_int, [P]),
+            "sqc_graph_end": (c_int, [P, POINTER(P)]),
+            "sqc_graph_launch": (c_int, [P, P]),
+            "sqc_graph_destroy": (c_int, [P]),
             "sqc_autotune_entries": (c_int32, []),
             "sqc_serve_create": (c_int, [c_int, c_int32, P, c_size_t, POINTER(P)]),
             "sqc_serve_destroy": (c_int, [P]),
@@ -403,6 +407,24 @@ def autotune(ctx: int, att: Sequence[Tensor], g: Graph, scope, M: int, prec: int
     _check(lib().sqc_autotune(ctx, arr, g.n_sub, g.cuts, g.n_cuts, sc, M, prec, _ptr(bins), bins_prec,
                               reps, ctypes.byref(rep)), ctx)
     return rep
+
+
+def graph_begin(ctx: int) -> None:
+    _check(lib().sqc_graph_begin(ctx), ctx)
+
+
+def graph_end(ctx: int) -> int:
+    h = c_void_p()
+    _check(lib().sqc_graph_end(ctx, ctypes.byref(h)), ctx)
+    return h.value
+
+
+def graph_launch(ctx: int, graph: int) -> None:
+    _check(lib().sqc_graph_launch(ctx, graph), ctx)
+
+
+def graph_destroy(graph: int) -> None:
+    _check(lib().sqc_graph_destroy(graph))
 
 
 def autotune_reset() -> None:
