@@ -207,11 +207,12 @@ int launch_gemm(const GemmArgs &g, int prec, hipStream_t s);
 // (precision path, FP64 fold of K stages, FP32 output, regular shape)...
 struct GemmSpec {
   int prec;
-  bool fold, outf, reg;
+  bool fold, outf;
+  int reg;  // 0 general, 1 regular shape, 2 regular with single-run index maps
 };
 // ...chosen after filling g's offset tables,
 GemmSpec prepare_gemm(GemmArgs &g, int prec);
-// a dense id of it (0 .. 23),
+// a dense id of it (0 .. 35),
 int gemm_spec_id(const GemmSpec &sp);
 // the work-groups launch_gemm would use (results, including the work-group
 // statistics, depend on this count),

@@ -126,11 +126,22 @@ __device__ __forceinline__ Sched schedule(int ntiles, int b, int G) {
 // (one chunk of 2^6 labels) is folded into FP64 with Neumaier compensation.
 // Otherwise the FP32 accumulator is the result.
 // OUTF: FP32 result (else FP64).
-// REG: M, N, K >= 64 and the lowest run of k spans >= 4 bits, so no tile,
+// REG (1 or 2): M, N, K >= 64 and the lowest run of k spans >= 4 bits, so no tile,
 // row or element needs a bound check and k rows are shifts.
 // One work-group `blk` of G working on the GEMM `g`.
-template <int PREC, bool FOLD, bool OUTF, bool REG>
+// REG = 2 adds: every index map is a single run of bits, so each offset is
+// one shift (no loop over runs in the per-tile address arithmetic).
+template <int PREC, bool FOLD, bool OUTF, int REG>
 __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
+  constexpr bool SIMPLE = REG == 2;
+  auto mx = [&](const IndexMap &mp, uint32_t v) -> int64_t {
+    if constexpr (SIMPLE) return (int64_t)v << mp.lx[0];
+    else return map_x(mp, v);
+  };
+  auto my = [&](const IndexMap &mp, uint32_t v) -> int64_t {
+    if constexpr (SIMPLE) return (int64_t)v << mp.ly[0];
+    else return map_y(mp, v);
+  };
   typedef typename Tr<PREC>::T T;
   typedef typename Tr<PREC>::Acc Acc;
   constexpr int NACC = Tr<PREC>::NACC;
@@ -188,10 +199,10 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
 
   // staging: the thread holds column `lane` (m of A, n of B) of the tile at
   // the 16 k rows 16 wave + j
-  const int64_t a_lane = map_x(g.m, lane);
-  const int64_t b_lane = map_x(g.n, lane);
-  const int64_t a_kw = map_x(g.k, 16 * wave);
-  const int64_t b_kw = map_y(g.k, 16 * wave);
+  const int64_t a_lane = mx(g.m, lane);
+  const int64_t b_lane = mx(g.n, lane);
+  const int64_t a_kw = mx(g.k, 16 * wave);
+  const int64_t b_kw = my(g.k, 16 * wave);
   T av[NJ], bv[NJ];
   // k offsets of rows j = 0..15: shifts when the lowest run of k spans >= 4
   // bits (the usual case), else a table staged in LDS
@@ -228,7 +239,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
     const uint32_t m0 = tile_m(tile) << 6;
     const uint32_t k0 = (uint32_t)ks << 6;
     const bool ok = REG || m0 + lane < M;  // columns past M read the column origin
-    const T *p = static_cast<const T *>(g.A) + (map_x(g.m, m0) + map_x(g.k, k0) + a_kw) + (ok ? a_lane : 0);
+    const T *p = static_cast<const T *>(g.A) + (mx(g.m, m0) + mx(g.k, k0) + a_kw) + (ok ? a_lane : 0);
     load_rows(p, av, 0, sa, k0);
     if (!ok)
 #pragma unroll
@@ -238,7 +249,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
     const uint32_t n0 = tile_n(tile) << 6;
     const uint32_t k0 = (uint32_t)ks << 6;
     const bool ok = REG || n0 + lane < N;
-    const T *p = static_cast<const T *>(g.B) + (map_x(g.n, n0) + map_y(g.k, k0) + b_kw) + (ok ? b_lane : 0);
+    const T *p = static_cast<const T *>(g.B) + (mx(g.n, n0) + my(g.k, k0) + b_kw) + (ok ? b_lane : 0);
     load_rows(p, bv, 1, sb, k0);
     if (!ok)
 #pragma unroll
@@ -326,11 +337,11 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   // per-lane parts of the result offsets
   int64_t c_lane_m, c_lane_n;
   if constexpr (PREC == SQC_F64) {
-    c_lane_m = map_y(g.m, lane & 15);
-    c_lane_n = map_y(g.n, lane >> 4);
+    c_lane_m = my(g.m, lane & 15);
+    c_lane_n = my(g.n, lane >> 4);
   } else {
-    c_lane_m = map_y(g.m, lane & 31);
-    c_lane_n = map_y(g.n, 4 * (lane >> 5));
+    c_lane_m = my(g.m, lane & 31);
+    c_lane_n = my(g.n, 4 * (lane >> 5));
   }
   reset();
 
@@ -377,7 +388,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
       const uint32_t nw = (tile_n(cur_tile) << 6) + wn * 32;
       double lsum = 0.0, lmax = -INFINITY;
       if (REG || (mw < M && nw < N)) {
-        const int64_t cw = map_y(g.m, mw) + map_y(g.n, nw);
+        const int64_t cw = my(g.m, mw) + my(g.n, nw);
         typedef typename std::conditional<OUTF, float, double>::type O;
         O *C = static_cast<O *>(g.C) + cw + c_lane_m + c_lane_n;
         // with M, N >= 32 every element of a wave inside the result is inside
@@ -398,8 +409,9 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const uint32_t nl = 16 * jn + 4 * r;
-                put(16 * im + (lane & 15), nl + (lane >> 4), (im ? g.coff_m16 : 0) + g.coff_n[4 * jn + r],
-                    acc[2 * jn + im][r]);
+                const int64_t om = SIMPLE ? (int64_t)(16 * im) << g.m.ly[0] : (im ? g.coff_m16 : 0);
+                const int64_t on = SIMPLE ? (int64_t)nl << g.n.ly[0] : g.coff_n[4 * jn + r];
+                put(16 * im + (lane & 15), nl + (lane >> 4), om + on, acc[2 * jn + im][r]);
               }
         } else {
 #pragma unroll
@@ -408,7 +420,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
             double v;
             if constexpr (FOLD) v = S[r] + Cc[r];
             else v = (double)acc[0][r];
-            put(lane & 31, nl + 4 * (lane >> 5), g.coff_n[r], v);
+            put(lane & 31, nl + 4 * (lane >> 5), SIMPLE ? (int64_t)nl << g.n.ly[0] : g.coff_n[r], v);
           }
         }
         lmax = (double)omax;
@@ -430,7 +442,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   write_wg_stats();
 }
 
-template <int PREC, bool FOLD, bool OUTF, bool REG>
+template <int PREC, bool FOLD, bool OUTF, int REG>
 __global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
   gemm_body<PREC, FOLD, OUTF, REG>(g, blockIdx.x, gridDim.x);
 }
@@ -450,7 +462,7 @@ __device__ __forceinline__ int find_job(const int *__restrict__ start, int n, in
 // Several GEMMs of one specialisation in one launch (requests batched by the
 // serving engine): job j owns work-groups [start[j], start[j + 1]) and runs
 // exactly as the single launch with start[j + 1] - start[j] work-groups.
-template <int PREC, bool FOLD, bool OUTF, bool REG>
+template <int PREC, bool FOLD, bool OUTF, int REG>
 __global__ __launch_bounds__(kThreads) void gemm_grouped(const GemmArgs *__restrict__ jobs,
                                                           const int *__restrict__ start, int n) {
   const int j = find_job(start, n, blockIdx.x);
@@ -882,7 +894,7 @@ int64_t host_map(const IndexMap &m, uint32_t idx, bool y) {
 }
 
 // Work-groups of one kernel resident on the device at once.
-template <int PREC, bool FOLD, bool OUTF, bool REG>
+template <int PREC, bool FOLD, bool OUTF, int REG>
 int resident_groups() {
   static int cached[64] = {0};
   int dev = 0;
@@ -900,10 +912,15 @@ int resident_groups() {
 }
 
 // Calls L::run<PREC, FOLD, OUTF, REG>() for the specialisation `sp`.
+template <int PREC, bool FOLD, bool OUTF, class L>
+int dispatch_r(const GemmSpec &sp, const L &l) {
+  if (sp.reg == 2) return l.template run<PREC, FOLD, OUTF, 2>();
+  if (sp.reg == 1) return l.template run<PREC, FOLD, OUTF, 1>();
+  return l.template run<PREC, FOLD, OUTF, 0>();
+}
 template <int PREC, bool FOLD, class L>
 int dispatch_o(const GemmSpec &sp, const L &l) {
-  if (sp.outf) return sp.reg ? l.template run<PREC, FOLD, true, true>() : l.template run<PREC, FOLD, true, false>();
-  return sp.reg ? l.template run<PREC, FOLD, false, true>() : l.template run<PREC, FOLD, false, false>();
+  return sp.outf ? dispatch_r<PREC, FOLD, true>(sp, l) : dispatch_r<PREC, FOLD, false>(sp, l);
 }
 template <class L>
 int dispatch(const GemmSpec &sp, const L &l) {
@@ -914,7 +931,7 @@ int dispatch(const GemmSpec &sp, const L &l) {
 
 struct GroupsQuery {
   int64_t tiles;
-  template <int PREC, bool FOLD, bool OUTF, bool REG>
+  template <int PREC, bool FOLD, bool OUTF, int REG>
   int run() const {
     int64_t cap = resident_groups<PREC, FOLD, OUTF, REG>();
     if (cap > kMaxGemmGroups) cap = kMaxGemmGroups;
@@ -926,7 +943,7 @@ struct DirectLaunch {
   const GemmArgs &g;
   int groups;
   hipStream_t s;
-  template <int PREC, bool FOLD, bool OUTF, bool REG>
+  template <int PREC, bool FOLD, bool OUTF, int REG>
   int run() const {
     hipLaunchKernelGGL((gemm<PREC, FOLD, OUTF, REG>), dim3((unsigned)groups), dim3(kThreads), 0, s, g);
     return groups;
@@ -938,7 +955,7 @@ struct GroupedLaunch {
   const int *start;
   int n, total;
   hipStream_t s;
-  template <int PREC, bool FOLD, bool OUTF, bool REG>
+  template <int PREC, bool FOLD, bool OUTF, int REG>
   int run() const {
     hipLaunchKernelGGL((gemm_grouped<PREC, FOLD, OUTF, REG>), dim3((unsigned)total), dim3(kThreads), 0, s,
                        jobs, start, n);
@@ -963,12 +980,14 @@ GemmSpec prepare_gemm(GemmArgs &g, int prec) {
   // a chunk is one K stage
   sp.fold = prec != SQC_F64 && g.final_step && g.kbits > 6;
   sp.outf = g.out_f32 != 0;
-  sp.reg = g.mbits >= 6 && g.nbits >= 6 && g.kbits >= 6 && g.k.nruns >= 1 && g.k.bits[0] >= 4;
+  const bool regular = g.mbits >= 6 && g.nbits >= 6 && g.kbits >= 6 && g.k.nruns >= 1 && g.k.bits[0] >= 4;
+  const bool simple = g.m.nruns == 1 && g.n.nruns == 1 && g.k.nruns == 1;
+  sp.reg = regular ? (simple ? 2 : 1) : 0;
   return sp;
 }
 
 int gemm_spec_id(const GemmSpec &sp) {
-  return ((sp.prec * 2 + (sp.fold ? 1 : 0)) * 2 + (sp.outf ? 1 : 0)) * 2 + (sp.reg ? 1 : 0);
+  return ((sp.prec * 2 + (sp.fold ? 1 : 0)) * 2 + (sp.outf ? 1 : 0)) * 3 + sp.reg;
 }
 
 int gemm_groups(const GemmArgs &g, const GemmSpec &sp) { return dispatch(sp, GroupsQuery{gemm_tiles(g)}); }
