@@ -71,6 +71,14 @@ __device__ __forceinline__ void neumaier(double &s, double &c, double x) {
   s = t;
 }
 
+// Merge a compensated pair (s2, c2) into (s, c).
+__device__ __forceinline__ void two_sum_merge(double &s, double &c, double s2, double c2) {
+  const double t = s + s2;
+  const double err = fabs(s) >= fabs(s2) ? (s - t) + s2 : (s2 - t) + s;
+  s = t;
+  c += c2 + err;
+}
+
 // lexicographic "better": larger value, then lower index
 __device__ __forceinline__ bool better(double v1, uint64_t i1, double v2, uint64_t i2) {
   return v1 > v2 || (v1 == v2 && i1 < i2);
@@ -169,14 +177,21 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   auto tile_m = [&](int t) -> uint32_t { return nmaj ? (uint32_t)(t & ((1 << lmt) - 1)) : (uint32_t)(t >> lnt); };
   auto tile_n = [&](int t) -> uint32_t { return nmaj ? (uint32_t)(t >> lmt) : (uint32_t)(t & ((1 << lnt) - 1)); };
   const Sched sc = schedule(1 << (lmt + lnt), blk, G);
-  // work-group statistics: running compensated sum and maximum of its waves
+  // work-group statistics: each lane keeps a compensated running sum of its
+  // elements over the work-group's tiles (merged across lanes and waves once,
+  // at the end) and the maximum of the sub-tiles it took part in
   __shared__ double wg_part[3][4];
   double wsum = 0.0, wcmp = 0.0, wmax = -INFINITY;
   auto write_wg_stats = [&]() {
     if (!g.stats) return;
+    double s = wsum, c = wcmp;
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double s2 = __shfl_xor(s, off), c2 = __shfl_xor(c, off);
+      two_sum_merge(s, c, s2, c2);
+    }
     if (lane == 0) {
-      wg_part[0][wave] = wsum;
-      wg_part[1][wave] = wcmp;
+      wg_part[0][wave] = s;
+      wg_part[1][wave] = c;
       wg_part[2][wave] = wmax;
     }
     __syncthreads();
@@ -386,10 +401,11 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
     if (cur_ks == nks - 1) {
       const uint32_t mw = (tile_m(cur_tile) << 6) + wm * 32;  // wave origin
       const uint32_t nw = (tile_n(cur_tile) << 6) + wn * 32;
-      double lsum = 0.0, lmax = -INFINITY;
+      typedef typename std::conditional<OUTF, float, double>::type O;
+      double lsum = 0.0;
+      O lmax = -INFINITY;
       if (REG || (mw < M && nw < N)) {
         const int64_t cw = my(g.m, mw) + my(g.n, nw);
-        typedef typename std::conditional<OUTF, float, double>::type O;
         O *C = static_cast<O *>(g.C) + cw + c_lane_m + c_lane_n;
         // with M, N >= 32 every element of a wave inside the result is inside
         const bool whole = REG || (g.mbits >= 5 && g.nbits >= 5);
@@ -423,16 +439,14 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
             put(lane & 31, nl + 4 * (lane >> 5), SIMPLE ? (int64_t)nl << g.n.ly[0] : g.coff_n[r], v);
           }
         }
-        lmax = (double)omax;
+        lmax = omax;
       }
       if (g.stats) {
-        for (int off = 32; off >= 1; off >>= 1) {
-          lsum += __shfl_xor(lsum, off);
-          lmax = fmax(lmax, __shfl_xor(lmax, off));
-        }
-        if (lane == 0) g.blk_max[(int64_t)cur_tile * 4 + wave] = lmax;
+        // sub-tile maximum in the stored type (one shuffle per step)
+        for (int off = 32; off >= 1; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
+        if (lane == 0) g.blk_max[(int64_t)cur_tile * 4 + wave] = (double)lmax;
         neumaier(wsum, wcmp, lsum);
-        wmax = fmax(wmax, lmax);
+        wmax = fmax(wmax, (double)lmax);
       }
       reset();
     }
@@ -520,12 +534,6 @@ __device__ int block_scan_excl(int v, int *wsum, int &total) {
   return before + incl - v;
 }
 
-__device__ __forceinline__ void two_sum_merge(double &s, double &c, double s2, double c2) {
-  const double t = s + s2;
-  const double err = fabs(s) >= fabs(s2) ? (s - t) + s2 : (s2 - t) + s;
-  s = t;
-  c += c2 + err;
-}
 
 // origin (m0, n0) of sub-tile sb of a GEMM with 2^lmt m tiles and 2^lnt n
 // tiles in the given tile order
