@@ -138,7 +138,9 @@ sqc_status sqc_ctx_set_stream(sqc_ctx *ctx, void *hip_stream);
  * initialisation, and the call is cheap enough to make before every request. */
 sqc_status sqc_ctx_set_workspace(sqc_ctx *ctx, void *dev, size_t bytes);
 /* Stage timing.  With a non-zero mask, every kernel launch of the selected
- * stages is bracketed by HIP events on the context's stream, and the library
+ * stages is bracketed by HIP events on the context's stream (for the
+ * contraction stages, events recorded by the kernel's dispatch itself through
+ * hipExtLaunchKernel, so they span its execution only), and the library
  * adds the launch's algorithmic bytes (inputs read once, outputs written once)
  * and useful flops (2 M N K per GEMM) to the stage's totals. */
 #define SQC_STAGE_ATTRIBUTE 1u

@@ -144,19 +144,24 @@ struct StageMark {
   sqc_ctx *ctx;
   uint32_t stage;
   bool on;
+  bool external;
   hipEvent_t a{}, b{};
   double bytes, flops;
-  StageMark(sqc_ctx *c, uint32_t st, double by, double fl)
-      : ctx(c), stage(st), on((c->timing_mask & st) != 0), bytes(by), flops(fl) {
+  // by_launch: the launch itself records a and b (hipExtLaunchKernel), so
+  // the span is the kernel's execution without the gap before its dispatch
+  StageMark(sqc_ctx *c, uint32_t st, double by, double fl, bool by_launch = false)
+      : ctx(c), stage(st), on((c->timing_mask & st) != 0), external(by_launch), bytes(by), flops(fl) {
     if (on) {
       a = take_event(ctx);
       b = take_event(ctx);
-      check_hip(hipEventRecord(a, ctx->stream), "hipEventRecord");
+      if (!external) check_hip(hipEventRecord(a, ctx->stream), "hipEventRecord");
     }
   }
+  hipEvent_t start() const { return on && external ? a : nullptr; }
+  hipEvent_t stop() const { return on && external ? b : nullptr; }
   void done() {
     if (!on) return;
-    check_hip(hipEventRecord(b, ctx->stream), "hipEventRecord");
+    if (!external) check_hip(hipEventRecord(b, ctx->stream), "hipEventRecord");
     ctx->marks.push_back(sqc_ctx::Mark{stage_index(stage), a, b, bytes, flops});
     on = false;
   }
@@ -422,8 +427,8 @@ void run_direct(sqc_ctx *ctx, const Launches &L) {
   for (size_t si = 0; si < n; ++si) {
     const GemmArgs &g = L.steps[si];
     StageMark mark(ctx, si + 1 == n ? SQC_STAGE_FINAL : SQC_STAGE_CONTRACT, gemm_bytes(g, L.path_f32),
-                   gemm_flops(g));
-    launch_gemm_spec(g, L.specs[si], L.groups[si], ctx->stream);
+                   gemm_flops(g), true);
+    launch_gemm_spec(g, L.specs[si], L.groups[si], ctx->stream, mark.start(), mark.stop());
     after_launch("contraction kernel launch");
     mark.done();
   }

@@ -220,8 +220,10 @@ int gemm_groups(const GemmArgs &g, const GemmSpec &sp);
 // the resident work-group capacity of the specialisation (at most
 // kMaxGemmGroups),
 int gemm_resident_cap(const GemmSpec &sp);
-// one launch,
-void launch_gemm_spec(const GemmArgs &g, const GemmSpec &sp, int groups, hipStream_t s);
+// one launch (with start / stop events recorded by the dispatch itself when
+// given: they time the kernel's execution, without the launch gap),
+void launch_gemm_spec(const GemmArgs &g, const GemmSpec &sp, int groups, hipStream_t s,
+                      hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // and n GEMMs of one specialisation in one launch from a device table: job j
 // takes work-groups [start[j], start[j + 1]) of `total` = start[n].
 void launch_gemm_grouped(const GemmSpec &sp, const GemmArgs *jobs_dev, const int *start_dev, int n,

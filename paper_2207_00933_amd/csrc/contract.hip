@@ -27,6 +27,8 @@
 // result store run along m, the contiguous output axis.
 #include "common.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <mutex>
 #include <type_traits>
 #include <unordered_map>
@@ -951,9 +953,14 @@ struct DirectLaunch {
   const GemmArgs &g;
   int groups;
   hipStream_t s;
+  hipEvent_t start, stop;
   template <int PREC, bool FOLD, bool OUTF, int REG>
   int run() const {
-    hipLaunchKernelGGL((gemm<PREC, FOLD, OUTF, REG>), dim3((unsigned)groups), dim3(kThreads), 0, s, g);
+    if (start)  // events recorded by the dispatch itself: the kernel's own span
+      hipExtLaunchKernelGGL((gemm<PREC, FOLD, OUTF, REG>), dim3((unsigned)groups), dim3(kThreads), 0, s, start,
+                            stop, 0, g);
+    else
+      hipLaunchKernelGGL((gemm<PREC, FOLD, OUTF, REG>), dim3((unsigned)groups), dim3(kThreads), 0, s, g);
     return groups;
   }
 };
@@ -1062,8 +1069,9 @@ size_t gemm_tune_size() {
   return tune_table.size();
 }
 
-void launch_gemm_spec(const GemmArgs &g, const GemmSpec &sp, int groups, hipStream_t s) {
-  dispatch(sp, DirectLaunch{g, groups, s});
+void launch_gemm_spec(const GemmArgs &g, const GemmSpec &sp, int groups, hipStream_t s, hipEvent_t start,
+                      hipEvent_t stop) {
+  dispatch(sp, DirectLaunch{g, groups, s, start, stop});
 }
 
 void launch_gemm_grouped(const GemmSpec &sp, const GemmArgs *jobs, const int *start, int n, int total,
