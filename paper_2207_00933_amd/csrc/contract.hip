@@ -494,8 +494,8 @@ __global__ __launch_bounds__(kThreads) void gemm_grouped(const GemmArgs *__restr
 //     sub-tiles): the GEMM's work-groups are joined
 //     into at most 256 groups of consecutive work-groups; threshold tau = the
 //     R-th largest group maximum (R groups hold a bin >= tau each, so tau is
-//     no larger than the R-th largest bin), found by sorting each wave's
-//     maxima and ranking every maximum against the other waves' sorted lists.
+//     no larger than the R-th largest bin), found by counting, for every
+//     group, the groups better than it.
 //     Work-group w then visits the sub-tiles of its runs of 256 (runs w,
 //     w + gather_groups, ...) whose maximum reaches tau (and the running R-th
 //     best) and keeps its R best bins in an LDS buffer: a bin
@@ -690,7 +690,6 @@ struct TopBuf {
 
 __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int nb) {
   __shared__ double sv[kNG];
-  __shared__ int si[kNG];
   __shared__ int wsum[kTW];
   __shared__ double ps[kTW], pc[kTW];
   __shared__ double s_tau;
@@ -733,39 +732,17 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
     }
   }
 
-  // ---- threshold: bitonic sort of each wave's maxima (value descending,
-  // group ascending), then every maximum's rank by binary search ----
-  double kv = gm;
-  int ki = tid;
-#pragma unroll 1
-  for (int k = 2; k <= 64; k <<= 1)
-#pragma unroll 1
-    for (int j = k >> 1; j >= 1; j >>= 1) {
-      const double ov = __shfl_xor(kv, j);
-      const int oi = __shfl_xor(ki, j);
-      const bool ob = better(ov, (uint64_t)oi, kv, (uint64_t)ki);
-      if (((lane & j) == 0) == ((lane & k) == 0) ? ob : !ob) {
-        kv = ov;
-        ki = oi;
-      }
-    }
-  sv[tid] = kv;
-  si[tid] = ki;
+  // ---- threshold: the R-th best group maximum (value descending, group
+  // ascending): each group counts the groups better than it, reading every
+  // maximum from LDS (all lanes read the same entry: one broadcast per step) ----
+  sv[tid] = gm;  // -inf past the ng groups
   if (tid == 0) s_tau = -INFINITY;
   __syncthreads();
-  if (ng >= R && ki < ng) {
-    int rank = lane;  // better entries of this wave
-    for (int w = 0; w < kTW; ++w) {
-      if (w == wave) continue;
-      int lo = 0, hi = 64;  // first entry of wave w that is not better
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (better(sv[64 * w + mid], (uint64_t)si[64 * w + mid], kv, (uint64_t)ki)) lo = mid + 1;
-        else hi = mid;
-      }
-      rank += lo;
-    }
-    if (rank == R - 1) s_tau = kv;
+  if (ng >= R && tid < ng) {
+    int rank = 0;
+#pragma unroll 8
+    for (int j = 0; j < ng; ++j) rank += better(sv[j], (uint64_t)j, gm, (uint64_t)tid) ? 1 : 0;
+    if (rank == R - 1) s_tau = gm;
   }
   __syncthreads();
   const double tau = s_tau;  // -inf with fewer groups than R
