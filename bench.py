@@ -254,6 +254,69 @@ def measured_traffic():
 
 
 # ---------------------------------------------------------------------------
+# the merging and large workloads: Algorithm 1 on the device
+# ---------------------------------------------------------------------------
+
+def run_workloads(reps: int = 5):
+    """Algorithm 1 (sqc_search) on the merging workload (60-qubit QAOA ring,
+    4 subcircuits, 8 cuts, M = 2^20, R = 12) and the large one (200-qubit
+    chain, 16 subcircuits, 24 cuts, M = 2^24, two recursions), split-BF16x3
+    and plain FP64, attributed tensors resident.  Reports reconstructed bins/s
+    (sum of 2^a over the recursions run, per wall second, host waits of the
+    search included) and the HBM roofline fraction of the recursions'
+    algorithmic bytes (merge reads and writes, contraction operands and
+    results, as the stage timing counts them)."""
+    import torch
+    from paper_2207_00933_amd import runner, sqc
+
+    out = {}
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s = runner.Session(0, 64 << 20)
+        for name, cc, M, R in (("merging", configs.merging(), 1 << 20, 12),
+                               ("large", configs.large(), 1 << 24, 2)):
+            var = qpu.all_variants(cc)
+            circ = runner.Circuit.from_cut_circuit(s, cc, var, sqc.F64)
+            res = {"qubits": cc.n, "subcircuits": cc.n_sub, "cuts": len(cc.cuts), "M": M,
+                   "max_recursions": R}
+            for pname, prec in (("bf16x3", sqc.BF16X3), ("f64", sqc.F64)):
+                att = sqc.F64 if prec == sqc.F64 else sqc.F32
+                bprec = att
+                circ.attribute(att)
+                bins = torch.empty(M, dtype=torch.float64 if bprec == sqc.F64 else torch.float32,
+                                   device=s.device)
+                masks = sqc.assign_bins(circ.g.n_data, None, M)
+                s.ensure_workspace(4 * sqc.recurse_workspace_bytes(circ.att, circ.g, masks, prec))
+                sols, infos = sqc.search(s.ctx, circ.att, circ.g, M, R, prec, bins, bprec)  # warm
+                stages = sqc.STAGE_MERGE | sqc.STAGE_CONTRACT | sqc.STAGE_FINAL | sqc.STAGE_TOPR
+                sqc.ctx_timing(s.ctx, 1, reset=True)
+                sqc.ctx_set_timing(s.ctx, stages)
+                sqc.search(s.ctx, circ.att, circ.g, M, R, prec, bins, bprec)
+                sqc.ctx_set_timing(s.ctx, 0)
+                nbytes = sum(sqc.ctx_timing(s.ctx, q).bytes for q in (sqc.STAGE_MERGE, sqc.STAGE_CONTRACT,
+                                                                     sqc.STAGE_FINAL))
+                sqc.ctx_timing(s.ctx, 1, reset=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    sols, infos = sqc.search(s.ctx, circ.att, circ.g, M, R, prec, bins, bprec)
+                torch.cuda.synchronize()
+                wall = (time.perf_counter() - t0) / reps
+                nb = float(sum(1 << a for (_, _, _, a, _) in infos))
+                res[pname] = {"recursions": len(infos), "bins": nb, "ms_per_search": wall * 1e3,
+                              "bins_per_s": nb / wall, "algorithmic_bytes": nbytes,
+                              "hbm_roofline_frac": nbytes / HBM_PEAK / wall,
+                              "solutions": len(sols), "top_prob": sols[0][0] if sols else None}
+                log(f"[workload] {name} {pname}: {len(infos)} recursions, {wall * 1e3:.3f} ms, "
+                    f"{nb / wall:.3e} bins/s, HBM fraction {nbytes / HBM_PEAK / wall:.3f}")
+            res["speedup_bf16x3_vs_f64"] = res["bf16x3"]["bins_per_s"] / res["f64"]["bins_per_s"]
+            out[name] = res
+            del circ
+        s.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
 # serving: Poisson arrivals of mixed recursions over a resident circuit pool
 # ---------------------------------------------------------------------------
 
@@ -437,6 +500,8 @@ def main():
                          "so that a kernel trace of the command holds only the timed launches")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the HIP-graph replay measurement of the step")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the merging and large workloads (Algorithm 1 on the device)")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving leg (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -464,6 +529,7 @@ def main():
         calib_copy(args.calib_copy_mb)
     gpu = run_gpu(cc, var32, args.steps, args.warmup, precs, autotune=args.autotune,
                   graph=not args.no_graph)
+    workloads = None if args.no_workloads else run_workloads()
     serving = run_serving(args.serve_requests, args.serve_slots) if args.serve_requests > 0 else None
     fast = [p for p in ("bf16x3", "f32") if p in gpu]
     head = max(fast, key=lambda p: gpu[p]["bins_per_s"]) if fast else precs[0]
@@ -503,6 +569,7 @@ def main():
                                                   ("value", "unit", "cores", "kind", "sample")},
         "paths": gpu,
         "latency_ms": {"p50": h["p50_ms"], "p99": h["p99_ms"]},
+        "workloads": workloads,
         "serving": serving,
     }
     if "f64" in gpu:

@@ -42,6 +42,7 @@ struct sqc_ctx {
   uint32_t timing_mask = 0;
   uint32_t saved_mask = 0;  // timing mask suspended while a graph is recorded
   bool recording = false;
+  void *plan_cache = nullptr;  // PlanCache of the recursions planned on this context
   struct Mark {
     int stage;
     hipEvent_t a, b;
@@ -500,8 +501,13 @@ struct RecursePlan {
 // recursions of the same graph.
 struct PlanCache {
   std::mutex mu;
-  std::map<std::pair<std::vector<int>, int>, Contraction> plans;
+  std::map<std::vector<int>, Contraction> plans;  // key: topology, active bits, precision
 };
+
+PlanCache *ctx_plans(sqc_ctx *ctx) {
+  if (!ctx->plan_cache) ctx->plan_cache = new PlanCache();
+  return static_cast<PlanCache *>(ctx->plan_cache);
+}
 
 RecursePlan plan_recursion(const Graph &g, const sqc_tensor *att, const sqc_masks *scope,
                            uint64_t M, int top_r, sqc_prec prec, PlanCache *cache = nullptr) {
@@ -513,10 +519,18 @@ RecursePlan plan_recursion(const Graph &g, const sqc_tensor *att, const sqc_mask
   rp.abits.resize(g.n_sub);
   for (int i = 0; i < g.n_sub; ++i) rp.abits[i] = __builtin_popcountll(rp.masks[i].active);
   if (cache) {
+    std::vector<int> key{g.n_sub, (int)prec};
+    for (const auto &c : g.cuts) {
+      key.push_back(c.up_sub);
+      key.push_back(c.down_sub);
+    }
+    key.insert(key.end(), rp.abits.begin(), rp.abits.end());
     std::lock_guard<std::mutex> lk(cache->mu);
-    auto key = std::make_pair(rp.abits, (int)prec);
     auto it = cache->plans.find(key);
-    if (it == cache->plans.end()) it = cache->plans.emplace(key, plan_for(g, rp.abits, prec)).first;
+    if (it == cache->plans.end()) {
+      if (cache->plans.size() >= 512) cache->plans.clear();  // bounded
+      it = cache->plans.emplace(key, plan_for(g, rp.abits, prec)).first;
+    }
     rp.con = it->second;
   } else {
     rp.con = plan_for(g, rp.abits, prec);
@@ -840,6 +854,7 @@ sqc_status sqc_ctx_destroy(sqc_ctx *ctx) {
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->unit) (void)hipFree(ctx->unit);
+  delete static_cast<PlanCache *>(ctx->plan_cache);
   delete ctx;
   return SQC_OK;
 }
@@ -1160,7 +1175,7 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
   check_storage_prec(bins_prec, "bins_prec");
   if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
   degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
-  RecursePlan rp = plan_recursion(g, attributed, scope, max_bins_M, top_r, prec);
+  RecursePlan rp = plan_recursion(g, attributed, scope, max_bins_M, top_r, prec, ctx_plans(ctx));
   need_ws(ctx, rp.total);
   use_device(ctx);
   enqueue_recursion(ctx, rp, attributed, prec, bins_dev, bins_prec, top_r, topr_dev, sum_dev);
@@ -1180,7 +1195,7 @@ sqc_status sqc_autotune(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_su
   check_path_prec(prec);
   check_storage_prec(bins_prec, "bins_prec");
   degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
-  RecursePlan rp = plan_recursion(g, attributed, scope, max_bins_M, 1, prec);
+  RecursePlan rp = plan_recursion(g, attributed, scope, max_bins_M, 1, prec, ctx_plans(ctx));
   need_ws(ctx, rp.total);
   use_device(ctx);
   void *top_dev = ctx->ws + kOffSearchTop;
@@ -1289,7 +1304,7 @@ sqc_status sqc_search(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
   while (r < R) {
     if (r > 0 && !have_scope) break;
     RecursePlan rp = plan_recursion(g, attributed, have_scope ? scope.data() : nullptr, max_bins_M,
-                                    R, prec);
+                                    R, prec, ctx_plans(ctx));
     need_ws(ctx, rp.total);
     enqueue_recursion(ctx, rp, attributed, prec, bins_dev, bins_prec, R, top_dev, sum_dev);
     const size_t nbytes = kOffSearchSum + 8 - kOffSearchTop;

@@ -571,6 +571,12 @@ struct SubTileBins {
 #pragma unroll
     for (int q = 0; q < 4; ++q) ok[q] = ml < M && nl0 + 8 * q < N;
   }
+  // index of the sub-tile's origin bin, the lowest index in it
+  __device__ uint64_t origin(const TopRArgs &t, int sb) const {
+    uint32_t m0, n0;
+    sub_origin(sb, lmt, lnt, nmaj, m0, n0);
+    return (uint64_t)(map_y(t.m, m0) + map_y(t.n, n0));
+  }
   // origins are multiples of 32: a bin exists iff the origin and (ml, nl) do
   __device__ void load(const TopRArgs &t, int sb, double v[4], uint64_t ix[4]) const {
     uint32_t m0, n0;
@@ -698,6 +704,9 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
   __shared__ double tval[SQC_MAX_TOPR];
   __shared__ uint64_t tidx[SQC_MAX_TOPR];
   __shared__ int list[kTThreads];
+  __shared__ double lmx[kTThreads];
+  __shared__ double rmx[kTThreads];
+  __shared__ double wmin[kTW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = t.top_r;
   const int G = t.ngroups;
@@ -762,21 +771,51 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
   buf.ti = tidx;
   SubTileBins stb;
   stb.init(t);
+  // A sub-tile can hold a bin that beats the running R-th best only if its
+  // maximum is larger, or equal with its lowest bin index (the index of its
+  // origin: offsets grow with both coordinates) below the R-th best's index.
+  auto may_improve = [&](int sbq, double mxq) -> bool {
+    if (!buf.have_bar || mxq > buf.bar_v) return true;
+    if (mxq < buf.bar_v) return false;
+    return stb.origin(t, sbq) < buf.bar_i;
+  };
   for (int base = bid * kTThreads; base < t.nsub; base += nb * kTThreads) {
     const int sb = base + tid;
     const double mx = sb < t.nsub ? t.blk_max[sb] : -INFINITY;
-    const int keep = (sb < t.nsub && mx >= tau && (!buf.have_bar || mx >= buf.bar_v)) ? 1 : 0;
+    int keep = (sb < t.nsub && mx >= tau && may_improve(sb, mx)) ? 1 : 0;
     int total;
-    const int at = block_scan_excl(keep, wsum, total);
-    if (keep) list[at] = sb;
+    int at = block_scan_excl(keep, wsum, total);
+    if (total > 2 * R) {
+      // many candidates (a flat top): the run's R best bins lie in sub-tiles
+      // whose maximum reaches the run's R-th largest maximum, so keep only
+      // those (counting, for each sub-tile, the maxima strictly larger)
+      rmx[tid] = mx;
+      __syncthreads();
+      int larger = 0;
+#pragma unroll 8
+      for (int j = 0; j < kTThreads; ++j) larger += rmx[j] > mx ? 1 : 0;
+      double cand = (sb < t.nsub && larger < R) ? mx : INFINITY;
+      for (int off = 32; off >= 1; off >>= 1) cand = fmin(cand, __shfl_xor(cand, off));
+      if (lane == 0) wmin[wave] = cand;
+      __syncthreads();
+      double tw = wmin[0];
+      for (int w = 1; w < kTW; ++w) tw = fmin(tw, wmin[w]);
+      keep = keep && mx >= tw ? 1 : 0;
+      at = block_scan_excl(keep, wsum, total);
+    }
+    if (keep) {
+      list[at] = sb;
+      lmx[at] = mx;
+    }
     __syncthreads();
-    // four sub-tiles' loads in flight at a time
+    // four sub-tiles' loads in flight at a time; each listed sub-tile is
+    // checked again against the running R-th best (ties are dropped early)
     for (int q = 0; q < total; q += 4) {
       double v[4][4];
       uint64_t ix[4][4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (q + u < total) {
+        if (q + u < total && may_improve(list[q + u], lmx[q + u])) {
           stb.load(t, list[q + u], v[u], ix[u]);
         } else {
 #pragma unroll

@@ -98,16 +98,24 @@ class Recursion:
         self.bins_prec = bins_prec
         self.top_r = top_r
         self.bins = torch.empty(1 << max_bits, dtype=_TORCH_DTYPE[bins_prec], device=s.device)
+        self._ws = {}
         self.top = torch.empty(2 * sqc.MAX_TOPR, dtype=torch.float64, device=s.device)
         self.sum = torch.empty(1, dtype=torch.float64, device=s.device)
 
     def run(self, prec: int, M: int, scope=None) -> List[sqc.Masks]:
         c = self.c
-        # reserve workspace for the masks this call will use
-        masks = sqc.assign_bins(c.g.n_data, scope, M)
-        need = sqc.recurse_workspace_bytes(c.att, c.g, masks, prec)
-        if need == 0:
-            raise RuntimeError(sqc.lib().sqc_last_error(None).decode())
+        # reserve workspace for the masks this call will use (remembered per
+        # scope, M and precision: planning is host work)
+        key = (prec, M, None if scope is None else tuple(sqc.masks_array(scope)[i].as_tuple()
+                                                         for i in range(len(scope))),
+               tuple((t.prec, t.n_bits, t.n_labels) for t in c.att))
+        need = self._ws.get(key)
+        if need is None:
+            masks = sqc.assign_bins(c.g.n_data, scope, M)
+            need = sqc.recurse_workspace_bytes(c.att, c.g, masks, prec)
+            if need == 0:
+                raise RuntimeError(sqc.lib().sqc_last_error(None).decode())
+            self._ws[key] = need
         c.s.ensure_workspace(need)
         return sqc.recurse(c.s.ctx, c.att, c.g, scope, M, self.top_r, prec, self.bins,
                            self.bins_prec, self.top, self.sum)
