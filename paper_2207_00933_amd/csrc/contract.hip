@@ -498,10 +498,11 @@ __global__ __launch_bounds__(kThreads) void gemm_grouped(const GemmArgs *__restr
 //     group, the groups better than it.
 //     Work-group w then visits the sub-tiles of its runs of 256 (runs w,
 //     w + gather_groups, ...) whose maximum reaches tau (and the running R-th
-//     best) and keeps its R best bins in an LDS buffer: a bin
-//     enters when it reaches tau and beats the buffer's R-th best so far; a
-//     full buffer is cut back to its R best by a bitonic sort.  Its R best go
-//     to slot w.
+//     best), best first; where many do, those whose maximum R others in the
+//     run provably beat are skipped.  It keeps its R best bins in an LDS
+//     buffer: a bin enters when it reaches tau and beats the buffer's R-th
+//     best so far, which is fixed as soon as R bins are in; a full buffer is
+//     cut back to its R best by a bitonic sort.  Its R best go to slot w.
 //   rank (one work-group): the slots are merged the same way.
 // The order is strict (larger value, then lower index), so the result is
 // unique: deterministic, no atomics.  Ties at the top cost no more than
@@ -553,6 +554,7 @@ struct SubTileBins {
   int lmt, lnt, nmaj;
   int64_t o_lane[4];  // thread's bins e = tid + 256 q: (e % 32, e / 32)
   bool ok[4];
+  uint64_t span;      // largest offset of a bin from its sub-tile's origin
   __device__ void init(const TopRArgs &t) {
     M = 1u << t.mbits;
     N = 1u << t.nbits;
@@ -570,11 +572,15 @@ struct SubTileBins {
     o_lane[3] = o0 + r8 + r16;
 #pragma unroll
     for (int q = 0; q < 4; ++q) ok[q] = ml < M && nl0 + 8 * q < N;
+    span = (uint64_t)(map_y(t.m, (M < 32 ? M : 32) - 1) + map_y(t.n, (N < 32 ? N : 32) - 1));
   }
-  // index of the sub-tile's origin bin, the lowest index in it
+  // index of the sub-tile's origin bin, the lowest index in it, or ~0 for a
+  // sub-tile wholly outside the result (distinct for distinct sub-tiles that
+  // hold bins: the maps are injective on disjoint bits)
   __device__ uint64_t origin(const TopRArgs &t, int sb) const {
     uint32_t m0, n0;
     sub_origin(sb, lmt, lnt, nmaj, m0, n0);
+    if (m0 >= M || n0 >= N) return ~uint64_t(0);
     return (uint64_t)(map_y(t.m, m0) + map_y(t.n, n0));
   }
   // origins are multiples of 32: a bin exists iff the origin and (ml, nl) do
@@ -691,6 +697,7 @@ struct TopBuf {
       }
     n += total;
     __syncthreads();
+    if (!have_bar && n >= R) cut(R);  // a bar as early as possible
   }
 };
 
@@ -705,8 +712,9 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
   __shared__ uint64_t tidx[SQC_MAX_TOPR];
   __shared__ int list[kTThreads];
   __shared__ double lmx[kTThreads];
+  __shared__ uint64_t lorg[kTThreads];
   __shared__ double rmx[kTThreads];
-  __shared__ double wmin[kTW];
+  __shared__ uint64_t rhi[kTThreads];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = t.top_r;
   const int G = t.ngroups;
@@ -772,50 +780,72 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
   SubTileBins stb;
   stb.init(t);
   // A sub-tile can hold a bin that beats the running R-th best only if its
-  // maximum is larger, or equal with its lowest bin index (the index of its
-  // origin: offsets grow with both coordinates) below the R-th best's index.
-  auto may_improve = [&](int sbq, double mxq) -> bool {
+  // maximum is larger, or equal with its lowest bin index (its origin's:
+  // offsets grow with both coordinates) below the R-th best's index.
+  auto may_improve = [&](double mxq, uint64_t orgq) -> bool {
     if (!buf.have_bar || mxq > buf.bar_v) return true;
-    if (mxq < buf.bar_v) return false;
-    return stb.origin(t, sbq) < buf.bar_i;
+    return mxq == buf.bar_v && orgq < buf.bar_i;
   };
   for (int base = bid * kTThreads; base < t.nsub; base += nb * kTThreads) {
     const int sb = base + tid;
-    const double mx = sb < t.nsub ? t.blk_max[sb] : -INFINITY;
-    int keep = (sb < t.nsub && mx >= tau && may_improve(sb, mx)) ? 1 : 0;
+    const uint64_t org = sb < t.nsub ? stb.origin(t, sb) : ~uint64_t(0);
+    const bool holds = org != ~uint64_t(0);
+    const double mx = holds ? t.blk_max[sb] : -INFINITY;
+    int keep = (holds && mx >= tau && may_improve(mx, org)) ? 1 : 0;
     int total;
     int at = block_scan_excl(keep, wsum, total);
     if (total > 2 * R) {
-      // many candidates (a flat top): the run's R best bins lie in sub-tiles
-      // whose maximum reaches the run's R-th largest maximum, so keep only
-      // those (counting, for each sub-tile, the maxima strictly larger)
+      // Many candidates (a flat top).  Sub-tile T's maximum is a bin that
+      // beats every bin of sub-tile S when it is larger than S's maximum, or
+      // equal to it with T's last bin below S's origin; a sub-tile beaten so
+      // by R others holds none of the R best.
       rmx[tid] = mx;
+      rhi[tid] = holds ? org + stb.span : ~uint64_t(0);
       __syncthreads();
-      int larger = 0;
-#pragma unroll 8
-      for (int j = 0; j < kTThreads; ++j) larger += rmx[j] > mx ? 1 : 0;
-      double cand = (sb < t.nsub && larger < R) ? mx : INFINITY;
-      for (int off = 32; off >= 1; off >>= 1) cand = fmin(cand, __shfl_xor(cand, off));
-      if (lane == 0) wmin[wave] = cand;
-      __syncthreads();
-      double tw = wmin[0];
-      for (int w = 1; w < kTW; ++w) tw = fmin(tw, wmin[w]);
-      keep = keep && mx >= tw ? 1 : 0;
+      int beaten = 0;
+#pragma unroll 4
+      for (int j = 0; j < kTThreads; ++j) {
+        const double xj = rmx[j];
+        beaten += (xj > mx || (xj == mx && rhi[j] < org)) ? 1 : 0;
+      }
+      keep = keep && beaten < R ? 1 : 0;
       at = block_scan_excl(keep, wsum, total);
     }
     if (keep) {
       list[at] = sb;
       lmx[at] = mx;
+      lorg[at] = org;
     }
     __syncthreads();
-    // four sub-tiles' loads in flight at a time; each listed sub-tile is
-    // checked again against the running R-th best (ties are dropped early)
-    for (int q = 0; q < total; q += 4) {
+    if (total > 4) {
+      // visit the candidates best first (larger maximum, then lower origin)
+      // so that the running R-th best rises fast and prunes the rest
+      int rank = 0, sbk = 0;
+      double mk = 0.0;
+      uint64_t gk = 0;
+      if (tid < total) {
+        sbk = list[tid];
+        mk = lmx[tid];
+        gk = lorg[tid];
+        for (int j = 0; j < total; ++j) rank += better(lmx[j], lorg[j], mk, gk) ? 1 : 0;
+      }
+      __syncthreads();
+      if (tid < total) {
+        list[rank] = sbk;
+        lmx[rank] = mk;
+        lorg[rank] = gk;
+      }
+      __syncthreads();
+    }
+    // up to four sub-tiles' loads in flight (one while there is no R-th best
+    // yet); each listed sub-tile is checked again against the running R-th best
+    for (int q = 0; q < total;) {
+      const int nl = min((buf.have_bar || q > 0) ? 4 : 1, total - q);
       double v[4][4];
       uint64_t ix[4][4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (q + u < total && may_improve(list[q + u], lmx[q + u])) {
+        if (u < nl && may_improve(lmx[q + u], lorg[q + u])) {
           stb.load(t, list[q + u], v[u], ix[u]);
         } else {
 #pragma unroll
@@ -825,7 +855,8 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
           }
         }
       }
-      for (int u = 0; u < 4; ++u) buf.add(v[u], ix[u], tau, R, wsum);
+      for (int u = 0; u < nl; ++u) buf.add(v[u], ix[u], tau, R, wsum);
+      q += nl;
     }
     __syncthreads();  // list is rewritten by the next round
   }

@@ -129,3 +129,40 @@ def test_topr_two_subcircuits_n_panel_order(session):
         assert np.array_equal(t[0:64:2], b[order])
         assert np.array_equal(t[1:64:2].view(np.uint64), order.astype(np.uint64))
         assert abs(bsum.item() - math.fsum(b.tolist())) <= 1e-12 * math.fsum(np.abs(b).tolist())
+
+
+@pytest.mark.parametrize("d0,d1", [(7, 15), (15, 7), (11, 11)])
+def test_topr_product_ties(session, d0, d1):
+    """Two subcircuits joined by one cut whose attributed entries are small
+    integers on label 0 and zero elsewhere: every bin is the product
+    A[x0] B[x1], exact in every precision, and a quarter of the bins tie at
+    the top value (a flat top spread over every sub-tile, the layout the
+    sub-tile pruning and the best-first visit order act on), in both
+    orientations of the final contraction."""
+    rng = np.random.default_rng(100 + d0)
+    g = sqc.Graph([d0 + 1, d1], [list(range(d0)), list(range(d1))], [(0, d0, 1, 0)])
+    A = np.zeros(((1 << d0), 4))
+    B = np.zeros(((1 << d1), 4))
+    A[:, 0] = rng.integers(1, 3, 1 << d0)
+    B[:, 0] = rng.integers(1, 3, 1 << d1)
+    bufs = [torch.from_numpy(A.reshape(-1)).cuda(), torch.from_numpy(B.reshape(-1)).cuda()]
+    att = [sqc.tensor_desc(bufs[0], 1, d0, sqc.F64, sqc.LAYOUT_ATTRIBUTED),
+           sqc.tensor_desc(bufs[1], 1, d1, sqc.F64, sqc.LAYOUT_ATTRIBUTED)]
+    M = 1 << (d0 + d1)
+    for pname, prec in PRECS:
+        masks = sqc.assign_bins([d0, d1], None, M)
+        session.ensure_workspace(sqc.recurse_workspace_bytes(att, g, masks, prec))
+        for R in (1, 2, 16, 64):
+            say(f"topr product ties {d0}+{d1} {pname} R={R}")
+            bins = torch.empty(M, dtype=torch.float64, device="cuda")
+            top = torch.empty(2 * sqc.MAX_TOPR, dtype=torch.float64, device="cuda")
+            bsum = torch.empty(1, dtype=torch.float64, device="cuda")
+            sqc.recurse(session.ctx, att, g, None, M, R, prec, bins, sqc.F64, top, bsum)
+            torch.cuda.synchronize()
+            b = bins.cpu().numpy()
+            t = top.cpu().numpy()
+            assert np.array_equal(np.sort(b), np.sort(np.outer(A[:, 0], B[:, 0]).ravel()))
+            order = np.argsort(-b, kind="stable")[:R]
+            assert np.array_equal(t[0:2 * R:2], b[order])
+            assert np.array_equal(t[1:2 * R:2].view(np.uint64), order.astype(np.uint64))
+            assert bsum.item() == math.fsum(b.tolist())
