@@ -6,11 +6,12 @@
 // tensor product of one small map per cut.  A work item is one combination of
 // measurement bases beta (a label Z, X or Y per out-cut) and a tile of XT
 // consecutive data states.  Its entries p[(s, beta)][x, b] for all
-// preparations s and out-cut outcomes b are staged in LDS, the per-cut maps
-// are applied in place, one pass per cut, and every label assignment
+// preparations s and out-cut outcomes b are loaded, the maps of the first
+// three out-cuts are applied in registers, the rest are staged in LDS and the
+// other maps applied in place, one pass per cut, and every label assignment
 // compatible with beta is written (beta(I) = beta(Z) = Z, so a Z basis serves
-// I and Z).  The code is kept in loops: a kernel's first pass over
-// straight-line code is bound by instruction fetch.
+// I and Z).  Loops over cuts have fixed bounds so that the parameters they
+// read are fetched together rather than one dependent read per iteration.
 //
 //   in-cut  (digit of s -> digit of sigma):  I = p0 + p1,  Z = p0 - p1,
 //            X = 2 p+ - p0 - p1,  Y = 2 p+i - p0 - p1
@@ -19,6 +20,7 @@
 #include "common.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace sqc {
 
@@ -29,146 +31,233 @@ constexpr int kLdsElems = 2048;   // doubles staged per work-group
 constexpr int kPer = kLdsElems / kThreads;
 constexpr int kMaxNS = 1024;
 constexpr int kMaxNB = 1024;
+constexpr int kMaxIn = 5;         // 4^n_in <= kMaxNS
+constexpr int kMaxOut = 11;       // 4^n_in 2^n_out <= kLdsElems
+constexpr int kMaxXt = 11;        // x-tile bits: 2^xt_bits <= kLdsElems
+constexpr int kEBits = 11;        // bits of a staged element index (E <= 2^11)
 
 __device__ __forceinline__ double load_prob(const void *p, int64_t i, int f32) {
   return f32 ? (double)static_cast<const float *>(p)[i] : static_cast<const double *>(p)[i];
 }
 
+// One subcircuit's parameters for the staged kernel, flattened by the host so
+// that a work-group reads each one directly (no table lookups in chains).
+// Entries past n_in, n_out and d are zero, so loops run to the fixed bounds
+// without guards and their reads are issued together.
+struct AttrJob {
+  const void *var;
+  void *out;
+  double scale;
+  int in_f32, out_f32;
+  int w, d, c, n_in, n_out, xt_bits;
+  int vec8;                 // a thread's 8 entries are consecutive in memory
+  int in_lab[kMaxIn];       // label bit position in sigma of in-cut j
+  int out_place[kMaxOut];   // variant place value of out-cut j's basis
+  int out_lab[kMaxOut];     // label bit position in sigma of out-cut j
+  // variant offset added by bit i of a staged element index e: an outcome
+  // bit, a tile bit or a bit of a preparation digit (with its place value)
+  int64_t edelta[kEBits];
+  uint32_t tile_nib[8][16]; // state bits of x-tile index bits 4q..4q+3
+};
+static_assert(sizeof(AttrJob) * kAttrJobs + 64 <= 4096, "attribution batch exceeds the kernel argument space");
+
+// Padded LDS position of staged element e (one pad per 32): the passes over
+// consecutive elements and the output reads at a stride of 32 elements then
+// fall on distinct banks.
+__device__ __forceinline__ int phys(int e) { return e + (e >> 5); }
+
 // Bytes of dynamic LDS a work-group uses.
 size_t attribute_lds_bytes(int xt_bits, int n_in, int n_out) {
   const size_t E = (size_t(1) << (2 * n_in)) << (n_out + xt_bits);
-  const size_t NS = size_t(1) << (2 * n_in), NB = size_t(1) << n_out, XT = size_t(1) << xt_bits;
-  return E * 8 + NS * 8 + NS * 4 + 3 * NB * 4 + XT * 4;
+  const size_t NS = size_t(1) << (2 * n_in), NB = size_t(1) << n_out;
+  return (E + (E >> 5)) * 8 + NS * 4 + 2 * NB * 4;
 }
 
 // One work-group = (basis combination beta, tile of XT consecutive data
-// states).  The threads first tabulate the offsets and label bits of the
-// preparations, outcome bits and tile states (one entry each), then issue all
-// variant loads at once.  LDS is sized to the subcircuit (dynamic), so small
-// stages leave room for many work-groups per CU.
-__device__ __forceinline__ void attribute_lds_body(const AttrArgs &a, int blk, unsigned char *dyn) {
+// states); staged element e = (s XT + xt) NB + b.  Thread t owns elements
+// [8t, 8t + 8): it computes their variant offsets directly and issues the
+// loads first, builds the label tables while they are in flight, applies the
+// maps of out-cuts 0..2 (bits 0..2 of e) in registers, and stages the result;
+// the remaining out-cuts and the in-cuts take one LDS pass each.  LDS is sized
+// to the subcircuit (dynamic), so small stages leave room for many
+// work-groups per CU.
+template <bool IN_F32, bool OUT_F32, bool VEC8>
+__device__ __forceinline__ void attribute_lds_body(const AttrJob &a, int blk, unsigned char *dyn) {
   const int tid = threadIdx.x;
   const int XT = 1 << a.xt_bits;
   const int NB = 1 << a.n_out;
   const int NS = 1 << (2 * a.n_in);
   const int E = NS * XT * NB;
-  double *buf = reinterpret_cast<double *>(dyn);            // [E]
-  int64_t *vin = reinterpret_cast<int64_t *>(buf + E);      // [NS] variant index of the in-cut digits of s
-  uint32_t *sinl = reinterpret_cast<uint32_t *>(vin + NS);  // [NS] their label bits
-  uint32_t *boff = sinl + NS;                               // [NB] wire offset of outcome bits b
-  uint32_t *sout = boff + NB;                               // [NV] label bits of valid out-cut slot v
-  uint32_t *slot = sout + NB;                               // [NV] its outcome bits
-  uint32_t *xoff = slot + NB;                               // [XT] wire offset of tile state xt
+  double *buf = reinterpret_cast<double *>(dyn);                      // [phys(E)]
+  uint32_t *sinl = reinterpret_cast<uint32_t *>(buf + E + (E >> 5));  // [NS] label bits of s
+  uint32_t *sout = sinl + NS;                                         // [NV] label bits of slot v
+  uint32_t *slot = sout + NB;                                         // [NV] its outcome bits
   const int lnxt = a.d - a.xt_bits;
   const int bidx = blk >> lnxt;
   const int64_t x0 = int64_t(blk & ((1 << lnxt) - 1)) << a.xt_bits;
 
-  // basis digits of this work-group
-  int zmask = 0;  // bit j: out-cut j measured in the Z basis
-  int64_t vbeta = 0;
+  // basis digits of this work-group: out-cut j measured in basis dig[j]
+  // (Z = 0, X = 1, Y = 2)
+  int dig[kMaxOut];  // 0 past n_out (bidx < 3^n_out)
+  int zmask = 0, vbeta = 0;
   {
+    // digits past the fourth only when there are more out-cuts (a uniform
+    // branch: most subcircuits have few)
     int rem = bidx;
-    for (int j = 0; j < a.n_out; ++j) {
-      const int bj = rem % 3;
+#pragma unroll
+    for (int j = 0; j < kMaxOut; ++j) dig[j] = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      dig[j] = rem % 3;
       rem /= 3;
-      vbeta += int64_t(bj) * a.place[a.out_pos[j]];
-      zmask |= (bj == 0 ? 1 : 0) << j;
     }
+    if (a.n_out > 4) {
+#pragma unroll
+      for (int j = 4; j < kMaxOut; ++j) {
+        dig[j] = rem % 3;
+        rem /= 3;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxOut; ++j) {
+      vbeta += dig[j] * a.out_place[j];
+      zmask |= (dig[j] == 0 ? 1 : 0) << j;
+    }
+    zmask &= (1 << a.n_out) - 1;
+  }
+  uint32_t base = 0;  // state bits of the tile's fixed data bits
+  {
+    const uint32_t xi = (uint32_t)(x0 >> a.xt_bits);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) base |= a.tile_nib[q][(xi >> (4 * q)) & 15];
+  }
+
+  // the thread's variant entries, loads in flight together
+  const int e0 = tid * kPer;
+  const bool mine = e0 < E;
+  typename std::conditional<IN_F32, float, double>::type raw[kPer];
+  {
+    int64_t off0 = ((int64_t)vbeta << a.w) + base;
+#pragma unroll
+    for (int i = 3; i < kEBits; ++i)
+      if ((e0 >> i) & 1) off0 += a.edelta[i];
+    // (converted where first used, so that the loads stay in flight while
+    // the label tables are built)
+    typedef typename std::conditional<IN_F32, float, double>::type I;
+    const I *in = static_cast<const I *>(a.var);
+    if constexpr (VEC8) {
+      // 16-byte loads (the entries of outcome bits 0..2 are adjacent)
+      typedef typename std::conditional<IN_F32, float4, double2>::type V;
+      constexpr int per = sizeof(V) / sizeof(I);
+      const V *pv = reinterpret_cast<const V *>(in + (mine ? off0 : 0));
+      V x[kPer / per];
+#pragma unroll
+      for (int u = 0; u < kPer / per; ++u) x[u] = pv[u];
+#pragma unroll
+      for (int u = 0; u < kPer / per; ++u) {
+        if constexpr (IN_F32) {
+          raw[4 * u] = x[u].x;
+          raw[4 * u + 1] = x[u].y;
+          raw[4 * u + 2] = x[u].z;
+          raw[4 * u + 3] = x[u].w;
+        } else {
+          raw[2 * u] = x[u].x;
+          raw[2 * u + 1] = x[u].y;
+        }
+      }
+    } else {
+      int64_t off[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k)
+        off[k] = (mine && e0 + k < E)
+                     ? off0 + ((k & 1) ? a.edelta[0] : 0) + ((k & 2) ? a.edelta[1] : 0) + ((k & 4) ? a.edelta[2] : 0)
+                     : 0;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) raw[k] = in[off[k]];
+    }
+  }
+
+  // label tables for the output
+  for (int t = tid; t < NS; t += kThreads) {
+    uint32_t sg = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxIn; ++j) sg |= uint32_t((t >> (2 * j)) & 3) << a.in_lab[j];
+    sinl[t] = sg;
   }
   const int nz = __builtin_popcount(zmask);
   const int NV = 1 << nz;  // a Z-basis cut carries both I and Z
-  int64_t base = 0;
-  for (int j = a.xt_bits; j < a.d; ++j)
-    if ((x0 >> j) & 1) base |= int64_t(1) << a.data_wire[j];
-  for (int t = tid; t < NS; t += kThreads) {
-    int64_t vr = 0;
-    uint32_t sg = 0;
-    for (int j = 0; j < a.n_in; ++j) {
-      const int dgt = (t >> (2 * j)) & 3;
-      vr += int64_t(dgt) * a.place[a.in_pos[j]];
-      sg |= uint32_t(dgt) << (2 * a.in_pos[j]);
-    }
-    vin[t] = vr;
-    sinl[t] = sg;
-  }
-  for (int t = tid; t < NB; t += kThreads) {
-    uint32_t o = 0;
-    for (int j = 0; j < a.n_out; ++j)
-      if ((t >> j) & 1) o |= uint32_t(1) << a.out_wire[j];
-    boff[t] = o;
-  }
-  for (int t = tid; t < XT; t += kThreads) {
-    uint32_t o = 0;
-    for (int j = 0; j < a.xt_bits; ++j)
-      if ((t >> j) & 1) o |= uint32_t(1) << a.data_wire[j];
-    xoff[t] = o;
-  }
   for (int t = tid; t < NV; t += kThreads) {
     uint32_t sg = 0, sl = 0;
-    int zb = 0, rem = bidx;
-    for (int j = 0; j < a.n_out; ++j) {
-      const int bj = rem % 3;  // basis digit j
-      rem /= 3;
-      int lab = bj;            // X = 1, Y = 2 coincide with the basis digits
-      if (bj == 0) {
+    int zb = 0;
+    // (past n_out: digit 0 and bit (t >> zb) & 1 = 0 as t < 2^nz, so
+    // nothing is added)
+#pragma unroll
+    for (int j = 0; j < kMaxOut; ++j) {
+      int lab = dig[j];  // X = 1, Y = 2 coincide with the basis digits
+      if (lab == 0) {
         const int bit = (t >> zb) & 1;
         ++zb;
         lab = bit ? 3 : 0;  // slot bit 0 holds I, bit 1 holds Z
         sl |= uint32_t(bit) << j;
       }
-      sg |= uint32_t(lab) << (2 * a.out_pos[j]);
+      sg |= uint32_t(lab) << a.out_lab[j];
     }
     sout[t] = sg;
     slot[t] = sl;
   }
-  __syncthreads();
 
-  // stage: element e = (s XT + xt) NB + b; all loads in flight together
-  {
-    int64_t off[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int e = tid + k * kThreads;
-      const int b = e & (NB - 1);
-      const int xt = (e >> a.n_out) & (XT - 1);
-      const int sdx = (e >> (a.n_out + a.xt_bits)) & (NS - 1);
-      off[k] = e < E ? ((vbeta + vin[sdx]) << a.w) + base + (int64_t)(xoff[xt] | boff[b]) : 0;
-    }
+  // out-cuts 0..2 in registers: pair (b_j = 0, b_j = 1) -> slot 0 / 1
+  if (mine) {
     double v[kPer];
-    if (a.in_f32) {
-      const float *in = static_cast<const float *>(a.var);
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) v[k] = (double)in[off[k]];
-    } else {
-      const double *in = static_cast<const double *>(a.var);
+    for (int k = 0; k < kPer; ++k) v[k] = (double)raw[k];
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) v[k] = in[off[k]];
+    for (int i = 0; i < 3; ++i) {
+      if (i < a.n_out) {
+        if ((zmask >> i) & 1) {
+#pragma unroll
+          for (int k = 0; k < kPer; ++k)
+            if (!((k >> i) & 1)) {
+              const double q0 = v[k], q1 = v[k | (1 << i)];
+              v[k] = q0 + q1;
+              v[k | (1 << i)] = q0 - q1;
+            }
+        } else {
+#pragma unroll
+          for (int k = 0; k < kPer; ++k)
+            if (!((k >> i) & 1)) {
+              v[k] -= v[k | (1 << i)];
+              v[k | (1 << i)] = 0.0;
+            }
+        }
+      }
     }
+    const int p0 = phys(e0);  // the thread's 8 elements share one pad
 #pragma unroll
     for (int k = 0; k < kPer; ++k)
-      if (tid + k * kThreads < E) buf[tid + k * kThreads] = v[k];
+      if (e0 + k < E) buf[p0 + k] = v[k];
   }
   __syncthreads();
 
-  // out-cut maps: pair (b_j = 0, b_j = 1) -> slot 0 / 1.  A thread's pairs
-  // of one pass are read together, then written (one LDS round trip).
-  for (int j = 0; j < a.n_out; ++j) {
+  // out-cuts 3.. : one LDS pass each; a thread's pairs of one pass are read
+  // together, then written
+  for (int j = 3; j < a.n_out; ++j) {
     const bool zb = (zmask >> j) & 1;
     for (int p0 = 0; p0 < E / 2; p0 += 4 * kThreads) {
       double q0[4], q1[4];
-      int e0[4];
+      int e1[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int p = p0 + u * kThreads + tid;
-        e0[u] = p < E / 2 ? ((p >> j) << (j + 1)) | (p & ((1 << j) - 1)) : -1;
-        q0[u] = e0[u] >= 0 ? buf[e0[u]] : 0.0;
-        q1[u] = e0[u] >= 0 ? buf[e0[u] | (1 << j)] : 0.0;
+        e1[u] = p < E / 2 ? ((p >> j) << (j + 1)) | (p & ((1 << j) - 1)) : -1;
+        q0[u] = e1[u] >= 0 ? buf[phys(e1[u])] : 0.0;
+        q1[u] = e1[u] >= 0 ? buf[phys(e1[u] | (1 << j))] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (e0[u] >= 0) {
-          buf[e0[u]] = zb ? q0[u] + q1[u] : q0[u] - q1[u];
-          buf[e0[u] | (1 << j)] = zb ? q0[u] - q1[u] : 0.0;
+        if (e1[u] >= 0) {
+          buf[phys(e1[u])] = zb ? q0[u] + q1[u] : q0[u] - q1[u];
+          buf[phys(e1[u] | (1 << j))] = zb ? q0[u] - q1[u] : 0.0;
         }
     }
     __syncthreads();
@@ -179,22 +268,22 @@ __device__ __forceinline__ void attribute_lds_body(const AttrArgs &a, int blk, u
     const int st = 1 << sh;
     for (int p0 = 0; p0 < E / 4; p0 += 2 * kThreads) {
       double q[2][4];
-      int e0[2];
+      int e1[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int p = p0 + u * kThreads + tid;
-        e0[u] = p < E / 4 ? ((p >> sh) << (sh + 2)) | (p & (st - 1)) : -1;
+        e1[u] = p < E / 4 ? ((p >> sh) << (sh + 2)) | (p & (st - 1)) : -1;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) q[u][r] = e0[u] >= 0 ? buf[e0[u] + r * st] : 0.0;
+        for (int r = 0; r < 4; ++r) q[u][r] = e1[u] >= 0 ? buf[phys(e1[u] + r * st)] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u)
-        if (e0[u] >= 0) {
+        if (e1[u] >= 0) {
           const double s01 = q[u][0] + q[u][1];
-          buf[e0[u]] = s01;
-          buf[e0[u] + st] = 2.0 * q[u][2] - s01;
-          buf[e0[u] + 2 * st] = 2.0 * q[u][3] - s01;
-          buf[e0[u] + 3 * st] = q[u][0] - q[u][1];
+          buf[phys(e1[u])] = s01;
+          buf[phys(e1[u] + st)] = 2.0 * q[u][2] - s01;
+          buf[phys(e1[u] + 2 * st)] = 2.0 * q[u][3] - s01;
+          buf[phys(e1[u] + 3 * st)] = q[u][0] - q[u][1];
         }
     }
     __syncthreads();
@@ -209,9 +298,9 @@ __device__ __forceinline__ void attribute_lds_body(const AttrArgs &a, int blk, u
     const int rest = q >> lNS;
     const int vv = rest & (NV - 1);
     const int xt = rest >> nz;
-    const double val = buf[(sdx * XT + xt) * NB + slot[vv]] * a.scale;
+    const double val = buf[phys((sdx * XT + xt) * NB + slot[vv])] * a.scale;
     const int64_t o = (x0 + xt) * L + (sinl[sdx] | sout[vv]);
-    if (a.out_f32) static_cast<float *>(a.out)[o] = (float)val;
+    if constexpr (OUT_F32) static_cast<float *>(a.out)[o] = (float)val;
     else static_cast<double *>(a.out)[o] = val;
   }
 }
@@ -221,14 +310,75 @@ __device__ __forceinline__ void attribute_lds_body(const AttrArgs &a, int blk, u
 struct AttrBatch {
   int n;
   int start[kAttrJobs + 1];
-  AttrArgs job[kAttrJobs];
+  AttrJob job[kAttrJobs];
 };
 
+// Input and output precisions and the load form are template parameters (one
+// combination per launch): no branch between a load and its use.
+template <bool IN_F32, bool OUT_F32, bool VEC8>
 __global__ __launch_bounds__(kThreads) void attribute_lds(AttrBatch b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
   int j = 0;
-  while (j + 1 < b.n && (int)blockIdx.x >= b.start[j + 1]) ++j;
-  attribute_lds_body(b.job[j], (int)blockIdx.x - b.start[j], dyn);
+#pragma unroll
+  for (int q = 1; q < kAttrJobs; ++q) j += (q < b.n && (int)blockIdx.x >= b.start[q]) ? 1 : 0;
+  attribute_lds_body<IN_F32, OUT_F32, VEC8>(b.job[j], (int)blockIdx.x - b.start[j], dyn);
+}
+
+// The vector-load form serves a batch whose jobs all allow it; the other form
+// serves any job.
+template <bool IN_F32, bool OUT_F32>
+void launch_lds(const AttrBatch &b, size_t lds, hipStream_t s) {
+  const dim3 grid((unsigned)b.start[b.n]), block(kThreads);
+  bool vec8 = true;
+  for (int j = 0; j < b.n; ++j) vec8 = vec8 && b.job[j].vec8;
+  if (vec8) hipLaunchKernelGGL((attribute_lds<IN_F32, OUT_F32, true>), grid, block, lds, s, b);
+  else hipLaunchKernelGGL((attribute_lds<IN_F32, OUT_F32, false>), grid, block, lds, s, b);
+}
+
+// The staged kernel's flattened parameters of a subcircuit.
+AttrJob attr_job(const AttrArgs &a) {
+  AttrJob J{};
+  J.var = a.var;
+  J.out = a.out;
+  J.scale = a.scale;
+  J.in_f32 = a.in_f32;
+  J.out_f32 = a.out_f32;
+  J.w = a.w;
+  J.d = a.d;
+  J.c = a.c;
+  J.n_in = a.n_in;
+  J.n_out = a.n_out;
+  J.xt_bits = a.xt_bits;
+  for (int j = 0; j < a.n_in; ++j) J.in_lab[j] = 2 * a.in_pos[j];
+  for (int j = 0; j < a.n_out; ++j) {
+    J.out_place[j] = (int)a.place[a.out_pos[j]];
+    J.out_lab[j] = 2 * a.out_pos[j];
+  }
+  // e = (s XT + xt) NB + b: bit i of e is outcome bit i, then tile bit
+  // i - n_out, then bit i' of s (digit i' / 2, weight 1 or 2)
+  for (int i = 0; i < kEBits; ++i) {
+    if (i < a.n_out) {
+      J.edelta[i] = int64_t(1) << a.out_wire[i];
+    } else if (i < a.n_out + a.xt_bits) {
+      J.edelta[i] = int64_t(1) << a.data_wire[i - a.n_out];
+    } else {
+      const int sb = i - a.n_out - a.xt_bits;
+      J.edelta[i] = sb < 2 * a.n_in ? (a.place[a.in_pos[sb >> 1]] * ((sb & 1) + 1)) << a.w : 0;
+    }
+  }
+  J.vec8 = J.edelta[0] == 1 && J.edelta[1] == 2 && J.edelta[2] == 4 &&
+           reinterpret_cast<uintptr_t>(a.var) % 16 == 0;
+  // data bits xt_bits + 4q + r of the tile index, nibble by nibble
+  for (int q = 0; q < 8; ++q)
+    for (int v = 0; v < 16; ++v) {
+      uint32_t o = 0;
+      for (int r = 0; r < 4; ++r) {
+        const int j = a.xt_bits + 4 * q + r;
+        if (((v >> r) & 1) && j < a.d) o |= 1u << a.data_wire[j];
+      }
+      J.tile_nib[q][v] = o;
+    }
+  return J;
 }
 
 // Direct evaluation for subcircuits whose per-state slice does not fit the LDS
@@ -289,7 +439,11 @@ void launch_attributes(const AttrArgs *jobs, int n, hipStream_t s) {
   size_t lds = 0;
   auto flush = [&]() {
     if (!b.n) return;
-    hipLaunchKernelGGL(attribute_lds, dim3((unsigned)b.start[b.n]), dim3(kThreads), lds, s, b);
+    const int fi = b.job[0].in_f32, fo = b.job[0].out_f32;
+    if (fi && fo) launch_lds<true, true>(b, lds, s);
+    else if (fi) launch_lds<true, false>(b, lds, s);
+    else if (fo) launch_lds<false, true>(b, lds, s);
+    else launch_lds<false, false>(b, lds, s);
     b = AttrBatch{};
     lds = 0;
   };
@@ -304,11 +458,18 @@ void launch_attributes(const AttrArgs *jobs, int n, hipStream_t s) {
       while ((per_x << (xb + 1)) <= kLdsElems && xb + 1 <= a.d) ++xb;
       int64_t nbeta = 1;
       for (int j = 0; j < a.n_out; ++j) nbeta *= 3;
-      while (xb > 0 && (nbeta << (a.d - xb)) < 1024 && (per_x << (xb - 1)) >= 256) --xb;
+      // (not below the 8 entries a thread takes when they are outcome and
+      // tile bits, so that they stay adjacent in memory)
+      const int xb_min = std::min(std::max(0, 3 - a.n_out), xb);
+      while (xb > xb_min && (nbeta << (a.d - xb)) < 1024 && (per_x << (xb - 1)) >= 256) --xb;
       a.xt_bits = xb;
       const int64_t blocks = nbeta << (a.d - xb);
-      if (b.n == kAttrJobs || b.start[b.n] + blocks > (int64_t(1) << 31) - 1) flush();
-      b.job[b.n] = a;
+      // one launch holds jobs of one input and one output precision
+      const AttrJob J = attr_job(a);
+      if (b.n == kAttrJobs || b.start[b.n] + blocks > (int64_t(1) << 31) - 1 ||
+          (b.n && (b.job[0].in_f32 != J.in_f32 || b.job[0].out_f32 != J.out_f32)))
+        flush();
+      b.job[b.n] = J;
       b.start[b.n + 1] = (int)(b.start[b.n] + blocks);
       ++b.n;
       lds = std::max(lds, attribute_lds_bytes(xb, a.n_in, a.n_out));
