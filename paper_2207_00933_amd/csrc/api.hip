@@ -746,18 +746,19 @@ void enqueue_batch(sqc_ctx *ctx, PreparedRecursion *const *p, int n, char *const
     }
   }
 
-  // top-R of every request
-  std::vector<TopRArgs> tops;
-  for (auto &L : Ls)
-    if (L.topr) tops.push_back(L.t);
-  if (!tops.empty()) {
+  // top-R of every request, one launch per bins precision
+  for (int outf = 0; outf < 2; ++outf) {
+    std::vector<TopRArgs> tops;
+    for (auto &L : Ls)
+      if (L.topr && L.t.out_f32 == outf) tops.push_back(L.t);
+    if (tops.empty()) continue;
     std::stable_sort(tops.begin(), tops.end(),
                      [](const TopRArgs &a, const TopRArgs &b) { return a.nsub > b.nsub; });
     std::vector<int64_t> nb;
     for (auto &t : tops) nb.push_back(t.gather_groups);
     const std::vector<int> start = block_prefix(nb);
     const size_t at = tab.put(tops.data(), tops.size());
-    descs.push_back(GroupedDesc{2, 0, GemmSpec{}, at, tab.put(start.data(), start.size()), (int)tops.size(),
+    descs.push_back(GroupedDesc{2, outf, GemmSpec{}, at, tab.put(start.data(), start.size()), (int)tops.size(),
                                 start.back()});
   }
 
@@ -772,7 +773,7 @@ void enqueue_batch(sqc_ctx *ctx, PreparedRecursion *const *p, int n, char *const
                           reinterpret_cast<const int *>(table_dev + d.start), d.n, d.total, ctx->stream);
     else
       launch_topr_grouped(reinterpret_cast<const TopRArgs *>(table_dev + d.jobs),
-                          reinterpret_cast<const int *>(table_dev + d.start), d.n, d.total, ctx->stream);
+                          reinterpret_cast<const int *>(table_dev + d.start), d.n, d.total, d.code, ctx->stream);
     after_launch("batched kernel launch");
   }
 }

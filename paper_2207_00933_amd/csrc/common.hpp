@@ -271,7 +271,8 @@ int topr_gather_groups(int64_t nsub);
 void launch_topr(const TopRArgs &t, hipStream_t s);
 // n top-R selections from a device table of n TopRArgs, in two launches;
 // job j's gather takes work-groups [start[j], start[j + 1]) of total.
-void launch_topr_grouped(const TopRArgs *jobs_dev, const int *start_dev, int n, int total, hipStream_t s);
+void launch_topr_grouped(const TopRArgs *jobs_dev, const int *start_dev, int n, int total, int out_f32,
+                         hipStream_t s);
 
 void launch_zero(void *p, size_t bytes, hipStream_t s);
 

@@ -552,6 +552,8 @@ __device__ __forceinline__ void sub_origin(int sb, int lmt, int lnt, int nmaj, u
 struct SubTileBins {
   uint32_t M, N;
   int lmt, lnt, nmaj;
+  bool shifts;        // both maps are single runs: offsets are shifts
+  int lym, lyn;
   int64_t o_lane[4];  // thread's bins e = tid + 256 q: (e % 32, e / 32)
   bool ok[4];
   uint64_t span;      // largest offset of a bin from its sub-tile's origin
@@ -561,44 +563,50 @@ struct SubTileBins {
     lnt = t.nbits > 6 ? t.nbits - 6 : 0;
     lmt = t.mbits > 6 ? t.mbits - 6 : 0;
     nmaj = t.nmajor;
+    shifts = t.m.nruns == 1 && t.n.nruns == 1;
+    lym = t.m.ly[0];
+    lyn = t.n.ly[0];
     // bins q and q + 1 differ by 8 rows: o_lane[q] = o(ml, nl0) + o(8 q)
     // (nl0 = tid / 32 < 8 for 256 threads, disjoint bits)
     const uint32_t ml = threadIdx.x & 31, nl0 = threadIdx.x >> 5;
-    const int64_t o0 = map_y(t.m, ml) + map_y(t.n, nl0);
-    const int64_t r8 = map_y(t.n, 8), r16 = map_y(t.n, 16);
+    const int64_t o0 = offset(t, ml, nl0);
+    const int64_t r8 = offset(t, 0, 8), r16 = offset(t, 0, 16);
     o_lane[0] = o0;
     o_lane[1] = o0 + r8;
     o_lane[2] = o0 + r16;
     o_lane[3] = o0 + r8 + r16;
 #pragma unroll
     for (int q = 0; q < 4; ++q) ok[q] = ml < M && nl0 + 8 * q < N;
-    span = (uint64_t)(map_y(t.m, (M < 32 ? M : 32) - 1) + map_y(t.n, (N < 32 ? N : 32) - 1));
+    span = (uint64_t)offset(t, (M < 32 ? M : 32) - 1, (N < 32 ? N : 32) - 1);
   }
   // index of the sub-tile's origin bin, the lowest index in it, or ~0 for a
   // sub-tile wholly outside the result (distinct for distinct sub-tiles that
   // hold bins: the maps are injective on disjoint bits)
+  __device__ int64_t offset(const TopRArgs &t, uint32_t m0, uint32_t n0) const {
+    return shifts ? ((int64_t)m0 << lym) + ((int64_t)n0 << lyn) : map_y(t.m, m0) + map_y(t.n, n0);
+  }
   __device__ uint64_t origin(const TopRArgs &t, int sb) const {
     uint32_t m0, n0;
     sub_origin(sb, lmt, lnt, nmaj, m0, n0);
     if (m0 >= M || n0 >= N) return ~uint64_t(0);
-    return (uint64_t)(map_y(t.m, m0) + map_y(t.n, n0));
+    return (uint64_t)offset(t, m0, n0);
   }
-  // origins are multiples of 32: a bin exists iff the origin and (ml, nl) do
-  __device__ void load(const TopRArgs &t, int sb, double v[4], uint64_t ix[4]) const {
+  // origins are multiples of 32: a bin exists iff the origin and (ml, nl) do.
+  // The bins' type is a template parameter: the loads of several sub-tiles
+  // stay in flight together (no branch between a load and its conversion).
+  // (an inactive call reads bin 0 and marks every entry absent: no branch
+  // around the loads, whose results must not be waited for one by one)
+  template <bool OUTF>
+  __device__ void load(const TopRArgs &t, int sb, bool active, double v[4], uint64_t ix[4]) const {
     uint32_t m0, n0;
     sub_origin(sb, lmt, lnt, nmaj, m0, n0);
-    const bool sub_ok = m0 < M && n0 < N;
-    const int64_t o0 = sub_ok ? map_y(t.m, m0) + map_y(t.n, n0) : 0;
+    const bool sub_ok = active && m0 < M && n0 < N;
+    const int64_t o0 = sub_ok ? offset(t, m0, n0) : 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) ix[q] = (sub_ok && ok[q]) ? (uint64_t)(o0 + o_lane[q]) : ~uint64_t(0);
-    if (t.out_f32) {
+    typedef typename std::conditional<OUTF, float, double>::type O;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        v[q] = (double)static_cast<const float *>(t.C)[ix[q] == ~uint64_t(0) ? 0 : ix[q]];
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = static_cast<const double *>(t.C)[ix[q] == ~uint64_t(0) ? 0 : ix[q]];
-    }
+    for (int q = 0; q < 4; ++q) v[q] = (double)static_cast<const O *>(t.C)[ix[q] == ~uint64_t(0) ? 0 : ix[q]];
   }
 };
 
@@ -628,7 +636,18 @@ struct TopBuf {
         v = val[e];
         i = idx[e];
         rank = 0;
-        for (int q = 0; q < n; ++q) rank += better(val[q], idx[q], v, i) ? 1 : 0;
+        // (entries past n compare as worse: the loop reads 4 at a time)
+        for (int q = 0; q < n; q += 4) {
+          double vq[4];
+          uint64_t iq[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            vq[u] = val[q + u];
+            iq[u] = idx[q + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) rank += (q + u < n && better(vq[u], iq[u], v, i)) ? 1 : 0;
+        }
       }
       if (rank < R) {
         tv[rank] = v;
@@ -675,32 +694,53 @@ struct TopBuf {
     }
     __syncthreads();
   }
-  // add the thread's up to 4 entries (at most 4 * kTThreads <= kBufCap - R
-  // in all, so one cut always makes room)
-  __device__ void add(const double v[4], const uint64_t ix[4], double tau, int R, int *wsum) {
-    int k = 0;
-    for (int q = 0; q < 4; ++q) k += wants(v[q], ix[q], tau) ? 1 : 0;
-    int total;
-    int at = block_scan_excl(k, wsum, total);
-    if (n + total > kBufCap) {
-      cut(R);
-      k = 0;
-      for (int q = 0; q < 4; ++q) k += wants(v[q], ix[q], tau) ? 1 : 0;
-      at = block_scan_excl(k, wsum, total);
-    }
-    at += n;
-    for (int q = 0; q < 4; ++q)
-      if (wants(v[q], ix[q], tau)) {
-        val[at] = v[q];
-        idx[at] = ix[q];
-        ++at;
+  // add the wanted entries of the thread's first nu of NU groups of 4 (one
+  // scan when they fit; otherwise the buffer is cut to its R best, which
+  // raises the bar, and what still qualifies is appended as room allows,
+  // bit `done` marking the entries taken)
+  template <int NU>
+  __device__ void add_many(const double (&v)[NU][4], const uint64_t (&ix)[NU][4], int nu, double tau, int R,
+                           int *wsum, bool early_bar) {
+    uint32_t done = 0;
+    for (;;) {
+      int k = 0;
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          k += (u < nu && !((done >> (4 * u + q)) & 1) && wants(v[u][q], ix[u][q], tau)) ? 1 : 0;
+      int total;
+      int at = block_scan_excl(k, wsum, total);
+      if (total == 0) break;
+      if (n + total > kBufCap && n > R) {
+        cut(R);
+        continue;
       }
-    n += total;
-    __syncthreads();
-    if (!have_bar && n >= R) cut(R);  // a bar as early as possible
+      const int room = kBufCap - n;
+      at += n;
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (u < nu && !((done >> (4 * u + q)) & 1) && wants(v[u][q], ix[u][q], tau)) {
+            if (at < kBufCap) {
+              val[at] = v[u][q];
+              idx[at] = ix[u][q];
+              done |= 1u << (4 * u + q);
+            }
+            ++at;
+          }
+      n += total < room ? total : room;
+      __syncthreads();
+      if (early_bar && !have_bar && n >= R) cut(R);  // a bar as early as possible
+      if (total <= room) break;
+    }
   }
 };
 
+constexpr int kVisit = 8;  // sub-tiles whose loads are in flight together
+
+template <bool OUTF>
 __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int nb) {
   __shared__ double sv[kNG];
   __shared__ int wsum[kTW];
@@ -715,10 +755,15 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
   __shared__ uint64_t lorg[kTThreads];
   __shared__ double rmx[kTThreads];
   __shared__ uint64_t rhi[kTThreads];
+  __shared__ double wmax[kTW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = t.top_r;
   const int G = t.ngroups;
   const int ng = G < kNG ? G : kNG;  // group g: GEMM work-groups [g G / ng, (g+1) G / ng)
+  // the first run's sub-tile maxima, loaded now so that their latency hides
+  // behind the threshold
+  const int sb_first = bid * kTThreads + tid;
+  const double mx_first = sb_first < t.nsub ? t.blk_max[sb_first] : -INFINITY;
 
   // ---- group maxima (and, in work-group 0, the total sum) ----
   double s = 0.0, c = 0.0, gm = -INFINITY;
@@ -749,17 +794,32 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
     }
   }
 
-  // ---- threshold: the R-th best group maximum (value descending, group
-  // ascending): each group counts the groups better than it, reading every
-  // maximum from LDS (all lanes read the same entry: one broadcast per step) ----
-  sv[tid] = gm;  // -inf past the ng groups
-  if (tid == 0) s_tau = -INFINITY;
+  // ---- threshold tau: the R-th largest maximum of nc groups, each 2^cs
+  // consecutive groups above (coarser when R is small: R groups still hold a
+  // bin >= tau each).  Group g counts the maxima >= its own; tau is the
+  // largest maximum reached by at least R of them. ----
+  int cs = 0;
+  while (cs < 2 && (ng >> (cs + 1)) >= 4 * R) ++cs;
+  const int nc = (ng + (1 << cs) - 1) >> cs;
+  double cm = gm;  // -inf past the ng groups
+  for (int off = 1; off < (1 << cs); off <<= 1) cm = fmax(cm, __shfl_xor(cm, off));
+  if ((tid & ((1 << cs) - 1)) == 0) sv[tid >> cs] = cm;
   __syncthreads();
-  if (ng >= R && tid < ng) {
-    int rank = 0;
+  double cand = -INFINITY;
+  if (nc >= R && tid < nc) {
+    const double me = sv[tid];
+    int cnt = 0;
 #pragma unroll 8
-    for (int j = 0; j < ng; ++j) rank += better(sv[j], (uint64_t)j, gm, (uint64_t)tid) ? 1 : 0;
-    if (rank == R - 1) s_tau = gm;
+    for (int j = 0; j < nc; ++j) cnt += sv[j] >= me ? 1 : 0;
+    if (cnt >= R) cand = me;
+  }
+  for (int off = 32; off >= 1; off >>= 1) cand = fmax(cand, __shfl_xor(cand, off));
+  if (lane == 0) wmax[wave] = cand;
+  __syncthreads();
+  if (tid == 0) {
+    double m = wmax[0];
+    for (int q = 1; q < kTW; ++q) m = fmax(m, wmax[q]);
+    s_tau = m;  // -inf with fewer groups than R
   }
   __syncthreads();
   const double tau = s_tau;  // -inf with fewer groups than R
@@ -790,7 +850,7 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
     const int sb = base + tid;
     const uint64_t org = sb < t.nsub ? stb.origin(t, sb) : ~uint64_t(0);
     const bool holds = org != ~uint64_t(0);
-    const double mx = holds ? t.blk_max[sb] : -INFINITY;
+    const double mx = !holds ? -INFINITY : (base == bid * kTThreads ? mx_first : t.blk_max[sb]);
     int keep = (holds && mx >= tau && may_improve(mx, org)) ? 1 : 0;
     int total;
     int at = block_scan_excl(keep, wsum, total);
@@ -817,7 +877,7 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
       lorg[at] = org;
     }
     __syncthreads();
-    if (total > 4) {
+    if (total > 1) {
       // visit the candidates best first (larger maximum, then lower origin)
       // so that the running R-th best rises fast and prunes the rest
       int rank = 0, sbk = 0;
@@ -837,25 +897,24 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
       }
       __syncthreads();
     }
-    // up to four sub-tiles' loads in flight (one while there is no R-th best
-    // yet); each listed sub-tile is checked again against the running R-th best
+    // up to kVisit sub-tiles' loads in flight together (a long list starts
+    // with one, to set an R-th best); each listed sub-tile is checked again
+    // against the running R-th best
     for (int q = 0; q < total;) {
-      const int nl = min((buf.have_bar || q > 0) ? 4 : 1, total - q);
-      double v[4][4];
-      uint64_t ix[4][4];
+      const int nl = min((buf.have_bar || q > 0 || total <= kVisit) ? kVisit : 1, total - q);
+      double v[kVisit][4];
+      uint64_t ix[kVisit][4];
+      bool go[kVisit];
+      int sbv[kVisit];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (u < nl && may_improve(lmx[q + u], lorg[q + u])) {
-          stb.load(t, list[q + u], v[u], ix[u]);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            v[u][e] = 0.0;
-            ix[u][e] = ~uint64_t(0);
-          }
-        }
+      for (int u = 0; u < kVisit; ++u) {
+        const int qu = q + u < total ? q + u : q;
+        go[u] = u < nl && may_improve(lmx[qu], lorg[qu]);
+        sbv[u] = list[qu];
       }
-      for (int u = 0; u < nl; ++u) buf.add(v[u], ix[u], tau, R, wsum);
+#pragma unroll
+      for (int u = 0; u < kVisit; ++u) stb.template load<OUTF>(t, sbv[u], go[u], v[u], ix[u]);
+      buf.add_many(v, ix, nl, tau, R, wsum, true);
       q += nl;
     }
     __syncthreads();  // list is rewritten by the next round
@@ -885,17 +944,17 @@ __device__ __forceinline__ void topr_rank_body(const TopRArgs &t) {
   // slot entries f = w R + j, j < slot_n[w]
   const int npos = t.gather_groups * R;
   for (int f0 = 0; f0 < npos; f0 += 4 * kTThreads) {
-    double v[4];
-    uint64_t ix[4];
+    double v[1][4];
+    uint64_t ix[1][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int f = f0 + q * kTThreads + tid, ff = f < npos ? f : 0;
       const int cn = t.slot_n[ff / R];
-      v[q] = t.slot_val[ff];
-      ix[q] = t.slot_idx[ff];
-      if (!(f < npos && ff % R < cn)) ix[q] = ~uint64_t(0);
+      v[0][q] = t.slot_val[ff];
+      ix[0][q] = t.slot_idx[ff];
+      if (!(f < npos && ff % R < cn)) ix[0][q] = ~uint64_t(0);
     }
-    buf.add(v, ix, tau, R, wsum);
+    buf.add_many(v, ix, 1, tau, R, wsum, false);
   }
   buf.cut(R);
   if (tid < R) {
@@ -905,18 +964,20 @@ __device__ __forceinline__ void topr_rank_body(const TopRArgs &t) {
   if (tid == 0) *t.sum_out = t.tau_sum[1];
 }
 
+template <bool OUTF>
 __global__ __launch_bounds__(kTThreads) void topr_gather(TopRArgs t) {
-  topr_gather_body(t, blockIdx.x, gridDim.x);
+  topr_gather_body<OUTF>(t, blockIdx.x, gridDim.x);
 }
 __global__ __launch_bounds__(kTThreads) void topr_rank(TopRArgs t) { topr_rank_body(t); }
 
 // Batched top-R: job j's gather takes work-groups [start[j], start[j + 1]),
 // then one rank work-group per job.
+template <bool OUTF>
 __global__ __launch_bounds__(kTThreads) void topr_gather_grouped(const TopRArgs *__restrict__ jobs,
                                                                  const int *__restrict__ start, int n) {
   const int j = find_job(start, n, blockIdx.x);
   const int s0 = start[j];
-  topr_gather_body(jobs[j], (int)blockIdx.x - s0, start[j + 1] - s0);
+  topr_gather_body<OUTF>(jobs[j], (int)blockIdx.x - s0, start[j + 1] - s0);
 }
 __global__ __launch_bounds__(kTThreads) void topr_rank_grouped(const TopRArgs *__restrict__ jobs) {
   topr_rank_body(jobs[blockIdx.x]);
@@ -1135,7 +1196,8 @@ int launch_gemm(const GemmArgs &g_in, int prec, hipStream_t s) {
 }
 
 void launch_topr(const TopRArgs &t, hipStream_t s) {
-  hipLaunchKernelGGL(topr_gather, dim3((unsigned)t.gather_groups), dim3(kTThreads), 0, s, t);
+  if (t.out_f32) hipLaunchKernelGGL(topr_gather<true>, dim3((unsigned)t.gather_groups), dim3(kTThreads), 0, s, t);
+  else hipLaunchKernelGGL(topr_gather<false>, dim3((unsigned)t.gather_groups), dim3(kTThreads), 0, s, t);
   hipLaunchKernelGGL(topr_rank, dim3(1), dim3(kTThreads), 0, s, t);
 }
 
@@ -1144,8 +1206,11 @@ int topr_gather_groups(int64_t nsub) {
   return (int)(g < 1 ? 1 : (g > kTopRSlots ? kTopRSlots : g));
 }
 
-void launch_topr_grouped(const TopRArgs *jobs, const int *start, int n, int total, hipStream_t s) {
-  hipLaunchKernelGGL(topr_gather_grouped, dim3((unsigned)total), dim3(kTThreads), 0, s, jobs, start, n);
+void launch_topr_grouped(const TopRArgs *jobs, const int *start, int n, int total, int out_f32, hipStream_t s) {
+  if (out_f32)
+    hipLaunchKernelGGL(topr_gather_grouped<true>, dim3((unsigned)total), dim3(kTThreads), 0, s, jobs, start, n);
+  else
+    hipLaunchKernelGGL(topr_gather_grouped<false>, dim3((unsigned)total), dim3(kTThreads), 0, s, jobs, start, n);
   hipLaunchKernelGGL(topr_rank_grouped, dim3((unsigned)n), dim3(kTThreads), 0, s, jobs);
 }
 
