@@ -54,6 +54,10 @@ __device__ __forceinline__ void merge_tiles_body(const MergeArgs &a, int64_t til
   const int RB = R < TB ? R : TB;             // rows that own distinct bins
   const int YG = R / RB;                      // rows that split y inside the group
   const int BPT = TB / RB;                    // bins per thread
+  // LDS row stride: one pad entry per row of 32 or more labels, so the
+  // transposed reads (consecutive lanes on consecutive rows) fall on distinct
+  // banks (at most 2048 / 32 = 64 pads: the tile's spare)
+  const int TSP = TS + (TS >= 32 ? 1 : 0);
   const int tid = threadIdx.x;
   const int sl = tid & (TS - 1);
   const int r = tid >> a.ts_bits;
@@ -107,14 +111,15 @@ __device__ __forceinline__ void merge_tiles_body(const MergeArgs &a, int64_t til
   }
 #pragma unroll
   for (int i = 0; i < kMaxBPT; ++i)
-    if (i < BPT) tile[(g * TB + brow + RB * i) * TS + sl] = acc[i];
+    if (i < BPT) tile[(g * TB + brow + RB * i) * TSP + sl] = acc[i];
   __syncthreads();
-  // combine the y groups in order; result at tile[bl * TS + sl]
+  // combine the y groups in order; result at tile[bl * TSP + sl]
   if (YG > 1) {
     for (int q = tid; q < TB * TS; q += kThreads) {
-      double s = tile[q];
-      for (int gg = 1; gg < YG; ++gg) s += tile[gg * TB * TS + q];
-      tile[q] = s;
+      const int row = q >> a.ts_bits, col = q & (TS - 1);
+      double s = tile[row * TSP + col];
+      for (int gg = 1; gg < YG; ++gg) s += tile[(gg * TB + row) * TSP + col];
+      tile[row * TSP + col] = s;
     }
     __syncthreads();
   }
@@ -124,7 +129,7 @@ __device__ __forceinline__ void merge_tiles_body(const MergeArgs &a, int64_t til
     for (int q = tid; q < TB * TS; q += kThreads) {
       int bl = q & (TB - 1);
       int s = q >> a.tb_bits;
-      double v = tile[bl * TS + s];
+      double v = tile[bl * TSP + s];
       int64_t o = ((int64_t(st) << a.ts_bits) + s) * nb + b0 + bl;
       if (a.out_f32) static_cast<float *>(a.out)[o] = (float)v;
       else static_cast<double *>(a.out)[o] = v;
@@ -133,7 +138,7 @@ __device__ __forceinline__ void merge_tiles_body(const MergeArgs &a, int64_t til
     for (int q = tid; q < TB * TS; q += kThreads) {
       int s = q & (TS - 1);
       int bl = q >> a.ts_bits;
-      a.partial[(int64_t(p) * nb + b0 + bl) * L + (int64_t(st) << a.ts_bits) + s] = tile[bl * TS + s];
+      a.partial[(int64_t(p) * nb + b0 + bl) * L + (int64_t(st) << a.ts_bits) + s] = tile[bl * TSP + s];
     }
   }
 }
