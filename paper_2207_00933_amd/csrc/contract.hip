@@ -27,6 +27,9 @@
 // result store run along m, the contiguous output axis.
 #include "common.hpp"
 
+#include <rocprim/warp/warp_reduce.hpp>
+#include <rocprim/warp/warp_scan.hpp>
+
 #include <hip/hip_ext.h>
 
 #include <mutex>
@@ -516,14 +519,14 @@ constexpr int kTThreads = 64 * kTW;
 constexpr int kNG = kTThreads;            // groups of GEMM work-groups
 constexpr int kBufCap = 2048;             // buffered entries per work-group
 
-// Exclusive prefix of v over the work-group; `total` gets the sum.
+// Exclusive prefix of v over the work-group; `total` gets the sum.  The wave
+// prefix is rocPRIM's (cross-lane DPP moves, no LDS round trips).
 __device__ int block_scan_excl(int v, int *wsum, int &total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int incl = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int o = __shfl_up(incl, off);
-    if (lane >= off) incl += o;
-  }
+  using WaveScan = rocprim::warp_scan<int, 64>;
+  __shared__ typename WaveScan::storage_type scan_st[kTW];
+  int incl;
+  WaveScan().inclusive_scan(v, incl, scan_st[w]);
   if (lane == 63) wsum[w] = incl;
   __syncthreads();
   int before = 0;
@@ -813,7 +816,13 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
     for (int j = 0; j < nc; ++j) cnt += sv[j] >= me ? 1 : 0;
     if (cnt >= R) cand = me;
   }
-  for (int off = 32; off >= 1; off >>= 1) cand = fmax(cand, __shfl_xor(cand, off));
+  {
+    using WaveMax = rocprim::warp_reduce<double, 64>;
+    __shared__ typename WaveMax::storage_type max_st[kTW];
+    double m;
+    WaveMax().reduce(cand, m, max_st[wave], rocprim::maximum<double>());
+    cand = m;  // lane 0 holds the wave's maximum
+  }
   if (lane == 0) wmax[wave] = cand;
   __syncthreads();
   if (tid == 0) {
