@@ -14,7 +14,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_util import say
+from gpu_util import error_bound, say
 
 pytestmark = pytest.mark.gpu
 
@@ -166,3 +166,68 @@ def test_topr_product_ties(session, d0, d1):
             assert np.array_equal(t[0:2 * R:2], b[order])
             assert np.array_equal(t[1:2 * R:2].view(np.uint64), order.astype(np.uint64))
             assert bsum.item() == math.fsum(b.tolist())
+
+
+class _Cuts:
+    """Cut-list view for the oracle's contraction (one wire per subcircuit,
+    bins taken as given)."""
+
+    class _C:
+        def __init__(self, u, v):
+            self.up_sub, self.up_wire, self.down_sub, self.down_wire = u, 0, v, 0
+
+    def __init__(self, n, cuts):
+        self.n_sub = n
+        self.cuts = [self._C(u, v) for u, v in cuts]
+
+    def incident(self, i):
+        out = []
+        for k, c in enumerate(self.cuts):
+            if c.down_sub == i:
+                out.append((k, "in"))
+            elif c.up_sub == i:
+                out.append((k, "out"))
+        return out
+
+
+@pytest.mark.parametrize("pname,prec", PRECS)
+def test_topr_interleaved_final_maps(session, pname, prec):
+    """Subcircuits 0 and 2 share two cuts and are contracted first, so the
+    final contraction's m side holds the bins of subcircuits 0 and 2, which
+    are not adjacent in the bin index (two-run index map: the top-R stage's
+    general sub-tile addressing).  Random signed tensors; bins against the
+    oracle's contraction, top-R against a stable sort of the same bins."""
+    from oracle import network
+    bits, cuts = [6, 7, 6], [(0, 2), (0, 2), (2, 1)]
+    cc = _Cuts(3, cuts)
+    rng = np.random.default_rng(77)
+    Ts = [rng.standard_normal((1 << (2 * len(cc.incident(i))), 1 << bits[i])) for i in range(3)]
+    if prec != sqc.F64:
+        Ts = [T.astype(np.float32).astype(np.float64) for T in Ts]
+    want = network.contract_all(Ts, cc)
+    g = sqc.Graph([1] * 3, [[] for _ in bits], [(u, 0, v, 0) for u, v in cuts])
+    in_prec = sqc.F64 if prec == sqc.F64 else sqc.F32
+    dt = torch.float64 if in_prec == sqc.F64 else torch.float32
+    # attributed layout [x][sigma]: the transpose of the oracle's [sigma][x]
+    bufs = [torch.from_numpy(np.ascontiguousarray(T.T)).to(dt).cuda() for T in Ts]
+    att = [sqc.tensor_desc(b, len(cc.incident(i)), bits[i], in_prec, sqc.LAYOUT_ATTRIBUTED)
+           for i, b in enumerate(bufs)]
+    M = 1 << sum(bits)
+    masks = sqc.assign_bins(bits, None, M)
+    session.ensure_workspace(sqc.recurse_workspace_bytes(att, g, masks, prec))
+    # error bound: unit roundoff of the path times the contraction of |T|
+    bound = error_bound(Ts, cc) * {sqc.F64: 1e-13, sqc.F32: 2.0 ** -20, sqc.BF16X3: 2.0 ** -13}[prec]
+    for R in (1, 16, 64):
+        say(f"topr interleaved {pname} R={R}")
+        bins = torch.empty(M, dtype=torch.float64, device="cuda")
+        top = torch.empty(2 * sqc.MAX_TOPR, dtype=torch.float64, device="cuda")
+        bsum = torch.empty(1, dtype=torch.float64, device="cuda")
+        sqc.recurse(session.ctx, att, g, None, M, R, prec, bins, sqc.F64, top, bsum)
+        torch.cuda.synchronize()
+        b = bins.cpu().numpy()
+        assert np.all(np.abs(b - want) <= bound + 1e-300)
+        t = top.cpu().numpy()
+        order = np.argsort(-b, kind="stable")[:R]
+        assert np.array_equal(t[0:2 * R:2], b[order])
+        assert np.array_equal(t[1:2 * R:2].view(np.uint64), order.astype(np.uint64))
+        assert abs(bsum.item() - math.fsum(b.tolist())) <= 1e-12 * math.fsum(np.abs(b).tolist())
