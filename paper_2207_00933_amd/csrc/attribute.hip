@@ -8,7 +8,8 @@
 // consecutive data states.  Its entries p[(s, beta)][x, b] for all
 // preparations s and out-cut outcomes b are loaded, the maps of the first
 // three out-cuts are applied in registers, the rest are staged in LDS and the
-// other maps applied in place, one pass per cut, and every label assignment
+// other maps applied in place (one pass per out-cut, one per two in-cuts),
+// and every label assignment
 // compatible with beta is written (beta(I) = beta(Z) = Z, so a Z basis serves
 // I and Z).  Loops over cuts have fixed bounds so that the parameters they
 // read are fetched together rather than one dependent read per iteration.
@@ -262,9 +263,37 @@ __device__ __forceinline__ void attribute_lds_body(const AttrJob &a, int blk, un
     }
     __syncthreads();
   }
-  // in-cut maps: digit j of s, 4 entries -> labels I, X, Y, Z
-  for (int j = 0; j < a.n_in; ++j) {
-    const int sh = 2 * j + a.xt_bits + a.n_out;
+  // in-cut maps: digit j of s, 4 entries -> labels I, X, Y, Z.  Two digits
+  // per LDS pass while two are left (a thread maps the 16 entries of one
+  // block of digits j and j + 1 in registers), then a last single digit.
+  auto map4 = [](double &p0, double &p1, double &p2, double &p3) {
+    const double s01 = p0 + p1;
+    const double z = p0 - p1;
+    p0 = s01;
+    p1 = 2.0 * p2 - s01;
+    p2 = 2.0 * p3 - s01;
+    p3 = z;
+  };
+  int jd = 0;
+  for (; jd + 1 < a.n_in; jd += 2) {
+    const int sh = 2 * jd + a.xt_bits + a.n_out;
+    const int st = 1 << sh;  // digit jd at stride st, digit jd + 1 at 4 st
+    for (int p = tid; p < E / 16; p += kThreads) {
+      const int e1 = ((p >> sh) << (sh + 4)) | (p & (st - 1));
+      double q[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) q[r] = buf[phys(e1 + (r & 3) * st + (r >> 2) * 4 * st)];
+#pragma unroll
+      for (int r1 = 0; r1 < 4; ++r1) map4(q[4 * r1], q[4 * r1 + 1], q[4 * r1 + 2], q[4 * r1 + 3]);
+#pragma unroll
+      for (int r0 = 0; r0 < 4; ++r0) map4(q[r0], q[r0 + 4], q[r0 + 8], q[r0 + 12]);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) buf[phys(e1 + (r & 3) * st + (r >> 2) * 4 * st)] = q[r];
+    }
+    __syncthreads();
+  }
+  if (jd < a.n_in) {
+    const int sh = 2 * jd + a.xt_bits + a.n_out;
     const int st = 1 << sh;
     for (int p0 = 0; p0 < E / 4; p0 += 2 * kThreads) {
       double q[2][4];
@@ -279,11 +308,9 @@ __device__ __forceinline__ void attribute_lds_body(const AttrJob &a, int blk, un
 #pragma unroll
       for (int u = 0; u < 2; ++u)
         if (e1[u] >= 0) {
-          const double s01 = q[u][0] + q[u][1];
-          buf[phys(e1[u])] = s01;
-          buf[phys(e1[u] + st)] = 2.0 * q[u][2] - s01;
-          buf[phys(e1[u] + 2 * st)] = 2.0 * q[u][3] - s01;
-          buf[phys(e1[u] + 3 * st)] = q[u][0] - q[u][1];
+          map4(q[u][0], q[u][1], q[u][2], q[u][3]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) buf[phys(e1[u] + r * st)] = q[u][r];
         }
     }
     __syncthreads();
