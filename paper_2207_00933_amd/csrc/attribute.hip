@@ -265,7 +265,7 @@ __device__ __forceinline__ void attribute_lds_body(const AttrJob &a, int blk, un
   }
   // in-cut maps: digit j of s, 4 entries -> labels I, X, Y, Z.  Two digits
   // per LDS pass while two are left (a thread maps the 16 entries of one
-  // block of digits j and j + 1 in registers), then a last single digit.
+  // block of digits j and j + 1 in registers).
   auto map4 = [](double &p0, double &p1, double &p2, double &p3) {
     const double s01 = p0 + p1;
     const double z = p0 - p1;
@@ -292,29 +292,11 @@ __device__ __forceinline__ void attribute_lds_body(const AttrJob &a, int blk, un
     }
     __syncthreads();
   }
-  if (jd < a.n_in) {
-    const int sh = 2 * jd + a.xt_bits + a.n_out;
-    const int st = 1 << sh;
-    for (int p0 = 0; p0 < E / 4; p0 += 2 * kThreads) {
-      double q[2][4];
-      int e1[2];
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int p = p0 + u * kThreads + tid;
-        e1[u] = p < E / 4 ? ((p >> sh) << (sh + 2)) | (p & (st - 1)) : -1;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) q[u][r] = e1[u] >= 0 ? buf[phys(e1[u] + r * st)] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-        if (e1[u] >= 0) {
-          map4(q[u][0], q[u][1], q[u][2], q[u][3]);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) buf[phys(e1[u] + r * st)] = q[u][r];
-        }
-    }
-    __syncthreads();
-  }
+  // an odd last digit is applied by the output loop, which reads the two or
+  // three entries each label needs (one LDS pass fewer)
+  const bool lazy = jd < a.n_in;
+  const int lsh = 2 * jd;
+  const int lst = 1 << (2 * jd + a.xt_bits + a.n_out);
 
   // every label assignment compatible with beta: q = (xt, v, s), s fastest
   const int lNS = 2 * a.n_in;
@@ -325,7 +307,19 @@ __device__ __forceinline__ void attribute_lds_body(const AttrJob &a, int blk, un
     const int rest = q >> lNS;
     const int vv = rest & (NV - 1);
     const int xt = rest >> nz;
-    const double val = buf[phys((sdx * XT + xt) * NB + slot[vv])] * a.scale;
+    const int eo = (sdx * XT + xt) * NB + slot[vv];
+    double val;
+    if (lazy) {
+      const int dl = (sdx >> lsh) & 3;  // label digit of the last in-cut
+      const int eb = eo - dl * lst;
+      const double p0 = buf[phys(eb)], p1 = buf[phys(eb + lst)];
+      const double pk = buf[phys(eb + (dl == 2 ? 3 : 2) * lst)];  // |+> for X, |+i> for Y
+      const double s01 = p0 + p1;
+      val = dl == 0 ? s01 : (dl == 3 ? p0 - p1 : 2.0 * pk - s01);
+    } else {
+      val = buf[phys(eo)];
+    }
+    val *= a.scale;
     const int64_t o = (x0 + xt) * L + (sinl[sdx] | sout[vv]);
     if constexpr (OUT_F32) static_cast<float *>(a.out)[o] = (float)val;
     else static_cast<double *>(a.out)[o] = val;
