@@ -627,10 +627,60 @@ struct TopBuf {
   double *tv;      // [SQC_MAX_TOPR] staging of a small selection
   uint64_t *ti;
   // keep the R best, in order (better first): few entries are ranked by
-  // counting the better ones, more are sorted by a bitonic network (padded
-  // to a power of two with entries worse than any bin)
+  // counting the better ones; of many, a few best are taken one at a time
+  // (work-group argmax), more are sorted by a bitonic network (padded to a
+  // power of two with entries worse than any bin)
   __device__ void cut(int R) {
-    if (n <= kTThreads) {
+    if (n > kTThreads && R <= 8) {
+      __shared__ double sel_v[kTW];
+      __shared__ uint64_t sel_i[kTW];
+      __shared__ int sel_e[kTW];
+      const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+      for (int r = 0; r < R; ++r) {
+        double bv = -INFINITY;
+        uint64_t bi = ~uint64_t(0);
+        int be = -1;
+        for (int e = threadIdx.x; e < n; e += kTThreads) {
+          const uint64_t ie = idx[e];
+          const double ve = val[e];
+          if (ie != ~uint64_t(0) && (be < 0 || better(ve, ie, bv, bi))) {
+            bv = ve;
+            bi = ie;
+            be = e;
+          }
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+          const double ov = __shfl_xor(bv, off);
+          const uint64_t oi = __shfl_xor(bi, off);
+          const int oe = __shfl_xor(be, off);
+          if (oe >= 0 && (be < 0 || better(ov, oi, bv, bi))) {
+            bv = ov;
+            bi = oi;
+            be = oe;
+          }
+        }
+        if (lane == 0) {
+          sel_v[w] = bv;
+          sel_i[w] = bi;
+          sel_e[w] = be;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          int q = -1;
+          for (int x = 0; x < kTW; ++x)
+            if (sel_e[x] >= 0 && (q < 0 || better(sel_v[x], sel_i[x], sel_v[q], sel_i[q]))) q = x;
+          tv[r] = sel_v[q];  // n > R: every round finds an entry
+          ti[r] = sel_i[q];
+          idx[sel_e[q]] = ~uint64_t(0);  // taken
+        }
+        __syncthreads();
+      }
+      if ((int)threadIdx.x < R) {
+        val[threadIdx.x] = tv[threadIdx.x];
+        idx[threadIdx.x] = ti[threadIdx.x];
+      }
+      __syncthreads();
+    } else if (n <= kTThreads) {
       const int e = threadIdx.x;
       double v = 0.0;
       uint64_t i = 0;
@@ -756,8 +806,6 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
   __shared__ int list[kTThreads];
   __shared__ double lmx[kTThreads];
   __shared__ uint64_t lorg[kTThreads];
-  __shared__ double rmx[kTThreads];
-  __shared__ uint64_t rhi[kTThreads];
   __shared__ double wmax[kTW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = t.top_r;
@@ -860,32 +908,45 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
     const uint64_t org = sb < t.nsub ? stb.origin(t, sb) : ~uint64_t(0);
     const bool holds = org != ~uint64_t(0);
     const double mx = !holds ? -INFINITY : (base == bid * kTThreads ? mx_first : t.blk_max[sb]);
-    int keep = (holds && mx >= tau && may_improve(mx, org)) ? 1 : 0;
+    const int keep = (holds && mx >= tau && may_improve(mx, org)) ? 1 : 0;
     int total;
-    int at = block_scan_excl(keep, wsum, total);
-    if (total > 2 * R) {
-      // Many candidates (a flat top).  Sub-tile T's maximum is a bin that
-      // beats every bin of sub-tile S when it is larger than S's maximum, or
-      // equal to it with T's last bin below S's origin; a sub-tile beaten so
-      // by R others holds none of the R best.
-      rmx[tid] = mx;
-      rhi[tid] = holds ? org + stb.span : ~uint64_t(0);
-      __syncthreads();
-      int beaten = 0;
-#pragma unroll 4
-      for (int j = 0; j < kTThreads; ++j) {
-        const double xj = rmx[j];
-        beaten += (xj > mx || (xj == mx && rhi[j] < org)) ? 1 : 0;
-      }
-      keep = keep && beaten < R ? 1 : 0;
-      at = block_scan_excl(keep, wsum, total);
-    }
+    const int at = block_scan_excl(keep, wsum, total);
     if (keep) {
       list[at] = sb;
       lmx[at] = mx;
       lorg[at] = org;
     }
     __syncthreads();
+    if (total > 2 * R) {
+      // Many candidates (a flat top).  Sub-tile T's maximum is a bin that
+      // beats every bin of sub-tile S when it is larger than S's maximum, or
+      // equal to it with T's last bin below S's origin; a sub-tile beaten so
+      // by R others holds none of the R best.  Every sub-tile that beats a
+      // listed one is listed itself, so the count runs over the list.
+      int keep2 = 0, sbk = 0;
+      double mk = 0.0;
+      uint64_t gk = 0;
+      if (tid < total) {
+        sbk = list[tid];
+        mk = lmx[tid];
+        gk = lorg[tid];
+        int beaten = 0;
+        for (int j = 0; j < total; ++j) {
+          const double xj = lmx[j];
+          beaten += (xj > mk || (xj == mk && lorg[j] + stb.span < gk)) ? 1 : 0;
+        }
+        keep2 = beaten < R ? 1 : 0;
+      }
+      int total2;
+      const int at2 = block_scan_excl(keep2, wsum, total2);  // (its barriers end the reads above)
+      if (keep2) {
+        list[at2] = sbk;
+        lmx[at2] = mk;
+        lorg[at2] = gk;
+      }
+      total = total2;
+      __syncthreads();
+    }
     if (total > 1) {
       // visit the candidates best first (larger maximum, then lower origin)
       // so that the running R-th best rises fast and prunes the rest
