@@ -447,8 +447,16 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
         lmax = omax;
       }
       if (g.stats) {
-        // sub-tile maximum in the stored type (one shuffle per step)
-        for (int off = 32; off >= 1; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
+        // sub-tile maximum in the stored type, reduced by rocPRIM's wave
+        // reduction (DPP lane moves; fmax keeps NaN out); valid in lane 0,
+        // the only lane that uses it
+        {
+          using WaveMax = rocprim::warp_reduce<O, 64>;
+          __shared__ typename WaveMax::storage_type max_st[4];
+          O m;
+          WaveMax().reduce(lmax, m, max_st[wave], [](O x, O y) { return fmax(x, y); });
+          lmax = m;
+        }
         if (lane == 0) g.blk_max[(int64_t)cur_tile * 4 + wave] = (double)lmax;
         neumaier(wsum, wcmp, lsum);
         wmax = fmax(wmax, (double)lmax);
