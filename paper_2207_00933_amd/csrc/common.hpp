@@ -186,7 +186,7 @@ struct GemmArgs {
   double *blk_max;       // [4 * tiles] largest stored bin of each 32 x 32 sub-tile
   double *wg_stats;      // [3 * work-groups] per work-group: FP64 sum, its
                          // compensation, largest stored bin (work-group g owns
-                         // the tiles [g T / G, (g + 1) T / G))
+                         // a contiguous chunk of the tiles, chunks in order)
   // filled by launch_gemm: offsets of the low index bits the kernel adds to
   // a wave's origin (index maps are linear in disjoint bit fields)
   int64_t koff_a[16];    // A offset of k = 0..15

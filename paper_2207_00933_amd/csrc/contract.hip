@@ -118,15 +118,18 @@ struct Sched {
   int id;          // its place in tile order
 };
 
-// Contiguous chunks of tiles per work-group; work-groups are dispatched
-// round-robin over 8 XCDs, so chunk order follows (XCD, work-group within the
-// XCD) and the chunks of one XCD are adjacent (shared A panels stay in its L2).
+// Contiguous chunks of tiles per work-group (the first ntiles % G chunks one
+// tile longer); work-groups are dispatched round-robin over 8 XCDs, so chunk
+// order follows (XCD, work-group within the XCD) and the chunks of one XCD are
+// adjacent (shared A panels stay in its L2).  32-bit quotient and remainder:
+// a 64-bit division costs a long scalar sequence per work-group.
 __device__ __forceinline__ Sched schedule(int ntiles, int b, int G) {
   const int lb = (G & 7) == 0 ? (b & 7) * (G >> 3) + (b >> 3) : b;
+  const int q = ntiles / G, r = ntiles - q * G;
   Sched s;
   s.id = lb;
-  s.first = (int)((int64_t)lb * ntiles / G);
-  s.end = (int)((int64_t)(lb + 1) * ntiles / G);
+  s.first = lb * q + (lb < r ? lb : r);
+  s.end = s.first + q + (lb < r ? 1 : 0);
   return s;
 }
 
