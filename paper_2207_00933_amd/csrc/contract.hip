@@ -243,8 +243,13 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   const bool kfull = REG || g.kbits >= 6;
   auto load_rows = [&](const T *p, T *v, int which, int s_shift, uint32_t k0) {
     if (kfull && kfast) {
+      // (the row step passes an empty asm statement, so its 16 multiples are
+      // formed here rather than hoisted into scalar registers for the whole
+      // kernel, which spills them)
+      int64_t step = (int64_t)1 << s_shift;
+      asm volatile("" : "+s"(step));
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) v[j] = p[(int64_t)j << s_shift];
+      for (int j = 0; j < NJ; ++j) v[j] = p[j * step];
     } else {
       const int kr = (int)(k0 + 16 * wave);
 #pragma unroll
@@ -438,13 +443,15 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
                 put(16 * im + (lane & 15), nl + (lane >> 4), om + on, acc[2 * jn + im][r]);
               }
         } else {
+          int64_t nstep = (int64_t)1 << g.n.ly[0];  // (formed per tile, as above)
+          asm volatile("" : "+s"(nstep));
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const uint32_t nl = 8 * (r >> 2) + (r & 3);
             double v;
             if constexpr (FOLD) v = S[r] + Cc[r];
             else v = (double)acc[0][r];
-            put(lane & 31, nl + 4 * (lane >> 5), SIMPLE ? (int64_t)nl << g.n.ly[0] : g.coff_n[r], v);
+            put(lane & 31, nl + 4 * (lane >> 5), SIMPLE ? (int64_t)nl * nstep : g.coff_n[r], v);
           }
         }
         lmax = omax;
