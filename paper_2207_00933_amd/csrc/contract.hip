@@ -772,16 +772,20 @@ struct TopBuf {
   template <int NU>
   __device__ void add_many(const double (&v)[NU][4], const uint64_t (&ix)[NU][4], int nu, double tau, int R,
                            int *wsum, bool early_bar) {
+    static_assert(4 * NU <= 32, "one bit per entry");
     uint32_t done = 0;
     for (;;) {
-      int k = 0;
+      // the entries this thread appends, one bit each (a per-lane register,
+      // not a lane mask per entry kept across the scan)
+      uint32_t want = 0;
 #pragma unroll
       for (int u = 0; u < NU; ++u)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          k += (u < nu && !((done >> (4 * u + q)) & 1) && wants(v[u][q], ix[u][q], tau)) ? 1 : 0;
+          want |= (u < nu && wants(v[u][q], ix[u][q], tau) ? 1u : 0u) << (4 * u + q);
+      want &= ~done;
       int total;
-      int at = block_scan_excl(k, wsum, total);
+      int at = block_scan_excl(__builtin_popcount(want), wsum, total);
       if (total == 0) break;
       if (n + total > kBufCap && n > R) {
         cut(R);
@@ -793,7 +797,7 @@ struct TopBuf {
       for (int u = 0; u < NU; ++u)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (u < nu && !((done >> (4 * u + q)) & 1) && wants(v[u][q], ix[u][q], tau)) {
+          if ((want >> (4 * u + q)) & 1) {
             if (at < kBufCap) {
               val[at] = v[u][q];
               idx[at] = ix[u][q];
