@@ -50,24 +50,26 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 // Offsets by index map: strides are powers of two, so each run is a shift.
-// Indices of one GEMM dimension fit 31 bits (checked on the host).
-__device__ __forceinline__ int64_t map_x(const IndexMap &m, uint32_t idx) {
+// Indices of one GEMM dimension fit 31 bits (checked on the host).  The first
+// four runs are evaluated unconditionally (runs past nruns are all-zero, so
+// they add nothing), which lets their parameters be fetched together instead
+// of one dependent scalar read per run; longer maps continue in a loop.
+template <bool Y>
+__device__ __forceinline__ int64_t map_off(const IndexMap &m, uint32_t idx) {
   int64_t off = 0;
-  for (int r = 0; r < m.nruns; ++r) {
-    off += int64_t(idx & ((1u << m.bits[r]) - 1u)) << m.lx[r];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    off += int64_t(idx & ((1u << m.bits[r]) - 1u)) << (Y ? m.ly[r] : m.lx[r]);
+    idx >>= m.bits[r];
+  }
+  for (int r = 4; r < m.nruns; ++r) {
+    off += int64_t(idx & ((1u << m.bits[r]) - 1u)) << (Y ? m.ly[r] : m.lx[r]);
     idx >>= m.bits[r];
   }
   return off;
 }
-
-__device__ __forceinline__ int64_t map_y(const IndexMap &m, uint32_t idx) {
-  int64_t off = 0;
-  for (int r = 0; r < m.nruns; ++r) {
-    off += int64_t(idx & ((1u << m.bits[r]) - 1u)) << m.ly[r];
-    idx >>= m.bits[r];
-  }
-  return off;
-}
+__device__ __forceinline__ int64_t map_x(const IndexMap &m, uint32_t idx) { return map_off<false>(m, idx); }
+__device__ __forceinline__ int64_t map_y(const IndexMap &m, uint32_t idx) { return map_off<true>(m, idx); }
 
 __device__ __forceinline__ void neumaier(double &s, double &c, double x) {
   double t = s + x;
