@@ -425,10 +425,14 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
         // with M, N >= 32 every element of a wave inside the result is inside
         const bool whole = REG || (g.mbits >= 5 && g.nbits >= 5);
         O omax = -INFINITY;
+        // FP32 results go out as non-temporal stores (the FP32 and
+        // split-BF16x3 steps measured faster so), FP64 results as ordinary
+        // stores (non-temporal measured slower there)
         auto put = [&](uint32_t mloc, uint32_t nloc, int64_t o, double v) {
           if (!whole && (mw + mloc >= M || nw + nloc >= N)) return;
           const O st = (O)v;
-          C[o] = st;
+          if constexpr (OUTF) __builtin_nontemporal_store(st, C + o);
+          else C[o] = st;
           lsum += v;
           omax = fmax(omax, st);
         };
