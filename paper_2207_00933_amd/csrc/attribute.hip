@@ -321,7 +321,7 @@ __device__ __forceinline__ void attribute_lds_body(const AttrJob &a, int blk, un
     }
     val *= a.scale;
     const int64_t o = (x0 + xt) * L + (sinl[sdx] | sout[vv]);
-    if constexpr (OUT_F32) static_cast<float *>(a.out)[o] = (float)val;
+    if constexpr (OUT_F32) __builtin_nontemporal_store((float)val, static_cast<float *>(a.out) + o);
     else static_cast<double *>(a.out)[o] = val;
   }
 }

@@ -131,7 +131,7 @@ __device__ __forceinline__ void merge_tiles_body(const MergeArgs &a, int64_t til
       int s = q >> a.tb_bits;
       double v = tile[bl * TSP + s];
       int64_t o = ((int64_t(st) << a.ts_bits) + s) * nb + b0 + bl;
-      if (a.out_f32) static_cast<float *>(a.out)[o] = (float)v;
+      if (a.out_f32) __builtin_nontemporal_store((float)v, static_cast<float *>(a.out) + o);
       else static_cast<double *>(a.out)[o] = v;
     }
   } else {
