@@ -68,3 +68,44 @@ def contract_all(Ts: Sequence[np.ndarray], cc) -> np.ndarray:
     spec += "->" + "".join(outl[::-1])  # subcircuit 0 least significant
     res = np.einsum(spec, *tens, optimize="greedy")
     return res.reshape(-1)
+
+
+class _WithoutCuts:
+    """The compute graph of ``cc`` with the cuts in ``drop`` removed (the
+    remaining cuts keep their order and are renumbered from 0)."""
+
+    def __init__(self, cc, drop):
+        drop = set(drop)
+        self.n_sub = cc.n_sub
+        self._keep = [k for k in range(len(cc.cuts)) if k not in drop]
+        self.cuts = [cc.cuts[k] for k in self._keep]
+        self._new = {k: j for j, k in enumerate(self._keep)}
+        self._cc = cc
+
+    def incident(self, i: int):
+        return [(self._new[k], role) for k, role in self._cc.incident(i) if k in self._new]
+
+
+def contract_sliced(Ts: Sequence[np.ndarray], cc, sliced: Sequence[int]) -> np.ndarray:
+    """First-level index slicing (Sec. 6.3): the cut indices in ``sliced``
+    are written out as an explicit outer sum.  For every label assignment of
+    those cuts (the first listed cut the least significant radix-4 digit),
+    each subcircuit's entries are restricted to the assigned labels, the graph
+    without the sliced cuts is contracted by ``contract_all``, and the slices'
+    vectors are added in ascending assignment order.  ``Ts`` carry the
+    1/2-per-cut factor."""
+    sliced = [int(k) for k in sliced]
+    if len(set(sliced)) != len(sliced):
+        raise ValueError("a cut is sliced twice")
+    rest = _WithoutCuts(cc, sliced)
+    total = None
+    for q in range(4 ** len(sliced)):
+        label = {k: (q >> (2 * j)) & 3 for j, k in enumerate(sliced)}
+        parts = []
+        for i in range(cc.n_sub):
+            t = _sub_tensor(cc, i, Ts[i])
+            sel = tuple(label[k] if k in label else slice(None) for k in _cut_axes(cc, i))
+            parts.append(t[sel + (slice(None),)].reshape(-1, Ts[i].shape[1]))
+        v = contract_all(parts, rest)
+        total = v if total is None else total + v
+    return total

@@ -168,3 +168,43 @@ def test_precision_config_sampled_brute_force():
             y |= ((idx >> (shift + j)) & 1) << q
         shift += sub.n_data
     assert np.abs(vals - Pb[y]).max() <= 1e-12
+
+
+# ---- first-level index slicing (Sec. 6.3): the sum over the slices' label
+# assignments is Eq. 1's sum split along the sliced cuts, so every slicing of
+# a circuit reproduces its brute-force reconstruction
+
+def _chain_half():
+    cc = configs.chain_brickwork(4, [3, 4, 3, 4], [2, 1, 1], 4, 12)
+    var = qpu.all_variants(cc)
+    Ts = [rc.attribute(cc, i, var[i]) for i in range(cc.n_sub)]
+    Th = [rc.fold_half(Ts[i], sum(1 for _, r in cc.incident(i) if r == "out"))
+          for i in range(cc.n_sub)]
+    return cc, Ts, Th
+
+
+@pytest.mark.parametrize("pick", ["none", "first", "last", "pair", "reversed", "all"])
+def test_sliced_contraction_matches_eq1(pick):
+    cc, Ts, Th = _chain_half()
+    K = len(cc.cuts)
+    sliced = {"none": [], "first": [0], "last": [K - 1], "pair": [0, K - 1],
+              "reversed": [K - 1, 1, 0], "all": list(range(K))}[pick]
+    P = rc.reconstruct_eq1(Ts, cc)
+    assert np.abs(network.contract_sliced(Th, cc, sliced) - P).max() <= 1e-14
+
+
+def test_sliced_contraction_restricts_both_sides():
+    """A slice restricted on one side of its cut only (the other side summed
+    over all four labels) must not reproduce Eq. 1: the pin above sees it."""
+    cc, Ts, Th = _chain_half()
+    P = rc.reconstruct_eq1(Ts, cc)
+    k = 0
+    up = cc.cuts[k].up_sub
+    # summing the upstream entries over the cut's labels first, then slicing
+    # only the downstream side, gives a different vector
+    t = network._sub_tensor(cc, up, Th[up])
+    ax = network._cut_axes(cc, up).index(k)
+    wrong_up = np.repeat(t.sum(axis=ax, keepdims=True), 4, axis=ax).reshape(Th[up].shape)
+    Tw = list(Th)
+    Tw[up] = wrong_up
+    assert np.abs(network.contract_sliced(Tw, cc, [k]) - P).max() > 1e-6
