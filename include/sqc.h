@@ -291,6 +291,35 @@ sqc_status sqc_contract(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n_sub,
                         const sqc_cut *cuts, int32_t n_cuts, sqc_prec prec,
                         void *bins_dev, sqc_prec bins_prec);
 
+/* Sliced contraction (Sec. 6.3, first-level index slicing): the result of
+ * sqc_contract, computed as a sum over slices.  `sliced` lists n_sliced
+ * distinct cut ids (0 <= n_sliced <= SQC_MAX_SLICED, each id in [0, n_cuts));
+ * a slice is one label assignment of those cuts, numbered with the first
+ * listed cut as the least significant radix-4 digit.  For each of the
+ * 4^n_sliced slices, in ascending order: every merged tensor incident to a
+ * sliced cut is restricted to the slice's labels (its rows gathered into the
+ * workspace, the remaining labels keeping their order), the network without
+ * the sliced cuts is contracted as by sqc_contract (same `prec`) into FP64
+ * bins, and these are added into FP64 running sums with Neumaier
+ * compensation; the compensated sums are written to `bins_dev` (2^a elements
+ * of bins_prec, a = sum of n_bits) after the last slice.  The contraction's
+ * intermediates are those of the sliced network (4x smaller per sliced label
+ * they would carry); the call adds the gathered operands and three 2^a FP64
+ * vectors to the workspace (sqc_contract_sliced_workspace_bytes).  Merged
+ * tensors and cuts as for sqc_contract.  Stage timing books the gathers
+ * under SQC_STAGE_MERGE and the additions under SQC_STAGE_CONTRACT.  Errors: SQC_E_ARG for a repeated or
+ * out-of-range cut id or n_sliced outside [0, SQC_MAX_SLICED], SQC_E_NOMEM
+ * for a small workspace, else as sqc_contract. */
+#define SQC_MAX_SLICED 8
+size_t sqc_contract_sliced_workspace_bytes(const sqc_tensor *merged, int32_t n_sub,
+                                           const sqc_cut *cuts, int32_t n_cuts,
+                                           const int32_t *sliced, int32_t n_sliced,
+                                           sqc_prec prec);
+sqc_status sqc_contract_sliced(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n_sub,
+                               const sqc_cut *cuts, int32_t n_cuts,
+                               const int32_t *sliced, int32_t n_sliced, sqc_prec prec,
+                               void *bins_dev, sqc_prec bins_prec);
+
 /* ---- one states-merging recursion (Algorithm 1 body) ------------------------- */
 
 /* One recursion: sqc_assign_bins on `scope` (NULL at recursion 0), merge of

@@ -796,6 +796,100 @@ void enqueue_batch(sqc_ctx *ctx, PreparedRecursion *const *p, int n, char *const
     return SQC_E_ARG;                               \
   }
 
+// ---- first-level index slicing (Sec. 6.3) ----
+
+namespace {
+
+// A sliced contraction: the network without the sliced cuts, how each
+// subcircuit's rows are gathered for a slice, and the workspace layout
+// (after the sliced network's intermediates: gathered operands, slice bins,
+// running sums, compensations).
+struct SlicedPlan {
+  std::vector<sqc_cut> rest;
+  Contraction con;
+  // per subcircuit: (digit position in its sigma, index in the sliced list)
+  // of each incident sliced cut, ascending digit position
+  std::vector<std::vector<std::pair<int, int>>> fixed;
+  std::vector<int> degree;
+  std::vector<size_t> gather_off;
+  size_t bins_off = 0, sum_off = 0, comp_off = 0, total = 0;
+  int64_t nbins = 0;
+};
+
+SlicedPlan plan_sliced(const sqc_tensor *merged, int32_t n_sub, const sqc_cut *cuts, int32_t n_cuts,
+                       const int32_t *sliced, int32_t n_sliced, sqc_prec prec) {
+  Graph g = build_topology(n_sub, cuts, n_cuts);
+  if (!merged) raise(SQC_E_ARG, "NULL argument");
+  if (n_sliced < 0 || n_sliced > SQC_MAX_SLICED) raise(SQC_E_ARG, "n_sliced outside [0, SQC_MAX_SLICED]");
+  if (n_sliced > 0 && !sliced) raise(SQC_E_ARG, "sliced is NULL");
+  std::vector<int> which(n_cuts, -1);
+  for (int q = 0; q < n_sliced; ++q) {
+    const int k = sliced[q];
+    if (k < 0 || k >= n_cuts) raise(SQC_E_ARG, "a sliced cut id is out of range");
+    if (which[k] >= 0) raise(SQC_E_ARG, "a cut is listed twice in sliced");
+    which[k] = q;
+  }
+  std::vector<int> bits = degrees_match(g, merged, SQC_LAYOUT_MERGED);
+  SlicedPlan sp;
+  for (int k = 0; k < n_cuts; ++k)
+    if (which[k] < 0) sp.rest.push_back(cuts[k]);
+  Graph g2 = build_topology(n_sub, sp.rest.data(), (int32_t)sp.rest.size());
+  sp.con = plan_for(g2, bits, prec);
+  int abits = 0;
+  for (int b : bits) abits += b;
+  if (abits > 40) raise(SQC_E_UNSUPPORTED, "more than 2^40 bins");
+  const size_t elem = prec == SQC_F64 ? 8 : 4;
+  Bump b;
+  b.off = kCtlBytes + align256(contraction_ws(sp.con, 1, false, prec));
+  sp.fixed.resize(n_sub);
+  sp.degree.resize(n_sub);
+  sp.gather_off.assign(n_sub, 0);
+  for (int i = 0; i < n_sub; ++i) {
+    const std::vector<int> &inc = g.subs[i].inc;
+    sp.degree[i] = (int)inc.size();
+    for (size_t j = 0; j < inc.size(); ++j)
+      if (which[inc[j]] >= 0) sp.fixed[i].push_back({(int)j, which[inc[j]]});
+    if (!sp.fixed[i].empty()) {
+      const int kept = sp.degree[i] - (int)sp.fixed[i].size();
+      sp.gather_off[i] = b.take((size_t(1) << (2 * kept + bits[i])) * elem);
+    }
+  }
+  sp.nbins = int64_t(1) << abits;
+  sp.bins_off = b.take((size_t)sp.nbins * 8);
+  sp.sum_off = b.take((size_t)sp.nbins * 8);
+  sp.comp_off = b.take((size_t)sp.nbins * 8);
+  sp.total = b.off;
+  return sp;
+}
+
+// Rows of subcircuit i's merged tensor kept by slice `q`.
+SliceArgs slice_args(const SlicedPlan &sp, int i, const sqc_tensor &t, void *out, int64_t q, size_t elem) {
+  SliceArgs a{};
+  a.in = t.data;
+  a.out = out;
+  const auto &fx = sp.fixed[i];
+  const int kept = sp.degree[i] - (int)fx.size();
+  a.rows = int64_t(1) << (2 * kept);
+  a.row_bytes_log2 = t.n_bits + (elem == 8 ? 3 : 2);
+  for (const auto &f : fx) a.fixed += ((q >> (2 * f.second)) & 3) << (2 * f.first);
+  // runs of kept digits: output digits [o, o + n) read input digits [p, p + n)
+  int o = 0, p = 0;
+  for (size_t r = 0; r <= fx.size(); ++r) {
+    const int end = r < fx.size() ? fx[r].first : sp.degree[i];
+    if (end > p) {
+      a.lo[a.nruns] = 2 * o;
+      a.len[a.nruns] = 2 * (end - p);
+      a.pos[a.nruns] = 2 * p;
+      a.nruns++;
+      o += end - p;
+    }
+    p = end + 1;
+  }
+  return a;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *sqc_version(void) { return "sqc 0.1.0 (gfx950)"; }
@@ -1142,6 +1236,64 @@ sqc_status sqc_contract(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n_sub, c
   for (int i = 0; i < n_sub; ++i) inputs[i] = merged[i].data;
   enqueue_contraction(ctx, c, inputs, kCtlBytes, bins_dev, bins_prec == SQC_F32, prec, 0, nullptr,
                       nullptr);
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+size_t sqc_contract_sliced_workspace_bytes(const sqc_tensor *merged, int32_t n_sub, const sqc_cut *cuts,
+                                           int32_t n_cuts, const int32_t *sliced, int32_t n_sliced,
+                                           sqc_prec prec) {
+  try {
+    return plan_sliced(merged, n_sub, cuts, n_cuts, sliced, n_sliced, prec).total;
+  } catch (const Error &e) {
+    set_thread_error(e.msg);
+    return 0;
+  }
+}
+
+sqc_status sqc_contract_sliced(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n_sub, const sqc_cut *cuts,
+                               int32_t n_cuts, const int32_t *sliced, int32_t n_sliced, sqc_prec prec,
+                               void *bins_dev, sqc_prec bins_prec) {
+  SQC_TRY(ctx)
+  if (!bins_dev) raise(SQC_E_ARG, "NULL argument");
+  check_path_prec(prec);
+  check_storage_prec(bins_prec, "bins_prec");
+  SlicedPlan sp = plan_sliced(merged, n_sub, cuts, n_cuts, sliced, n_sliced, prec);
+  for (int i = 0; i < n_sub; ++i)
+    if ((merged[i].prec == SQC_F64) != (prec == SQC_F64))
+      raise(SQC_E_ARG, "merged tensors must be FP64 for the FP64 path and FP32 otherwise");
+  need_ws(ctx, sp.total);
+  use_device(ctx);
+  const size_t elem = prec == SQC_F64 ? 8 : 4;
+  double *bins = reinterpret_cast<double *>(ctx->ws + sp.bins_off);
+  double *sum = reinterpret_cast<double *>(ctx->ws + sp.sum_off);
+  double *comp = reinterpret_cast<double *>(ctx->ws + sp.comp_off);
+  const int64_t nslices = int64_t(1) << (2 * n_sliced);
+  std::vector<const void *> inputs(n_sub);
+  for (int64_t q = 0; q < nslices; ++q) {
+    {
+      StageMark mark(ctx, SQC_STAGE_MERGE, 0.0, 0.0);
+      for (int i = 0; i < n_sub; ++i) {
+        if (sp.fixed[i].empty()) {
+          inputs[i] = merged[i].data;
+          continue;
+        }
+        const SliceArgs a = slice_args(sp, i, merged[i], ctx->ws + sp.gather_off[i], q, elem);
+        launch_slice_rows(a, ctx->stream);
+        after_launch("slice gather launch");
+        inputs[i] = a.out;
+      }
+      mark.done();
+    }
+    enqueue_contraction(ctx, sp.con, inputs, kCtlBytes, bins, 0, prec, 0, nullptr, nullptr);
+    {
+      StageMark mark(ctx, SQC_STAGE_CONTRACT, 0.0, 0.0);
+      launch_slice_accumulate(bins, sum, comp, bins_dev, bins_prec == SQC_F32, q == 0, q == nslices - 1, sp.nbins,
+                              ctx->stream);
+      after_launch("slice accumulate launch");
+      mark.done();
+    }
+  }
   return SQC_OK;
   SQC_CATCH(ctx)
 }

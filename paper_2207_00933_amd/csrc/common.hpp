@@ -276,4 +276,24 @@ void launch_topr_grouped(const TopRArgs *jobs_dev, const int *start_dev, int n, 
 
 void launch_zero(void *p, size_t bytes, hipStream_t s);
 
+// ---- first-level index slicing (slice.hip) ----
+// Rows of a merged tensor kept by one slice: output row r (of `rows`) reads
+// input row fixed + sum_j ((r >> lo[j]) & (2^len[j] - 1)) << pos[j]; a row is
+// 2^row_bytes_log2 bytes (>= 4).
+struct SliceArgs {
+  const void *in;
+  void *out;
+  int64_t rows;
+  int64_t fixed;
+  int row_bytes_log2;
+  int row_shift;  // set by the launcher
+  int nruns;
+  int lo[SQC_MAX_SLICED + 1], len[SQC_MAX_SLICED + 1], pos[SQC_MAX_SLICED + 1];
+};
+void launch_slice_rows(const SliceArgs &a, hipStream_t s);
+// sum/comp (n FP64 each) += bins with Neumaier compensation; `first` starts
+// them, `last` writes sum + comp to out (FP32 when out_f32) instead.
+void launch_slice_accumulate(const double *bins, double *sum, double *comp, void *out, int out_f32, int first,
+                             int last, int64_t n, hipStream_t s);
+
 }  // namespace sqc

@@ -144,6 +144,11 @@ def lib():
                                                         c_int32, c_int]),
             "sqc_contract": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32, c_int,
                                      P, c_int]),
+            "sqc_contract_sliced_workspace_bytes": (c_size_t, [POINTER(Tensor), c_int32,
+                                                               POINTER(Cut), c_int32,
+                                                               POINTER(c_int32), c_int32, c_int]),
+            "sqc_contract_sliced": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
+                                            POINTER(c_int32), c_int32, c_int, P, c_int]),
             "sqc_recurse_workspace_bytes": (c_size_t, [POINTER(Tensor), c_int32, POINTER(Cut),
                                                        c_int32, POINTER(Masks), c_int]),
             "sqc_recurse": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
@@ -381,6 +386,24 @@ def contract_workspace_bytes(merged: Sequence[Tensor], g: Graph, prec: int) -> i
 def contract(ctx: int, merged: Sequence[Tensor], g: Graph, prec: int, bins, bins_prec: int) -> None:
     arr = tensor_array(merged)
     _check(lib().sqc_contract(ctx, arr, g.n_sub, g.cuts, g.n_cuts, prec, _ptr(bins), bins_prec), ctx)
+
+
+def _sliced_array(sliced: Sequence[int]):
+    return (c_int32 * max(1, len(sliced)))(*[int(k) for k in sliced])
+
+
+def contract_sliced_workspace_bytes(merged: Sequence[Tensor], g: Graph, sliced: Sequence[int],
+                                    prec: int) -> int:
+    arr = tensor_array(merged)
+    return int(lib().sqc_contract_sliced_workspace_bytes(arr, g.n_sub, g.cuts, g.n_cuts,
+                                                         _sliced_array(sliced), len(sliced), prec))
+
+
+def contract_sliced(ctx: int, merged: Sequence[Tensor], g: Graph, sliced: Sequence[int], prec: int,
+                    bins, bins_prec: int) -> None:
+    arr = tensor_array(merged)
+    _check(lib().sqc_contract_sliced(ctx, arr, g.n_sub, g.cuts, g.n_cuts, _sliced_array(sliced),
+                                     len(sliced), prec, _ptr(bins), bins_prec), ctx)
 
 
 def recurse_workspace_bytes(att: Sequence[Tensor], g: Graph, masks, prec: int) -> int:

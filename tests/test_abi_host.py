@@ -166,3 +166,45 @@ def test_slicing_paper_example():
     assert len(chosen) == 1 and tuple(cuts[chosen[0]]) == (0, 2)
     ts = [(frozenset(k for k, c in enumerate(cuts) if i in c), 1 << q) for i, q in enumerate(qubits)]
     assert chosen == ocost.greedy_slices(ts, EX["sliced_input_floats"])
+
+
+def _sliced_descs(bits, cuts, prec):
+    import torch
+    g = sqc.Graph([1] * len(bits), [[] for _ in bits], [(u, 0, v, 0) for u, v in cuts])
+    deg = [sum(1 for c in cuts if i in c) for i in range(len(bits))]
+    dt = torch.float64 if prec == sqc.F64 else torch.float32
+    bufs = [torch.zeros((4 ** deg[i]) << bits[i], dtype=dt) for i in range(len(bits))]
+    descs = [sqc.tensor_desc(b, deg[i], bits[i], sqc.F64 if prec == sqc.F64 else sqc.F32, sqc.LAYOUT_MERGED)
+             for i, b in enumerate(bufs)]
+    return g, descs, bufs
+
+
+def test_sliced_workspace_layout():
+    """Host planning of a sliced contraction (Sec. 6.3): the workspace covers
+    the sliced network, the gathered operands and three FP64 bin vectors."""
+    bits, cuts = [5, 3, 4], [(0, 1), (0, 1), (1, 2), (1, 2), (1, 2)]
+    for prec in (sqc.F64, sqc.F32, sqc.BF16X3):
+        g, descs, _ = _sliced_descs(bits, cuts, prec)
+        elem = 8 if prec == sqc.F64 else 4
+        nb = 1 << sum(bits)
+        for sliced in ([], [0], [2, 4], [0, 1, 2, 3, 4]):
+            ws = sqc.contract_sliced_workspace_bytes(descs, g, sliced, prec)
+            # gathered copies of the tensors touching a sliced cut
+            gathered = 0
+            for i in range(3):
+                deg = sum(1 for c in cuts if i in c)
+                s = sum(1 for k in sliced if i in cuts[k])
+                if s:
+                    gathered += ((4 ** (deg - s)) << bits[i]) * elem
+            assert ws >= gathered + 3 * nb * 8
+            # the sliced network's own workspace is part of it
+            rest = [c for k, c in enumerate(cuts) if k not in sliced]
+            g2, d2, _ = _sliced_descs(bits, rest, prec)
+            assert ws >= sqc.contract_workspace_bytes(d2, g2, prec) + gathered + 3 * nb * 8
+
+
+@pytest.mark.parametrize("sliced", [[0, 0], [5], [-1], list(range(5)) + [0, 1, 2, 3]])
+def test_sliced_rejects_bad_lists(sliced):
+    bits, cuts = [5, 3, 4], [(0, 1), (0, 1), (1, 2), (1, 2), (1, 2)]
+    g, descs, _ = _sliced_descs(bits, cuts, sqc.F64)
+    assert sqc.contract_sliced_workspace_bytes(descs, g, sliced, sqc.F64) == 0

@@ -1,0 +1,162 @@
+"""GPU parity of the sliced contraction (Sec. 6.3, first-level index slicing)
+against the oracle's sliced sum, through the C interface.
+
+Small graphs: every element, for several slicings per graph (one cut, cuts on
+different subcircuits, a cut on a subcircuit with no data bits, every cut so
+the sliced network falls apart into outer products, none), the three
+contraction precisions and both bin precisions; tolerances as for the plain
+contraction (a multiple of the unit roundoff times the contraction of |T|,
+which bounds every slice's error as well, since the slices split its terms).
+Full size: the precision workload (2^24 bins) sliced on one and on two cuts,
+4096 sampled bins against Eq. 1 evaluated bin by bin by the oracle."""
+import numpy as np
+import pytest
+
+from oracle import network
+from workloads import configs, qpu
+
+from gpu_util import error_bound, oracle_attributed, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+sqc = pytest.importorskip("paper_2207_00933_amd.sqc")
+runner = pytest.importorskip("paper_2207_00933_amd.runner")
+
+PRECS = [("f64", 0), ("f32", 1), ("bf16x3", 2)]
+TOL_REL = {0: 1e-13, 1: 2.0 ** -20, 2: 2.0 ** -13}
+
+
+@pytest.fixture(scope="module")
+def session():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = runner.Session(0, 64 << 20)
+    yield s
+    s.close()
+
+
+class _View:
+    """Compute graph from (up, down) subcircuit pairs, for the oracle."""
+
+    class _C:
+        def __init__(self, u, v):
+            self.up_sub, self.down_sub = u, v
+
+    def __init__(self, n, cuts):
+        self.n_sub = n
+        self.cuts = [self._C(u, v) for u, v in cuts]
+
+    def incident(self, i):
+        return [(k, "in" if c.down_sub == i else "out") for k, c in enumerate(self.cuts)
+                if i in (c.up_sub, c.down_sub)]
+
+
+CASES = {
+    "pair": ([4, 6], [(0, 1), (0, 1)], [[0], [1, 0]]),
+    "chain3": ([5, 3, 4], [(0, 1), (0, 1), (1, 2), (1, 2), (1, 2)], [[0], [2, 4], [0, 1, 2, 3, 4], []]),
+    "ring4": ([3, 2, 3, 2], [(0, 1), (0, 1), (1, 2), (1, 2), (2, 3), (2, 3), (3, 0), (3, 0)], [[0, 4], [7]]),
+    "zero_bits": ([3, 0, 4], [(0, 1), (1, 2), (2, 1)], [[1], [0, 2]]),
+    "star5": ([2, 3, 1, 2, 3], [(0, 1), (0, 2), (0, 3), (0, 4), (1, 2), (3, 4)], [[0, 5], [3]]),
+    "wide": ([9, 8], [(0, 1)] * 3, [[2], [0, 1, 2]]),
+}
+SLICINGS = [(name, j) for name in sorted(CASES) for j in range(len(CASES[name][2]))]
+
+
+def _upload(Ts, cc, bits, prec):
+    dt = torch.float64 if prec == sqc.F64 else torch.float32
+    bufs = [torch.from_numpy(np.ascontiguousarray(T)).to(dt).cuda() for T in Ts]
+    descs = [sqc.tensor_desc(b, len(cc.incident(i)), bits[i], sqc.F64 if prec == sqc.F64 else sqc.F32,
+                             sqc.LAYOUT_MERGED) for i, b in enumerate(bufs)]
+    return bufs, descs
+
+
+@pytest.mark.parametrize("name,j", SLICINGS)
+@pytest.mark.parametrize("pname,prec", PRECS)
+def test_contract_sliced_random(session, name, j, pname, prec):
+    bits, cuts, slicings = CASES[name]
+    sliced = slicings[j]
+    cc = _View(len(bits), cuts)
+    rng = np.random.default_rng(1000 + 17 * j + len(name))
+    Ts = [rng.standard_normal((1 << (2 * len(cc.incident(i))), 1 << bits[i])) for i in range(len(bits))]
+    if prec != sqc.F64:
+        Ts = [T.astype(np.float32).astype(np.float64) for T in Ts]
+    want = network.contract_sliced(Ts, cc, sliced)
+    bound = error_bound(Ts, cc)
+    g = sqc.Graph([1] * len(bits), [[] for _ in bits], [(u, 0, v, 0) for u, v in cuts])
+    bufs, descs = _upload(Ts, cc, bits, prec)
+    session.ensure_workspace(sqc.contract_sliced_workspace_bytes(descs, g, sliced, prec))
+    for bins_prec in (sqc.F64, sqc.F32):
+        say(f"contract_sliced {name} sliced={sliced} prec={pname} bins={bins_prec}")
+        out = torch.empty(len(want), dtype=torch.float64 if bins_prec == sqc.F64 else torch.float32,
+                          device="cuda")
+        sqc.contract_sliced(session.ctx, descs, g, sliced, prec, out, bins_prec)
+        torch.cuda.synchronize()
+        got = out.double().cpu().numpy()
+        tol = TOL_REL[prec] * bound + (2.0 ** -24 * np.abs(want) if bins_prec == sqc.F32 else 0) + 1e-300
+        assert np.all(np.abs(got - want) <= tol), np.abs(got - want).max()
+
+
+def test_contract_sliced_twice_in_a_row(session):
+    """The running sums start over on every call: two calls with different
+    slicings into the same output both match the oracle."""
+    bits, cuts, _ = CASES["chain3"]
+    cc = _View(len(bits), cuts)
+    rng = np.random.default_rng(7)
+    Ts = [rng.standard_normal((1 << (2 * len(cc.incident(i))), 1 << bits[i])) for i in range(len(bits))]
+    bound = error_bound(Ts, cc)
+    g = sqc.Graph([1] * len(bits), [[] for _ in bits], [(u, 0, v, 0) for u, v in cuts])
+    bufs, descs = _upload(Ts, cc, bits, sqc.F64)
+    out = torch.empty(1 << sum(bits), dtype=torch.float64, device="cuda")
+    for sliced in ([1, 3], [4]):
+        session.ensure_workspace(sqc.contract_sliced_workspace_bytes(descs, g, sliced, sqc.F64))
+        sqc.contract_sliced(session.ctx, descs, g, sliced, sqc.F64, out, sqc.F64)
+        torch.cuda.synchronize()
+        want = network.contract_sliced(Ts, cc, sliced)
+        assert np.abs(out.cpu().numpy() - want).max() <= 1e-13 * bound.max() + 1e-300
+
+
+@pytest.mark.parametrize("sliced", [[0, 0], [5], [-1]])
+def test_contract_sliced_rejects(session, sliced):
+    bits, cuts, _ = CASES["chain3"]
+    cc = _View(len(bits), cuts)
+    Ts = [np.zeros((1 << (2 * len(cc.incident(i))), 1 << bits[i])) for i in range(len(bits))]
+    g = sqc.Graph([1] * len(bits), [[] for _ in bits], [(u, 0, v, 0) for u, v in cuts])
+    bufs, descs = _upload(Ts, cc, bits, sqc.F64)
+    out = torch.zeros(1 << sum(bits), dtype=torch.float64, device="cuda")
+    with pytest.raises(sqc.SqcError) as e:
+        sqc.contract_sliced(session.ctx, descs, g, sliced, sqc.F64, out, sqc.F64)
+    assert e.value.status == sqc.E_ARG
+    assert float(out.abs().max()) == 0.0  # nothing was enqueued
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("sliced", [[0], [0, 3]])
+def test_precision_sliced_full_size_sampled(session, sliced):
+    """The precision workload's recursion-0 contraction (2^24 bins; every
+    data bit active, so the attributed entries are the merged tensors),
+    sliced, against Eq. 1 at 4096 sampled bins."""
+    cc = configs.precision()
+    var32 = [v.astype(np.float32) for v in qpu.all_variants(cc)]
+    Th = oracle_attributed(cc, [v.astype(np.float64) for v in var32])
+    bits = [T.shape[1].bit_length() - 1 for T in Th]
+    g = sqc.Graph.from_cut_circuit(cc)
+    rng = np.random.default_rng(3)
+    sample = np.unique(rng.integers(0, 1 << cc.n, size=4096))
+    for pname, prec in (("f64", sqc.F64), ("bf16x3", sqc.BF16X3)):
+        T_in = Th if prec == sqc.F64 else [T.astype(np.float32).astype(np.float64) for T in Th]
+        want = network.eval_bins(T_in, cc, sample)
+        bufs, descs = _upload(T_in, cc, bits, prec)
+        bins_prec = sqc.F64 if prec == sqc.F64 else sqc.F32
+        session.ensure_workspace(sqc.contract_sliced_workspace_bytes(descs, g, sliced, prec))
+        out = torch.empty(1 << cc.n, dtype=torch.float64 if bins_prec == sqc.F64 else torch.float32, device="cuda")
+        say(f"precision sliced={sliced} {pname}")
+        sqc.contract_sliced(session.ctx, descs, g, sliced, prec, out, bins_prec)
+        torch.cuda.synchronize()
+        got = out.double().cpu().numpy()
+        err = np.abs(got[sample] - want).max()
+        say(f"  max |gpu - oracle| over {len(sample)} sampled bins: {err:.3e}")
+        assert err <= (1e-12 if prec == sqc.F64 else 1e-6)
+        # the bins still sum to one (Sec. 3 invariant at recursion 0)
+        assert abs(float(out.double().sum()) - 1.0) <= 1e-6
+        del bufs, descs, out
