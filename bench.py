@@ -326,8 +326,89 @@ def run_workloads(reps: int = 5):
             res["speedup_bf16x3_vs_f64"] = res["bf16x3"]["bins_per_s"] / res["f64"]["bins_per_s"]
             out[name] = res
             del circ
+        out["slicing"] = run_slicing(s, reps)
         s.close()
     return out
+
+
+def run_slicing(s, reps: int):
+    """First-level index slicing (Sec. 6.3) on the precision workload's
+    recursion-0 contraction (every data bit active, 2^24 bins): the plain
+    contraction against sqc_contract_sliced on the cuts the slicing planner
+    picks for a budget of 1/4 and 1/16 of the input floats.  Reports ms per
+    contraction, bins/s, the workspace each needs, and the HBM fraction of
+    the algorithmic bytes (GEMM operands and results as the stage timing
+    counts them, plus each slice's row gathers, read and written once, and
+    its FP64 running-sum traffic)."""
+    import torch
+    from paper_2207_00933_amd import runner, sqc
+
+    cc = configs.precision()
+    var32 = [v.astype(np.float32) for v in qpu.all_variants(cc)]
+    circ = runner.Circuit.from_cut_circuit(s, cc, var32, sqc.F32)
+    g = circ.g
+    M = 1 << cc.n
+    masks = sqc.assign_bins(g.n_data, None, M)
+    cuts = [(c.up_sub, c.down_sub) for c in cc.cuts]
+    inputs = sum((4 ** len(cc.incident(i))) << g.n_data[i] for i in range(cc.n_sub))
+    res = {"workload": "precision recursion 0: 24 qubits, 3 subcircuits, 6 cuts, 2^24 bins",
+           "input_floats": inputs}
+    for pname, prec in (("bf16x3", sqc.BF16X3), ("f64", sqc.F64)):
+        att = sqc.F64 if prec == sqc.F64 else sqc.F32
+        elem = 8 if att == sqc.F64 else 4
+        circ.attribute(att)
+        merged, bufs = [], []
+        for i in range(cc.n_sub):
+            n = (4 ** len(cc.incident(i))) << g.n_data[i]
+            b = torch.empty(n, dtype=torch.float64 if att == sqc.F64 else torch.float32, device=s.device)
+            s.ensure_workspace(sqc.merge_workspace_bytes(circ.att[i], masks[i]))
+            merged.append(sqc.merge(s.ctx, circ.att[i], masks[i], b, att))
+            bufs.append(b)
+        bins = torch.empty(M, dtype=torch.float64 if att == sqc.F64 else torch.float32, device=s.device)
+        rows = {}
+        for label, budget in (("none", None), ("quarter", inputs / 4), ("sixteenth", inputs / 16)):
+            sliced = [] if budget is None else sqc.slice_plan(list(g.n_data), cuts, budget)
+            if budget is None:
+                ws = sqc.contract_workspace_bytes(merged, g, prec)
+                run = lambda: sqc.contract(s.ctx, merged, g, prec, bins, att)  # noqa: E731
+            else:
+                ws = sqc.contract_sliced_workspace_bytes(merged, g, sliced, prec)
+                run = lambda: sqc.contract_sliced(s.ctx, merged, g, sliced, prec, bins, att)  # noqa: E731
+            s.ensure_workspace(ws)
+            run()
+            stages = sqc.STAGE_CONTRACT | sqc.STAGE_FINAL
+            sqc.ctx_timing(s.ctx, 1, reset=True)
+            sqc.ctx_set_timing(s.ctx, stages)
+            run()
+            sqc.ctx_set_timing(s.ctx, 0)
+            gemm_bytes = sum(sqc.ctx_timing(s.ctx, q).bytes for q in (sqc.STAGE_CONTRACT, sqc.STAGE_FINAL))
+            sqc.ctx_timing(s.ctx, 1, reset=True)
+            nsl = 4 ** len(sliced)
+            gathered = sum(((4 ** (len(cc.incident(i)) - sum(1 for k in sliced if i in cuts[k])))
+                            << g.n_data[i]) * elem for i in range(cc.n_sub)
+                           if any(i in cuts[k] for k in sliced))
+            extra = 0.0
+            if sliced:
+                # per slice: gathers; FP64 slice bins written by the last GEMM
+                # (counted above) and read; running sums read and written
+                # between slices; the result written once
+                extra = nsl * 2 * gathered + nsl * 8 * M + (nsl - 1) * 2 * 16 * M + elem * M
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                run()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / reps
+            nbytes = gemm_bytes + extra
+            rows[label] = {"sliced_cuts": sliced, "slices": nsl, "ms": wall * 1e3, "bins_per_s": M / wall,
+                           "workspace_bytes": ws, "algorithmic_bytes": nbytes,
+                           "hbm_roofline_frac": nbytes / HBM_PEAK / wall}
+            log(f"[slicing] {pname} {label}: cuts {sliced} ({nsl} slices), {wall * 1e3:.3f} ms, "
+                f"{M / wall:.3e} bins/s, workspace {ws / 2 ** 20:.1f} MiB, HBM fraction {nbytes / HBM_PEAK / wall:.3f}")
+        res[pname] = rows
+        del merged, bufs, bins
+    del circ
+    return res
 
 
 # ---------------------------------------------------------------------------
