@@ -257,6 +257,12 @@ CONTRACT_CASES = {
     "zero_bits": ([3, 0, 4], [(0, 1), (1, 2), (2, 1)]),
     "star5": ([2, 3, 1, 2, 3], [(0, 1), (0, 2), (0, 3), (0, 4), (1, 2), (3, 4)]),
     "wide": ([9, 8], [(0, 1)] * 3),
+    # random compute graphs (Erdos-Renyi: each pair cut with probability 0.5
+    # and 0.35, seeds 1 and 2, redrawn until connected with degree <= 5):
+    # neither chains nor rings, so the greedy pairwise planner picks the order
+    "erdos6": ([2, 3, 1, 2, 2, 3], [(0, 3), (0, 5), (1, 2), (1, 4), (2, 3), (3, 4), (4, 5)]),
+    "erdos8": ([1, 2, 1, 2, 1, 2, 1, 2], [(0, 1), (0, 2), (0, 4), (0, 7), (1, 2), (1, 3), (1, 6), (3, 5),
+                                          (3, 6), (4, 7)]),
 }
 
 

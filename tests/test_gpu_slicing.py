@@ -59,6 +59,8 @@ CASES = {
     "zero_bits": ([3, 0, 4], [(0, 1), (1, 2), (2, 1)], [[1], [0, 2]]),
     "star5": ([2, 3, 1, 2, 3], [(0, 1), (0, 2), (0, 3), (0, 4), (1, 2), (3, 4)], [[0, 5], [3]]),
     "wide": ([9, 8], [(0, 1)] * 3, [[2], [0, 1, 2]]),
+    "erdos8": ([1, 2, 1, 2, 1, 2, 1, 2], [(0, 1), (0, 2), (0, 4), (0, 7), (1, 2), (1, 3), (1, 6), (3, 5),
+                                          (3, 6), (4, 7)], [[1, 6], [9]]),
 }
 SLICINGS = [(name, j) for name in sorted(CASES) for j in range(len(CASES[name][2]))]
 
