@@ -342,6 +342,29 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
                        sqc_prec bins_prec, sqc_masks *masks_out,
                        void *topr_dev, void *sum_dev);
 
+/* Probabilities of chosen output states (Sec. 3: an arbitrary subset of
+ * states evaluated in one recursion without merging into bins).  states[j]
+ * (host array, n_states entries) is a full output index, subcircuit-major as
+ * the bins of a recursion with every data bit active (subcircuit 0's data
+ * bits least significant), each < 2^(sum of d_i).  For every state the
+ * attributed tensors are restricted to that state's data bits (a merge with
+ * every data bit fixed) and the cut indices are contracted as in sqc_recurse
+ * with M = 1; probs_dev[j] (probs_prec) receives the reconstructed value.
+ * States are processed in batches whose merges, contraction steps and
+ * selections share launches (job tables staged through the context's pinned
+ * buffer); the call waits for the device after each batch, so it cannot be
+ * recorded into a graph.  Repeated states are allowed.  Workspace:
+ * sqc_query_states_workspace_bytes (independent of n_states).  Errors:
+ * SQC_E_ARG for a NULL buffer, a state out of range or while recording, else
+ * as sqc_recurse. */
+size_t sqc_query_states_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub,
+                                        const sqc_cut *cuts, int32_t n_cuts,
+                                        sqc_prec prec);
+sqc_status sqc_query_states(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
+                            const sqc_cut *cuts, int32_t n_cuts, const uint64_t *states,
+                            int64_t n_states, sqc_prec prec, void *probs_dev,
+                            sqc_prec probs_prec);
+
 /* ---- HIP graphs of enqueued work (not part of the paper) ----------------------- */
 
 /* Record the work later calls enqueue on the context's stream (sqc_attribute,

@@ -890,6 +890,59 @@ SliceArgs slice_args(const SlicedPlan &sp, int i, const sqc_tensor &t, void *out
 
 }  // namespace
 
+// ---- arbitrary-subset queries (Sec. 3) ----
+
+namespace {
+
+constexpr size_t kQueryStaging = 64 * 1024;  // the context's pinned buffer
+constexpr int kQueryMaxBatch = 64;
+
+// Every data bit fixed: the bin of one state.
+std::vector<sqc_masks> state_scope(const std::vector<int> &d, uint64_t state) {
+  std::vector<sqc_masks> sc(d.size());
+  int off = 0;
+  for (size_t i = 0; i < d.size(); ++i) {
+    const uint64_t all = d[i] >= 64 ? ~uint64_t(0) : ((uint64_t(1) << d[i]) - 1);
+    sc[i].fixed = all;
+    sc[i].fixed_val = off < 64 ? (state >> off) & all : 0;
+    sc[i].active = 0;
+    sc[i].merged = 0;
+    off += d[i];
+  }
+  return sc;
+}
+
+struct QueryPlan {
+  std::shared_ptr<const CircuitTopo> c;
+  std::vector<int> d;
+  int total_bits = 0;
+  int batch = 1;
+  size_t req_ws = 0, table = 0, outs = 0, total = 0;
+};
+
+QueryPlan plan_query(const sqc_tensor *att, int32_t n_sub, const sqc_cut *cuts, int32_t n_cuts, sqc_prec prec) {
+  QueryPlan q;
+  q.c = make_circuit(att, n_sub, cuts, n_cuts);
+  for (int i = 0; i < n_sub; ++i) {
+    q.d.push_back(att[i].n_bits);
+    q.total_bits += att[i].n_bits;
+  }
+  if (q.total_bits > 64) raise(SQC_E_UNSUPPORTED, "more than 64 data bits in total");
+  // one representative request (the shape is the same for every state)
+  std::vector<sqc_masks> sc = state_scope(q.d, 0);
+  char dummy[64];
+  PreparedPtr p = prepare_recursion(q.c, sc.data(), 1, 1, prec, dummy, SQC_F64, dummy, dummy);
+  q.req_ws = prepared_workspace(*p);
+  const size_t tb = prepared_table_bytes(*p);
+  q.batch = (int)std::max<size_t>(1, std::min<size_t>(kQueryMaxBatch, kQueryStaging / tb));
+  q.table = align256(tb * q.batch);
+  q.outs = 256;  // per request: top-1 record and sum
+  q.total = kCtlBytes + q.table + (size_t)q.batch * (q.req_ws + q.outs);
+  return q;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *sqc_version(void) { return "sqc 0.1.0 (gfx950)"; }
@@ -1293,6 +1346,59 @@ sqc_status sqc_contract_sliced(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n
       after_launch("slice accumulate launch");
       mark.done();
     }
+  }
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+size_t sqc_query_states_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,
+                                        int32_t n_cuts, sqc_prec prec) {
+  try {
+    return plan_query(attributed, n_sub, cuts, n_cuts, prec).total;
+  } catch (const Error &e) {
+    set_thread_error(e.msg);
+    return 0;
+  }
+}
+
+sqc_status sqc_query_states(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,
+                            int32_t n_cuts, const uint64_t *states, int64_t n_states, sqc_prec prec,
+                            void *probs_dev, sqc_prec probs_prec) {
+  SQC_TRY(ctx)
+  if (ctx->recording) raise(SQC_E_ARG, "sqc_query_states waits for the device and cannot be recorded");
+  if (n_states < 0) raise(SQC_E_ARG, "n_states must be >= 0");
+  if (n_states > 0 && (!states || !probs_dev)) raise(SQC_E_ARG, "NULL argument");
+  check_storage_prec(probs_prec, "probs_prec");
+  QueryPlan q = plan_query(attributed, n_sub, cuts, n_cuts, prec);
+  for (int64_t j = 0; j < n_states; ++j)
+    if (q.total_bits < 64 && (states[j] >> q.total_bits) != 0) {
+      std::ostringstream m;
+      m << "state " << states[j] << " (entry " << j << ") is outside [0, 2^" << q.total_bits << ")";
+      raise(SQC_E_ARG, m.str());
+    }
+  if (n_states == 0) return SQC_OK;
+  need_ws(ctx, q.total);
+  use_device(ctx);
+  const size_t elem = probs_prec == SQC_F32 ? 4 : 8;
+  char *table = ctx->ws + kCtlBytes;
+  char *reqs = table + q.table;
+  for (int64_t j0 = 0; j0 < n_states; j0 += q.batch) {
+    const int n = (int)std::min<int64_t>(q.batch, n_states - j0);
+    std::vector<PreparedPtr> ps;
+    std::vector<PreparedRecursion *> raw;
+    std::vector<char *> ws;
+    for (int r = 0; r < n; ++r) {
+      std::vector<sqc_masks> sc = state_scope(q.d, states[j0 + r]);
+      char *w = reqs + (size_t)r * (q.req_ws + q.outs);
+      char *o = w + q.req_ws;
+      ps.push_back(prepare_recursion(q.c, sc.data(), 1, 1, prec, static_cast<char *>(probs_dev) + (j0 + r) * elem,
+                                     probs_prec, o, o + 2 * sizeof(double)));
+      raw.push_back(ps.back().get());
+      ws.push_back(w);
+    }
+    enqueue_batch(ctx, raw.data(), n, ws.data(), table, q.table, ctx->pinned, kQueryStaging);
+    // the next batch rewrites the pinned staging buffer and the workspace
+    check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
   }
   return SQC_OK;
   SQC_CATCH(ctx)

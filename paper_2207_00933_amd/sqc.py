@@ -149,6 +149,10 @@ def lib():
                                                                POINTER(c_int32), c_int32, c_int]),
             "sqc_contract_sliced": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
                                             POINTER(c_int32), c_int32, c_int, P, c_int]),
+            "sqc_query_states_workspace_bytes": (c_size_t, [POINTER(Tensor), c_int32, POINTER(Cut),
+                                                            c_int32, c_int]),
+            "sqc_query_states": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
+                                         POINTER(c_uint64), ctypes.c_int64, c_int, P, c_int]),
             "sqc_recurse_workspace_bytes": (c_size_t, [POINTER(Tensor), c_int32, POINTER(Cut),
                                                        c_int32, POINTER(Masks), c_int]),
             "sqc_recurse": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
@@ -404,6 +408,19 @@ def contract_sliced(ctx: int, merged: Sequence[Tensor], g: Graph, sliced: Sequen
     arr = tensor_array(merged)
     _check(lib().sqc_contract_sliced(ctx, arr, g.n_sub, g.cuts, g.n_cuts, _sliced_array(sliced),
                                      len(sliced), prec, _ptr(bins), bins_prec), ctx)
+
+
+def query_states_workspace_bytes(att: Sequence[Tensor], g: Graph, prec: int) -> int:
+    arr = tensor_array(att)
+    return int(lib().sqc_query_states_workspace_bytes(arr, g.n_sub, g.cuts, g.n_cuts, prec))
+
+
+def query_states(ctx: int, att: Sequence[Tensor], g: Graph, states: Sequence[int], prec: int, probs,
+                 probs_prec: int) -> None:
+    arr = tensor_array(att)
+    st = (c_uint64 * max(1, len(states)))(*[int(x) for x in states])
+    _check(lib().sqc_query_states(ctx, arr, g.n_sub, g.cuts, g.n_cuts, st, len(states), prec, _ptr(probs),
+                                  probs_prec), ctx)
 
 
 def recurse_workspace_bytes(att: Sequence[Tensor], g: Graph, masks, prec: int) -> int:

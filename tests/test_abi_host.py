@@ -208,3 +208,21 @@ def test_sliced_rejects_bad_lists(sliced):
     bits, cuts = [5, 3, 4], [(0, 1), (0, 1), (1, 2), (1, 2), (1, 2)]
     g, descs, _ = _sliced_descs(bits, cuts, sqc.F64)
     assert sqc.contract_sliced_workspace_bytes(descs, g, sliced, sqc.F64) == 0
+
+
+def test_query_workspace_is_fixed_and_validated():
+    """Host planning of a subset query (Sec. 3): a fixed workspace whatever
+    the number of states; bad tensors are rejected before any launch."""
+    import torch
+    cc = configs.chain_brickwork(3, [4, 5, 4], [1, 2], 4, 11)
+    g = sqc.Graph.from_cut_circuit(cc)
+    descs = []
+    for i in range(cc.n_sub):
+        c = len(cc.incident(i))
+        b = torch.zeros((4 ** c) << g.n_data[i], dtype=torch.float64)
+        descs.append(sqc.tensor_desc(b, c, g.n_data[i], sqc.F64, sqc.LAYOUT_ATTRIBUTED))
+    for prec in (sqc.F64, sqc.F32, sqc.BF16X3):
+        assert sqc.query_states_workspace_bytes(descs, g, prec) > 0
+    bad = list(descs)
+    bad[0] = sqc.tensor_desc(torch.zeros(4), 0, 1, sqc.F64, sqc.LAYOUT_ATTRIBUTED)  # wrong degree
+    assert sqc.query_states_workspace_bytes(bad, g, sqc.F64) == 0

@@ -1,0 +1,105 @@
+"""GPU parity of arbitrary-subset queries (Sec. 3: chosen states evaluated in
+one recursion without merging) against Eq. 1 evaluated state by state by the
+oracle, through the C interface.  Small physical circuits (every precision,
+random states plus the first, the last and a repeated one, more states than
+one batch holds) and the precision workload (24 qubits, 256 random states).
+Tolerances: 1e-12 for FP64, 1e-6 for the FP32-MFMA and split-BF16x3 paths
+(physical data, probabilities <= 1)."""
+import numpy as np
+import pytest
+
+from oracle import reconstruction as rc
+from workloads import configs, qpu
+from workloads.circuits import planted_qaoa
+from workloads.cutgraph import build_cut_circuit
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+sqc = pytest.importorskip("paper_2207_00933_amd.sqc")
+runner = pytest.importorskip("paper_2207_00933_amd.runner")
+
+TOL = {sqc.F64: 1e-12, sqc.F32: 1e-6, sqc.BF16X3: 1e-6}
+PRECS = [("f64", sqc.F64), ("f32", sqc.F32), ("bf16x3", sqc.BF16X3)]
+
+
+@pytest.fixture(scope="module")
+def session():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = runner.Session(0, 64 << 20)
+    yield s
+    s.close()
+
+
+def _cases():
+    return {
+        "tiny": configs.tiny(),
+        "chain3": configs.chain_brickwork(3, [4, 5, 4], [1, 2], 4, 11),
+        "chain4": configs.chain_brickwork(4, [3, 4, 3, 4], [2, 1, 1], 4, 12),
+        "qaoa3": build_cut_circuit(planted_qaoa([4, 4, 4], seed=5)),
+    }
+
+
+def _query(session, cc, var, prec, states):
+    att = sqc.F64 if prec == sqc.F64 else sqc.F32
+    circ = runner.Circuit.from_cut_circuit(session, cc, var)
+    circ.attribute(att)
+    session.ensure_workspace(sqc.query_states_workspace_bytes(circ.att, circ.g, prec))
+    out = torch.full((max(1, len(states)),), -1.0, dtype=torch.float64 if att == sqc.F64 else torch.float32,
+                     device="cuda")
+    sqc.query_states(session.ctx, circ.att, circ.g, states, prec, out, att)
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()[: len(states)]
+
+
+@pytest.mark.parametrize("name", ["tiny", "chain3", "chain4", "qaoa3"])
+@pytest.mark.parametrize("pname,prec", PRECS)
+def test_query_states_small(session, name, pname, prec):
+    cc = _cases()[name]
+    var = qpu.all_variants(cc)
+    Ts = [rc.attribute(cc, i, var[i]) for i in range(cc.n_sub)]
+    n = cc.n
+    rng = np.random.default_rng(11 + len(name))
+    states = [0, (1 << n) - 1] + [int(x) for x in rng.integers(0, 1 << n, size=90)]
+    states.append(states[5])  # a repeated state
+    want = rc.eval_bins(Ts, cc, np.array(states))
+    say(f"query {name} {pname}: {len(states)} states")
+    got = _query(session, cc, var, prec, states)
+    err = np.abs(got - want).max()
+    say(f"  max |gpu - oracle| = {err:.3e}")
+    assert err <= TOL[prec]
+
+
+@pytest.mark.timeout(600)
+def test_query_states_precision_workload(session):
+    cc = configs.precision()
+    var32 = [v.astype(np.float32) for v in qpu.all_variants(cc)]
+    var = [v.astype(np.float64) for v in var32]
+    Ts = [rc.attribute(cc, i, var[i]) for i in range(cc.n_sub)]
+    rng = np.random.default_rng(5)
+    states = [int(x) for x in rng.integers(0, 1 << cc.n, size=256)]
+    want = rc.eval_bins(Ts, cc, np.array(states))
+    for pname, prec in (("f64", sqc.F64), ("bf16x3", sqc.BF16X3)):
+        say(f"query precision {pname}")
+        got = _query(session, cc, var, prec, states)
+        err = np.abs(got - want).max()
+        say(f"  max |gpu - oracle| = {err:.3e}")
+        assert err <= TOL[prec]
+
+
+def test_query_states_rejects_and_empty(session):
+    cc = _cases()["chain3"]
+    var = qpu.all_variants(cc)
+    circ = runner.Circuit.from_cut_circuit(session, cc, var)
+    circ.attribute(sqc.F64)
+    session.ensure_workspace(sqc.query_states_workspace_bytes(circ.att, circ.g, sqc.F64))
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(sqc.SqcError) as e:
+        sqc.query_states(session.ctx, circ.att, circ.g, [3, 1 << cc.n], sqc.F64, out, sqc.F64)
+    assert e.value.status == sqc.E_ARG
+    sqc.query_states(session.ctx, circ.att, circ.g, [], sqc.F64, out, sqc.F64)
+    torch.cuda.synchronize()
+    assert float(out.abs().max()) == 0.0
