@@ -327,8 +327,41 @@ def run_workloads(reps: int = 5):
             out[name] = res
             del circ
         out["slicing"] = run_slicing(s, reps)
+        out["subset_query"] = run_query(s, reps)
         s.close()
     return out
+
+
+def run_query(s, reps: int, n_states: int = 1024):
+    """Arbitrary-subset queries (Sec. 3) on the precision workload: the
+    probabilities of n_states seeded random output states (of 2^24), each a
+    recursion with every data bit fixed, batched.  Reports states/s (the
+    call waits for the device after every batch)."""
+    import torch
+    from paper_2207_00933_amd import runner, sqc
+
+    cc = configs.precision()
+    var32 = [v.astype(np.float32) for v in qpu.all_variants(cc)]
+    circ = runner.Circuit.from_cut_circuit(s, cc, var32, sqc.F32)
+    rng = np.random.default_rng(6)
+    states = [int(x) for x in rng.integers(0, 1 << cc.n, size=n_states)]
+    res = {"workload": "precision: 24 qubits, 3 subcircuits, 6 cuts", "states": n_states}
+    for pname, prec in (("bf16x3", sqc.BF16X3), ("f64", sqc.F64)):
+        att = sqc.F64 if prec == sqc.F64 else sqc.F32
+        circ.attribute(att)
+        s.ensure_workspace(sqc.query_states_workspace_bytes(circ.att, circ.g, prec))
+        probs = torch.empty(n_states, dtype=torch.float64 if att == sqc.F64 else torch.float32, device=s.device)
+        sqc.query_states(s.ctx, circ.att, circ.g, states, prec, probs, att)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sqc.query_states(s.ctx, circ.att, circ.g, states, prec, probs, att)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        res[pname] = {"ms": wall * 1e3, "states_per_s": n_states / wall}
+        log(f"[query] {pname}: {n_states} states in {wall * 1e3:.3f} ms, {n_states / wall:.3e} states/s")
+    del circ
+    return res
 
 
 def run_slicing(s, reps: int):
