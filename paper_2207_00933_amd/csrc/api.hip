@@ -60,6 +60,9 @@ namespace {
 
 // Control region at the start of the workspace.
 constexpr size_t kCtlBytes = 4096;
+// Pinned host buffer of a context: small device results (search) and the
+// job tables of a subset query's batches.
+constexpr size_t kPinnedBytes = 1 << 20;
 constexpr size_t kOffSearchTop = 256;    // SQC_MAX_TOPR x 16 bytes
 constexpr size_t kOffSearchSum = 256 + 16 * SQC_MAX_TOPR;
 
@@ -894,8 +897,8 @@ SliceArgs slice_args(const SlicedPlan &sp, int i, const sqc_tensor &t, void *out
 
 namespace {
 
-constexpr size_t kQueryStaging = 64 * 1024;  // the context's pinned buffer
-constexpr int kQueryMaxBatch = 64;
+constexpr size_t kQueryStaging = kPinnedBytes;
+constexpr int kQueryMaxBatch = 128;
 
 // Every data bit fixed: the bin of one state.
 std::vector<sqc_masks> state_scope(const std::vector<int> &d, uint64_t state) {
@@ -969,7 +972,7 @@ sqc_status sqc_ctx_create(int device, void *hip_stream, sqc_ctx **out) {
     sqc_ctx *c = new sqc_ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
-    if (hipHostMalloc(&c->pinned, 64 * 1024, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&c->pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
       delete c;
       raise(SQC_E_DEVICE, "hipHostMalloc of the staging buffer failed");
     }
