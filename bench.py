@@ -11,9 +11,9 @@ pairwise contraction into all 2^24 bins, the top-R bins and the FP64 bin sum.
 The step is timed for three contraction precisions (FP64 plain, FP32 MFMA,
 split-BF16x3 with an FP64-compensated final sum); ``value`` is the faster of
 the two fast forms, whose bins are also compared with the FP64 GPU path.
-The final contraction kernel of every fourth step is launched with HIP events
-recorded by its dispatch inside the timed loop (its live duration, for the
-roofline fraction); per-step latencies (p50 / p99) come from a separate pass
+The final contraction kernel of every fourth step, and the contraction step
+before it, are launched with HIP events recorded by their dispatch inside the
+timed loop (the final kernel's live duration, for the roofline fraction); per-step latencies (p50 / p99) come from a separate pass
 with an event per step, since per-step events cost several microseconds.  The CPU baseline is the FP64 oracle
 (Eq. 1 evaluated bin by bin) on a bounded sample of bins, timed on the host's
 cores before the GPU is touched.
@@ -166,11 +166,15 @@ def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph):
         torch.cuda.synchronize()
         # timed region: the final contraction of every FINAL_EVERY-th step is
         # launched with HIP events recorded by its dispatch (its live
-        # duration); the other steps carry no instrumentation, which costs
-        # several microseconds per step on this platform
+        # duration); the contraction step before it carries dispatch events
+        # too, since without them the final kernel's start stamp falls before
+        # the previous kernel has drained (about 3.5 us more on this
+        # platform); the other steps carry no instrumentation, which costs
+        # several microseconds per step
         t0 = time.perf_counter()
+        timed = sqc.STAGE_FINAL | sqc.STAGE_CONTRACT
         for k in range(steps):
-            sqc.ctx_set_timing(s.ctx, sqc.STAGE_FINAL if k % FINAL_EVERY == 0 else 0)
+            sqc.ctx_set_timing(s.ctx, timed if k % FINAL_EVERY == 0 else 0)
             step()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
