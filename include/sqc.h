@@ -224,6 +224,27 @@ sqc_status sqc_slice_plan(int32_t n_sub, const int32_t *out_bits,
                           double budget_floats, int32_t *sliced,
                           int32_t *n_sliced);
 
+/* Cut search (Sec. 5, MIP model, constraints and objective), host only.  The
+ * circuit's two-qubit gates, in circuit order, are gates[2 v], gates[2 v + 1]
+ * (qubit ids in [0, n_qubits)); they are the DAG's vertices, and each qubit
+ * line between two consecutive two-qubit gates on that qubit is an edge
+ * (input and output vertices are left out).  The call assigns every gate to
+ * one of n_sub subcircuits, each holding at least one and at most
+ * floor(alpha * n_gates) gates (Eq. 2), minimising the largest number of cut
+ * edges on one subcircuit, L = max_c (I_c + O_c) (Eq. 3), with the total
+ * number of cut edges as the tie-break.  Method: branch and bound over the
+ * gates in circuit order (subcircuit ids opened in order), started from the
+ * best contiguous split, pruned by the running L, which only grows; it stops
+ * after max_nodes search nodes (<= 0: no limit) and returns the best
+ * partition found (*optimal = 1 when the search completed).  Writes
+ * assign[n_gates], *L and *n_cut_edges.  Errors: SQC_E_ARG for NULL
+ * pointers, n_sub outside [1, n_gates], a qubit id out of range or a gate on
+ * one qubit; SQC_E_SHAPE when no partition meets Eq. 2. */
+sqc_status sqc_find_cuts(int32_t n_qubits, const int32_t *gates, int32_t n_gates,
+                         int32_t n_sub, double alpha, int64_t max_nodes,
+                         int32_t *assign, int32_t *L, int32_t *n_cut_edges,
+                         int32_t *optimal);
+
 /* ---- attribution (Sec. 2.1, Fig. 1) ---------------------------------------- */
 
 /* Bytes of subcircuit sub_id's attributed tensor: 4^c * 2^d elements of

@@ -531,3 +531,200 @@ extern "C" sqc_status sqc_slice_plan(int32_t n_sub, const int32_t *out_bits,
   return SQC_OK;
   SQC_HOST_CATCH
 }
+
+// ---------------------------------------------------------------------------
+// cut search (Sec. 5): partition the two-qubit-gate DAG
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct CutSearch {
+  int n = 0, n_sub = 0, cap = 0;
+  std::vector<std::vector<int>> pred;  // pred[v]: tail gates of v's in-edges (with repeats)
+  std::vector<int> assign, count, deg;
+  int L = 0, cut = 0, used = 0;
+  std::vector<int> best;
+  int best_L = 0, best_cut = 0;
+  bool have = false;
+  int64_t nodes = 0, max_nodes = 0;
+  bool stopped = false;
+
+  bool better(int l, int c) const { return !have || l < best_L || (l == best_L && c < best_cut); }
+
+  // (L, cut edges) of a full assignment; false when it breaks Eq. 2 or
+  // leaves a subcircuit empty
+  bool score(const std::vector<int> &a, int &l, int &c) const {
+    std::vector<int> d(n_sub, 0), cnt(n_sub, 0);
+    c = 0;
+    for (int v = 0; v < n; ++v) {
+      cnt[a[v]]++;
+      for (int u : pred[v])
+        if (a[u] != a[v]) {
+          d[a[u]]++;
+          d[a[v]]++;
+          c++;
+        }
+    }
+    for (int k : cnt)
+      if (k < 1 || k > cap) return false;
+    l = 0;
+    for (int x : d) l = std::max(l, x);
+    return true;
+  }
+
+  void evaluate(const std::vector<int> &a) {
+    int l, c;
+    if (score(a, l, c) && better(l, c)) {
+      best = a;
+      best_L = l;
+      best_cut = c;
+      have = true;
+    }
+  }
+
+  // single-gate moves that lower (L, cut edges), until none does (at most
+  // `passes` sweeps over the gates)
+  void improve(std::vector<int> &a, int passes) const {
+    int l, c;
+    if (!score(a, l, c)) return;
+    for (int p = 0; p < passes; ++p) {
+      bool moved = false;
+      for (int v = 0; v < n; ++v) {
+        const int from = a[v];
+        for (int to = 0; to < n_sub; ++to) {
+          if (to == from) continue;
+          a[v] = to;
+          int l2, c2;
+          if (score(a, l2, c2) && (l2 < l || (l2 == l && c2 < c))) {
+            l = l2;
+            c = c2;
+            moved = true;
+            break;
+          }
+          a[v] = from;
+        }
+      }
+      if (!moved) break;
+    }
+  }
+
+  void dfs(int v) {
+    if (stopped) return;
+    if (max_nodes > 0 && ++nodes > max_nodes) {
+      stopped = true;
+      return;
+    }
+    if (v == n) {
+      if (used == n_sub && better(L, cut)) {
+        best = assign;
+        best_L = L;
+        best_cut = cut;
+        have = true;
+      }
+      return;
+    }
+    // candidate subcircuits, fewest new cut edges first
+    const int top = std::min(used, n_sub - 1);
+    std::vector<std::pair<int, int>> cand;
+    for (int c = 0; c <= top; ++c) {
+      if (count[c] >= cap) continue;
+      const int opened = used + (c == used ? 1 : 0);
+      if (n - v - 1 < n_sub - opened) continue;  // too few gates left to open the rest
+      int add = 0;
+      for (int u : pred[v]) add += assign[u] != c;
+      cand.push_back({add, c});
+    }
+    std::stable_sort(cand.begin(), cand.end());
+    for (auto &pc : cand) {
+      const int c = pc.second;
+      const int saveL = L, saveCut = cut, saveUsed = used;
+      std::vector<std::pair<int, int>> touched;  // (subcircuit, increment)
+      int l = L;
+      for (int u : pred[v])
+        if (assign[u] != c) {
+          deg[assign[u]]++;
+          deg[c]++;
+          touched.push_back({assign[u], 1});
+          l = std::max(l, std::max(deg[assign[u]], deg[c]));
+        }
+      const int ncut = cut + (int)touched.size();
+      if (better(l, ncut)) {  // (L, cut) only grow: else the subtree cannot win
+        assign[v] = c;
+        count[c]++;
+        if (c == used) used++;
+        L = l;
+        cut = ncut;
+        dfs(v + 1);
+        count[c]--;
+        assign[v] = -1;
+      }
+      for (auto &t : touched) {
+        deg[t.first]--;
+        deg[c]--;
+      }
+      L = saveL;
+      cut = saveCut;
+      used = saveUsed;
+      if (stopped) return;
+    }
+  }
+};
+
+}  // namespace
+
+extern "C" sqc_status sqc_find_cuts(int32_t n_qubits, const int32_t *gates, int32_t n_gates, int32_t n_sub,
+                                    double alpha, int64_t max_nodes, int32_t *assign, int32_t *L,
+                                    int32_t *n_cut_edges, int32_t *optimal) {
+  SQC_HOST_TRY
+  if (!gates || !assign || !L || !n_cut_edges || !optimal) raise(SQC_E_ARG, "NULL argument");
+  if (n_gates < 1 || n_gates > (1 << 20)) raise(SQC_E_ARG, "n_gates must be in [1, 2^20]");
+  if (n_sub < 1 || n_sub > n_gates) raise(SQC_E_ARG, "n_sub must be in [1, n_gates]");
+  if (n_qubits < 2) raise(SQC_E_ARG, "n_qubits must be >= 2");
+  if (!(alpha > 0.0) || !(alpha <= 1.0)) raise(SQC_E_ARG, "alpha must be in (0, 1]");
+  CutSearch s;
+  s.n = n_gates;
+  s.n_sub = n_sub;
+  s.cap = (int)std::floor(alpha * n_gates + 1e-9);
+  if ((int64_t)s.cap * n_sub < n_gates || s.cap < 1)
+    raise(SQC_E_SHAPE, "no partition meets the load constraint alpha |V|");
+  s.pred.resize(n_gates);
+  std::vector<int> last(n_qubits, -1);
+  for (int v = 0; v < n_gates; ++v) {
+    const int a = gates[2 * v], b = gates[2 * v + 1];
+    if (a < 0 || a >= n_qubits || b < 0 || b >= n_qubits) raise(SQC_E_ARG, "gate qubit id out of range");
+    if (a == b) raise(SQC_E_ARG, "a two-qubit gate acts on one qubit twice");
+    for (int q : {a, b}) {
+      if (last[q] >= 0) s.pred[v].push_back(last[q]);
+      last[q] = v;
+    }
+  }
+  // starts: the contiguous split of the gate order into n_sub blocks, and
+  // qubit bands (a gate goes to the band of its lowest qubit), each improved
+  // by single-gate moves; the best is the incumbent of the exact search
+  const int passes = n_gates <= 4096 ? 64 : 4;
+  std::vector<int> a0(n_gates), a1(n_gates);
+  for (int v = 0; v < n_gates; ++v) {
+    a0[v] = (int)((int64_t)v * n_sub / n_gates);
+    const int q = std::min(gates[2 * v], gates[2 * v + 1]);
+    a1[v] = (int)((int64_t)q * n_sub / n_qubits);
+  }
+  s.evaluate(a0);
+  s.evaluate(a1);
+  s.improve(a0, passes);
+  s.evaluate(a0);
+  s.improve(a1, passes);
+  s.evaluate(a1);
+  s.assign.assign(n_gates, -1);
+  s.count.assign(n_sub, 0);
+  s.deg.assign(n_sub, 0);
+  s.max_nodes = max_nodes;
+  s.dfs(0);
+  if (!s.have) raise(SQC_E_SHAPE, "no partition meets the load constraint alpha |V|");
+  for (int v = 0; v < n_gates; ++v) assign[v] = s.best[v];
+  *L = s.best_L;
+  *n_cut_edges = s.best_cut;
+  *optimal = s.stopped ? 0 : 1;
+  set_thread_error("");
+  return SQC_OK;
+  SQC_HOST_CATCH
+}

@@ -132,6 +132,9 @@ def lib():
                                       POINTER(c_int32), POINTER(Cost)]),
             "sqc_slice_plan": (c_int, [c_int32, POINTER(c_int32), POINTER(Cut), c_int32,
                                        c_double, POINTER(c_int32), POINTER(c_int32)]),
+            "sqc_find_cuts": (c_int, [c_int32, POINTER(c_int32), c_int32, c_int32, c_double,
+                                      ctypes.c_int64, POINTER(c_int32), POINTER(c_int32),
+                                      POINTER(c_int32), POINTER(c_int32)]),
             "sqc_attribute_bytes": (c_size_t, [POINTER(Sub), c_int32, c_int32, POINTER(Cut),
                                                c_int32, c_int]),
             "sqc_attribute": (c_int, [P, POINTER(Sub), c_int32, c_int32, POINTER(Cut), c_int32,
@@ -342,6 +345,18 @@ def slice_plan(out_bits: Sequence[int], cuts: Sequence[Sequence[int]], budget: f
     ns = c_int32()
     _check(lib().sqc_slice_plan(n, ob, cs, len(cuts), float(budget), sl, ctypes.byref(ns)))
     return list(sl[:ns.value])
+
+
+def find_cuts(n_qubits: int, gates: Sequence[Sequence[int]], n_sub: int, alpha: float,
+              max_nodes: int = 0):
+    """Cut search of Sec. 5: (assignment per gate, L, cut edges, optimal)."""
+    n = len(gates)
+    flat = (c_int32 * max(2, 2 * n))(*[int(q) for g in gates for q in g])
+    out = (c_int32 * max(1, n))()
+    L, nc, opt = c_int32(), c_int32(), c_int32()
+    _check(lib().sqc_find_cuts(n_qubits, flat, n, n_sub, float(alpha), int(max_nodes), out,
+                               ctypes.byref(L), ctypes.byref(nc), ctypes.byref(opt)))
+    return list(out[:n]), L.value, nc.value, bool(opt.value)
 
 
 def attribute_bytes(g: Graph, sub_id: int, out_prec: int) -> int:

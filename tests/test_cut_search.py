@@ -1,0 +1,72 @@
+"""The library's cut search (Sec. 5) against the exhaustive oracle: on random
+tiny circuits the branch and bound reaches the oracle's optimum L, and every
+partition it returns meets Eq. 2 with the L and cut count it reports.  Host
+code only (no GPU)."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import cut_search as cs
+from workloads import configs
+
+sqc = pytest.importorskip("paper_2207_00933_amd.sqc")
+
+
+def _random_gates(rng, n_qubits, n_gates):
+    out = []
+    for _ in range(n_gates):
+        a, b = rng.choice(n_qubits, size=2, replace=False)
+        out.append((int(a), int(b)))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_matches_exhaustive_optimum(seed):
+    rng = np.random.default_rng(seed)
+    n_q = int(rng.integers(3, 6))
+    n_g = int(rng.integers(3, 10))
+    n_sub = int(rng.integers(2, 4))
+    alpha = float(rng.choice([0.5, 0.7, 1.0]))
+    gates = _random_gates(rng, n_q, n_g)
+    want = cs.brute_force(gates, n_sub, alpha)
+    if want is None:
+        with pytest.raises(sqc.SqcError):
+            sqc.find_cuts(n_q, gates, n_sub, alpha)
+        return
+    assign, L, ncut, optimal = sqc.find_cuts(n_q, gates, n_sub, alpha)
+    assert optimal
+    edges = cs.dag_edges(gates)
+    assert cs.feasible(assign, n_sub, alpha)
+    assert L == cs.objective(assign, edges, n_sub) == want
+    assert ncut == sum(1 for u, v in edges if assign[u] != assign[v])
+
+
+def test_budgeted_search_on_a_workload_circuit():
+    """A 24-qubit, 5-layer brickwork (the precision workload's circuit, its
+    two-qubit gates in order): with a node budget the search returns a
+    feasible partition no worse than the contiguous split it starts from."""
+    cc = configs.precision()
+    gates = [tuple(g.qubits) for g in cc.circuit.gates if len(g.qubits) == 2]
+    edges = cs.dag_edges(gates)
+    n_sub = 3
+    t0 = time.perf_counter()
+    assign, L, ncut, optimal = sqc.find_cuts(24, gates, n_sub, 0.5, max_nodes=200000)
+    dt = time.perf_counter() - t0
+    assert cs.feasible(assign, n_sub, 0.5)
+    assert L == cs.objective(assign, edges, n_sub)
+    start = [v * n_sub // len(gates) for v in range(len(gates))]
+    assert (L, ncut) <= (cs.objective(start, edges, n_sub),
+                         sum(1 for u, v in edges if start[u] != start[v]))
+    assert dt < 30.0
+
+
+@pytest.mark.parametrize("args", [
+    (2, [(0, 0)], 1, 1.0),      # a gate on one qubit
+    (2, [(0, 2)], 1, 1.0),      # qubit out of range
+    (2, [(0, 1)], 2, 1.0),      # more subcircuits than gates
+    (2, [(0, 1)] * 4, 2, 0.2),  # Eq. 2 cannot hold
+])
+def test_rejects(args):
+    with pytest.raises(sqc.SqcError):
+        sqc.find_cuts(*args)
