@@ -232,11 +232,15 @@ sqc_status sqc_slice_plan(int32_t n_sub, const int32_t *out_bits,
  * one of n_sub subcircuits, each holding at least one and at most
  * floor(alpha * n_gates) gates (Eq. 2), minimising the largest number of cut
  * edges on one subcircuit, L = max_c (I_c + O_c) (Eq. 3), with the total
- * number of cut edges as the tie-break.  Method: branch and bound over the
- * gates in circuit order (subcircuit ids opened in order), started from the
- * best contiguous split, pruned by the running L, which only grows; it stops
- * after max_nodes search nodes (<= 0: no limit) and returns the best
- * partition found (*optimal = 1 when the search completed).  Writes
+ * number of cut edges as the tie-break.  Method: two starts (the gate order
+ * cut into n_sub blocks; bands of qubits, a gate in the band of its lowest
+ * qubit) improved by single-gate moves, then iterated local search (a few
+ * gates moved at random with a fixed seed, improved again, kept when
+ * better), then branch and bound over the gates in circuit order
+ * (subcircuit ids opened in order) from that incumbent, pruned by the
+ * running (L, cut edges), which only grow; it stops after max_nodes search
+ * nodes (<= 0: no limit) and returns the best partition found (*optimal = 1
+ * when the search completed).  Writes
  * assign[n_gates], *L and *n_cut_edges.  Errors: SQC_E_ARG for NULL
  * pointers, n_sub outside [1, n_gates], a qubit id out of range or a gate on
  * one qubit; SQC_E_SHAPE when no partition meets Eq. 2. */

@@ -714,6 +714,26 @@ extern "C" sqc_status sqc_find_cuts(int32_t n_qubits, const int32_t *gates, int3
   s.evaluate(a0);
   s.improve(a1, passes);
   s.evaluate(a1);
+  // iterated local search: perturb the best partition (a few gates moved to
+  // random subcircuits, fixed-seed xorshift so results are reproducible),
+  // improve it again, keep it when it wins
+  if (s.have && n_sub > 1) {
+    uint64_t x = 0x9E3779B97F4A7C15ull;
+    auto rnd = [&]() {
+      x ^= x << 13;
+      x ^= x >> 7;
+      x ^= x << 17;
+      return x;
+    };
+    const int rounds = n_gates <= 512 ? 200 : 16;
+    for (int r = 0; r < rounds; ++r) {
+      std::vector<int> a = s.best;
+      const int kick = 2 + (int)(rnd() % 4);
+      for (int t = 0; t < kick; ++t) a[rnd() % n_gates] = (int)(rnd() % n_sub);
+      s.improve(a, passes);
+      s.evaluate(a);
+    }
+  }
   s.assign.assign(n_gates, -1);
   s.count.assign(n_sub, 0);
   s.deg.assign(n_sub, 0);

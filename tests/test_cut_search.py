@@ -58,6 +58,9 @@ def test_budgeted_search_on_a_workload_circuit():
     start = [v * n_sub // len(gates) for v in range(len(gates))]
     assert (L, ncut) <= (cs.objective(start, edges, n_sub),
                          sum(1 for u, v in edges if start[u] != start[v]))
+    # no worse than the workload's own moving-boundary partition
+    given = [g.sub for g in cc.circuit.gates if len(g.qubits) == 2]
+    assert L <= cs.objective(given, edges, n_sub)
     assert dt < 30.0
 
 
