@@ -190,8 +190,18 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        _typed.update(sig)
         _lib = L
     return _lib
+
+
+_typed = set()  # entry points given a ctypes signature by lib()
+
+
+def typed_symbols() -> List[str]:
+    """Entry points the binding declares argument and result types for."""
+    lib()
+    return sorted(_typed)
 
 
 def declared_symbols() -> List[str]:

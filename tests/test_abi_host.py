@@ -28,6 +28,12 @@ def test_library_exports_every_declared_symbol():
     assert "gfx950" in sqc.version()
 
 
+def test_binding_types_every_declared_symbol():
+    # an untyped ctypes call would pass 64-bit sizes and pointers as int
+    missing = sorted(set(sqc.declared_symbols()) - set(sqc.typed_symbols()))
+    assert not missing, missing
+
+
 def test_no_gpu_is_reported():
     import torch
     if torch.cuda.is_available():
