@@ -232,3 +232,11 @@ def test_query_workspace_is_fixed_and_validated():
     bad = list(descs)
     bad[0] = sqc.tensor_desc(torch.zeros(4), 0, 1, sqc.F64, sqc.LAYOUT_ATTRIBUTED)  # wrong degree
     assert sqc.query_states_workspace_bytes(bad, g, sqc.F64) == 0
+
+
+def test_sliced_count_limit():
+    # ten cuts between two subcircuits: eight may be sliced, nine may not
+    bits, cuts = [2, 2], [(0, 1)] * 10
+    g, descs, _ = _sliced_descs(bits, cuts, sqc.F32)
+    assert sqc.contract_sliced_workspace_bytes(descs, g, list(range(8)), sqc.F32) > 0
+    assert sqc.contract_sliced_workspace_bytes(descs, g, list(range(9)), sqc.F32) == 0
