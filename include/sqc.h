@@ -393,8 +393,9 @@ sqc_status sqc_query_states(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t 
 /* ---- HIP graphs of enqueued work (not part of the paper) ----------------------- */
 
 /* Record the work later calls enqueue on the context's stream (sqc_attribute,
- * sqc_attribute_all, sqc_merge, sqc_contract, sqc_recurse) into a HIP graph
- * instead of running it, then replay it with one launch.  For repeated
+ * sqc_attribute_all, sqc_merge, sqc_contract, sqc_contract_sliced,
+ * sqc_recurse) into a HIP graph instead of running it, then replay it with one
+ * launch.  For repeated
  * queries whose buffers do not change (the graph keeps every pointer and
  * argument of the recorded calls, including the workspace, so the caller
  * keeps them alive and unchanged in size until sqc_graph_destroy).  The

@@ -162,3 +162,54 @@ def test_precision_sliced_full_size_sampled(session, sliced):
         # the bins still sum to one (Sec. 3 invariant at recursion 0)
         assert abs(float(out.double().sum()) - 1.0) <= 1e-6
         del bufs, descs, out
+
+
+def test_contract_sliced_in_a_graph():
+    """Recorded into a HIP graph (gathers, contraction steps and additions:
+    no memset nodes), every replay matches the oracle, with an eager sliced
+    contraction on the same stream and workspace between replays."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bits, cuts, _ = CASES["ring4"]
+    cc = _View(len(bits), cuts)
+    rng = np.random.default_rng(21)
+    Ts = [rng.standard_normal((1 << (2 * len(cc.incident(i))), 1 << bits[i])).astype(np.float32).astype(np.float64)
+          for i in range(len(bits))]
+    bound = error_bound(Ts, cc)
+    want = network.contract_sliced(Ts, cc, [0, 4])
+    want_other = network.contract_sliced(Ts, cc, [7])
+    tol = TOL_REL[sqc.BF16X3] * bound + 2.0 ** -24 * np.abs(want) + 1e-300
+    tol_other = TOL_REL[sqc.BF16X3] * bound + 2.0 ** -24 * np.abs(want_other) + 1e-300
+    g = sqc.Graph([1] * len(bits), [[] for _ in bits], [(u, 0, v, 0) for u, v in cuts])
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s = runner.Session(0, 64 << 20)
+    sqc.ctx_set_stream(s.ctx, st.cuda_stream)
+    try:
+        with torch.cuda.stream(st):
+            bufs, descs = _upload(Ts, cc, bits, sqc.BF16X3)
+            s.ensure_workspace(max(sqc.contract_sliced_workspace_bytes(descs, g, [0, 4], sqc.BF16X3),
+                                   sqc.contract_sliced_workspace_bytes(descs, g, [7], sqc.BF16X3)))
+            out = torch.empty(len(want), dtype=torch.float32, device="cuda")
+            other = torch.empty(len(want), dtype=torch.float32, device="cuda")
+            st.synchronize()
+            sqc.graph_begin(s.ctx)
+            sqc.contract_sliced(s.ctx, descs, g, [0, 4], sqc.BF16X3, out, sqc.F32)
+            gr = sqc.graph_end(s.ctx)
+            try:
+                for k in range(4):
+                    out.fill_(float("nan"))
+                    sqc.graph_launch(s.ctx, gr)
+                    st.synchronize()
+                    got = out.double().cpu().numpy()
+                    say(f"sliced graph replay {k}: max err {np.abs(got - want).max():.3e}")
+                    assert np.all(np.abs(got - want) <= tol), k
+                    other.fill_(float("nan"))
+                    sqc.contract_sliced(s.ctx, descs, g, [7], sqc.BF16X3, other, sqc.F32)
+                    st.synchronize()
+                    assert np.all(np.abs(other.double().cpu().numpy() - want_other) <= tol_other), k
+            finally:
+                sqc.graph_destroy(gr)
+    finally:
+        st.synchronize()
+        s.close()
