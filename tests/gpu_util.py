@@ -6,6 +6,16 @@ import numpy as np
 
 from oracle import network, reconstruction as rc
 
+# Relative factor of the a-priori rounding bound per contraction path
+# (0 = FP64, 1 = FP32 MFMA, 2 = split-BF16x3): a bin computed as a sum of
+# products of the entries T_i is off by at most TOL_REL * sum_sigma prod_i
+# |T_i[sigma, x_i]|.  FP32 accumulation over the plan's steps costs a small
+# multiple of 2^-24 per term; split-BF16x3 drops lo*lo and keeps each
+# operand to 2^-16 relative, so each product is good to about 3 * 2^-16.
+TOL_REL = {0: 1e-13, 1: 2.0 ** -20, 2: 2.0 ** -13}
+# The absolute tolerances stated for physical data (probabilities <= 1).
+TOL_ABS = {0: 1e-12, 1: 1e-6, 2: 1e-6}
+
 
 def say(*a):
     print(*a, flush=True)
@@ -41,3 +51,37 @@ def bins_from_masks(m, d):
 def error_bound(Ts, cc):
     """Sum of |terms| per output (contraction of |T|), the scale of rounding."""
     return network.contract_all([np.abs(T) for T in Ts], cc)
+
+
+def sampled_bound(Ts, cc, bins):
+    """The same sum of |terms| at selected subcircuit-major outputs only."""
+    return network.eval_bins([np.abs(T) for T in Ts], cc, bins)
+
+
+def bound_tol(prec, bound, ref, bins_f32):
+    """Per-bin tolerance: the path's a-priori bound, plus the rounding of the
+    stored bin when bins are FP32."""
+    tol = TOL_REL[prec] * np.asarray(bound, dtype=np.float64)
+    if bins_f32:
+        tol = tol + 2.0 ** -24 * np.abs(ref)
+    return tol + 1e-300
+
+
+def bound_violations(got, want, bound, prec, bins_f32):
+    """Indices where |got - want| exceeds the per-bin tolerance (NaN counts)."""
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    ok = np.abs(got - want) <= bound_tol(prec, bound, want, bins_f32)
+    return np.flatnonzero(~ok)
+
+
+def assert_bound(got, want, bound, prec, bins_f32, what="", physical=True):
+    """Every bin within its a-priori bound, and (physical data) within the
+    absolute tolerance."""
+    bad = bound_violations(got, want, bound, prec, bins_f32)
+    err = np.abs(np.asarray(got, dtype=np.float64) - want)
+    rel = err / bound_tol(prec, bound, want, bins_f32)
+    say(f"  {what}: max-abs {err.max():.3e}, max err / bound-tol {rel.max():.3f} over {len(err)} bins")
+    assert len(bad) == 0, (what, bad[:8], err[bad[:8]])
+    if physical:
+        assert err.max() <= TOL_ABS[prec], (what, err.max())

@@ -1,15 +1,20 @@
 """GPU parity at the full sizes of the three reconstruction workloads, on
 sampled outputs the oracle evaluates one by one, plus the invariants that hold
-at any size.
+at any size.  Every sampled bin is held to the path's a-priori rounding bound
+(a multiple of its unit roundoff times the oracle's contraction of |T| at that
+bin) and, as a second check, to the absolute tolerance for physical data.
 
 - precision (24 qubits, 3 subcircuits, 6 cuts, FP32-cast outputs): the
   2^24-bin reconstruction in the launch configuration bench.py times (FP32
   bins on the fast paths), 4096 sampled bins against Eq. 1 evaluated by the
-  oracle on the same cast inputs; the sum of all bins is 1 to rounding.
+  oracle on the same cast inputs; all 2^24 bins of each fast path against the
+  FP64 GPU path at the per-bin bound (the oracle's |T| contraction over the
+  whole output); the sum of all bins is 1 to rounding.
 - merging (60-qubit QAOA, 4 subcircuits, 8 cuts, M = 2^20): recursions that
   expand the top bin down to single states, with sampled bins of every
   recursion against the oracle's merged entries contracted bin by bin, child
-  bins summing to the parent bin and FP32 MFMA against the FP64 GPU path; and
+  bins summing to the parent bin, FP32 MFMA and split-BF16x3 against the FP64
+  GPU path on every bin; and
   Algorithm 1 on the device with R = 12 (twelve recursions, each summing to the
   bin it expands, FP32 expanding the same bins as FP64).
 - large (200 qubits, 16 subcircuits, 24 cuts, M = 2^24): two recursions,
@@ -22,7 +27,7 @@ import pytest
 from oracle import network, reconstruction as rc, states_merging as sm
 from workloads import configs, qpu
 
-from gpu_util import oracle_attributed, say
+from gpu_util import TOL_REL, assert_bound, error_bound, oracle_attributed, sampled_bound, say
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +55,10 @@ def test_precision_full_reconstruction_sampled(session):
     rng = np.random.default_rng(2)
     sample = np.unique(rng.integers(0, 1 << cc.n, size=4096))
     want = network.eval_bins(Th, cc, sample)
+    bound = sampled_bound(Th, cc, sample)
+    bound_all = error_bound(Th, cc)  # whole output, for the path-to-path check
     circ = runner.Circuit.from_cut_circuit(session, cc, var32, sqc.F32)
+    ref64 = None
     for pname, prec in (("f64", sqc.F64), ("f32", sqc.F32), ("bf16x3", sqc.BF16X3)):
         att = sqc.F64 if prec == sqc.F64 else sqc.F32
         bins_prec = sqc.F64 if prec == sqc.F64 else sqc.F32
@@ -60,9 +68,18 @@ def test_precision_full_reconstruction_sampled(session):
         rec.run(prec, 1 << cc.n)
         torch.cuda.synchronize()
         bins = rec.bins.double().cpu().numpy()
-        err = np.abs(bins[sample] - want).max()
-        say(f"  max |gpu - oracle| over {len(sample)} sampled bins: {err:.3e}")
-        assert err <= TOL[prec]
+        assert_bound(bins[sample], want, bound, prec, prec != sqc.F64, f"{pname} vs oracle, sampled")
+        if prec == sqc.F64:
+            ref64 = bins
+        else:
+            # every bin against the FP64 GPU path: the fast path's bound plus
+            # the FP64 path's own
+            tol = (TOL_REL[prec] + TOL_REL[sqc.F64]) * bound_all + 2.0 ** -24 * np.abs(ref64) + 1e-300
+            err = np.abs(bins - ref64)
+            bad = np.flatnonzero(~(err <= tol))
+            say(f"  {pname} vs FP64 GPU, all {len(bins)} bins: max-abs {err.max():.3e}, "
+                f"max err / tol {(err / tol).max():.3f}")
+            assert len(bad) == 0, (bad[:8], err[bad[:8]], tol[bad[:8]])
         assert abs(rec.sum.item() - 1.0) <= 1e-6
         vals, idx = rec.top_list()
         assert np.all(np.diff(vals) <= 0)
@@ -75,12 +92,14 @@ def _merged_oracle(Th, cc, lit):
     return [rc.merge_entries(Th[i], lit[i]) for i in range(cc.n_sub)]
 
 
-def _run_recursions(session, cc, circ, Th, M, n_rec, precs, n_sample, seed):
+def _run_recursions(session, cc, circ, Th, M, n_rec, precs, n_sample, seed, full_bound=True):
     """Recursions expanding the top bin of the FP64 GPU path; every precision
-    follows the same bins.  Returns per precision the list of bin vectors."""
+    follows the same bins.  Returns per precision the list of bin vectors
+    (and under "bound" the oracle's |T| contraction of every bin)."""
     d = [s.n_data for s in cc.subs]
     rng = np.random.default_rng(seed)
     out = {p: [] for p in precs}
+    out["bound"] = []
     scope, lit_states, parent = None, None, None
     for r in range(n_rec):
         lit = sm.assign_states(r, lit_states, M, d)
@@ -89,6 +108,14 @@ def _run_recursions(session, cc, circ, Th, M, n_rec, precs, n_sample, seed):
         Tm = _merged_oracle(Th, cc, lit)
         sample = np.unique(rng.integers(0, nb, size=n_sample))
         want = network.eval_bins(Tm, cc, sample)
+        # rounding scale of a merged bin: the attributed entries are stored in
+        # the path's precision before merging, so the bound contracts the
+        # merged |T| (not |merged T|)
+        absm = [np.abs(T) for T in Th]
+        Tabs = _merged_oracle(absm, cc, lit)
+        bound = network.eval_bins(Tabs, cc, sample)
+        if full_bound:
+            out["bound"].append(network.contract_all(Tabs, cc))
         pick = None
         for p in precs:
             att = sqc.F64 if p == sqc.F64 else sqc.F32
@@ -99,9 +126,7 @@ def _run_recursions(session, cc, circ, Th, M, n_rec, precs, n_sample, seed):
             masks = rec.run(p, M, scope)
             torch.cuda.synchronize()
             got = rec.bins.cpu().numpy()[:nb]
-            err = np.abs(got[sample] - want).max()
-            say(f"  max |gpu - oracle| over {len(sample)} sampled bins: {err:.3e}")
-            assert err <= TOL[p]
+            assert_bound(got[sample], want, bound, p, False, f"r={r} prec={p} vs oracle, sampled")
             if parent is not None:
                 # child bins sum to the parent bin (linearity, any data)
                 assert abs(got.sum() - parent) <= max(1e-12, TOL[p] * 10)
@@ -127,9 +152,14 @@ def test_merging_twelve_recursions(session):
     say("merging: oracle entries")
     Th = oracle_attributed(cc, var)
     circ = runner.Circuit.from_cut_circuit(session, cc, var, sqc.F64)
-    out = _run_recursions(session, cc, circ, Th, 1 << 20, 12, [sqc.F64, sqc.F32], 256, seed=3)
-    for g64, g32 in zip(out[sqc.F64], out[sqc.F32]):
-        assert np.abs(g64 - g32).max() <= 1e-6
+    out = _run_recursions(session, cc, circ, Th, 1 << 20, 12, [sqc.F64, sqc.F32, sqc.BF16X3], 256, seed=3)
+    for p in (sqc.F32, sqc.BF16X3):
+        for g64, gp, bnd in zip(out[sqc.F64], out[p], out["bound"]):
+            tol = (TOL_REL[p] + TOL_REL[sqc.F64]) * bnd + 1e-300
+            err = np.abs(g64 - gp)
+            say(f"  prec={p} vs FP64 GPU, all bins: max-abs {err.max():.3e}, max err / tol {(err / tol).max():.3f}")
+            assert np.all(err <= tol)
+            assert err.max() <= 1e-6
     assert len(out[sqc.F64]) >= 3
 
 
@@ -141,10 +171,12 @@ def test_large_chain_two_recursions(session):
     Th = oracle_attributed(cc, var)
     circ = runner.Circuit.from_cut_circuit(session, cc, var, sqc.F64)
     out = _run_recursions(session, cc, circ, Th, 1 << 24, 2, [sqc.F64, sqc.BF16X3], 128, seed=5)
-    for g64, gb in zip(out[sqc.F64], out[sqc.BF16X3]):
-        err = np.abs(g64 - gb).max()
-        say(f"  bf16x3 vs fp64 GPU max-abs {err:.3e}")
-        assert err <= 1e-6
+    for g64, gb, bnd in zip(out[sqc.F64], out[sqc.BF16X3], out["bound"]):
+        tol = (TOL_REL[sqc.BF16X3] + TOL_REL[sqc.F64]) * bnd + 1e-300
+        err = np.abs(g64 - gb)
+        say(f"  bf16x3 vs fp64 GPU, all bins: max-abs {err.max():.3e}, max err / tol {(err / tol).max():.3f}")
+        assert np.all(err <= tol)
+        assert err.max() <= 1e-6
 
 
 @pytest.mark.timeout(900)

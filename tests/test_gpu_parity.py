@@ -13,7 +13,7 @@ from workloads import configs, qpu
 from workloads.circuits import planted_qaoa
 from workloads.cutgraph import build_cut_circuit
 
-from gpu_util import bins_from_masks, error_bound, oracle_attributed, say
+from gpu_util import TOL_REL, bins_from_masks, error_bound, oracle_attributed, say
 
 pytestmark = pytest.mark.gpu
 
@@ -23,7 +23,6 @@ runner = pytest.importorskip("paper_2207_00933_amd.runner")
 
 PRECS = [("f64", 0), ("f32", 1), ("bf16x3", 2)]
 TOL_ABS = {0: 1e-12, 1: 1e-6, 2: 1e-6}
-TOL_REL = {0: 1e-13, 1: 2.0 ** -20, 2: 2.0 ** -13}
 
 
 @pytest.fixture(scope="module")

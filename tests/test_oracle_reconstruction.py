@@ -151,8 +151,9 @@ def test_planted_basis_swap_is_caught(monkeypatch):
     assert _err_with(monkeypatch, "MEAS_BASIS", (0, 2, 1, 0), cc) > 1e-6
 
 
-@pytest.mark.slow
 def test_precision_config_sampled_brute_force():
+    """Degree-6 middle subcircuit (1728 variants) of the 24-qubit workload:
+    Eq. 1 at sampled outputs equals the full 24-qubit statevector."""
     cc = configs.precision()
     var = qpu.all_variants(cc)
     Ts = [rc.attribute(cc, i, var[i]) for i in range(cc.n_sub)]
