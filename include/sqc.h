@@ -42,8 +42,10 @@
  *
  * Ownership and asynchrony
  * ------------------------
- * Every device buffer is allocated by the caller (the Python binding uses
- * PyTorch's allocator).  Device pointers are plain addresses on the context's
+ * Every device buffer that a call reads or writes is allocated by the
+ * caller (the Python binding uses PyTorch's allocator); the library itself
+ * allocates no device memory (its constants are file-scope device arrays,
+ * present on every device from the library's load).  Device pointers are plain addresses on the context's
  * device.  Calls validate their arguments synchronously on the host; on any
  * error nothing is enqueued, outputs are untouched, and a message is kept for
  * sqc_last_error().  Calls that launch kernels enqueue them on the context's

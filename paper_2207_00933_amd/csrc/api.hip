@@ -15,6 +15,11 @@ namespace sqc {
 
 namespace {
 
+// The one-element tensor of a single-subcircuit contraction: FP64 1.0, then
+// FP32 1.0 in the low half of the second word.  Each device holds its own
+// copy; its address on a device comes from hipGetSymbolAddress.
+__device__ __align__(16) uint64_t unit_const[2] = {0x3FF0000000000000ull, 0x000000003F800000ull};
+
 __global__ void cast_copy(const void *src, int src_f32, void *dst, int dst_f32, int64_t n) {
   for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n;
        q += int64_t(gridDim.x) * blockDim.x) {
@@ -37,7 +42,7 @@ struct sqc_ctx {
   size_t ws_bytes = 0;
   std::string err;
   void *pinned = nullptr;  // host staging for small device results
-  double *unit = nullptr;  // device: double 1.0 then float 1.0 (one-element tensor)
+  double *unit = nullptr;  // device address of unit_const on this context's device
   // stage timing
   uint32_t timing_mask = 0;
   uint32_t saved_mask = 0;  // timing mask suspended while a graph is recorded
@@ -185,6 +190,28 @@ void settle_timing(sqc_ctx *ctx) {
     ctx->pool.push_back(m.b);
   }
   ctx->marks.clear();
+}
+
+// Device addresses of the library's file-scope device arrays, per device,
+// taken once with that device current (each device holds its own copies).
+struct DeviceStatics {
+  void *unit = nullptr;
+};
+constexpr int kMaxDevices = 64;
+std::mutex statics_mu;
+DeviceStatics statics[kMaxDevices];
+
+// The current device must be `device`.  Null when a lookup fails.
+const DeviceStatics *device_statics(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(statics_mu);
+  DeviceStatics &d = statics[device];
+  if (!d.unit) {
+    void *u = nullptr;
+    if (hipGetSymbolAddress(&u, HIP_SYMBOL(unit_const)) != hipSuccess || !u) return nullptr;
+    d.unit = u;
+  }
+  return &d;
 }
 
 // ---------------------------------------------------------------------------
@@ -976,16 +1003,13 @@ sqc_status sqc_ctx_create(int device, void *hip_stream, sqc_ctx **out) {
       delete c;
       raise(SQC_E_DEVICE, "hipHostMalloc of the staging buffer failed");
     }
-    double unit[2] = {1.0, 0.0};
-    const float one = 1.0f;
-    std::memcpy(&unit[1], &one, sizeof(one));
-    if (hipMalloc(reinterpret_cast<void **>(&c->unit), sizeof(unit)) != hipSuccess ||
-        hipMemcpy(c->unit, unit, sizeof(unit), hipMemcpyHostToDevice) != hipSuccess) {
-      if (c->unit) (void)hipFree(c->unit);
+    const DeviceStatics *ds = device_statics(device);
+    if (!ds) {
       (void)hipHostFree(c->pinned);
       delete c;
-      raise(SQC_E_DEVICE, "allocation of the context's constants failed");
+      raise(SQC_E_DEVICE, "hipGetSymbolAddress of the library's device constants failed");
     }
+    c->unit = static_cast<double *>(ds->unit);
     *out = c;
     return SQC_OK;
   } catch (const Error &e) {
@@ -1004,7 +1028,6 @@ sqc_status sqc_ctx_destroy(sqc_ctx *ctx) {
   }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-  if (ctx->unit) (void)hipFree(ctx->unit);
   delete static_cast<PlanCache *>(ctx->plan_cache);
   delete ctx;
   return SQC_OK;
