@@ -369,6 +369,30 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
                        sqc_prec bins_prec, sqc_masks *masks_out,
                        void *topr_dev, void *sum_dev);
 
+/* Allocation-free recursion, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same work, kernels and results as sqc_recurse (bitwise),
+ * with the workspace taken from a device array inside the library instead of
+ * the context's workspace (sqc_ctx_set_workspace is not needed).  The array
+ * holds SQC_NOALLOC_SCRATCH_BYTES (64 MiB) on each device the library runs
+ * on, from the library's load until the process ends; its address is taken
+ * once per device by sqc_ctx_create.  A recursion whose workspace
+ * (sqc_recurse_workspace_bytes) exceeds it fails with SQC_E_NOMEM and
+ * enqueues nothing.  The call allocates nothing (no hipMalloc, no events:
+ * stage timing does not apply).  Every call on one device shares that
+ * device's array, and the array keeps the last call's contents (nothing in
+ * it needs to start at zero: every byte a call reads, the same call wrote
+ * first); calls that overlap on one device, on any streams or contexts, race
+ * and give undefined results, so the caller orders them (one stream, or
+ * events).  Arguments, outputs and the other errors as sqc_recurse. */
+#define SQC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sqc_status sqc_recurse_noalloc(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
+                               const sqc_cut *cuts, int32_t n_cuts,
+                               const sqc_masks *scope, uint64_t max_bins_M,
+                               int32_t top_r, sqc_prec prec, void *bins_dev,
+                               sqc_prec bins_prec, sqc_masks *masks_out,
+                               void *topr_dev, void *sum_dev);
+
 /* Probabilities of chosen output states (Sec. 3: an arbitrary subset of
  * states evaluated in one recursion without merging into bins).  states[j]
  * (host array, n_states entries) is a full output index, subcircuit-major as

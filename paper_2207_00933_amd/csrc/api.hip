@@ -20,6 +20,11 @@ namespace {
 // copy; its address on a device comes from hipGetSymbolAddress.
 __device__ __align__(16) uint64_t unit_const[2] = {0x3FF0000000000000ull, 0x000000003F800000ull};
 
+// Workspace of sqc_recurse_noalloc: a file-scope device array, so that call
+// allocates nothing.  Each device holds its own copy from the first load of
+// the library until the process ends; every call on a device shares it.
+__device__ __align__(256) unsigned char scratch[SQC_NOALLOC_SCRATCH_BYTES];
+
 __global__ void cast_copy(const void *src, int src_f32, void *dst, int dst_f32, int64_t n) {
   for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n;
        q += int64_t(gridDim.x) * blockDim.x) {
@@ -196,6 +201,7 @@ void settle_timing(sqc_ctx *ctx) {
 // taken once with that device current (each device holds its own copies).
 struct DeviceStatics {
   void *unit = nullptr;
+  char *scratch = nullptr;  // the device address of `scratch` (never its host-side name)
 };
 constexpr int kMaxDevices = 64;
 std::mutex statics_mu;
@@ -207,9 +213,11 @@ const DeviceStatics *device_statics(int device) {
   std::lock_guard<std::mutex> lk(statics_mu);
   DeviceStatics &d = statics[device];
   if (!d.unit) {
-    void *u = nullptr;
+    void *u = nullptr, *w = nullptr;
     if (hipGetSymbolAddress(&u, HIP_SYMBOL(unit_const)) != hipSuccess || !u) return nullptr;
+    if (hipGetSymbolAddress(&w, HIP_SYMBOL(scratch)) != hipSuccess || !w) return nullptr;
     d.unit = u;
+    d.scratch = static_cast<char *>(w);
   }
   return &d;
 }
@@ -448,6 +456,23 @@ void describe_contraction(Launches &L, const Contraction &c, const std::vector<c
       t.top_out = static_cast<double *>(top_dev);
       t.sum_out = static_cast<double *>(sum_dev);
     }
+  }
+}
+
+// Enqueue the launches one by one on the context's stream, with no stage
+// timing (no events taken): the allocation-free recursion.
+void run_untimed(sqc_ctx *ctx, const Launches &L) {
+  if (!L.merges.empty()) {
+    launch_merges(L.merges.data(), (int)L.merges.size(), ctx->stream);
+    after_launch("merge kernel launch");
+  }
+  for (size_t si = 0; si < L.steps.size(); ++si) {
+    launch_gemm_spec(L.steps[si], L.specs[si], L.groups[si], ctx->stream);
+    after_launch("contraction kernel launch");
+  }
+  if (L.topr) {
+    launch_topr(L.t, ctx->stream);
+    after_launch("top-R kernel launch");
   }
 }
 
@@ -1464,6 +1489,38 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
   need_ws(ctx, rp.total);
   use_device(ctx);
   enqueue_recursion(ctx, rp, attributed, prec, bins_dev, bins_prec, top_r, topr_dev, sum_dev);
+  if (masks_out) std::copy(rp.masks.begin(), rp.masks.end(), masks_out);
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_recurse_noalloc(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,
+                               int32_t n_cuts, const sqc_masks *scope, uint64_t max_bins_M, int32_t top_r,
+                               sqc_prec prec, void *bins_dev, sqc_prec bins_prec, sqc_masks *masks_out,
+                               void *topr_dev, void *sum_dev) {
+  SQC_TRY(ctx)
+  Graph g = build_topology(n_sub, cuts, n_cuts);
+  if (!attributed || !bins_dev || !topr_dev || !sum_dev) raise(SQC_E_ARG, "NULL argument");
+  check_path_prec(prec);
+  check_storage_prec(bins_prec, "bins_prec");
+  if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
+  degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+  RecursePlan rp = plan_recursion(g, attributed, scope, max_bins_M, top_r, prec, ctx_plans(ctx));
+  if (rp.total > SQC_NOALLOC_SCRATCH_BYTES) {
+    std::ostringstream s;
+    s << "this recursion needs " << rp.total << " bytes of workspace; the allocation-free recursion has "
+      << SQC_NOALLOC_SCRATCH_BYTES << " (use sqc_recurse with a caller workspace)";
+    raise(SQC_E_NOMEM, s.str());
+  }
+  char *ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(statics_mu);
+    ws = ctx->device >= 0 && ctx->device < kMaxDevices ? statics[ctx->device].scratch : nullptr;
+  }
+  if (!ws) raise(SQC_E_DEVICE, "the device scratch of this context's device has no address");
+  use_device(ctx);
+  run_untimed(ctx, describe_recursion(rp, attributed, prec, ws, ctx->unit, bins_dev, bins_prec, top_r, topr_dev,
+                                      sum_dev));
   if (masks_out) std::copy(rp.masks.begin(), rp.masks.end(), masks_out);
   return SQC_OK;
   SQC_CATCH(ctx)

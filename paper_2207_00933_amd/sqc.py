@@ -26,6 +26,7 @@ F64, F32, BF16X3 = 0, 1, 2
 LAYOUT_ATTRIBUTED, LAYOUT_MERGED = 0, 1
 MAX_DEGREE = 15
 MAX_TOPR = 64
+NOALLOC_SCRATCH_BYTES = 64 << 20
 STATUS_NAMES = ["SQC_OK", "SQC_E_ARG", "SQC_E_SHAPE", "SQC_E_NOMEM", "SQC_E_DEVICE",
                 "SQC_E_NUMERIC", "SQC_E_BUSY", "SQC_E_UNSUPPORTED"]
 
@@ -161,6 +162,9 @@ def lib():
             "sqc_recurse": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
                                     POINTER(Masks), c_uint64, c_int32, c_int, P, c_int,
                                     POINTER(Masks), P, P]),
+            "sqc_recurse_noalloc": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
+                                            POINTER(Masks), c_uint64, c_int32, c_int, P, c_int,
+                                            POINTER(Masks), P, P]),
             "sqc_search": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32, c_uint64,
                                    c_int32, c_int, P, c_int, POINTER(Found), POINTER(c_uint64),
                                    c_int32, POINTER(c_int32), POINTER(RecursionInfo),
@@ -461,6 +465,16 @@ def recurse(ctx: int, att: Sequence[Tensor], g: Graph, scope, M: int, top_r: int
     out = (Masks * g.n_sub)()
     _check(lib().sqc_recurse(ctx, arr, g.n_sub, g.cuts, g.n_cuts, sc, M, top_r, prec, _ptr(bins),
                              bins_prec, out, _ptr(topr), _ptr(bsum)), ctx)
+    return list(out)
+
+
+def recurse_noalloc(ctx: int, att: Sequence[Tensor], g: Graph, scope, M: int, top_r: int, prec: int,
+                    bins, bins_prec: int, topr, bsum) -> List[Masks]:
+    arr = tensor_array(att)
+    sc = masks_array(scope) if scope is not None else None
+    out = (Masks * g.n_sub)()
+    _check(lib().sqc_recurse_noalloc(ctx, arr, g.n_sub, g.cuts, g.n_cuts, sc, M, top_r, prec, _ptr(bins),
+                                     bins_prec, out, _ptr(topr), _ptr(bsum)), ctx)
     return list(out)
 
 
