@@ -275,15 +275,54 @@ def measured_traffic():
 # the merging and large workloads: Algorithm 1 on the device
 # ---------------------------------------------------------------------------
 
+def replay_bytes(s, circ, M, R, prec, bprec, infos):
+    """Algorithmic bytes of a search's recursions (merge reads and writes,
+    contraction operands and results, as the stage timing counts them): the
+    same Algorithm 1 driven from the host, one sqc_recurse per recursion with
+    stage timing on; its records must equal the device search's."""
+    import math
+    import torch
+    from paper_2207_00933_amd import runner, sqc
+    stages = sqc.STAGE_MERGE | sqc.STAGE_CONTRACT | sqc.STAGE_FINAL | sqc.STAGE_TOPR
+    sqc.ctx_timing(s.ctx, 1, reset=True)
+    sqc.ctx_set_timing(s.ctx, stages)
+    L, scope, parent, recs = [], None, 1.0, []
+    for r in range(R):
+        if r > 0 and scope is None:
+            break
+        rec = runner.Recursion(circ, int(math.log2(M)), bprec, R)
+        masks = rec.run(prec, M, scope)
+        vals, idx = rec.top_list()
+        a = sum(bin(m.active).count("1") for m in masks)
+        leaf = all(m.merged == 0 for m in masks)
+        recs.append((rec.sum.item(), parent, float(vals[0]), a, leaf))
+        if not leaf:
+            for q in range(min(R, 1 << a)):
+                if vals[q] == vals[q] and vals[q] != -math.inf:
+                    L.append((float(vals[q]), r, int(idx[q]), masks))
+        L.sort(key=lambda e: (-e[0], e[1], e[2]))
+        L = L[:R]
+        if not L:
+            scope = None
+            continue
+        e = L.pop(0)
+        scope, parent = sqc.bin_scope(e[3], e[2]), e[0]
+    sqc.ctx_set_timing(s.ctx, 0)
+    nbytes = sum(sqc.ctx_timing(s.ctx, q).bytes for q in (sqc.STAGE_MERGE, sqc.STAGE_CONTRACT, sqc.STAGE_FINAL))
+    sqc.ctx_timing(s.ctx, 1, reset=True)
+    torch.cuda.synchronize()
+    return nbytes, recs == list(infos)
+
+
 def run_workloads(reps: int = 5):
-    """Algorithm 1 (sqc_search) on the merging workload (60-qubit QAOA ring,
-    4 subcircuits, 8 cuts, M = 2^20, R = 12) and the large one (200-qubit
-    chain, 16 subcircuits, 24 cuts, M = 2^24, two recursions), split-BF16x3
-    and plain FP64, attributed tensors resident.  Reports reconstructed bins/s
-    (sum of 2^a over the recursions run, per wall second, host waits of the
-    search included) and the HBM roofline fraction of the recursions'
-    algorithmic bytes (merge reads and writes, contraction operands and
-    results, as the stage timing counts them)."""
+    """Algorithm 1 (sqc_search, the whole loop on the device) on the merging
+    workload (60-qubit QAOA ring, 4 subcircuits, 8 cuts, M = 2^20, R = 12)
+    and the large one (200-qubit chain, 16 subcircuits, 24 cuts, M = 2^24,
+    R = 20), split-BF16x3 and plain FP64, attributed tensors resident.
+    Reports reconstructed bins/s (sum of 2^a over the recursions run, per
+    wall second of the whole call: host planning, the enqueue and the final
+    wait included) and the HBM roofline fraction of the recursions'
+    algorithmic bytes."""
     import torch
     from paper_2207_00933_amd import runner, sqc
 
@@ -292,7 +331,7 @@ def run_workloads(reps: int = 5):
     with torch.cuda.stream(st):
         s = runner.Session(0, 64 << 20)
         for name, cc, M, R in (("merging", configs.merging(), 1 << 20, 12),
-                               ("large", configs.large(), 1 << 24, 2)):
+                               ("large", configs.large(), 1 << 24, 20)):
             var = qpu.all_variants(cc)
             circ = runner.Circuit.from_cut_circuit(s, cc, var, sqc.F64)
             res = {"qubits": cc.n, "subcircuits": cc.n_sub, "cuts": len(cc.cuts), "M": M,
@@ -303,18 +342,9 @@ def run_workloads(reps: int = 5):
                 circ.attribute(att)
                 bins = torch.empty(M, dtype=torch.float64 if bprec == sqc.F64 else torch.float32,
                                    device=s.device)
-                masks = sqc.assign_bins(circ.g.n_data, None, M)
-                s.ensure_workspace(4 * sqc.recurse_workspace_bytes(circ.att, circ.g, masks, prec))
+                s.ensure_workspace(sqc.search_workspace_bytes(circ.att, circ.g, M, R, prec))
                 sols, infos = sqc.search(s.ctx, circ.att, circ.g, M, R, prec, bins, bprec)  # warm
-                stages = sqc.STAGE_MERGE | sqc.STAGE_CONTRACT | sqc.STAGE_FINAL | sqc.STAGE_TOPR
-                sqc.ctx_timing(s.ctx, 1, reset=True)
-                sqc.ctx_set_timing(s.ctx, stages)
-                sqc.search(s.ctx, circ.att, circ.g, M, R, prec, bins, bprec)
-                sqc.ctx_set_timing(s.ctx, 0)
-                nbytes = sum(sqc.ctx_timing(s.ctx, q).bytes for q in (sqc.STAGE_MERGE, sqc.STAGE_CONTRACT,
-                                                                     sqc.STAGE_FINAL))
-                sqc.ctx_timing(s.ctx, 1, reset=True)
-                torch.cuda.synchronize()
+                nbytes, same = replay_bytes(s, circ, M, R, prec, bprec, infos)
                 t0 = time.perf_counter()
                 for _ in range(reps):
                     sols, infos = sqc.search(s.ctx, circ.att, circ.g, M, R, prec, bins, bprec)
@@ -324,7 +354,8 @@ def run_workloads(reps: int = 5):
                 res[pname] = {"recursions": len(infos), "bins": nb, "ms_per_search": wall * 1e3,
                               "bins_per_s": nb / wall, "algorithmic_bytes": nbytes,
                               "hbm_roofline_frac": nbytes / HBM_PEAK / wall,
-                              "solutions": len(sols), "top_prob": sols[0][0] if sols else None}
+                              "solutions": len(sols), "top_prob": sols[0][0] if sols else None,
+                              "host_loop_records_equal": same}
                 log(f"[workload] {name} {pname}: {len(infos)} recursions, {wall * 1e3:.3f} ms, "
                     f"{nb / wall:.3e} bins/s, HBM fraction {nbytes / HBM_PEAK / wall:.3f}")
             res["speedup_bf16x3_vs_f64"] = res["bf16x3"]["bins_per_s"] / res["f64"]["bins_per_s"]

@@ -492,12 +492,25 @@ typedef struct {
  * (probability descending, then earlier recursion, then lower bin index) and
  * truncated to R, and the first entry is popped for the next recursion.  Bins
  * of single states are reported as solutions (the R largest of each leaf
- * recursion).  Waits for the device after every recursion.
- * `solutions` / `solution_states` receive up to max_solutions entries; for
- * solution k, solution_states[k * n_sub + i] is subcircuit i's data state.
- * `info` (optional) receives one record per recursion run (capacity
- * max_recursions).  `bins_dev` must hold 2^a elements of bins_prec for the
- * largest a the search uses (at most floor(log2 M)). */
+ * recursion).  The whole loop runs on the device: a recursion's shape
+ * depends only on its depth below the first one (Algorithm 2 sees only how
+ * many states the popped bin holds), so every depth is planned once, all R
+ * recursions are enqueued back to back, and after each a one-work-group
+ * kernel updates L, pops the next bin and sets up its recursion's job tables;
+ * once L is empty the remaining launches do nothing.  The call waits for the
+ * device once, at the end.  Workspace: sqc_search_workspace_bytes (the
+ * largest recursion's workspace, then the search's tables and results).
+ * `solutions` / `solution_states` receive up to max_solutions entries (at
+ * most R * R); for solution k, solution_states[k * n_sub + i] is subcircuit
+ * i's data state.  `info` (optional) receives one record per recursion run
+ * (capacity max_recursions).  `bins_dev` must hold 2^a elements of bins_prec
+ * for the largest a the search uses (at most floor(log2 M)); it holds the
+ * last recursion's bins.  Errors: SQC_E_NOMEM when the workspace is too
+ * small, SQC_E_UNSUPPORTED above 64 subcircuits, else as sqc_recurse. */
+size_t sqc_search_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub,
+                                  const sqc_cut *cuts, int32_t n_cuts, uint64_t max_bins_M,
+                                  int32_t max_recursions, sqc_prec prec,
+                                  int32_t max_solutions);
 sqc_status sqc_search(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
                       const sqc_cut *cuts, int32_t n_cuts, uint64_t max_bins_M,
                       int32_t max_recursions, sqc_prec prec, void *bins_dev,

@@ -998,6 +998,491 @@ QueryPlan plan_query(const sqc_tensor *att, int32_t n_sub, const sqc_cut *cuts, 
 
 }  // namespace
 
+// ---- Algorithm 1 on the device: the search loop without host waits ----
+//
+// A recursion's shape (the fixed, active and merged bit positions of every
+// subcircuit, hence its contraction plan and launches) depends only on its
+// depth below the first recursion: Algorithm 2 sees how many states the
+// popped bin holds, which its depth fixes; only the fixed values (which bin)
+// come from the data.  The host plans every depth once and writes, per
+// depth, an image of the job tables that a recursion's grouped launches read
+// ("live" tables at fixed addresses, one layout for every depth, grids sized
+// for the largest).  All recursions are then enqueued back to back; after
+// each, search_step (one work-group) does what the host loop does (records
+// the recursion, appends its R largest bins to L or to the solutions, sorts
+// and truncates L, pops the best bin), then copies the popped bin's depth
+// image into the live tables and writes the bin's fixed values into their
+// merge jobs.  When L is empty the remaining launches find depth -1 and do
+// nothing.
+
+namespace {
+
+struct SearchState {
+  int depth;  // depth of the recursion about to run (-1: finished)
+  int nL, nsol, nrec, bank;
+  double parent;
+};
+
+struct SearchPatch {  // one field of the live tables written per recursion
+  uint32_t off;       // byte offset in the live tables
+  int32_t kind;       // 0: fixed_val of subcircuit `sub`, 1: top-R output, 2: sum output
+  int32_t sub;
+};
+
+struct SearchDepth {
+  int leaf;   // every bin a single state
+  int a;      // active bits in total
+  int patch0, npatch;
+};
+
+struct SearchArgs {
+  SearchState *st;
+  uint64_t *F;             // [n_sub] fixed values of the recursion about to run
+  double *Lp;              // [2][2R] probability
+  int *Lr, *Ld;            // [2][2R] recursion, depth
+  uint64_t *Lb;            // [2][2R] bin
+  uint64_t *LF;            // [2][2R][n_sub] fixed values of the bin's children
+  const SearchDepth *dep;  // [D]
+  const int *abits;        // [D][n_sub]
+  const uint64_t *active;  // [D][n_sub]
+  const SearchPatch *patch;
+  const unsigned char *images;  // [D][live_bytes]
+  unsigned char *live;
+  int64_t live_bytes;
+  double *res_top;         // [R + 1][2R] value, index bits
+  double *res_sum;         // [R + 1]
+  sqc_recursion_info *info;  // [R]
+  sqc_found *sols;           // [max_sol]
+  uint64_t *sol_states;      // [max_sol][n_sub]
+  int n_sub, R, max_sol, D;
+};
+
+__device__ uint64_t deposit_dev(uint64_t v, uint64_t mask) {
+  uint64_t out = 0;
+  for (uint64_t m = mask; m; m &= m - 1) {
+    if (v & 1) out |= m & (~m + 1);
+    v >>= 1;
+  }
+  return out;
+}
+
+constexpr int kStepThreads = 256;
+constexpr int kStepMaxSub = 64;  // subcircuits the step stages in LDS
+constexpr int kStepMaxDepth = 32;  // depth records prefetched with everything else
+
+// After recursion r (the slot's index): update L and the solutions, pop the
+// next bin and set up its recursion's tables (unless r is the last slot).
+// The inputs are staged in LDS by all threads at once (a single thread's
+// chain of dependent loads would cost microseconds each); L is ordered by
+// ranking each entry against all others (the order is strict: every entry
+// has its own (recursion, bin)).
+__global__ __launch_bounds__(kStepThreads) void search_step(SearchArgs a, int r, int last) {
+  constexpr int L2max = 2 * SQC_MAX_TOPR;
+  __shared__ double kp[L2max];
+  __shared__ int kr[L2max], kd[L2max], src[L2max];
+  __shared__ uint64_t kb[L2max];
+  __shared__ double tv[SQC_MAX_TOPR];
+  __shared__ uint64_t ti[SQC_MAX_TOPR];
+  __shared__ int tslot[SQC_MAX_TOPR];  // where entry q goes (L or solutions), -1: skipped
+  __shared__ uint64_t F[kStepMaxSub], act[kStepMaxSub];
+  __shared__ int ab[kStepMaxSub], ab0[kStepMaxSub];
+  __shared__ SearchState st;
+  __shared__ SearchDepth D;
+  __shared__ int n_app, n_sol_new, pop, nkeep;
+  __shared__ double kp2[L2max];  // the other bank's keys (read before the bank is known)
+  __shared__ int kr2[L2max], kd2[L2max];
+  __shared__ uint64_t kb2[L2max];
+  __shared__ SearchDepth deps[kStepMaxDepth];
+  __shared__ uint64_t actd[kStepMaxDepth * 8];
+  __shared__ int abd[kStepMaxDepth * 8];
+  __shared__ double rsum;
+  const int tid = threadIdx.x;
+  const int R = a.R, ns = a.n_sub, L2 = 2 * R;
+  // one round of loads: everything the step may read, for both banks of L
+  // and every depth when they are small (most searches), before the state
+  // says which
+  if (tid == 0) {
+    st = *a.st;
+    rsum = a.res_sum[r];
+  }
+  const double *top = a.res_top + (int64_t)r * 2 * R;
+  if (tid < R) {
+    tv[tid] = top[2 * tid];
+    ti[tid] = reinterpret_cast<const uint64_t *>(top)[2 * tid + 1];
+  }
+  if (tid < ns) F[tid] = a.F[tid];
+  const bool small = a.D <= kStepMaxDepth && ns <= 8;
+  if (small) {
+    if (tid < a.D) deps[tid] = a.dep[tid];
+    if (tid < a.D * ns) {
+      actd[tid] = a.active[tid];
+      abd[tid] = a.abits[tid];
+    }
+  }
+  for (int e = tid; e < 2 * L2; e += kStepThreads) {
+    const bool first = e < L2;
+    const int k = first ? e : e - L2;
+    (first ? kp : kp2)[k] = a.Lp[e];
+    (first ? kr : kr2)[k] = a.Lr[e];
+    (first ? kd : kd2)[k] = a.Ld[e];
+    (first ? kb : kb2)[k] = a.Lb[e];
+  }
+  __syncthreads();
+  if (st.depth < 0) return;  // finished: nothing to record (every thread returns)
+  const int d = st.depth, b = st.bank, nb = 1 - b;
+  if (tid == 0) D = small ? deps[d] : a.dep[d];
+  if (tid < ns) {
+    act[tid] = small ? actd[d * ns + tid] : a.active[d * ns + tid];
+    ab[tid] = small ? abd[d * ns + tid] : a.abits[d * ns + tid];
+  }
+  if (b == 1)
+    for (int e = tid; e < st.nL; e += kStepThreads) {
+      kp[e] = kp2[e];
+      kr[e] = kr2[e];
+      kd[e] = kd2[e];
+      kb[e] = kb2[e];
+    }
+  for (int e = tid; e < st.nL; e += kStepThreads) src[e] = e;  // entry e of bank b
+  __syncthreads();
+  // the recursion's record; where each of its R largest bins goes
+  if (tid == 0) {
+    sqc_recursion_info inf;
+    inf.bins_sum = rsum;
+    inf.parent_prob = st.parent;
+    inf.top_prob = tv[0];
+    inf.active_bits = D.a;
+    inf.leaf = D.leaf;
+    a.info[r] = inf;
+    int o = 0;
+    for (int i = 0; i < ns; ++i) {
+      ab0[i] = o;
+      o += ab[i];
+    }
+    const uint64_t nbins = D.a >= 63 ? ~0ull : (1ull << D.a);
+    const int take = (uint64_t)R < nbins ? R : (int)nbins;
+    int napp = 0, nsol = 0;
+    for (int q = 0; q < R; ++q) {
+      const double v = tv[q];
+      int slot = -1;
+      if (q < take && v == v && v != -INFINITY) {
+        if (!D.leaf) slot = st.nL + napp++;
+        else if (st.nsol + nsol < a.max_sol) slot = st.nsol + nsol++;
+      }
+      tslot[q] = slot;
+    }
+    n_app = napp;
+    n_sol_new = nsol;
+  }
+  __syncthreads();
+  // children's fixed values (and the appended keys), one (bin, subcircuit) per thread
+  for (int e = tid; e < R * ns; e += kStepThreads) {
+    const int q = e / ns, i = e % ns;
+    const int slot = tslot[q];
+    if (slot < 0) continue;
+    const uint64_t bin = ti[q];
+    const int sh = ab0[i], ai = ab[i];
+    const uint64_t beta = sh >= 64 ? 0 : (bin >> sh) & (ai >= 64 ? ~0ull : ((1ull << ai) - 1));
+    const uint64_t fc = F[i] | deposit_dev(beta, act[i]);
+    if (!D.leaf) a.LF[((int64_t)b * L2 + slot) * ns + i] = fc;
+    else a.sol_states[(int64_t)slot * ns + i] = fc;
+    if (i == 0) {
+      if (!D.leaf) {
+        kp[slot] = tv[q];
+        kr[slot] = r;
+        kd[slot] = d;
+        kb[slot] = bin;
+        src[slot] = slot;
+      } else {
+        sqc_found f;
+        f.prob = tv[q];
+        f.recursion = r;
+        f.pad = 0;
+        f.bin = bin;
+        a.sols[slot] = f;
+      }
+    }
+  }
+  __syncthreads();
+  // rank every entry of L (probability descending, then earlier recursion,
+  // then lower bin index); keep the R best
+  const int nL = st.nL + n_app;
+  __shared__ int at_rank[L2max];
+  for (int e = tid; e < nL; e += kStepThreads) {
+    int rank = 0;
+    for (int f = 0; f < nL; ++f)
+      rank += (kp[f] > kp[e] || (kp[f] == kp[e] && (kr[f] < kr[e] || (kr[f] == kr[e] && kb[f] < kb[e])))) ? 1 : 0;
+    at_rank[rank] = e;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int kept = nL < R ? nL : R;
+    pop = 0;
+    if (kept == 0) {
+      st.depth = -1;
+    } else if (!last) {
+      pop = 1;
+      const int e = at_rank[0];
+      st.depth = kd[e] + 1;
+      st.parent = kp[e];
+      if (st.depth >= a.D) st.depth = -1;  // (cannot happen: a leaf depth ends every branch)
+    }
+    nkeep = kept - pop;
+    st.nL = nkeep;
+    st.nsol += n_sol_new;
+    st.nrec = r + 1;
+    st.bank = nb;
+  }
+  __syncthreads();
+  // the kept entries, sorted, into the other bank; the popped bin's
+  // children's fixed values become the next recursion's
+  for (int j = tid; j < nkeep; j += kStepThreads) {
+    const int e = at_rank[j + pop];
+    a.Lp[nb * L2 + j] = kp[e];
+    a.Lr[nb * L2 + j] = kr[e];
+    a.Ld[nb * L2 + j] = kd[e];
+    a.Lb[nb * L2 + j] = kb[e];
+  }
+  for (int x = tid; x < nkeep * ns; x += kStepThreads) {
+    const int j = x / ns, i = x % ns;
+    a.LF[((int64_t)nb * L2 + j) * ns + i] = a.LF[((int64_t)b * L2 + src[at_rank[j + pop]]) * ns + i];
+  }
+  if (pop)
+    for (int i = tid; i < ns; i += kStepThreads) {
+      const uint64_t fn = a.LF[((int64_t)b * L2 + src[at_rank[0]]) * ns + i];
+      a.F[i] = fn;
+      act[i] = fn;  // (LDS copy for the patches below: act is not needed any more)
+    }
+  if (tid == 0) *a.st = st;
+  if (!pop || st.depth < 0) return;
+  __syncthreads();
+  // the next recursion's tables: its depth's image, then its fixed values
+  // and output slots
+  const int dn = st.depth;
+  const uint4 *srcimg = reinterpret_cast<const uint4 *>(a.images + (int64_t)dn * a.live_bytes);
+  uint4 *dst = reinterpret_cast<uint4 *>(a.live);
+  for (int64_t q = tid; q < a.live_bytes / 16; q += kStepThreads) dst[q] = srcimg[q];
+  __syncthreads();
+  const SearchDepth Dn = a.dep[dn];
+  for (int q = tid; q < Dn.npatch; q += kStepThreads) {
+    const SearchPatch pt = a.patch[Dn.patch0 + q];
+    unsigned char *f = a.live + pt.off;
+    if (pt.kind == 0) *reinterpret_cast<uint64_t *>(f) = act[pt.sub];
+    else if (pt.kind == 1) *reinterpret_cast<double **>(f) = a.res_top + (int64_t)(r + 1) * 2 * R;
+    else *reinterpret_cast<double **>(f) = a.res_sum + (r + 1);
+  }
+}
+
+// One grouped launch of the live tables: merge pass 0 / 1 / 2, a GEMM, or
+// the top-R stages; its jobs and work-group prefixes per depth.
+struct LiveGroup {
+  int kind;   // 0 merge tiles, 1 merge rows (passes 1 and 2), 2 GEMM, 3 top-R
+  int level;  // GEMM level (step index)
+  GemmSpec spec;
+  int spec_id = -1;
+  int cap = 0;           // jobs slots
+  size_t jobs = 0, start[2] = {0, 0};
+  int grid0[2] = {0, 0}, grid1[2] = {0, 0};  // grids: first recursion, later ones
+};
+
+struct SearchPlan {
+  std::vector<RecursePlan> rp;  // per depth
+  std::vector<Launches> L;
+  std::vector<LiveGroup> groups;
+  size_t live_bytes = 0;
+  size_t rec_ws = 0;  // recursion workspace (the largest depth's)
+  // search region, offsets from its base
+  size_t o_live, o_images, o_patch, o_dep, o_abits, o_active, o_state, o_F, o_L, o_res, o_info, o_sols, o_states,
+      region;
+  int D = 0, max_sol = 0;
+  std::vector<unsigned char> upload;  // live .. F
+  char *base = nullptr;               // the search region on the device
+};
+
+// jobs of a depth's launches split by live group
+struct DepthJobs {
+  std::vector<std::pair<MergeArgs, int>> tiles, rows;  // (shaped job, subcircuit)
+};
+
+DepthJobs split_merges(const Launches &L) {
+  DepthJobs j;
+  for (size_t i = 0; i < L.merges.size(); ++i) {
+    MergeArgs a = L.merges[i];
+    merge_shape(a);
+    (merge_pass_blocks(a, 0) ? j.tiles : j.rows).push_back({a, (int)i});
+  }
+  return j;
+}
+
+SearchPlan plan_search(sqc_ctx *ctx, const Graph &g, const sqc_tensor *att, uint64_t M, int R, sqc_prec prec,
+                       void *bins_dev, sqc_prec bins_prec, int max_solutions) {
+  SearchPlan sp;
+  const int n_sub = g.n_sub;
+  // every depth: depth d + 1 is the scope of a bin of depth d (bin 0: the
+  // fixed values are written on the device)
+  std::vector<sqc_masks> scope;
+  for (int d = 0; d < R; ++d) {
+    sp.rp.push_back(plan_recursion(g, att, d ? scope.data() : nullptr, M, R, prec, ctx_plans(ctx)));
+    bool leaf = true;
+    for (int i = 0; i < n_sub; ++i)
+      if (sp.rp.back().masks[i].merged) leaf = false;
+    if (leaf) break;
+    scope.assign(n_sub, sqc_masks{});
+    if (sqc_bin_scope(n_sub, sp.rp.back().masks.data(), 0, scope.data()) != SQC_OK) raise(SQC_E_ARG, thread_error());
+  }
+  sp.D = (int)sp.rp.size();
+  for (const RecursePlan &rp : sp.rp) sp.rec_ws = std::max(sp.rec_ws, rp.total);
+  // placeholders for the output slots (patched per recursion)
+  for (const RecursePlan &rp : sp.rp)
+    sp.L.push_back(describe_recursion(rp, att, prec, ctx->ws, ctx->unit, bins_dev, bins_prec, R, ctx->ws, ctx->ws));
+
+  // live groups: merges, GEMM (level, specialisation), top-R
+  std::vector<DepthJobs> dj;
+  for (const Launches &L : sp.L) dj.push_back(split_merges(L));
+  LiveGroup mt{0, -1, GemmSpec{}}, mr{1, -1, GemmSpec{}};
+  for (auto &j : dj) {
+    mt.cap = std::max<int>(mt.cap, (int)j.tiles.size());
+    mr.cap = std::max<int>(mr.cap, (int)j.rows.size());
+  }
+  if (mt.cap) sp.groups.push_back(mt);
+  if (mr.cap) sp.groups.push_back(mr);
+  std::map<std::pair<int, int>, GemmSpec> gkeys;
+  for (const Launches &L : sp.L)
+    for (size_t s = 0; s < L.steps.size(); ++s) gkeys[{(int)s, gemm_spec_id(L.specs[s])}] = L.specs[s];
+  for (auto &kv : gkeys) {
+    LiveGroup gg{2, kv.first.first, kv.second};
+    gg.spec_id = kv.first.second;
+    gg.cap = 1;
+    sp.groups.push_back(gg);
+  }
+  LiveGroup tg{3, -1, GemmSpec{}};
+  tg.cap = 1;
+  sp.groups.push_back(tg);
+  // layout of the live tables
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  for (LiveGroup &lg : sp.groups) {
+    const size_t jb = lg.kind <= 1 ? sizeof(MergeArgs) : lg.kind == 2 ? sizeof(GemmArgs) : sizeof(TopRArgs);
+    lg.jobs = take(jb * lg.cap);
+    lg.start[0] = take(sizeof(int) * (lg.cap + 1));
+    if (lg.kind == 1) lg.start[1] = take(sizeof(int) * (lg.cap + 1));
+  }
+  sp.live_bytes = align256(off);
+
+  // search region
+  sp.max_sol = std::max(0, std::min(max_solutions, R * R));
+  off = 0;
+  sp.o_live = take(sp.live_bytes);
+  sp.o_images = take(sp.live_bytes * sp.D);
+  std::vector<SearchPatch> patches;
+  std::vector<SearchDepth> deps(sp.D);
+  std::vector<std::vector<unsigned char>> images(sp.D, std::vector<unsigned char>(sp.live_bytes, 0));
+  for (int d = 0; d < sp.D; ++d) {
+    const Launches &L = sp.L[d];
+    unsigned char *img = images[d].data();
+    deps[d].patch0 = (int)patches.size();
+    int a = 0;
+    bool leaf = true;
+    for (int i = 0; i < n_sub; ++i) {
+      a += sp.rp[d].abits[i];
+      if (sp.rp[d].masks[i].merged) leaf = false;
+    }
+    deps[d].a = a;
+    deps[d].leaf = leaf ? 1 : 0;
+    for (LiveGroup &lg : sp.groups) {
+      int *st0 = reinterpret_cast<int *>(img + lg.start[0]);
+      int *st1 = lg.kind == 1 ? reinterpret_cast<int *>(img + lg.start[1]) : nullptr;
+      int total0 = 0, total1 = 0;
+      if (lg.kind <= 1) {
+        const auto &jobs = lg.kind == 0 ? dj[d].tiles : dj[d].rows;
+        for (size_t k = 0; k < jobs.size(); ++k) {
+          std::memcpy(img + lg.jobs + k * sizeof(MergeArgs), &jobs[k].first, sizeof(MergeArgs));
+          patches.push_back(SearchPatch{(uint32_t)(lg.jobs + k * sizeof(MergeArgs) + offsetof(MergeArgs, fixed_val)),
+                                        0, jobs[k].second});
+          st0[k] = total0;
+          total0 += (int)merge_pass_blocks(jobs[k].first, lg.kind == 0 ? 0 : 1);
+          if (st1) {
+            st1[k] = total1;
+            total1 += (int)merge_pass_blocks(jobs[k].first, 2);
+          }
+        }
+        for (int k = (int)jobs.size(); k <= lg.cap; ++k) {
+          st0[k] = total0;
+          if (st1) st1[k] = total1;
+        }
+      } else if (lg.kind == 2) {
+        const bool has = lg.level < (int)L.steps.size() && gemm_spec_id(L.specs[lg.level]) == lg.spec_id;
+        if (has) {
+          std::memcpy(img + lg.jobs, &L.steps[lg.level], sizeof(GemmArgs));
+          total0 = L.groups[lg.level];
+        }
+        st0[0] = 0;
+        st0[1] = total0;
+      } else {
+        TopRArgs t = L.t;
+        std::memcpy(img + lg.jobs, &t, sizeof(TopRArgs));
+        patches.push_back(SearchPatch{(uint32_t)(lg.jobs + offsetof(TopRArgs, top_out)), 1, 0});
+        patches.push_back(SearchPatch{(uint32_t)(lg.jobs + offsetof(TopRArgs, sum_out)), 2, 0});
+        total0 = t.gather_groups;
+        st0[0] = 0;
+        st0[1] = total0;
+      }
+      int *g0 = d == 0 ? lg.grid0 : lg.grid1;
+      g0[0] = std::max(g0[0], total0);
+      g0[1] = std::max(g0[1], total1);
+    }
+    deps[d].npatch = (int)patches.size() - deps[d].patch0;
+  }
+  sp.o_patch = take(sizeof(SearchPatch) * std::max<size_t>(1, patches.size()));
+  sp.o_dep = take(sizeof(SearchDepth) * sp.D);
+  sp.o_abits = take(sizeof(int) * sp.D * n_sub);
+  sp.o_active = take(sizeof(uint64_t) * sp.D * n_sub);
+  sp.o_state = take(sizeof(SearchState));
+  sp.o_F = take(sizeof(uint64_t) * n_sub);
+  const size_t upload_end = off;
+  sp.o_L = take((8 + 4 + 4 + 8) * 2 * 2 * (size_t)R + 8 * 2 * 2 * (size_t)R * n_sub + 4 * 256);
+  sp.o_res = take(8 * (size_t)(R + 1) * (2 * R + 1));
+  sp.o_info = take(sizeof(sqc_recursion_info) * R);
+  sp.o_sols = take(sizeof(sqc_found) * std::max(1, sp.max_sol));
+  sp.o_states = take(sizeof(uint64_t) * std::max(1, sp.max_sol) * n_sub);
+  sp.region = off;
+
+  // the upload image: live tables (depth 0, first recursion's slots), the
+  // depth images, patches, depth records, masks, state, fixed values
+  sp.upload.assign(upload_end, 0);
+  unsigned char *U = sp.upload.data();
+  std::memcpy(U + sp.o_live, images[0].data(), sp.live_bytes);
+  for (int d = 0; d < sp.D; ++d) std::memcpy(U + sp.o_images + d * sp.live_bytes, images[d].data(), sp.live_bytes);
+  if (!patches.empty()) std::memcpy(U + sp.o_patch, patches.data(), sizeof(SearchPatch) * patches.size());
+  std::memcpy(U + sp.o_dep, deps.data(), sizeof(SearchDepth) * sp.D);
+  for (int d = 0; d < sp.D; ++d)
+    for (int i = 0; i < n_sub; ++i) {
+      reinterpret_cast<int *>(U + sp.o_abits)[d * n_sub + i] = sp.rp[d].abits[i];
+      reinterpret_cast<uint64_t *>(U + sp.o_active)[d * n_sub + i] = sp.rp[d].masks[i].active;
+    }
+  SearchState st0{};
+  st0.depth = 0;
+  st0.parent = 1.0;
+  std::memcpy(U + sp.o_state, &st0, sizeof(st0));
+  // the search region follows the recursions' workspace; the first
+  // recursion's output slots are set here (later ones by search_step)
+  sp.base = ctx->ws + align256(sp.rec_ws);
+  double *res_top = reinterpret_cast<double *>(sp.base + sp.o_res);
+  double *res_sum = res_top + (size_t)(R + 1) * 2 * R;
+  for (int q = 0; q < deps[0].npatch; ++q) {
+    const SearchPatch &pt = patches[deps[0].patch0 + q];
+    unsigned char *f = U + sp.o_live + pt.off;
+    if (pt.kind == 1) std::memcpy(f, &res_top, sizeof(res_top));
+    else if (pt.kind == 2) std::memcpy(f, &res_sum, sizeof(res_sum));
+  }
+  return sp;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *sqc_version(void) { return "sqc 0.1.0 (gfx950)"; }
@@ -1613,6 +2098,29 @@ sqc_status sqc_autotune_reset(void) {
 
 int32_t sqc_autotune_entries(void) { return (int32_t)gemm_tune_size(); }
 
+size_t sqc_search_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,
+                                  int32_t n_cuts, uint64_t max_bins_M, int32_t max_recursions, sqc_prec prec,
+                                  int32_t max_solutions) {
+  try {
+    Graph g = build_topology(n_sub, cuts, n_cuts);
+    if (!attributed) return 0;
+    if (max_recursions < 1 || max_recursions > SQC_MAX_TOPR) raise(SQC_E_ARG, "max_recursions must be in [1, 64]");
+    check_path_prec(prec);
+    degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+    sqc_ctx probe;  // sizes only: no device memory is touched
+    char *fake = reinterpret_cast<char *>(uintptr_t(1) << 40);
+    probe.ws = fake;
+    probe.unit = reinterpret_cast<double *>(fake);
+    SearchPlan sp = plan_search(&probe, g, attributed, max_bins_M, max_recursions, prec, fake, SQC_F64,
+                                max_solutions);
+    delete static_cast<PlanCache *>(probe.plan_cache);
+    return align256(sp.rec_ws) + sp.region;
+  } catch (const Error &e) {
+    set_thread_error(e.msg);
+    return 0;
+  }
+}
+
 sqc_status sqc_search(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,
                       int32_t n_cuts, uint64_t max_bins_M, int32_t max_recursions, sqc_prec prec,
                       void *bins_dev, sqc_prec bins_prec, sqc_found *solutions,
@@ -1628,92 +2136,82 @@ sqc_status sqc_search(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
   const int R = max_recursions;
   if (R < 1 || R > SQC_MAX_TOPR) raise(SQC_E_ARG, "max_recursions must be in [1, 64]");
   degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+  if (!ctx->ws) raise(SQC_E_NOMEM, "no workspace: call sqc_ctx_set_workspace first");
+  if (n_sub > kStepMaxSub) raise(SQC_E_UNSUPPORTED, "the search supports up to 64 subcircuits");
   use_device(ctx);
-
-  struct Entry {
-    double prob;
-    int r;
-    uint64_t bin;
-    std::vector<sqc_masks> masks;
-  };
-  std::vector<Entry> L;
-  std::vector<sqc_masks> scope;
-  bool have_scope = false;
-  double parent_prob = 1.0;
-  int nsol = 0, r = 0;
-  void *top_dev = ctx->ws ? ctx->ws + kOffSearchTop : nullptr;
-  void *sum_dev = ctx->ws ? ctx->ws + kOffSearchSum : nullptr;
-  while (r < R) {
-    if (r > 0 && !have_scope) break;
-    RecursePlan rp = plan_recursion(g, attributed, have_scope ? scope.data() : nullptr, max_bins_M,
-                                    R, prec, ctx_plans(ctx));
-    need_ws(ctx, rp.total);
-    enqueue_recursion(ctx, rp, attributed, prec, bins_dev, bins_prec, R, top_dev, sum_dev);
-    const size_t nbytes = kOffSearchSum + 8 - kOffSearchTop;
-    check_hip(hipMemcpyAsync(ctx->pinned, top_dev, nbytes, hipMemcpyDeviceToHost, ctx->stream),
-              "hipMemcpyAsync");
-    check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    const double *top = static_cast<const double *>(ctx->pinned);
-    const double bsum = top[(kOffSearchSum - kOffSearchTop) / 8];
-    int a = 0;
-    bool leaf = true;
-    for (int i = 0; i < n_sub; ++i) {
-      a += rp.abits[i];
-      if (rp.masks[i].merged) leaf = false;
-    }
-    const uint64_t nbins = a >= 63 ? ~0ull : (uint64_t(1) << a);
-    const int take = (uint64_t)R < nbins ? R : (int)nbins;
-    if (info) {
-      info[r].bins_sum = bsum;
-      info[r].parent_prob = parent_prob;
-      info[r].top_prob = top[0];
-      info[r].active_bits = a;
-      info[r].leaf = leaf ? 1 : 0;
-    }
-    for (int q = 0; q < take; ++q) {
-      double v = top[2 * q];
-      uint64_t bin;
-      std::memcpy(&bin, &top[2 * q + 1], 8);
-      if (!(v == v) || v == -INFINITY) continue;
-      if (!leaf) {
-        L.push_back(Entry{v, r, bin, rp.masks});
-      } else if (nsol < max_solutions) {
-        solutions[nsol].prob = v;
-        solutions[nsol].recursion = r;
-        solutions[nsol].pad = 0;
-        solutions[nsol].bin = bin;
-        uint64_t rem = bin;
-        for (int i = 0; i < n_sub; ++i) {
-          int ai = rp.abits[i];
-          uint64_t beta = ai >= 64 ? rem : (rem & ((uint64_t(1) << ai) - 1));
-          rem = ai >= 64 ? 0 : (rem >> ai);
-          solution_states[(size_t)nsol * n_sub + i] =
-              rp.masks[i].fixed_val | deposit_bits(beta, rp.masks[i].active);
-        }
-        ++nsol;
+  SearchPlan sp = plan_search(ctx, g, attributed, max_bins_M, R, prec, bins_dev, bins_prec, max_solutions);
+  need_ws(ctx, align256(sp.rec_ws) + sp.region);
+  char *B = sp.base;
+  check_hip(hipMemcpyAsync(B, sp.upload.data(), sp.upload.size(), hipMemcpyHostToDevice, ctx->stream),
+            "hipMemcpyAsync of the search tables");
+  SearchArgs a{};
+  a.st = reinterpret_cast<SearchState *>(B + sp.o_state);
+  a.F = reinterpret_cast<uint64_t *>(B + sp.o_F);
+  char *Lb = B + sp.o_L;
+  const size_t L2 = 2 * (size_t)R;
+  a.Lp = reinterpret_cast<double *>(Lb);
+  a.Lb = reinterpret_cast<uint64_t *>(Lb + 8 * 2 * L2);
+  a.LF = reinterpret_cast<uint64_t *>(Lb + 16 * 2 * L2);
+  a.Lr = reinterpret_cast<int *>(Lb + (16 + 8 * (size_t)n_sub) * 2 * L2);
+  a.Ld = a.Lr + 2 * L2;
+  a.dep = reinterpret_cast<const SearchDepth *>(B + sp.o_dep);
+  a.abits = reinterpret_cast<const int *>(B + sp.o_abits);
+  a.active = reinterpret_cast<const uint64_t *>(B + sp.o_active);
+  a.patch = reinterpret_cast<const SearchPatch *>(B + sp.o_patch);
+  a.images = reinterpret_cast<const unsigned char *>(B + sp.o_images);
+  a.live = reinterpret_cast<unsigned char *>(B + sp.o_live);
+  a.live_bytes = (int64_t)sp.live_bytes;
+  a.res_top = reinterpret_cast<double *>(B + sp.o_res);
+  a.res_sum = a.res_top + (size_t)(R + 1) * 2 * R;
+  a.info = reinterpret_cast<sqc_recursion_info *>(B + sp.o_info);
+  a.sols = reinterpret_cast<sqc_found *>(B + sp.o_sols);
+  a.sol_states = reinterpret_cast<uint64_t *>(B + sp.o_states);
+  a.n_sub = n_sub;
+  a.R = R;
+  a.max_sol = sp.max_sol;
+  a.D = sp.D;
+  // every recursion back to back: the grouped launches read the live tables
+  for (int r = 0; r < R; ++r) {
+    for (const LiveGroup &lg : sp.groups) {
+      const int *grid = r == 0 ? lg.grid0 : lg.grid1;
+      const char *J = B + sp.o_live + lg.jobs;
+      const int *S0 = reinterpret_cast<const int *>(B + sp.o_live + lg.start[0]);
+      const int *S1 = reinterpret_cast<const int *>(B + sp.o_live + lg.start[1]);
+      if (lg.kind <= 1) {
+        if (grid[0] > 0)
+          launch_merge_grouped(lg.kind == 0 ? 0 : 1, reinterpret_cast<const MergeArgs *>(J), S0, lg.cap, grid[0],
+                               ctx->stream);
+        if (lg.kind == 1 && grid[1] > 0)
+          launch_merge_grouped(2, reinterpret_cast<const MergeArgs *>(J), S1, lg.cap, grid[1], ctx->stream);
+      } else if (lg.kind == 2) {
+        if (grid[0] > 0)
+          launch_gemm_grouped(lg.spec, reinterpret_cast<const GemmArgs *>(J), S0, lg.cap, grid[0], ctx->stream);
+      } else if (grid[0] > 0) {
+        launch_topr_grouped(reinterpret_cast<const TopRArgs *>(J), S0, lg.cap, grid[0], bins_prec == SQC_F32,
+                            ctx->stream);
       }
     }
-    std::stable_sort(L.begin(), L.end(), [](const Entry &x, const Entry &y) {
-      if (x.prob != y.prob) return x.prob > y.prob;
-      if (x.r != y.r) return x.r < y.r;
-      return x.bin < y.bin;
-    });
-    if ((int)L.size() > R) L.resize(R);
-    ++r;
-    if (L.empty()) {
-      have_scope = false;
-      continue;
-    }
-    Entry e = L.front();
-    L.erase(L.begin());
-    scope.resize(n_sub);
-    if (sqc_bin_scope(n_sub, e.masks.data(), e.bin, scope.data()) != SQC_OK)
-      raise(SQC_E_ARG, thread_error());
-    have_scope = true;
-    parent_prob = e.prob;
+    hipLaunchKernelGGL(search_step, dim3(1), dim3(kStepThreads), 0, ctx->stream, a, r, r == R - 1 ? 1 : 0);
+    after_launch("search kernel launch");
+  }
+  // one wait: the records, the solutions and the counts
+  std::vector<unsigned char> back(sp.region - sp.o_info);
+  SearchState st{};
+  check_hip(hipMemcpyAsync(back.data(), B + sp.o_info, back.size(), hipMemcpyDeviceToHost, ctx->stream),
+            "hipMemcpyAsync of the search results");
+  check_hip(hipMemcpyAsync(&st, B + sp.o_state, sizeof(st), hipMemcpyDeviceToHost, ctx->stream),
+            "hipMemcpyAsync of the search state");
+  check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  const unsigned char *bk = back.data();
+  if (info)
+    std::memcpy(info, bk, sizeof(sqc_recursion_info) * st.nrec);
+  const int nsol = std::min(st.nsol, std::max(0, max_solutions));
+  if (nsol > 0) {
+    std::memcpy(solutions, bk + (sp.o_sols - sp.o_info), sizeof(sqc_found) * nsol);
+    std::memcpy(solution_states, bk + (sp.o_states - sp.o_info), sizeof(uint64_t) * nsol * n_sub);
   }
   *n_solutions = nsol;
-  *n_recursions = r;
+  *n_recursions = st.nrec;
   return SQC_OK;
   SQC_CATCH(ctx)
 }

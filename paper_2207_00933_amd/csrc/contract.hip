@@ -508,6 +508,7 @@ __device__ __forceinline__ int find_job(const int *__restrict__ start, int n, in
 template <int PREC, bool FOLD, bool OUTF, int REG>
 __global__ __launch_bounds__(kThreads) void gemm_grouped(const GemmArgs *__restrict__ jobs,
                                                           const int *__restrict__ start, int n) {
+  if ((int)blockIdx.x >= start[n]) return;  // (a grid sized for a larger table)
   const int j = find_job(start, n, blockIdx.x);
   const int s0 = start[j];
   gemm_body<PREC, FOLD, OUTF, REG>(jobs[j], (int)blockIdx.x - s0, start[j + 1] - s0);
@@ -1073,6 +1074,7 @@ __global__ __launch_bounds__(kTThreads) void topr_rank(TopRArgs t) { topr_rank_b
 template <bool OUTF>
 __global__ __launch_bounds__(kTThreads) void topr_gather_grouped(const TopRArgs *__restrict__ jobs,
                                                                  const int *__restrict__ start, int n) {
+  if ((int)blockIdx.x >= start[n]) return;  // (a grid sized for a larger table)
   const int j = find_job(start, n, blockIdx.x);
   const int s0 = start[j];
   topr_gather_body<OUTF>(jobs[j], (int)blockIdx.x - s0, start[j + 1] - s0);

@@ -317,15 +317,19 @@ __device__ __forceinline__ int find_job(const int *__restrict__ start, int n, in
 
 // The same passes over a device table of shaped jobs (requests batched by the
 // serving engine).
+// (work-groups past start[n] do nothing: a launch may size its grid for the
+// largest of several tables that its jobs are later copied from)
 __global__ __launch_bounds__(kThreads) void merge_tiles_grouped(const MergeArgs *__restrict__ jobs,
                                                                  const int *__restrict__ start, int n) {
   __shared__ double tile[kTile + 64];
+  if ((int)blockIdx.x >= start[n]) return;
   const int j = find_job(start, n, blockIdx.x);
   merge_tiles_body(jobs[j], int64_t(blockIdx.x) - start[j], 0, tile);
 }
 
 __global__ __launch_bounds__(kThreads) void merge_rows_grouped(const MergeArgs *__restrict__ jobs,
                                                                 const int *__restrict__ start, int n) {
+  if ((int)blockIdx.x >= start[n]) return;
   const int j = find_job(start, n, blockIdx.x);
   const MergeArgs &a = jobs[j];
   const int64_t w = int64_t(blockIdx.x) - start[j];
@@ -334,6 +338,7 @@ __global__ __launch_bounds__(kThreads) void merge_rows_grouped(const MergeArgs *
 
 __global__ __launch_bounds__(kThreads) void merge_finish_grouped(const MergeArgs *__restrict__ jobs,
                                                                   const int *__restrict__ start, int n) {
+  if ((int)blockIdx.x >= start[n]) return;
   const int j = find_job(start, n, blockIdx.x);
   merge_finish_body(jobs[j], int64_t(blockIdx.x) - start[j], jobs[j].fin_blocks);
 }

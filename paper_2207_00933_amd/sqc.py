@@ -165,6 +165,8 @@ def lib():
             "sqc_recurse_noalloc": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
                                             POINTER(Masks), c_uint64, c_int32, c_int, P, c_int,
                                             POINTER(Masks), P, P]),
+            "sqc_search_workspace_bytes": (c_size_t, [POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
+                                                      c_uint64, c_int32, c_int, c_int32]),
             "sqc_search": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32, c_uint64,
                                    c_int32, c_int, P, c_int, POINTER(Found), POINTER(c_uint64),
                                    c_int32, POINTER(c_int32), POINTER(RecursionInfo),
@@ -512,6 +514,12 @@ def autotune_reset() -> None:
 
 def autotune_entries() -> int:
     return int(lib().sqc_autotune_entries())
+
+
+def search_workspace_bytes(att: Sequence[Tensor], g: Graph, M: int, R: int, prec: int,
+                           max_solutions: int = 64) -> int:
+    arr = tensor_array(att)
+    return int(lib().sqc_search_workspace_bytes(arr, g.n_sub, g.cuts, g.n_cuts, M, R, prec, max_solutions))
 
 
 def search(ctx: int, att: Sequence[Tensor], g: Graph, M: int, R: int, prec: int, bins,

@@ -240,3 +240,28 @@ def test_sliced_count_limit():
     g, descs, _ = _sliced_descs(bits, cuts, sqc.F32)
     assert sqc.contract_sliced_workspace_bytes(descs, g, list(range(8)), sqc.F32) > 0
     assert sqc.contract_sliced_workspace_bytes(descs, g, list(range(9)), sqc.F32) == 0
+
+
+def test_search_workspace_covers_every_depth():
+    """Host planning of the device search (Algorithm 1): the workspace holds
+    the largest recursion of any depth plus the search tables, grows with R,
+    and bad arguments are rejected before any launch."""
+    import torch
+    cc = configs.merging()
+    g = sqc.Graph.from_cut_circuit(cc)
+    descs = []
+    for i in range(cc.n_sub):
+        c = len(cc.incident(i))
+        descs.append(sqc.tensor_desc(torch.zeros(1), c, g.n_data[i], sqc.F32, sqc.LAYOUT_ATTRIBUTED))
+    M = 1 << 20
+    masks = sqc.assign_bins(g.n_data, None, M)
+    rec = sqc.recurse_workspace_bytes(descs, g, masks, sqc.BF16X3)
+    s12 = sqc.search_workspace_bytes(descs, g, M, 12, sqc.BF16X3)
+    s20 = sqc.search_workspace_bytes(descs, g, M, 20, sqc.BF16X3)
+    # (the recursion query sizes the top-R slots for R = 64)
+    assert rec > 0 and s12 > rec - 2 * 64 * 64 * 8 and s20 > s12
+    assert sqc.search_workspace_bytes(descs, g, M, 0, sqc.BF16X3) == 0
+    assert sqc.search_workspace_bytes(descs, g, M, 65, sqc.BF16X3) == 0
+    bad = list(descs)
+    bad[1] = sqc.tensor_desc(torch.zeros(1), 1, g.n_data[1], sqc.F32, sqc.LAYOUT_ATTRIBUTED)
+    assert sqc.search_workspace_bytes(bad, g, M, 12, sqc.BF16X3) == 0
