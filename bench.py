@@ -61,7 +61,22 @@ def _cpu_worker(chunk):
     return len(chunk), time.perf_counter() - t0
 
 
-def cpu_baseline(cc, var32, seconds: float):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cc, var32, seconds: float, n_check: int = 4096):
+    """The oracle (Eq. 1 bin by bin, FP64) timed on the host's cores on a
+    bounded random sample of the 2^24 outputs.  Also returns the oracle's
+    values at n_check of those bins, against which every GPU path's bins are
+    compared."""
     import multiprocessing as mp
     from oracle import reconstruction as rc
     Ts = [rc.attribute(cc, i, var32[i].astype(np.float64)) for i in range(cc.n_sub)]
@@ -73,10 +88,12 @@ def cpu_baseline(cc, var32, seconds: float):
     rc.eval_bins(Ts, cc, probe)
     per_bin = (time.perf_counter() - t0) / len(probe)
     try:
-        cores = len(os.sched_getaffinity(0))
+        affinity = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    workers = max(1, min(16, cores))
+        affinity = os.cpu_count() or 1
+    # one GPU's share of the host is 16 cores on the GPU machines: never more
+    # worker processes than that, nor than the process may run on
+    workers = max(1, min(16, affinity))
     per_worker = max(16, int(seconds / per_bin))
     sample = rng.integers(0, 1 << cc.n, size=per_worker * workers)
     chunks = [sample[w * per_worker:(w + 1) * per_worker] for w in range(workers)]
@@ -86,18 +103,21 @@ def cpu_baseline(cc, var32, seconds: float):
         res = pool.map(_cpu_worker, chunks)
     wall = time.perf_counter() - t0
     nb = sum(r[0] for r in res)
+    check_idx = np.unique(sample[:n_check])
+    check_want = rc.eval_bins(Ts, cc, check_idx)
     return {"value": nb / wall, "unit": "bins/s", "cores": workers, "kind": "oracle",
             "sample": f"{nb} bins drawn uniformly from the 2^24 outputs, Eq. 1 evaluated "
                       f"bin by bin (4^6 label assignments each) in FP64 by {workers} worker "
                       f"processes; {wall:.1f} s wall; attribution excluded",
-            "wall_s": wall}
+            "cpu_model": cpu_model(), "affinity_cpus": affinity,
+            "wall_s": wall, "check_idx": check_idx, "check_want": check_want}
 
 
 # ---------------------------------------------------------------------------
 # GPU
 # ---------------------------------------------------------------------------
 
-def run_gpu(cc, var32, steps: int, warmup: int, precs, autotune: bool = True, graph: bool = True):
+def run_gpu(cc, var32, steps: int, warmup: int, precs, autotune: bool = True, graph: bool = True, check=None):
     import torch
 
     if not torch.cuda.is_available():
@@ -105,13 +125,13 @@ def run_gpu(cc, var32, steps: int, warmup: int, precs, autotune: bool = True, gr
     # a created stream: the steps can then also be recorded into a HIP graph
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
-        return _run_gpu(cc, var32, steps, warmup, precs, autotune, graph)
+        return _run_gpu(cc, var32, steps, warmup, precs, autotune, graph, check)
 
 
 FINAL_EVERY = 4  # steps per final-contraction launch timed with dispatch events
 
 
-def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph):
+def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph, check):
     import torch
     from paper_2207_00933_amd import runner, sqc
 
@@ -137,6 +157,16 @@ def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph):
     sqc.graph_destroy(sqc.graph_end(s.ctx))
     del warm
     torch.cuda.synchronize()
+    # the precision selector's choice for this workload at the stated
+    # tolerance (a certified bound of every bin's sum of |terms|)
+    circ.attribute(sqc.F32)
+    masks = sqc.assign_bins(circ.g.n_data, None, M)
+    s.ensure_workspace(sqc.recurse_workspace_bytes(circ.att, circ.g, masks, sqc.AUTO))
+    choice, bound = sqc.select_precision(s.ctx, circ.att, circ.g, None, M)
+    out["_selector"] = {"choice": {v: k for k, v in PREC_ID.items()}[choice], "bound": bound,
+                        "tolerance": 1e-6, "bf16x3_bound": (2.0 ** -13 + 2.0 ** -24) * bound,
+                        "f32_bound": (2.0 ** -20 + 2.0 ** -24) * bound}
+    log(f"[bench] precision selector: {out['_selector']['choice']} (bound {bound:.3e})")
     for pname in precs:
         prec = PREC_ID[pname]
         att_prec = sqc.F64 if prec == sqc.F64 else sqc.F32
@@ -224,6 +254,13 @@ def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph):
             ref_bins = b.clone()
         elif ref_bins is not None:
             res["max_abs_vs_fp64_gpu"] = (b - ref_bins).abs().max().item()
+        if check is not None:
+            got = b[torch.from_numpy(check[0]).to(b.device)].cpu().numpy()
+            want = check[1]
+            err = np.abs(got - want)
+            nz = np.abs(want) > 0
+            res["vs_oracle"] = {"bins": int(len(want)), "max_abs": float(err.max()),
+                                "max_rel": float((err[nz] / np.abs(want[nz])).max()) if nz.any() else None}
         out[pname] = res
         log(f"[bench] {pname}: {ms:.4f} ms/step, {res['bins_per_s']:.3e} bins/s, "
             f"final kernel {res['final_kernel_us']:.2f} us")
@@ -691,24 +728,38 @@ def main():
     if args.calib_copy_mb > 0:
         calib_copy(args.calib_copy_mb)
     gpu = run_gpu(cc, var32, args.steps, args.warmup, precs, autotune=args.autotune,
-                  graph=not args.no_graph)
+                  graph=not args.no_graph,
+                  check=None if cpu is None else (cpu["check_idx"], cpu["check_want"]))
+    selector = gpu.pop("_selector")
     workloads = None if args.no_workloads else run_workloads()
     serving = run_serving(args.serve_requests, args.serve_slots) if args.serve_requests > 0 else None
+    # the headline path: the one the precision selector picks at the stated
+    # tolerance (split-BF16x3 where its bound holds), else the faster fast path
     fast = [p for p in ("bf16x3", "f32") if p in gpu]
-    head = max(fast, key=lambda p: gpu[p]["bins_per_s"]) if fast else precs[0]
+    head = selector["choice"] if selector["choice"] in gpu else (
+        max(fast, key=lambda p: gpu[p]["bins_per_s"]) if fast else precs[0])
     h = gpu[head]
-    t_hbm = h["final_kernel_bytes"] / HBM_PEAK
-    t_mfma = h["final_kernel_flops"] / PEAK[head]
-    if t_hbm >= t_mfma:
-        roof = {"bound": "hbm", "achieved": h["final_kernel_bytes"] / (h["final_kernel_us"] * 1e-6) / 1e9,
-                "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
-    else:
-        roof = {"bound": "mfma", "achieved": h["final_kernel_flops"] / (h["final_kernel_us"] * 1e-6) / 1e12,
-                "peak": PEAK[head] / 1e12, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic() if head == "bf16x3" else None
-    roof["kernel"] = f"final contraction step ({head})"
-    roof["kernel_us"] = h["final_kernel_us"]
+
+    def roofline(p):
+        x = gpu[p]
+        t_hbm = x["final_kernel_bytes"] / HBM_PEAK
+        t_mfma = x["final_kernel_flops"] / PEAK[p]
+        if t_hbm >= t_mfma:
+            r = {"bound": "hbm", "achieved": x["final_kernel_bytes"] / (x["final_kernel_us"] * 1e-6) / 1e9,
+                 "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+        else:
+            r = {"bound": "mfma", "achieved": x["final_kernel_flops"] / (x["final_kernel_us"] * 1e-6) / 1e12,
+                 "peak": PEAK[p] / 1e12, "unit": "TFLOP/s"}
+        r["frac"] = r["achieved"] / r["peak"]
+        r["traffic"] = measured_traffic() if p == "bf16x3" else None
+        r["kernel"] = f"final contraction step ({p})"
+        r["kernel_us"] = x["final_kernel_us"]
+        return r
+
+    roof = roofline(head)
+    for p in ("f32", "bf16x3", "f64"):
+        if p in gpu:
+            gpu[p]["roofline"] = roofline(p)
     line = {
         "metric": METRIC,
         "value": h["bins_per_s"],
@@ -729,7 +780,14 @@ def main():
                    "bins": 1 << cc.n},
         "roofline": roof,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in
-                                                  ("value", "unit", "cores", "kind", "sample")},
+                                                  ("value", "unit", "cores", "kind", "sample", "cpu_model",
+                                                   "affinity_cpus")},
+        "precision_selector": selector,
+        "paper_context": {"note": "context, not the target: the paper gives no kernel times; from its "
+                                  "100-qubit runs (5 and 100 recursions, about 50 s and 160 s end to end, "
+                                  "QPU time excluded) one 2^20-bin recursion costs about 1.16 s",
+                          "bins_per_s": (1 << 20) / 1.16, "hardware": "1 node: 64 CPUs + 1 Nvidia A100",
+                          "workload": "100-qubit Supremacy, M = 2^20, random subcircuit outputs"},
         "paths": gpu,
         "latency_ms": {"p50": h["p50_ms"], "p99": h["p99_ms"]},
         "workloads": workloads,

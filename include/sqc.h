@@ -78,9 +78,11 @@ typedef enum {
 typedef enum {
   SQC_F64 = 0,     /* IEEE binary64                                         */
   SQC_F32 = 1,     /* IEEE binary32; as a contraction precision: FP32 MFMA  */
-  SQC_BF16X3 = 2   /* contraction only: each FP32 operand split into bf16
+  SQC_BF16X3 = 2,  /* contraction only: each FP32 operand split into bf16
                       hi + lo, three bf16 MFMA products (hi*hi + hi*lo +
                       lo*hi) accumulated in FP32                            */
+  SQC_AUTO = 3     /* sqc_recurse only: the library picks SQC_BF16X3,
+                      SQC_F32 or SQC_F64 by sqc_select_precision first     */
 } sqc_prec;
 
 /* Largest compute-graph degree (cuts on one subcircuit), Sec. 6.2. */
@@ -358,7 +360,9 @@ sqc_status sqc_contract_sliced(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n
  * are written to `masks_out` (host, n_sub entries) before the call returns;
  * the device results are ready when the stream reaches them.
  * `attributed[i].prec` may differ from `prec` (SQC_F64 attributed with an
- * FP32 path is allowed). */
+ * FP32 path is allowed).  prec = SQC_AUTO selects the precision first
+ * (sqc_select_precision: waits for the device, not while recording a graph);
+ * its workspace query covers every choice. */
 size_t sqc_recurse_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub,
                                    const sqc_cut *cuts, int32_t n_cuts,
                                    const sqc_masks *masks, sqc_prec prec);
@@ -368,6 +372,32 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
                        int32_t top_r, sqc_prec prec, void *bins_dev,
                        sqc_prec bins_prec, sqc_masks *masks_out,
                        void *topr_dev, void *sum_dev);
+
+/* Precision selection (Eq. 1's terms summed in the path's arithmetic).  A
+ * bin computed as a sum over label assignments of products of the merged
+ * entries is off by at most c_path * u * S(x), S(x) = sum_sigma prod_i
+ * |T_i[sigma, x_i]| (the a-priori bound of a sum of products), with
+ * c * u = 2^-13 for split-BF16x3 (each operand kept to 2^-16 relative, lo*lo
+ * dropped), 2^-20 for FP32 MFMA, plus 2^-24 |bin| when bins are stored in
+ * FP32.  The call bounds max_x S(x) from above without forming S: it merges
+ * the attributed tensors for the recursion on `scope` (FP32, as the fast
+ * paths contract them), takes each label row's largest |entry| m_i[sigma]
+ * (row_absmax), and contracts the m_i over the cut graph in FP64 (labels
+ * only, one number): B = sum_sigma prod_i m_i[sigma|_i] >= S(x) for every x.
+ * It then picks SQC_BF16X3 when (2^-13 + 2^-24) B <= the context's
+ * tolerance, else SQC_F32 when (2^-20 + 2^-24) B <= it, else SQC_F64, and
+ * returns the choice and B.  Enqueued on the context's stream; waits for the
+ * device (it cannot be recorded into a graph).  Workspace as sqc_recurse
+ * with SQC_AUTO.  The tolerance (an absolute error per bin) is 1e-6 unless
+ * set by sqc_ctx_set_tolerance (> 0).  sqc_recurse with prec = SQC_AUTO
+ * calls this first and keeps the choice and bound for
+ * sqc_ctx_auto_choice. */
+sqc_status sqc_ctx_set_tolerance(sqc_ctx *ctx, double max_abs_error);
+sqc_status sqc_select_precision(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
+                                const sqc_cut *cuts, int32_t n_cuts,
+                                const sqc_masks *scope, uint64_t max_bins_M,
+                                sqc_prec *chosen, double *bound);
+sqc_status sqc_ctx_auto_choice(const sqc_ctx *ctx, sqc_prec *chosen, double *bound);
 
 /* Allocation-free recursion, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

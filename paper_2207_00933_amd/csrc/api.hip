@@ -53,6 +53,9 @@ struct sqc_ctx {
   uint32_t saved_mask = 0;  // timing mask suspended while a graph is recorded
   bool recording = false;
   void *plan_cache = nullptr;  // PlanCache of the recursions planned on this context
+  double tol = 1e-6;           // per-bin absolute error the precision selector keeps
+  sqc_prec auto_choice = SQC_F64;
+  double auto_bound = -1.0;    // (-1: no SQC_AUTO recursion yet)
   struct Mark {
     int stage;
     hipEvent_t a, b;
@@ -615,6 +618,73 @@ Launches describe_recursion(const RecursePlan &rp, const sqc_tensor *att, sqc_pr
   describe_contraction(L, rp.con, inputs, ws, unit2, rp.con_base, bins, bins_prec == SQC_F32, prec,
                        top_r, top_dev, sum_dev);
   return L;
+}
+
+// ---- precision selection: the certified bound B >= max_x sum_sigma prod_i
+// |T_i[sigma, x_i]| of a recursion ----
+
+// Relative factors of the a-priori error bound per contraction path, and the
+// rounding of FP32-stored bins.
+constexpr double kRelBF16x3 = 0x1p-13, kRelF32 = 0x1p-20, kRelStoreF32 = 0x1p-24;
+
+// Workspace of the selector for this scope (FP32 merged tensors, row maxima,
+// the label-only FP64 contraction and its result).
+size_t selector_ws(const Graph &g, const sqc_tensor *att, const sqc_masks *scope, uint64_t M, PlanCache *cache,
+                   RecursePlan *rp_out = nullptr, Contraction *c0_out = nullptr, size_t *m_off = nullptr,
+                   size_t *res_off = nullptr, size_t *c0_base = nullptr) {
+  RecursePlan rp = plan_recursion(g, att, scope, M, 1, SQC_F32, cache);
+  Bump b;
+  b.off = rp.con_base;  // after the merged tensors and their partial sums
+  std::vector<size_t> mo(g.n_sub);
+  for (int i = 0; i < g.n_sub; ++i) mo[i] = b.take((size_t(1) << (2 * att[i].n_labels)) * sizeof(double));
+  const size_t ro = b.take(sizeof(double));
+  Contraction c0 = plan_for(g, std::vector<int>(g.n_sub, 0), SQC_F64);
+  const size_t base = b.off;
+  const size_t total = base + contraction_ws(c0, 1, false, SQC_F64);
+  if (rp_out) *rp_out = rp;
+  if (c0_out) *c0_out = c0;
+  if (m_off) std::copy(mo.begin(), mo.end(), m_off);
+  if (res_off) *res_off = ro;
+  if (c0_base) *c0_base = base;
+  return total;
+}
+
+sqc_prec select_precision(sqc_ctx *ctx, const Graph &g, const sqc_tensor *att, const sqc_masks *scope, uint64_t M,
+                          double *bound) {
+  if (ctx->recording) raise(SQC_E_ARG, "precision selection waits for the device and cannot be recorded");
+  RecursePlan rp;
+  Contraction c0;
+  std::vector<size_t> mo(g.n_sub);
+  size_t ro = 0, base = 0;
+  const size_t need = selector_ws(g, att, scope, M, ctx_plans(ctx), &rp, &c0, mo.data(), &ro, &base);
+  need_ws(ctx, need);
+  use_device(ctx);
+  std::vector<MergeArgs> merges(g.n_sub);
+  std::vector<const void *> inputs(g.n_sub);
+  for (int i = 0; i < g.n_sub; ++i) {
+    void *out = ctx->ws + rp.ml.merged_off[i];
+    merges[i] = merge_args(att[i], rp.masks[i], out, 1, reinterpret_cast<double *>(ctx->ws + rp.ml.partial_off[i]));
+  }
+  enqueue_merges(ctx, merges);
+  for (int i = 0; i < g.n_sub; ++i) {
+    const int64_t rows = int64_t(1) << (2 * att[i].n_labels);
+    const int64_t cols = int64_t(1) << rp.abits[i];
+    double *m = reinterpret_cast<double *>(ctx->ws + mo[i]);
+    launch_row_absmax(ctx->ws + rp.ml.merged_off[i], 1, m, rows, cols, ctx->stream);
+    after_launch("row maximum kernel launch");
+    inputs[i] = m;
+  }
+  double *res = reinterpret_cast<double *>(ctx->ws + ro);
+  enqueue_contraction(ctx, c0, inputs, base, res, 0, SQC_F64, 0, nullptr, nullptr);
+  check_hip(hipMemcpyAsync(ctx->pinned, res, sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+            "hipMemcpyAsync of the bound");
+  check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  const double B = *static_cast<const double *>(ctx->pinned);
+  if (bound) *bound = B;
+  if (!(B == B)) return SQC_F64;  // a non-finite entry: the plain path
+  if ((kRelBF16x3 + kRelStoreF32) * B <= ctx->tol) return SQC_BF16X3;
+  if ((kRelF32 + kRelStoreF32) * B <= ctx->tol) return SQC_F32;
+  return SQC_F64;
 }
 
 void enqueue_recursion(sqc_ctx *ctx, const RecursePlan &rp, const sqc_tensor *att, sqc_prec prec,
@@ -1949,10 +2019,22 @@ size_t sqc_recurse_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub, 
     // the masks given fix the bin counts: use them as the scope with M large
     std::vector<int> abits(n_sub);
     for (int i = 0; i < n_sub; ++i) abits[i] = __builtin_popcountll(masks[i].active);
+    const bool autop = prec == SQC_AUTO;
+    if (autop) prec = SQC_F64;  // the largest of the choices
     Bump b;
     layout_merges(b, attributed, masks, n_sub, prec == SQC_F64 ? 8 : 4);
     Contraction c = plan_for(g, abits, prec);
-    return b.off + contraction_ws(c, SQC_MAX_TOPR, true, prec);
+    size_t need = b.off + contraction_ws(c, SQC_MAX_TOPR, true, prec);
+    if (autop) {
+      // the selector's own pass: FP32 merged tensors, row maxima, label-only contraction
+      Bump b2;
+      layout_merges(b2, attributed, masks, n_sub, 4);
+      for (int i = 0; i < n_sub; ++i) b2.take((size_t(1) << (2 * attributed[i].n_labels)) * sizeof(double));
+      b2.take(sizeof(double));
+      need = std::max(need, b2.off + contraction_ws(plan_for(g, std::vector<int>(n_sub, 0), SQC_F64), 1, false,
+                                                    SQC_F64));
+    }
+    return need;
   } catch (const Error &e) {
     set_thread_error(e.msg);
     return 0;
@@ -1966,6 +2048,15 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
   SQC_TRY(ctx)
   Graph g = build_topology(n_sub, cuts, n_cuts);
   if (!attributed || !bins_dev || !topr_dev || !sum_dev) raise(SQC_E_ARG, "NULL argument");
+  if (prec == SQC_AUTO) {
+    check_storage_prec(bins_prec, "bins_prec");
+    if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
+    degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+    double B = 0.0;
+    prec = select_precision(ctx, g, attributed, scope, max_bins_M, &B);
+    ctx->auto_choice = prec;
+    ctx->auto_bound = B;
+  }
   check_path_prec(prec);
   check_storage_prec(bins_prec, "bins_prec");
   if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
@@ -1977,6 +2068,33 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
   if (masks_out) std::copy(rp.masks.begin(), rp.masks.end(), masks_out);
   return SQC_OK;
   SQC_CATCH(ctx)
+}
+
+sqc_status sqc_ctx_set_tolerance(sqc_ctx *ctx, double max_abs_error) {
+  SQC_TRY(ctx)
+  if (!(max_abs_error > 0.0) || max_abs_error == INFINITY) raise(SQC_E_ARG, "the tolerance must be finite and > 0");
+  ctx->tol = max_abs_error;
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_select_precision(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,
+                                int32_t n_cuts, const sqc_masks *scope, uint64_t max_bins_M, sqc_prec *chosen,
+                                double *bound) {
+  SQC_TRY(ctx)
+  Graph g = build_topology(n_sub, cuts, n_cuts);
+  if (!attributed || !chosen) raise(SQC_E_ARG, "NULL argument");
+  degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+  *chosen = select_precision(ctx, g, attributed, scope, max_bins_M, bound);
+  return SQC_OK;
+  SQC_CATCH(ctx)
+}
+
+sqc_status sqc_ctx_auto_choice(const sqc_ctx *ctx, sqc_prec *chosen, double *bound) {
+  if (!ctx || !chosen) return SQC_E_ARG;
+  *chosen = ctx->auto_choice;
+  if (bound) *bound = ctx->auto_bound;
+  return ctx->auto_bound < 0 ? SQC_E_ARG : SQC_OK;
 }
 
 sqc_status sqc_recurse_noalloc(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts,

@@ -169,6 +169,8 @@ void merge_shape(MergeArgs &a);
 int64_t merge_pass_blocks(const MergeArgs &a, int pass);
 void launch_merge_grouped(int pass, const MergeArgs *jobs_dev, const int *start_dev, int n, int total,
                           hipStream_t s);
+// out[r] = max_c |in[r * cols + c]| (FP64) for a merged tensor [rows][cols].
+void launch_row_absmax(const void *in, int in_f32, double *out, int64_t rows, int64_t cols, hipStream_t s);
 // FP64 partial-sum elements the merge of these bit counts needs (0: none).
 int64_t merge_partial_elems(int abits, int lbits, int mbits);
 

@@ -343,6 +343,31 @@ __global__ __launch_bounds__(kThreads) void merge_finish_grouped(const MergeArgs
   merge_finish_body(jobs[j], int64_t(blockIdx.x) - start[j], jobs[j].fin_blocks);
 }
 
+// Largest |entry| of every label row of a merged tensor [rows][cols]: one
+// work-group per row at a time, FP64 result.  The precision selector
+// contracts these maxima into a certified bound of the bins' sums of |terms|.
+__global__ __launch_bounds__(kThreads) void row_absmax(const void *in, int in_f32, double *out, int64_t rows,
+                                                       int64_t cols) {
+  __shared__ double part[kThreads / 64];
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    double m = 0.0;
+    for (int64_t c = threadIdx.x; c < cols; c += kThreads) {
+      const double v = in_f32 ? (double)static_cast<const float *>(in)[r * cols + c]
+                              : static_cast<const double *>(in)[r * cols + c];
+      m = fmax(m, fabs(v));
+    }
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double x = part[0];
+      for (int w = 1; w < kThreads / 64; ++w) x = fmax(x, part[w]);
+      out[r] = x;
+    }
+    __syncthreads();
+  }
+}
+
 enum Pass { kTiles, kRows, kFinish };
 
 int64_t pass_blocks(const MergeArgs &a, Pass p) { return p == kFinish ? a.fin_blocks : a.blocks; }
@@ -396,6 +421,11 @@ void launch_merge_grouped(int pass, const MergeArgs *jobs, const int *start, int
     hipLaunchKernelGGL(merge_rows_grouped, dim3((unsigned)total), dim3(kThreads), 0, s, jobs, start, n);
   else
     hipLaunchKernelGGL(merge_finish_grouped, dim3((unsigned)total), dim3(kThreads), 0, s, jobs, start, n);
+}
+
+void launch_row_absmax(const void *in, int in_f32, double *out, int64_t rows, int64_t cols, hipStream_t s) {
+  const int64_t g = rows < 4096 ? rows : 4096;
+  if (g > 0) hipLaunchKernelGGL(row_absmax, dim3((unsigned)g), dim3(kThreads), 0, s, in, in_f32, out, rows, cols);
 }
 
 void launch_merges(const MergeArgs *jobs, int n, hipStream_t s) {

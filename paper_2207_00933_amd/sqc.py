@@ -22,7 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsqc.so")
 
 OK, E_ARG, E_SHAPE, E_NOMEM, E_DEVICE, E_NUMERIC, E_BUSY, E_UNSUPPORTED = range(8)
-F64, F32, BF16X3 = 0, 1, 2
+F64, F32, BF16X3, AUTO = 0, 1, 2, 3
 LAYOUT_ATTRIBUTED, LAYOUT_MERGED = 0, 1
 MAX_DEGREE = 15
 MAX_TOPR = 64
@@ -165,6 +165,10 @@ def lib():
             "sqc_recurse_noalloc": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
                                             POINTER(Masks), c_uint64, c_int32, c_int, P, c_int,
                                             POINTER(Masks), P, P]),
+            "sqc_ctx_set_tolerance": (c_int, [P, c_double]),
+            "sqc_select_precision": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32, POINTER(Masks),
+                                             c_uint64, POINTER(c_int), POINTER(c_double)]),
+            "sqc_ctx_auto_choice": (c_int, [P, POINTER(c_int), POINTER(c_double)]),
             "sqc_search_workspace_bytes": (c_size_t, [POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
                                                       c_uint64, c_int32, c_int, c_int32]),
             "sqc_search": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32, c_uint64,
@@ -514,6 +518,26 @@ def autotune_reset() -> None:
 
 def autotune_entries() -> int:
     return int(lib().sqc_autotune_entries())
+
+
+def ctx_set_tolerance(ctx: int, max_abs_error: float) -> None:
+    _check(lib().sqc_ctx_set_tolerance(ctx, max_abs_error), ctx)
+
+
+def select_precision(ctx: int, att: Sequence[Tensor], g: Graph, scope, M: int):
+    """(chosen precision, certified bound of the bins' sums of |terms|)."""
+    arr = tensor_array(att)
+    sc = masks_array(scope) if scope is not None else None
+    ch, b = c_int(), c_double()
+    _check(lib().sqc_select_precision(ctx, arr, g.n_sub, g.cuts, g.n_cuts, sc, M, ctypes.byref(ch),
+                                      ctypes.byref(b)), ctx)
+    return ch.value, b.value
+
+
+def ctx_auto_choice(ctx: int):
+    ch, b = c_int(), c_double()
+    _check(lib().sqc_ctx_auto_choice(ctx, ctypes.byref(ch), ctypes.byref(b)), ctx)
+    return ch.value, b.value
 
 
 def search_workspace_bytes(att: Sequence[Tensor], g: Graph, M: int, R: int, prec: int,
