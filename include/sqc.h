@@ -238,13 +238,16 @@ sqc_status sqc_slice_plan(int32_t n_sub, const int32_t *out_bits,
  * edges on one subcircuit, L = max_c (I_c + O_c) (Eq. 3), with the total
  * number of cut edges as the tie-break.  Method: two starts (the gate order
  * cut into n_sub blocks; bands of qubits, a gate in the band of its lowest
- * qubit) improved by single-gate moves, then iterated local search (a few
- * gates moved at random with a fixed seed, improved again, kept when
- * better), then branch and bound over the gates in circuit order
- * (subcircuit ids opened in order) from that incumbent, pruned by the
- * running (L, cut edges), which only grow; it stops after max_nodes search
- * nodes (<= 0: no limit) and returns the best partition found (*optimal = 1
- * when the search completed).  Writes
+ * qubit) improved by single-gate moves (each scored incrementally in
+ * O(gate degree); with more than 32 subcircuits only the neighbours'
+ * subcircuits are tried), then iterated local search (a few gates moved at
+ * random with a fixed seed, improved again, kept when better), then branch
+ * and bound over the gates in circuit order (subcircuit ids opened in
+ * order) from that incumbent, on an explicit stack of one frame per gate,
+ * pruned by the running (L, cut edges), which only grow; it stops after
+ * max_nodes search nodes (<= 0: no limit) and returns the best partition
+ * found (*optimal = 1 when the search completed).  Host memory
+ * O(n_gates * n_sub).  Writes
  * assign[n_gates], *L and *n_cut_edges.  Errors: SQC_E_ARG for NULL
  * pointers, n_sub outside [1, n_gates], a qubit id out of range or a gate on
  * one qubit; SQC_E_SHAPE when no partition meets Eq. 2. */

@@ -541,6 +541,7 @@ namespace {
 struct CutSearch {
   int n = 0, n_sub = 0, cap = 0;
   std::vector<std::vector<int>> pred;  // pred[v]: tail gates of v's in-edges (with repeats)
+  std::vector<std::vector<int>> adj;   // adj[v]: both ends' other gate, one entry per edge
   std::vector<int> assign, count, deg;
   int L = 0, cut = 0, used = 0;
   std::vector<int> best;
@@ -582,90 +583,213 @@ struct CutSearch {
     }
   }
 
-  // single-gate moves that lower (L, cut edges), until none does (at most
-  // `passes` sweeps over the gates)
+  // Single-gate moves that lower (L, cut edges), first improving move per
+  // gate, until a sweep moves nothing (at most `passes` sweeps).  A move is
+  // scored incrementally: it changes the degrees of at most the two
+  // subcircuits involved and those of v's neighbours, and a histogram of
+  // degree values gives the new maximum, so one trial costs O(deg v).
+  // With more than 32 subcircuits only the neighbours' subcircuits are
+  // tried as targets.
   void improve(std::vector<int> &a, int passes) const {
     int l, c;
     if (!score(a, l, c)) return;
+    std::vector<int> d(n_sub, 0), cnt(n_sub, 0);
+    for (int v = 0; v < n; ++v) {
+      cnt[a[v]]++;
+      for (int u : pred[v])
+        if (a[u] != a[v]) {
+          d[a[u]]++;
+          d[a[v]]++;
+        }
+    }
+    int top = 0;
+    for (int x : d) top = std::max(top, x);
+    std::vector<int> hist((size_t)4 * n + 8, 0);  // a degree is at most 4 n
+    for (int x : d) hist[x]++;
+    // pending degree changes of one trial move (sub, delta), at most 2 + 2|adj|
+    std::vector<std::pair<int, int>> ch;
+    auto add = [&](int s, int delta) {
+      for (auto &p : ch)
+        if (p.first == s) {
+          p.second += delta;
+          return;
+        }
+      ch.push_back({s, delta});
+    };
+    std::vector<int> targets;
     for (int p = 0; p < passes; ++p) {
       bool moved = false;
       for (int v = 0; v < n; ++v) {
         const int from = a[v];
-        for (int to = 0; to < n_sub; ++to) {
-          if (to == from) continue;
-          a[v] = to;
-          int l2, c2;
-          if (score(a, l2, c2) && (l2 < l || (l2 == l && c2 < c))) {
-            l = l2;
-            c = c2;
+        if (cnt[from] <= 1) continue;  // a subcircuit may not become empty
+        targets.clear();
+        if (n_sub <= 32) {
+          for (int t = 0; t < n_sub; ++t) targets.push_back(t);
+        } else {
+          for (int u : adj[v])
+            if (std::find(targets.begin(), targets.end(), a[u]) == targets.end()) targets.push_back(a[u]);
+          std::sort(targets.begin(), targets.end());
+        }
+        for (int to : targets) {
+          if (to == from || cnt[to] >= cap) continue;
+          ch.clear();
+          int dc = 0;
+          for (int u : adj[v]) {
+            const int s = a[u];
+            if (s != from) {  // edge cut now: uncut or re-cut after the move
+              add(s, -1);
+              add(from, -1);
+              dc--;
+            }
+            if (s != to) {
+              add(s, +1);
+              add(to, +1);
+              dc++;
+            }
+          }
+          // new maximum: changed subcircuits' new degrees, else the largest
+          // degree value still held by some unchanged subcircuit
+          int nl = 0;
+          for (auto &q : ch) {
+            hist[d[q.first]]--;
+            nl = std::max(nl, d[q.first] + q.second);
+          }
+          int h = top;
+          while (h > nl && hist[h] == 0) --h;
+          nl = std::max(nl, h);
+          for (auto &q : ch) hist[d[q.first]]++;
+          if (nl < l || (nl == l && c + dc < c)) {
+            for (auto &q : ch) {
+              hist[d[q.first]]--;
+              d[q.first] += q.second;
+              hist[d[q.first]]++;
+            }
+            top = std::max(top, nl);
+            while (top > 0 && hist[top] == 0) --top;
+            cnt[from]--;
+            cnt[to]++;
+            a[v] = to;
+            l = nl;
+            c += dc;
             moved = true;
             break;
           }
-          a[v] = from;
         }
       }
       if (!moved) break;
     }
   }
 
-  void dfs(int v) {
-    if (stopped) return;
+  // Branch and bound over the gates in circuit order with an explicit stack
+  // (one frame per placed gate), so the depth is bounded by memory, not by
+  // the thread's call stack.  Frame k holds the candidate subcircuits of
+  // gate k in the order tried (fewest new cut edges first), the one being
+  // tried, and what placing it changed.
+  struct Frame {
+    int next = 0, ncand = 0, chosen = -1;
+    int saveL = 0, saveCut = 0, saveUsed = 0;
+    int ntouched = 0;
+    int touched[2] = {0, 0};
+  };
+
+  void dfs() {
+    std::vector<Frame> st(n + 1);
+    std::vector<int> pool;  // frame v's candidates at [v n_sub, v n_sub + ncand)
+    auto fill = [&](int v) {
+      Frame &f = st[v];
+      f.next = 0;
+      f.ncand = 0;
+      f.chosen = -1;
+      const int top = std::min(used, n_sub - 1);
+      std::vector<std::pair<int, int>> cs;
+      for (int c = 0; c <= top; ++c) {
+        if (count[c] >= cap) continue;
+        const int opened = used + (c == used ? 1 : 0);
+        if (n - v - 1 < n_sub - opened) continue;  // too few gates left to open the rest
+        int add = 0;
+        for (int u : pred[v]) add += assign[u] != c;
+        cs.push_back({add, c});
+      }
+      std::stable_sort(cs.begin(), cs.end());
+      for (size_t i = 0; i < cs.size(); ++i) pool[(size_t)v * n_sub + i] = cs[i].second;
+      f.ncand = (int)cs.size();
+    };
+    auto undo = [&](int v) {
+      Frame &f = st[v];
+      if (f.chosen < 0) return;
+      const int c = f.chosen;
+      count[c]--;
+      assign[v] = -1;
+      for (int i = 0; i < f.ntouched; ++i) {
+        deg[f.touched[i]]--;
+        deg[c]--;
+      }
+      L = f.saveL;
+      cut = f.saveCut;
+      used = f.saveUsed;
+      f.chosen = -1;
+    };
+    pool.assign((size_t)(n + 1) * n_sub, 0);
+    int v = 0;
     if (max_nodes > 0 && ++nodes > max_nodes) {
       stopped = true;
       return;
     }
-    if (v == n) {
-      if (used == n_sub && better(L, cut)) {
-        best = assign;
-        best_L = L;
-        best_cut = cut;
-        have = true;
-      }
-      return;
-    }
-    // candidate subcircuits, fewest new cut edges first
-    const int top = std::min(used, n_sub - 1);
-    std::vector<std::pair<int, int>> cand;
-    for (int c = 0; c <= top; ++c) {
-      if (count[c] >= cap) continue;
-      const int opened = used + (c == used ? 1 : 0);
-      if (n - v - 1 < n_sub - opened) continue;  // too few gates left to open the rest
-      int add = 0;
-      for (int u : pred[v]) add += assign[u] != c;
-      cand.push_back({add, c});
-    }
-    std::stable_sort(cand.begin(), cand.end());
-    for (auto &pc : cand) {
-      const int c = pc.second;
-      const int saveL = L, saveCut = cut, saveUsed = used;
-      std::vector<std::pair<int, int>> touched;  // (subcircuit, increment)
-      int l = L;
-      for (int u : pred[v])
-        if (assign[u] != c) {
-          deg[assign[u]]++;
-          deg[c]++;
-          touched.push_back({assign[u], 1});
-          l = std::max(l, std::max(deg[assign[u]], deg[c]));
+    fill(0);
+    while (v >= 0) {
+      Frame &f = st[v];
+      undo(v);
+      bool descended = false;
+      while (f.next < f.ncand) {
+        const int c = pool[(size_t)v * n_sub + f.next++];
+        int l = L, nt = 0, tt[2] = {0, 0};
+        for (int u : pred[v])
+          if (assign[u] != c) {
+            tt[nt++] = assign[u];
+            deg[assign[u]]++;
+            deg[c]++;
+            l = std::max(l, std::max(deg[assign[u]], deg[c]));
+          }
+        const int ncut = cut + nt;
+        if (!better(l, ncut)) {  // (L, cut) only grow: the subtree cannot win
+          for (int i = 0; i < nt; ++i) {
+            deg[tt[i]]--;
+            deg[c]--;
+          }
+          continue;
         }
-      const int ncut = cut + (int)touched.size();
-      if (better(l, ncut)) {  // (L, cut) only grow: else the subtree cannot win
+        f.saveL = L;
+        f.saveCut = cut;
+        f.saveUsed = used;
+        f.ntouched = nt;
+        f.touched[0] = tt[0];
+        f.touched[1] = tt[1];
+        f.chosen = c;
         assign[v] = c;
         count[c]++;
         if (c == used) used++;
         L = l;
         cut = ncut;
-        dfs(v + 1);
-        count[c]--;
-        assign[v] = -1;
+        if (max_nodes > 0 && ++nodes > max_nodes) {
+          stopped = true;
+          return;
+        }
+        if (v + 1 == n) {
+          if (used == n_sub && better(L, cut)) {
+            best = assign;
+            best_L = L;
+            best_cut = cut;
+            have = true;
+          }
+          undo(v);
+          continue;
+        }
+        ++v;
+        fill(v);
+        descended = true;
+        break;
       }
-      for (auto &t : touched) {
-        deg[t.first]--;
-        deg[c]--;
-      }
-      L = saveL;
-      cut = saveCut;
-      used = saveUsed;
-      if (stopped) return;
+      if (!descended) --v;
     }
   }
 };
@@ -688,13 +812,18 @@ extern "C" sqc_status sqc_find_cuts(int32_t n_qubits, const int32_t *gates, int3
   if ((int64_t)s.cap * n_sub < n_gates || s.cap < 1)
     raise(SQC_E_SHAPE, "no partition meets the load constraint alpha |V|");
   s.pred.resize(n_gates);
+  s.adj.resize(n_gates);
   std::vector<int> last(n_qubits, -1);
   for (int v = 0; v < n_gates; ++v) {
     const int a = gates[2 * v], b = gates[2 * v + 1];
     if (a < 0 || a >= n_qubits || b < 0 || b >= n_qubits) raise(SQC_E_ARG, "gate qubit id out of range");
     if (a == b) raise(SQC_E_ARG, "a two-qubit gate acts on one qubit twice");
     for (int q : {a, b}) {
-      if (last[q] >= 0) s.pred[v].push_back(last[q]);
+      if (last[q] >= 0) {
+        s.pred[v].push_back(last[q]);
+        s.adj[v].push_back(last[q]);
+        s.adj[last[q]].push_back(v);
+      }
       last[q] = v;
     }
   }
@@ -738,7 +867,7 @@ extern "C" sqc_status sqc_find_cuts(int32_t n_qubits, const int32_t *gates, int3
   s.count.assign(n_sub, 0);
   s.deg.assign(n_sub, 0);
   s.max_nodes = max_nodes;
-  s.dfs(0);
+  s.dfs();
   if (!s.have) raise(SQC_E_SHAPE, "no partition meets the load constraint alpha |V|");
   for (int v = 0; v < n_gates; ++v) assign[v] = s.best[v];
   *L = s.best_L;

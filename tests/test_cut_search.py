@@ -73,3 +73,30 @@ def test_budgeted_search_on_a_workload_circuit():
 def test_rejects(args):
     with pytest.raises(sqc.SqcError):
         sqc.find_cuts(*args)
+
+
+@pytest.mark.parametrize("n_q,n_sub", [(64, 4), (96, 40)])
+def test_large_circuit(n_q, n_sub):
+    """About 100k gates (random nearest-neighbour pairs on a line of qubits):
+    the search neither exhausts the call stack (its branch and bound keeps an
+    explicit stack, one frame per gate) nor takes quadratic time in its local
+    moves, and the partition it returns meets Eq. 2 with the L and cut count
+    it reports.  With 40 subcircuits the moves try only the neighbours'
+    subcircuits."""
+    rng = np.random.default_rng(7)
+    n_g = 100_000
+    lo = rng.integers(0, n_q - 1, size=n_g)
+    gates = [(int(a), int(a) + 1) for a in lo]
+    alpha = 0.5 if n_sub == 4 else 0.05
+    t0 = time.perf_counter()
+    assign, L, ncut, optimal = sqc.find_cuts(n_q, gates, n_sub, alpha, max_nodes=300_000)
+    dt = time.perf_counter() - t0
+    edges = cs.dag_edges(gates)
+    assert cs.feasible(assign, n_sub, alpha)
+    assert L == cs.objective(assign, edges, n_sub)
+    assert ncut == sum(1 for u, v in edges if assign[u] != assign[v])
+    # no worse than the qubit-band start (a gate in the band of its lowest qubit)
+    band = [min(a, b) * n_sub // n_q for a, b in gates]
+    if cs.feasible(band, n_sub, alpha):
+        assert L <= cs.objective(band, edges, n_sub)
+    assert dt < 60.0, dt
