@@ -221,8 +221,12 @@ sqc_status sqc_plan_cost(int32_t n_sub, const int32_t *out_bits,
 
 /* First-level index slicing heuristic of Sec. 6.3: repeatedly write out the
  * cut whose removal reduces the total input floats the most (lowest cut id on
- * ties) until the total is <= budget_floats.  Writes the chosen cut ids to
- * `sliced` (capacity n_cuts) and their count to `n_sliced`. */
+ * ties) until the total is <= budget_floats, slicing at most SQC_MAX_SLICED
+ * cuts (the most sqc_contract_sliced takes).  Writes the chosen cut ids to
+ * `sliced` (capacity min(n_cuts, SQC_MAX_SLICED)) and their count to
+ * `n_sliced`.  Errors: SQC_E_ARG for NULL pointers or a bad graph;
+ * SQC_E_NOMEM when the budget is still unmet after slicing every cut or
+ * SQC_MAX_SLICED of them (sliced/n_sliced then hold that best effort). */
 sqc_status sqc_slice_plan(int32_t n_sub, const int32_t *out_bits,
                           const sqc_cut *cuts, int32_t n_cuts,
                           double budget_floats, int32_t *sliced,

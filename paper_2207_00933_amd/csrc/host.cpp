@@ -509,7 +509,7 @@ extern "C" sqc_status sqc_slice_plan(int32_t n_sub, const int32_t *out_bits,
   };
   int cnt = 0;
   std::vector<bool> gone(n_cuts, false);
-  while (total(labs) > budget_floats) {
+  while (total(labs) > budget_floats && cnt < SQC_MAX_SLICED) {
     int best = -1;
     double best_t = 0;
     for (int e = 0; e < n_cuts; ++e) {
@@ -528,6 +528,12 @@ extern "C" sqc_status sqc_slice_plan(int32_t n_sub, const int32_t *out_bits,
     sliced[cnt++] = best;
   }
   *n_sliced = cnt;
+  if (total(labs) > budget_floats) {
+    std::ostringstream m;
+    m << "slice_plan: " << cnt << " sliced cut(s) leave " << total(labs) << " input floats, above the budget "
+      << budget_floats << (cnt == SQC_MAX_SLICED ? " (at most SQC_MAX_SLICED cuts are sliced)" : "");
+    raise(SQC_E_NOMEM, m.str());
+  }
   return SQC_OK;
   SQC_HOST_CATCH
 }

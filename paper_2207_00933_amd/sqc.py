@@ -22,6 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsqc.so")
 
 OK, E_ARG, E_SHAPE, E_NOMEM, E_DEVICE, E_NUMERIC, E_BUSY, E_UNSUPPORTED = range(8)
+MAX_SLICED = 8  # SQC_MAX_SLICED
 F64, F32, BF16X3, AUTO = 0, 1, 2, 3
 LAYOUT_ATTRIBUTED, LAYOUT_MERGED = 0, 1
 MAX_DEGREE = 15

@@ -174,6 +174,31 @@ def test_slicing_paper_example():
     assert chosen == ocost.greedy_slices(ts, EX["sliced_input_floats"])
 
 
+def test_slicing_budget_unmet_and_cap():
+    """An unreachable budget is an error (SQC_E_NOMEM), not a silent plan
+    that misses it; slicing stops at SQC_MAX_SLICED cuts."""
+    qubits = EX["graph"]["qubits"]
+    cuts = EX["graph"]["cuts"]
+    with pytest.raises(sqc.SqcError) as e:  # below the unsliced data floats
+        sqc.slice_plan(qubits, cuts, sum(1 << q for q in qubits) - 1)
+    assert e.value.status == sqc.E_NOMEM
+    # a chain of 12 subcircuits, each pair joined by one cut: meeting the
+    # budget of all-sliced inputs would need all 11 cuts, above the cap
+    bits = [2] * 12
+    chain = [(i, i + 1) for i in range(11)]
+    with pytest.raises(sqc.SqcError) as e:
+        sqc.slice_plan(bits, chain, 12 * 4)
+    assert e.value.status == sqc.E_NOMEM and "SQC_MAX_SLICED" in str(e.value)
+    # 120 floats (the total after 8 greedy slices) is met with exactly 8
+    # cuts; 119 would need a ninth
+    ts = [(frozenset(k for k, c in enumerate(chain) if i in c), 4) for i in range(12)]
+    got = sqc.slice_plan(bits, chain, 120)
+    assert got == ocost.greedy_slices(ts, 120) and len(got) == sqc.MAX_SLICED
+    with pytest.raises(sqc.SqcError) as e:
+        sqc.slice_plan(bits, chain, 119)
+    assert e.value.status == sqc.E_NOMEM
+
+
 def _sliced_descs(bits, cuts, prec):
     import torch
     g = sqc.Graph([1] * len(bits), [[] for _ in bits], [(u, 0, v, 0) for u, v in cuts])
