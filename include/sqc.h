@@ -70,7 +70,7 @@ typedef enum {
   SQC_E_SHAPE = 2,       /* inconsistent graph or tensor shape; degree > 15  */
   SQC_E_NOMEM = 3,       /* workspace or buffer too small for the request    */
   SQC_E_DEVICE = 4,      /* HIP runtime error, or no usable GPU              */
-  SQC_E_NUMERIC = 5,     /* non-finite value found by an opt-in check        */
+  SQC_E_NUMERIC = 5,     /* non-finite input found by precision selection   */
   SQC_E_BUSY = 6,        /* serving engine: no free slot for a request       */
   SQC_E_UNSUPPORTED = 7  /* valid input outside this build's limits          */
 } sqc_status;
@@ -398,7 +398,10 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
  * with SQC_AUTO.  The tolerance (an absolute error per bin) is 1e-6 unless
  * set by sqc_ctx_set_tolerance (> 0).  sqc_recurse with prec = SQC_AUTO
  * calls this first and keeps the choice and bound for
- * sqc_ctx_auto_choice. */
+ * sqc_ctx_auto_choice.  This is also the library's check for non-finite
+ * input: a NaN or infinity in a merged tensor (or a bound that overflows)
+ * makes B non-finite, and the call (or sqc_recurse with SQC_AUTO, before
+ * any contraction) fails with SQC_E_NUMERIC, *bound set to that B. */
 sqc_status sqc_ctx_set_tolerance(sqc_ctx *ctx, double max_abs_error);
 sqc_status sqc_select_precision(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
                                 const sqc_cut *cuts, int32_t n_cuts,

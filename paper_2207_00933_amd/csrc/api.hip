@@ -681,7 +681,11 @@ sqc_prec select_precision(sqc_ctx *ctx, const Graph &g, const sqc_tensor *att, c
   check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
   const double B = *static_cast<const double *>(ctx->pinned);
   if (bound) *bound = B;
-  if (!(B == B)) return SQC_F64;  // a non-finite entry: the plain path
+  if (!std::isfinite(B)) {
+    std::ostringstream m;
+    m << "precision selection: the merged inputs hold a non-finite value (bound " << B << ")";
+    raise(SQC_E_NUMERIC, m.str());
+  }
   if ((kRelBF16x3 + kRelStoreF32) * B <= ctx->tol) return SQC_BF16X3;
   if ((kRelF32 + kRelStoreF32) * B <= ctx->tol) return SQC_F32;
   return SQC_F64;

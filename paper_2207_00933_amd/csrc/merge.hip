@@ -346,6 +346,9 @@ __global__ __launch_bounds__(kThreads) void merge_finish_grouped(const MergeArgs
 // Largest |entry| of every label row of a merged tensor [rows][cols]: one
 // work-group per row at a time, FP64 result.  The precision selector
 // contracts these maxima into a certified bound of the bins' sums of |terms|.
+// max that keeps a NaN (fmax drops it), so a NaN entry reaches the bound
+__device__ inline double nan_max(double m, double a) { return (a > m || a != a) ? a : m; }
+
 __global__ __launch_bounds__(kThreads) void row_absmax(const void *in, int in_f32, double *out, int64_t rows,
                                                        int64_t cols) {
   __shared__ double part[kThreads / 64];
@@ -354,14 +357,14 @@ __global__ __launch_bounds__(kThreads) void row_absmax(const void *in, int in_f3
     for (int64_t c = threadIdx.x; c < cols; c += kThreads) {
       const double v = in_f32 ? (double)static_cast<const float *>(in)[r * cols + c]
                               : static_cast<const double *>(in)[r * cols + c];
-      m = fmax(m, fabs(v));
+      m = nan_max(m, fabs(v));
     }
-    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    for (int off = 32; off >= 1; off >>= 1) m = nan_max(m, __shfl_xor(m, off));
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
       double x = part[0];
-      for (int w = 1; w < kThreads / 64; ++w) x = fmax(x, part[w]);
+      for (int w = 1; w < kThreads / 64; ++w) x = nan_max(x, part[w]);
       out[r] = x;
     }
     __syncthreads();

@@ -115,3 +115,30 @@ def test_tolerance_is_validated(session):
     with pytest.raises(sqc.SqcError):
         sqc.ctx_set_tolerance(session.ctx, 0.0)
     sqc.ctx_set_tolerance(session.ctx, 1e-6)
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_non_finite_input_is_reported(session, bad):
+    """A NaN or infinity in an attributed tensor reaches the bound (the row
+    maxima keep NaN), and selection fails with SQC_E_NUMERIC before any
+    contraction, for sqc_select_precision and sqc_recurse with SQC_AUTO."""
+    cc, Ts, g, att, bufs, nbits = _planted(session, 0.04, seed=17)
+    bufs[1][7, 3] = bad
+    with pytest.raises(sqc.SqcError) as e:
+        sqc.select_precision(session.ctx, att, g, None, 1 << nbits)
+    assert e.value.status == sqc.E_NUMERIC
+    M = 1 << nbits
+    masks = sqc.assign_bins(g.n_data, None, M)
+    session.ensure_workspace(sqc.recurse_workspace_bytes(att, g, masks, sqc.AUTO))
+    bins = torch.zeros(M, dtype=torch.float64, device="cuda")
+    top = torch.empty(2 * sqc.MAX_TOPR, dtype=torch.float64, device="cuda")
+    bsum = torch.empty(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(sqc.SqcError) as e:
+        sqc.recurse(session.ctx, att, g, None, M, 4, sqc.AUTO, bins, sqc.F64, top, bsum)
+    assert e.value.status == sqc.E_NUMERIC
+    torch.cuda.synchronize()
+    assert float(bins.abs().max()) == 0.0  # nothing was contracted
+    # the context still works on finite input afterwards
+    bufs[1][7, 3] = 0.5
+    choice, B = sqc.select_precision(session.ctx, att, g, None, M)
+    assert np.isfinite(B) and choice in (sqc.F32, sqc.F64, sqc.BF16X3)

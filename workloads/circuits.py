@@ -7,10 +7,13 @@ subcircuit it is assigned to.
 
 Benchmark families (paper Sec. 7.2): ``Supremacy``-like random brickwork
 circuits, ``Regular`` (p=1 QAOA on 3-regular graphs with random angles) and
-``BV`` (Bernstein-Vazirani, a single solution state).  How a circuit is split
-into subcircuits is chosen here by construction (the cut search of Sec. 5 is
-not part of this library); the assignment follows the paper's rule that a
-single-qubit gate belongs to the subcircuit of its neighbouring two-qubit gate.
+``BV`` (Bernstein-Vazirani, a single solution state).  The generators assign
+gates to subcircuits by construction, so that each workload has a fixed,
+known cut structure; the library's own cut search of Sec. 5
+(``sqc_find_cuts``) partitions an arbitrary circuit's two-qubit gates and is
+tested against these assignments.  The assignment follows the paper's rule
+that a single-qubit gate belongs to the subcircuit of its neighbouring
+two-qubit gate.
 """
 from __future__ import annotations
 
