@@ -1,22 +1,27 @@
-"""States merging: Algorithm 2 (states assignment) and Algorithm 1 (the
-recursion loop), paper Sec. 3-4, on explicit lists of states.
+"""States merging on explicit lists of states: the bin assignment of Alg. 2
+and the recursion driver of Alg. 1 (Sec. 3-4).  Test infrastructure only.
 
-Readings where the paper is silent (shared with the GPU library's host code):
+Each recursion analyses, per subcircuit, an ascending list of data states
+(all 2^d_i states at the first recursion, else the states of the bin being
+expanded).  Bin counts start at the list lengths; while their product exceeds
+M, the largest count is halved, rounding up.  A subcircuit's bins are then the
+residue classes of positions in its ordered list modulo its bin count.
 
-* enumeration: "the j-th state" of a subcircuit is the j-th smallest state
-  index among the states under analysis (ascending order);
-* bin labels: the assignment uses the printed 1-based rule k = j mod l'_i; the
-  resulting bins are then numbered in ascending order of their smallest member
-  (the same partition; only the labels rotate);
-* ties in "the subcircuit with the largest l'_i": the lowest subcircuit index
-  wins -- parity unpinned, any rule is valid;
-* Algorithm 1's list L: a bin is "not yet fully expanded" when it holds more
-  than one state; L is ordered by probability (largest first), then earlier
-  recursion, then lower bin index -- parity unpinned beyond the recursion count
-  of a single-solution circuit; bins of single states are reported as
-  solutions (the paper leaves their reporting open);
-* "bin is None" means L is empty; R is both the recursion cap and the capacity
-  of L, as printed.
+Readings where the paper is silent (shared with the library's host code):
+
+* order: a subcircuit's states are enumerated in ascending index order;
+* labels: the paper's 1-based residue rule gives the same partition as the
+  0-based classes used here; bins are numbered by their smallest member, which
+  for residue classes is the class index itself;
+* ties between equally large bin counts halve the lowest subcircuit index
+  first -- parity unpinned, any rule is valid;
+* Alg. 1's candidate list holds bins with more than one state, ordered by
+  probability (largest first), then earlier recursion, then lower bin index,
+  and is cut to R entries -- parity unpinned beyond the recursion count of a
+  single-solution circuit; bins of single states are reported as solutions
+  (the paper leaves their reporting open);
+* the driver stops when the candidate list is empty or after R recursions
+  (R bounds both the recursion count and the list's length).
 """
 from __future__ import annotations
 
@@ -28,38 +33,28 @@ import numpy as np
 from .reconstruction import merge_entries, reconstruct_eq1
 
 
+def bin_counts(lengths: List[int], M: int) -> List[int]:
+    """Per-subcircuit bin counts of Alg. 2: the list lengths, with the largest
+    count (lowest index on ties) halved, rounding up, as long as the product
+    of the counts exceeds M."""
+    counts = list(lengths)
+    while int(np.prod(counts, dtype=object)) > M:
+        i = counts.index(max(counts))
+        counts[i] = (counts[i] + 1) // 2
+    return counts
+
+
 def assign_states(r: int, bin_states: Optional[List[List[int]]], M: int,
                   n_list: List[int]) -> List[List[List[int]]]:
-    """Algorithm 2.  Returns, per subcircuit i, its list of bins, each bin the
-    ascending list of state indices (over the d_i data qubits) it holds."""
-    n_C = len(n_list)
+    """Alg. 2.  Returns, per subcircuit i, its bins, each the ascending list of
+    data states (over the d_i data qubits) it holds: bin b of subcircuit i is
+    every counts[i]-th state of the ordered list, starting at position b."""
     if r == 0:
-        states = [list(range(1 << n_list[i])) for i in range(n_C)]
+        ordered = [list(range(1 << d)) for d in n_list]
     else:
-        states = [sorted(bin_states[i]) for i in range(n_C)]
-    l = [len(s) for s in states]
-    lp = list(l)
-    total = 1
-    for v in lp:
-        total *= v
-    while total > M:
-        i_max = 0
-        for i in range(1, n_C):
-            if lp[i] > lp[i_max]:
-                i_max = i
-        lp[i_max] = -(-lp[i_max] // 2)
-        total = 1
-        for v in lp:
-            total *= v
-    out = []
-    for i in range(n_C):
-        bins = [[] for _ in range(lp[i])]
-        for j in range(1, l[i] + 1):
-            k = j % lp[i]
-            bins[k].append(states[i][j - 1])
-        bins.sort(key=lambda b: b[0])  # label bins by their smallest member
-        out.append(bins)
-    return out
+        ordered = [sorted(b) for b in bin_states]
+    counts = bin_counts([len(o) for o in ordered], M)
+    return [[o[b::c] for b in range(c)] for o, c in zip(ordered, counts)]
 
 
 def bin_size(bins_per_sub: List[List[List[int]]]) -> int:
@@ -102,42 +97,38 @@ def split_index(idx: int, counts: List[int]) -> List[int]:
 
 
 def search(Ts_half: List[np.ndarray], cc, M: int, R: int) -> SearchResult:
-    """Algorithm 1 with the cut search and QPU steps replaced by given
-    attributed entries (the QPU's merged bins are obtained by summing entries,
-    which equals merging measured outcomes because merging touches only data
-    qubits)."""
+    """Alg. 1 with the cut search and the QPU runs replaced by given attributed
+    entries (summing entries over a bin equals merging the measured outcomes,
+    as merging acts on data qubits only).  Each recursion evaluates the bins of
+    one parent (the whole output space first), reports the R most probable as
+    solutions when they are single states, else adds them to a candidate list
+    kept best first and cut to R; the next parent is the list's best."""
     n_list = [s.n_data for s in cc.subs]
-    L: List[Entry] = []
     res = SearchResult()
-    r = 0
-    chosen: Optional[Entry] = None
-    while r < R:
-        if r > 0 and chosen is None:
-            break
-        bins = assign_states(r, None if chosen is None else chosen.states, M, n_list)
+    frontier: List[Entry] = []
+    parent: Optional[Entry] = None
+    for r in range(R):
+        bins = assign_states(r, None if parent is None else parent.states, M, n_list)
         P = recursion_bins(Ts_half, cc, bins)
         counts = [len(b) for b in bins]
-        order = sorted(range(len(P)), key=lambda k: (-P[k], k))
-        top = order[:R]
-        rec = {"r": r, "a": [int(np.log2(c)) for c in counts],
-               "leaf": bin_size(bins) == 1,
-               "sum": float(P.sum()), "top": [(int(k), float(P[k])) for k in top],
-               "parent": None if chosen is None else (chosen.r, chosen.index, chosen.prob)}
-        res.history.append(rec)
-        if bin_size(bins) > 1:
-            for k in top:
-                ks = split_index(k, counts)
-                L.append(Entry(float(P[k]), r, int(k),
-                               [bins[i][ks[i]] for i in range(cc.n_sub)]))
+        top = sorted(range(len(P)), key=lambda k: (-P[k], k))[:R]
+        leaf = bin_size(bins) == 1
+        res.history.append({
+            "r": r, "a": [int(np.log2(c)) for c in counts], "leaf": leaf,
+            "sum": float(P.sum()), "top": [(int(k), float(P[k])) for k in top],
+            "parent": None if parent is None else (parent.r, parent.index, parent.prob)})
+        picked = [(int(k), split_index(k, counts)) for k in top]
+        if leaf:
+            res.solutions += [(float(P[k]), [bins[i][ks[i]][0] for i in range(cc.n_sub)])
+                              for k, ks in picked]
         else:
-            for k in top:
-                ks = split_index(k, counts)
-                res.solutions.append((float(P[k]), [bins[i][ks[i]][0] for i in range(cc.n_sub)]))
-        L.sort(key=lambda e: (-e.prob, e.r, e.index))
-        L = L[:R]
-        chosen = L.pop(0) if L else None
-        r += 1
-    res.recursions = r
+            frontier += [Entry(float(P[k]), r, k, [bins[i][ks[i]] for i in range(cc.n_sub)])
+                         for k, ks in picked]
+            frontier = sorted(frontier, key=lambda e: (-e.prob, e.r, e.index))[:R]
+        res.recursions = r + 1
+        if not frontier:
+            break
+        parent = frontier.pop(0)
     return res
 
 
