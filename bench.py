@@ -351,7 +351,7 @@ def replay_bytes(s, circ, M, R, prec, bprec, infos):
     return nbytes, recs == list(infos)
 
 
-def run_workloads(reps: int = 5):
+def run_workloads(reps: int = 5, which=("merging", "large", "slicing", "query")):
     """Algorithm 1 (sqc_search, the whole loop on the device) on the merging
     workload (60-qubit QAOA ring, 4 subcircuits, 8 cuts, M = 2^20, R = 12)
     and the large one (200-qubit chain, 16 subcircuits, 24 cuts, M = 2^24,
@@ -367,8 +367,11 @@ def run_workloads(reps: int = 5):
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
         s = runner.Session(0, 64 << 20)
-        for name, cc, M, R in (("merging", configs.merging(), 1 << 20, 12),
-                               ("large", configs.large(), 1 << 24, 20)):
+        searches = [(name, cc, M, R) for name, cc, M, R in
+                    (("merging", lambda: configs.merging(), 1 << 20, 12),
+                     ("large", lambda: configs.large(), 1 << 24, 20)) if name in which]
+        for name, make, M, R in searches:
+            cc = make()
             var = qpu.all_variants(cc)
             circ = runner.Circuit.from_cut_circuit(s, cc, var, sqc.F64)
             res = {"qubits": cc.n, "subcircuits": cc.n_sub, "cuts": len(cc.cuts), "M": M,
@@ -398,8 +401,10 @@ def run_workloads(reps: int = 5):
             res["speedup_bf16x3_vs_f64"] = res["bf16x3"]["bins_per_s"] / res["f64"]["bins_per_s"]
             out[name] = res
             del circ
-        out["slicing"] = run_slicing(s, reps)
-        out["subset_query"] = run_query(s, reps)
+        if "slicing" in which:
+            out["slicing"] = run_slicing(s, reps)
+        if "query" in which:
+            out["subset_query"] = run_query(s, reps)
         s.close()
     return out
 
@@ -492,12 +497,9 @@ def run_slicing(s, reps: int):
             gathered = sum(((4 ** (len(cc.incident(i)) - sum(1 for k in sliced if i in cuts[k])))
                             << g.n_data[i]) * elem for i in range(cc.n_sub)
                            if any(i in cuts[k] for k in sliced))
-            extra = 0.0
-            if sliced:
-                # per slice: gathers; FP64 slice bins written by the last GEMM
-                # (counted above) and read; running sums read and written
-                # between slices; the result written once
-                extra = nsl * 2 * gathered + nsl * 8 * M + (nsl - 1) * 2 * 16 * M + elem * M
+            # per slice: the gathers (read and written once); the final
+            # GEMM's running-sum traffic is in the stage bytes above
+            extra = nsl * 2 * gathered if sliced else 0.0
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
@@ -701,7 +703,10 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the HIP-graph replay measurement of the step")
     ap.add_argument("--no-workloads", action="store_true",
-                    help="skip the merging and large workloads (Algorithm 1 on the device)")
+                    help="skip the workloads leg (Algorithm 1 on the device, slicing, queries)")
+    ap.add_argument("--workloads", default="merging,large,slicing,query",
+                    help="which legs of the workloads leg to run (comma list)")
+    ap.add_argument("--workload-reps", type=int, default=5)
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving leg (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -731,7 +736,8 @@ def main():
                   graph=not args.no_graph,
                   check=None if cpu is None else (cpu["check_idx"], cpu["check_want"]))
     selector = gpu.pop("_selector")
-    workloads = None if args.no_workloads else run_workloads()
+    which = [w for w in args.workloads.split(",") if w]
+    workloads = None if args.no_workloads or not which else run_workloads(args.workload_reps, which)
     serving = run_serving(args.serve_requests, args.serve_slots) if args.serve_requests > 0 else None
     # the headline path: the one the precision selector picks at the stated
     # tolerance (split-BF16x3 where its bound holds), else the faster fast path

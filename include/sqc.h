@@ -335,17 +335,18 @@ sqc_status sqc_contract(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n_sub,
  * 4^n_sliced slices, in ascending order: every merged tensor incident to a
  * sliced cut is restricted to the slice's labels (its rows gathered into the
  * workspace, the remaining labels keeping their order), the network without
- * the sliced cuts is contracted as by sqc_contract (same `prec`) into FP64
- * bins, and these are added into FP64 running sums with Neumaier
- * compensation; the compensated sums are written to `bins_dev` (2^a elements
- * of bins_prec, a = sum of n_bits) after the last slice.  The contraction's
- * intermediates are those of the sliced network (4x smaller per sliced label
- * they would carry); the call adds the gathered operands and three 2^a FP64
- * vectors to the workspace (sqc_contract_sliced_workspace_bytes).  Merged
- * tensors and cuts as for sqc_contract.  Stage timing books the gathers
- * under SQC_STAGE_MERGE and the additions under SQC_STAGE_CONTRACT.  Errors: SQC_E_ARG for a repeated or
- * out-of-range cut id or n_sliced outside [0, SQC_MAX_SLICED], SQC_E_NOMEM
- * for a small workspace, else as sqc_contract. */
+ * the sliced cuts is contracted as by sqc_contract (same `prec`), and its
+ * final step adds the slice's bins into FP64 running sums with Neumaier
+ * compensation (no slice vector is stored); the last slice's final step
+ * writes sum + compensation to `bins_dev` (2^a elements of bins_prec, a = sum
+ * of n_bits).  The contraction's intermediates are those of the sliced
+ * network (4x smaller per sliced label they would carry); the call adds the
+ * gathered operands and two 2^a FP64 vectors (sums, compensations) to the
+ * workspace (sqc_contract_sliced_workspace_bytes).  n_sliced = 0 is the
+ * plain contraction.  Merged tensors and cuts as for sqc_contract.  Stage
+ * timing books the gathers under SQC_STAGE_MERGE.  Errors: SQC_E_ARG for a
+ * repeated or out-of-range cut id or n_sliced outside [0, SQC_MAX_SLICED],
+ * SQC_E_NOMEM for a small workspace, else as sqc_contract. */
 #define SQC_MAX_SLICED 8
 size_t sqc_contract_sliced_workspace_bytes(const sqc_tensor *merged, int32_t n_sub,
                                            const sqc_cut *cuts, int32_t n_cuts,
@@ -369,10 +370,40 @@ sqc_status sqc_contract_sliced(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n
  * `attributed[i].prec` may differ from `prec` (SQC_F64 attributed with an
  * FP32 path is allowed).  prec = SQC_AUTO selects the precision first
  * (sqc_select_precision: waits for the device, not while recording a graph);
- * its workspace query covers every choice. */
+ * its workspace query covers every choice.
+ *
+ * Memory-driven slicing (Sec. 6.3): when the context's workspace is smaller
+ * than the unsliced recursion needs (sqc_recurse_workspace_bytes), the call
+ * slices cuts, chosen as sqc_recurse_slices reports: repeatedly the cut whose
+ * removal shrinks the merged tensors' total size the most (the higher id on
+ * ties: the higher label digit, so that a slice reads long contiguous runs of
+ * labels), until the sliced layout fits, at most SQC_MAX_SLICED cuts, else
+ * SQC_E_NOMEM.  Each of the 4^s slices merges, straight from the attributed
+ * tensors, only the label rows it keeps (subcircuits with no sliced cut are
+ * merged once), contracts the network without the sliced cuts, and its
+ * final step adds the slice into FP64 running sums (Neumaier); the last
+ * slice writes the bins and the top-R statistics.  Slices are added in
+ * ascending order (the first chosen cut the least significant radix-4
+ * digit), so results are deterministic; they equal the unsliced results up
+ * to rounding.  The sliced workspace holds each subcircuit's slice of merged
+ * rows, the sliced network's intermediates and two 2^a FP64 vectors.  With
+ * SQC_AUTO the precision selector's own pass must fit unsliced. */
 size_t sqc_recurse_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub,
                                    const sqc_cut *cuts, int32_t n_cuts,
                                    const sqc_masks *masks, sqc_prec prec);
+/* The cuts a recursion with these masks (prec SQC_F64, SQC_F32 or
+ * SQC_BF16X3, top_r in [1, 64]) slices under a workspace of workspace_bytes:
+ * writes them to `sliced` (capacity SQC_MAX_SLICED; none when the unsliced
+ * plan fits) in slice-digit order, their count to `n_sliced` and the bytes
+ * the chosen layout needs to *need_bytes (optional).  Host only.  Errors:
+ * SQC_E_ARG for NULL pointers or bad arguments, SQC_E_SHAPE for an
+ * inconsistent graph, SQC_E_NOMEM when SQC_MAX_SLICED cuts do not make it
+ * fit. */
+sqc_status sqc_recurse_slices(const sqc_tensor *attributed, int32_t n_sub,
+                              const sqc_cut *cuts, int32_t n_cuts,
+                              const sqc_masks *masks, sqc_prec prec, int32_t top_r,
+                              size_t workspace_bytes, int32_t *sliced,
+                              int32_t *n_sliced, size_t *need_bytes);
 sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
                        const sqc_cut *cuts, int32_t n_cuts,
                        const sqc_masks *scope, uint64_t max_bins_M,
@@ -545,8 +576,11 @@ typedef struct {
  * i's data state.  `info` (optional) receives one record per recursion run
  * (capacity max_recursions).  `bins_dev` must hold 2^a elements of bins_prec
  * for the largest a the search uses (at most floor(log2 M)); it holds the
- * last recursion's bins.  Errors: SQC_E_NOMEM when the workspace is too
- * small, SQC_E_UNSUPPORTED above 64 subcircuits, else as sqc_recurse. */
+ * last recursion's bins.  The search does not slice (its recursions are
+ * laid out once, unsliced); a graph whose recursions fit only sliced is
+ * searched by calling sqc_recurse per recursion.  Errors: SQC_E_NOMEM when
+ * the workspace is too small, SQC_E_UNSUPPORTED above 64 subcircuits, else
+ * as sqc_recurse. */
 size_t sqc_search_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub,
                                   const sqc_cut *cuts, int32_t n_cuts, uint64_t max_bins_M,
                                   int32_t max_recursions, sqc_prec prec,

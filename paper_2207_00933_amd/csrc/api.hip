@@ -239,6 +239,9 @@ MergeArgs merge_args(const sqc_tensor &at, const sqc_masks &mk, void *out, int o
   a.out_f32 = out_f32;
   a.d = at.n_bits;
   a.lbits = 2 * at.n_labels;
+  a.in_lbits = a.lbits;
+  a.lab_fixed = 0;
+  a.lab_keep = (uint64_t(1) << a.lbits) - 1;
   a.abits = __builtin_popcountll(mk.active);
   a.mbits = __builtin_popcountll(mk.merged);
   a.fixed_val = mk.fixed_val;
@@ -378,11 +381,14 @@ size_t contraction_ws(const Contraction &c, int top_r, bool stats, int prec) {
 }
 
 // Algorithmic bytes of one GEMM step: each operand element read once, each
-// result written once.
+// result written once (a slice's final step instead writes its FP64 running
+// sum and compensation, reads them unless it is the first slice, and the last
+// slice writes the result as well).
 double gemm_bytes(const GemmArgs &g, int path_f32) {
   const double eb = path_f32 ? 4 : 8, ob = g.out_f32 ? 4 : 8;
+  const double per_out = g.acc_mode == 1 ? 16 : g.acc_mode == 2 ? 32 : g.acc_mode == 3 ? 16 + ob : ob;
   return (std::ldexp(1.0, g.mbits + g.kbits) + std::ldexp(1.0, g.nbits + g.kbits)) * eb +
-         std::ldexp(1.0, g.mbits + g.nbits) * ob;
+         std::ldexp(1.0, g.mbits + g.nbits) * per_out;
 }
 double gemm_flops(const GemmArgs &g) { return std::ldexp(2.0, g.mbits + g.nbits + g.kbits); }
 
@@ -400,11 +406,19 @@ struct Launches {
   int path_f32 = 1;
 };
 
+// One slice of a sliced contraction: how its final step adds into the FP64
+// running sums (GemmArgs::acc_mode; 0 = not sliced).
+struct SliceAcc {
+  int mode = 0;
+  double *sum = nullptr, *comp = nullptr;
+};
+
 // GEMM steps of a contraction whose intermediates start at ws + base.  With
 // `top_dev` non-null, the final step gathers statistics for the top-R stage.
 void describe_contraction(Launches &L, const Contraction &c, const std::vector<const void *> &inputs,
                           char *ws, const double *unit2, size_t base, void *bins, int bins_f32,
-                          sqc_prec prec, int top_r, void *top_dev, void *sum_dev) {
+                          sqc_prec prec, int top_r, void *top_dev, void *sum_dev,
+                          const SliceAcc &acc = SliceAcc{}) {
   const void *unit = reinterpret_cast<const char *>(unit2) + (c.path_f32 ? 8 : 0);
   L.path_f32 = c.path_f32;
   size_t inter_base = base;
@@ -424,6 +438,12 @@ void describe_contraction(Launches &L, const Contraction &c, const std::vector<c
       g.stats = 1;
       g.blk_max = reinterpret_cast<double *>(ws + bp.take(nsub * sizeof(double)));
       g.wg_stats = reinterpret_cast<double *>(ws + bp.take(3 * kMaxGemmGroups * sizeof(double)));
+    }
+    if (last && acc.mode) {
+      if (acc.mode != 3 && g.stats) raise(SQC_E_ARG, "internal: statistics of a slice that is not the last");
+      g.acc_mode = acc.mode;
+      g.acc_sum = acc.sum;
+      g.acc_comp = acc.comp;
     }
     const GemmSpec sp = prepare_gemm(g, prec);
     int groups = gemm_groups(g, sp);
@@ -600,6 +620,22 @@ RecursePlan plan_recursion(const Graph &g, const sqc_tensor *att, const sqc_mask
   return rp;
 }
 
+// The plan of a recursion with the given masks (the bins of each subcircuit
+// fixed by them rather than derived from a scope and M).
+RecursePlan plan_from_masks(const Graph &g, const sqc_tensor *att, const sqc_masks *masks, int top_r,
+                            sqc_prec prec) {
+  RecursePlan rp;
+  rp.masks.assign(masks, masks + g.n_sub);
+  rp.abits.resize(g.n_sub);
+  for (int i = 0; i < g.n_sub; ++i) rp.abits[i] = __builtin_popcountll(masks[i].active);
+  rp.con = plan_for(g, rp.abits, prec);
+  Bump b;
+  rp.ml = layout_merges(b, att, rp.masks.data(), g.n_sub, prec == SQC_F64 ? 8 : 4);
+  rp.con_base = b.off;
+  rp.total = b.off + contraction_ws(rp.con, top_r, true, prec);
+  return rp;
+}
+
 // The launches of one recursion whose workspace starts at ws.
 Launches describe_recursion(const RecursePlan &rp, const sqc_tensor *att, sqc_prec prec, char *ws,
                             const double *unit2, void *bins, sqc_prec bins_prec, int top_r,
@@ -618,6 +654,150 @@ Launches describe_recursion(const RecursePlan &rp, const sqc_tensor *att, sqc_pr
   describe_contraction(L, rp.con, inputs, ws, unit2, rp.con_base, bins, bins_prec == SQC_F32, prec,
                        top_r, top_dev, sum_dev);
   return L;
+}
+
+// ---- memory-driven first-level slicing of a recursion (Sec. 6.3) ----
+
+// A recursion whose contraction is split over the label values of some cuts:
+// each slice merges, straight from the attributed tensors, only the label rows
+// it keeps (so the whole merged tensors never exist), contracts the network
+// without the sliced cuts, and its final step adds the slice's bins into FP64
+// running sums; the last slice writes sum + compensation and the statistics
+// for top-R.  Subcircuits with no sliced cut are merged once.
+struct SlicedRecursion {
+  RecursePlan rp;            // masks and active bits
+  std::vector<int> sliced;   // cut ids; slice digit j belongs to sliced[j]
+  Contraction con;           // the network without the sliced cuts
+  // per subcircuit: (digit position in its sigma, index in `sliced`) of each
+  // incident sliced cut, ascending digit position
+  std::vector<std::vector<std::pair<int, int>>> fixed;
+  std::vector<size_t> merged_off, partial_off;
+  size_t sum_off = 0, comp_off = 0, con_base = 0, total = 0;
+};
+
+SlicedRecursion layout_sliced(const Graph &g, const sqc_tensor *att, const RecursePlan &rp,
+                              const std::vector<int> &sliced, sqc_prec prec, int top_r) {
+  SlicedRecursion sr;
+  sr.rp = rp;
+  sr.sliced = sliced;
+  std::vector<int> which(g.cuts.size(), -1);
+  for (size_t q = 0; q < sliced.size(); ++q) which[sliced[q]] = (int)q;
+  std::vector<sqc_cut> rest;
+  for (size_t k = 0; k < g.cuts.size(); ++k)
+    if (which[k] < 0) rest.push_back(g.cuts[k]);
+  const Graph g2 = build_topology(g.n_sub, rest.data(), (int32_t)rest.size());
+  sr.con = plan_for(g2, rp.abits, prec);
+  const size_t eb = prec == SQC_F64 ? 8 : 4;
+  Bump b;
+  sr.fixed.resize(g.n_sub);
+  for (int i = 0; i < g.n_sub; ++i) {
+    const std::vector<int> &inc = g.subs[i].inc;
+    for (size_t j = 0; j < inc.size(); ++j)
+      if (which[inc[j]] >= 0) sr.fixed[i].push_back({(int)j, which[inc[j]]});
+    const int kept = (int)inc.size() - (int)sr.fixed[i].size();
+    sr.merged_off.push_back(b.take((size_t(1) << (2 * kept + rp.abits[i])) * eb));
+  }
+  for (int i = 0; i < g.n_sub; ++i) {
+    const int kept = (int)g.subs[i].inc.size() - (int)sr.fixed[i].size();
+    const int64_t pe = merge_partial_elems(rp.abits[i], 2 * kept, __builtin_popcountll(rp.masks[i].merged));
+    sr.partial_off.push_back(pe ? b.take((size_t)pe * sizeof(double)) : 0);
+  }
+  int abits = 0;
+  for (int a : rp.abits) abits += a;
+  sr.sum_off = b.take((size_t(1) << abits) * sizeof(double));
+  sr.comp_off = b.take((size_t(1) << abits) * sizeof(double));
+  sr.con_base = b.off;
+  sr.total = b.off + contraction_ws(sr.con, top_r, true, prec);
+  return sr;
+}
+
+// The cuts a recursion slices to fit `budget` bytes of workspace: none when
+// the unsliced plan fits, else, as Sec. 6.3 does for memory, repeatedly the
+// cut whose removal shrinks the merged inputs' total size the most until the
+// sliced layout fits.  Ties go to the higher cut id: label digits follow the
+// incident cuts in id order, so the higher digits are sliced first and each
+// slice's label rows stay long contiguous runs of the attributed tensors
+// (labels are their fastest index).  SQC_E_NOMEM when SQC_MAX_SLICED cuts
+// do not suffice.
+std::vector<int> choose_slices(const Graph &g, const sqc_tensor *att, const RecursePlan &rp, sqc_prec prec,
+                               int top_r, size_t budget, size_t *need) {
+  std::vector<int> sliced;
+  *need = rp.total;
+  if (rp.total <= budget) return sliced;
+  std::vector<std::vector<int>> labs(g.n_sub);
+  for (int i = 0; i < g.n_sub; ++i) labs[i] = g.subs[i].inc;
+  std::vector<bool> gone(g.cuts.size(), false);
+  auto floats = [&](int drop) {
+    double t = 0;
+    for (int i = 0; i < g.n_sub; ++i) {
+      int c = 0;
+      for (int k : labs[i]) c += !gone[k] && k != drop;
+      t += std::ldexp(1.0, 2 * c + rp.abits[i]);
+    }
+    return t;
+  };
+  while (sliced.size() < (size_t)SQC_MAX_SLICED) {
+    int best = -1;
+    double best_t = 0;
+    for (size_t k = 0; k < g.cuts.size(); ++k) {
+      if (gone[k]) continue;
+      const double t = floats((int)k);
+      if (best < 0 || t <= best_t) {  // (k ascending: the higher id wins a tie)
+        best = (int)k;
+        best_t = t;
+      }
+    }
+    if (best < 0) break;
+    gone[best] = true;
+    sliced.push_back(best);
+    const size_t n = layout_sliced(g, att, rp, sliced, prec, top_r).total;
+    *need = n;
+    if (n <= budget) return sliced;
+  }
+  std::ostringstream m;
+  m << "the recursion needs " << rp.total << " bytes of workspace unsliced and " << *need << " with "
+    << sliced.size() << " sliced cut(s), above the " << budget << " bytes available";
+  raise(SQC_E_NOMEM, m.str());
+}
+
+// Enqueue a sliced recursion: 4^s slices, each its merges and contraction.
+void enqueue_sliced_recursion(sqc_ctx *ctx, const SlicedRecursion &sr, const sqc_tensor *att, sqc_prec prec,
+                              void *bins, sqc_prec bins_prec, int top_r, void *top_dev, void *sum_dev) {
+  const int n_sub = (int)sr.rp.masks.size();
+  const int path_f32 = prec != SQC_F64;
+  const int64_t nslices = int64_t(1) << (2 * sr.sliced.size());
+  std::vector<const void *> inputs(n_sub);
+  for (int i = 0; i < n_sub; ++i) inputs[i] = ctx->ws + sr.merged_off[i];
+  for (int64_t q = 0; q < nslices; ++q) {
+    Launches L;
+    for (int i = 0; i < n_sub; ++i) {
+      const auto &fx = sr.fixed[i];
+      if (fx.empty() && q > 0) continue;  // merged once
+      MergeArgs a = merge_args(att[i], sr.rp.masks[i], ctx->ws + sr.merged_off[i], path_f32,
+                               reinterpret_cast<double *>(ctx->ws + sr.partial_off[i]));
+      if (!fx.empty()) {
+        // output label s' keeps the unsliced digits in order; the sliced
+        // digits take this slice's values
+        const int deg = att[i].n_labels;
+        a.lbits = 2 * (deg - (int)fx.size());
+        a.lab_fixed = 0;
+        a.lab_keep = (uint64_t(1) << (2 * deg)) - 1;
+        for (const auto &f : fx) {
+          a.lab_fixed |= (uint64_t)((q >> (2 * f.second)) & 3) << (2 * f.first);
+          a.lab_keep &= ~(uint64_t(3) << (2 * f.first));
+        }
+      }
+      L.merges.push_back(a);
+    }
+    SliceAcc acc;
+    acc.mode = q == 0 ? 1 : q == nslices - 1 ? 3 : 2;
+    acc.sum = reinterpret_cast<double *>(ctx->ws + sr.sum_off);
+    acc.comp = reinterpret_cast<double *>(ctx->ws + sr.comp_off);
+    const bool last = q == nslices - 1;
+    describe_contraction(L, sr.con, inputs, ctx->ws, ctx->unit, sr.con_base, bins, bins_prec == SQC_F32, prec,
+                         top_r, last ? top_dev : nullptr, last ? sum_dev : nullptr, acc);
+    run_direct(ctx, L);
+  }
 }
 
 // ---- precision selection: the certified bound B >= max_x sum_sigma prod_i
@@ -931,8 +1111,9 @@ namespace {
 
 // A sliced contraction: the network without the sliced cuts, how each
 // subcircuit's rows are gathered for a slice, and the workspace layout
-// (after the sliced network's intermediates: gathered operands, slice bins,
-// running sums, compensations).
+// (after the sliced network's intermediates: gathered operands, FP64 running
+// sums and their compensations, which the final step of every slice adds
+// into).
 struct SlicedPlan {
   std::vector<sqc_cut> rest;
   Contraction con;
@@ -941,7 +1122,7 @@ struct SlicedPlan {
   std::vector<std::vector<std::pair<int, int>>> fixed;
   std::vector<int> degree;
   std::vector<size_t> gather_off;
-  size_t bins_off = 0, sum_off = 0, comp_off = 0, total = 0;
+  size_t sum_off = 0, comp_off = 0, total = 0;
   int64_t nbins = 0;
 };
 
@@ -984,9 +1165,10 @@ SlicedPlan plan_sliced(const sqc_tensor *merged, int32_t n_sub, const sqc_cut *c
     }
   }
   sp.nbins = int64_t(1) << abits;
-  sp.bins_off = b.take((size_t)sp.nbins * 8);
-  sp.sum_off = b.take((size_t)sp.nbins * 8);
-  sp.comp_off = b.take((size_t)sp.nbins * 8);
+  if (n_sliced > 0) {
+    sp.sum_off = b.take((size_t)sp.nbins * 8);
+    sp.comp_off = b.take((size_t)sp.nbins * 8);
+  }
   sp.total = b.off;
   return sp;
 }
@@ -1928,11 +2110,15 @@ sqc_status sqc_contract_sliced(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n
   need_ws(ctx, sp.total);
   use_device(ctx);
   const size_t elem = prec == SQC_F64 ? 8 : 4;
-  double *bins = reinterpret_cast<double *>(ctx->ws + sp.bins_off);
   double *sum = reinterpret_cast<double *>(ctx->ws + sp.sum_off);
   double *comp = reinterpret_cast<double *>(ctx->ws + sp.comp_off);
   const int64_t nslices = int64_t(1) << (2 * n_sliced);
   std::vector<const void *> inputs(n_sub);
+  if (nslices == 1) {  // nothing sliced: the plain contraction
+    for (int i = 0; i < n_sub; ++i) inputs[i] = merged[i].data;
+    enqueue_contraction(ctx, sp.con, inputs, kCtlBytes, bins_dev, bins_prec == SQC_F32, prec, 0, nullptr, nullptr);
+    return SQC_OK;
+  }
   for (int64_t q = 0; q < nslices; ++q) {
     {
       StageMark mark(ctx, SQC_STAGE_MERGE, 0.0, 0.0);
@@ -1948,14 +2134,14 @@ sqc_status sqc_contract_sliced(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n
       }
       mark.done();
     }
-    enqueue_contraction(ctx, sp.con, inputs, kCtlBytes, bins, 0, prec, 0, nullptr, nullptr);
-    {
-      StageMark mark(ctx, SQC_STAGE_CONTRACT, 0.0, 0.0);
-      launch_slice_accumulate(bins, sum, comp, bins_dev, bins_prec == SQC_F32, q == 0, q == nslices - 1, sp.nbins,
-                              ctx->stream);
-      after_launch("slice accumulate launch");
-      mark.done();
-    }
+    SliceAcc acc;
+    acc.mode = q == 0 ? 1 : q == nslices - 1 ? 3 : 2;
+    acc.sum = sum;
+    acc.comp = comp;
+    Launches L;
+    describe_contraction(L, sp.con, inputs, ctx->ws, ctx->unit, kCtlBytes, bins_dev, bins_prec == SQC_F32, prec, 0,
+                         nullptr, nullptr, acc);
+    run_direct(ctx, L);
   }
   return SQC_OK;
   SQC_CATCH(ctx)
@@ -2066,12 +2252,41 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
   if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
   degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
   RecursePlan rp = plan_recursion(g, attributed, scope, max_bins_M, top_r, prec, ctx_plans(ctx));
-  need_ws(ctx, rp.total);
+  if (!ctx->ws) need_ws(ctx, rp.total);
+  size_t need = 0;
+  const std::vector<int> sl = choose_slices(g, attributed, rp, prec, top_r, ctx->ws_bytes, &need);
   use_device(ctx);
-  enqueue_recursion(ctx, rp, attributed, prec, bins_dev, bins_prec, top_r, topr_dev, sum_dev);
+  if (sl.empty())
+    enqueue_recursion(ctx, rp, attributed, prec, bins_dev, bins_prec, top_r, topr_dev, sum_dev);
+  else
+    enqueue_sliced_recursion(ctx, layout_sliced(g, attributed, rp, sl, prec, top_r), attributed, prec, bins_dev,
+                             bins_prec, top_r, topr_dev, sum_dev);
   if (masks_out) std::copy(rp.masks.begin(), rp.masks.end(), masks_out);
   return SQC_OK;
   SQC_CATCH(ctx)
+}
+
+sqc_status sqc_recurse_slices(const sqc_tensor *attributed, int32_t n_sub, const sqc_cut *cuts, int32_t n_cuts,
+                              const sqc_masks *masks, sqc_prec prec, int32_t top_r, size_t workspace_bytes,
+                              int32_t *sliced, int32_t *n_sliced, size_t *need_bytes) {
+  try {
+  Graph g = build_topology(n_sub, cuts, n_cuts);
+  if (!attributed || !masks || !sliced || !n_sliced) raise(SQC_E_ARG, "NULL argument");
+  check_path_prec(prec);
+  if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
+  degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+  RecursePlan rp = plan_from_masks(g, attributed, masks, top_r, prec);
+  size_t need = 0;
+  const std::vector<int> sl = choose_slices(g, attributed, rp, prec, top_r, workspace_bytes, &need);
+  std::copy(sl.begin(), sl.end(), sliced);
+  *n_sliced = (int32_t)sl.size();
+  if (need_bytes) *need_bytes = need;
+  set_thread_error("");
+  return SQC_OK;
+  } catch (const Error &e) {
+    set_thread_error(e.msg);
+    return e.code;
+  }
 }
 
 sqc_status sqc_ctx_set_tolerance(sqc_ctx *ctx, double max_abs_error) {

@@ -156,7 +156,18 @@ struct MergeArgs {
   int64_t grid_x;   // work-groups along the outputs (set by the launcher)
   int64_t blocks;   // work-groups of the main pass
   int64_t fin_blocks;  // work-groups of the partial-sum pass (0: none)
+  // label rows of one slice (first-level slicing): the input rows hold
+  // 2^in_lbits labels, and output label s reads input label
+  // lab_fixed | deposit(s, lab_keep).  Unsliced: in_lbits = lbits,
+  // lab_fixed = 0, lab_keep = 2^lbits - 1.
+  int in_lbits;
+  uint64_t lab_fixed, lab_keep;
 };
+// Labels a merge_rows thread reads as one vector: 4 consecutive output labels
+// are 4 consecutive input labels when the lowest label digit is kept.
+__host__ __device__ inline int merge_vec(const MergeArgs &a) {
+  return a.lbits >= 2 && (a.in_lbits == a.lbits || (a.lab_keep & 3) == 3) ? 4 : 1;
+}
 // Merges launched together (at most this many per launch; more are split).
 constexpr int kMergeJobs = 8;
 // Enqueue n merges; jobs with merged bits >= 6 need their own partial buffer.
@@ -189,6 +200,13 @@ struct GemmArgs {
   double *wg_stats;      // [3 * work-groups] per work-group: FP64 sum, its
                          // compensation, largest stored bin (work-group g owns
                          // a contiguous chunk of the tiles, chunks in order)
+  // slices of a sliced contraction (final step only): the result is added
+  // into FP64 running sums acc_sum/acc_comp (laid out as C) with Neumaier
+  // compensation.  1: the first slice starts them; 2: a later slice adds;
+  // 3: the last slice adds and writes sum + compensation to C (statistics
+  // from the written values).  0: plain store.
+  int acc_mode;
+  double *acc_sum, *acc_comp;
   // filled by launch_gemm: offsets of the low index bits the kernel adds to
   // a wave's origin (index maps are linear in disjoint bit fields)
   int64_t koff_a[16];    // A offset of k = 0..15
@@ -210,11 +228,12 @@ int launch_gemm(const GemmArgs &g, int prec, hipStream_t s);
 struct GemmSpec {
   int prec;
   bool fold, outf;
-  int reg;  // 0 general, 1 regular shape, 2 regular with single-run index maps
+  int reg;  // 0 general, 1 regular shape, 2 regular with single-run index
+            // maps, 3 general with the slice-accumulating epilogue
 };
 // ...chosen after filling g's offset tables,
 GemmSpec prepare_gemm(GemmArgs &g, int prec);
-// a dense id of it (0 .. 35),
+// a dense id of it (0 .. 47),
 int gemm_spec_id(const GemmSpec &sp);
 // the work-groups launch_gemm would use (results, including the work-group
 // statistics, depend on this count),
@@ -293,9 +312,5 @@ struct SliceArgs {
   int lo[SQC_MAX_SLICED + 1], len[SQC_MAX_SLICED + 1], pos[SQC_MAX_SLICED + 1];
 };
 void launch_slice_rows(const SliceArgs &a, hipStream_t s);
-// sum/comp (n FP64 each) += bins with Neumaier compensation; `first` starts
-// them, `last` writes sum + comp to out (FP32 when out_f32) instead.
-void launch_slice_accumulate(const double *bins, double *sum, double *comp, void *out, int out_f32, int first,
-                             int last, int64_t n, hipStream_t s);
 
 }  // namespace sqc

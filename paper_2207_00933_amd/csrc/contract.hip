@@ -149,9 +149,13 @@ __device__ __forceinline__ Sched schedule(int ntiles, int b, int G) {
 // One work-group `blk` of G working on the GEMM `g`.
 // REG = 2 adds: every index map is a single run of bits, so each offset is
 // one shift (no loop over runs in the per-tile address arithmetic).
+// REG = 3: general index maps, and the final step of one slice of a sliced
+// contraction adds its result into FP64 running sums (GemmArgs::acc_mode).
 template <int PREC, bool FOLD, bool OUTF, int REG>
 __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
-  constexpr bool SIMPLE = REG == 2;
+  constexpr bool ACC = REG == 3;  // slice-accumulating epilogue
+  constexpr int RG = ACC ? 0 : REG;  // index-map class
+  constexpr bool SIMPLE = RG == 2;
   auto mx = [&](const IndexMap &mp, uint32_t v) -> int64_t {
     if constexpr (SIMPLE) return (int64_t)v << mp.lx[0];
     else return map_x(mp, v);
@@ -231,7 +235,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   T av[NJ], bv[NJ];
   // k offsets of rows j = 0..15: shifts when the lowest run of k spans >= 4
   // bits (the usual case), else a table staged in LDS
-  const bool kfast = REG || (g.k.nruns >= 1 && g.k.bits[0] >= 4);
+  const bool kfast = RG || (g.k.nruns >= 1 && g.k.bits[0] >= 4);
   const int sa = g.k.lx[0], sb = g.k.ly[0];
   __shared__ int64_t ktab[2][NJ];
   if (!kfast) {
@@ -242,7 +246,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
     __syncthreads();
   }
   // a full K stage needs no per-row bound; rows past K (K < 64) read offset 0
-  const bool kfull = REG || g.kbits >= 6;
+  const bool kfull = RG || g.kbits >= 6;
   auto load_rows = [&](const T *p, T *v, int which, int s_shift, uint32_t k0) {
     if (kfull && kfast) {
       // (the row step passes an empty asm statement, so its 16 multiples are
@@ -268,7 +272,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   auto load_a = [&](int tile, int ks) {
     const uint32_t m0 = tile_m(tile) << 6;
     const uint32_t k0 = (uint32_t)ks << 6;
-    const bool ok = REG || m0 + lane < M;  // columns past M read the column origin
+    const bool ok = RG || m0 + lane < M;  // columns past M read the column origin
     const T *p = static_cast<const T *>(g.A) + (mx(g.m, m0) + mx(g.k, k0) + a_kw) + (ok ? a_lane : 0);
     load_rows(p, av, 0, sa, k0);
     if (!ok)
@@ -278,7 +282,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   auto load_b = [&](int tile, int ks) {
     const uint32_t n0 = tile_n(tile) << 6;
     const uint32_t k0 = (uint32_t)ks << 6;
-    const bool ok = REG || n0 + lane < N;
+    const bool ok = RG || n0 + lane < N;
     const T *p = static_cast<const T *>(g.B) + (mx(g.n, n0) + my(g.k, k0) + b_kw) + (ok ? b_lane : 0);
     load_rows(p, bv, 1, sb, k0);
     if (!ok)
@@ -404,7 +408,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
     }
     // ---- MFMA on the staged stage ----
     const uint32_t k0 = (uint32_t)cur_ks << 6;
-    const int kend = (REG || (K - k0) >= (uint32_t)BK) ? BK : (int)(K - k0);
+    const int kend = (RG || (K - k0) >= (uint32_t)BK) ? BK : (int)(K - k0);
     if (kend == BK) {
 #pragma unroll
       for (int kk = 0; kk < BK / KSTEP; ++kk) mfma_step(kk);
@@ -419,17 +423,37 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
       typedef typename std::conditional<OUTF, float, double>::type O;
       double lsum = 0.0;
       O lmax = -INFINITY;
-      if (REG || (mw < M && nw < N)) {
+      if (RG || (mw < M && nw < N)) {
         const int64_t cw = my(g.m, mw) + my(g.n, nw);
         O *C = static_cast<O *>(g.C) + cw + c_lane_m + c_lane_n;
+        double *AS = nullptr, *AC = nullptr;
+        if constexpr (ACC) {
+          AS = g.acc_sum + cw + c_lane_m + c_lane_n;
+          AC = g.acc_comp + cw + c_lane_m + c_lane_n;
+        }
         // with M, N >= 32 every element of a wave inside the result is inside
-        const bool whole = REG || (g.mbits >= 5 && g.nbits >= 5);
+        const bool whole = RG || (g.mbits >= 5 && g.nbits >= 5);
         O omax = -INFINITY;
         // FP32 results go out as non-temporal stores (the FP32 and
         // split-BF16x3 steps measured faster so), FP64 results as ordinary
         // stores (non-temporal measured slower there)
         auto put = [&](uint32_t mloc, uint32_t nloc, int64_t o, double v) {
           if (!whole && (mw + mloc >= M || nw + nloc >= N)) return;
+          if constexpr (ACC) {
+            if (g.acc_mode == 1) {
+              AS[o] = v;
+              AC[o] = 0.0;
+              return;
+            }
+            double sm = AS[o], cp = AC[o];
+            neumaier(sm, cp, v);
+            if (g.acc_mode == 2) {
+              AS[o] = sm;
+              AC[o] = cp;
+              return;
+            }
+            v = sm + cp;
+          }
           const O st = (O)v;
           if constexpr (OUTF) __builtin_nontemporal_store(st, C + o);
           else C[o] = st;
@@ -1132,6 +1156,7 @@ int resident_groups() {
 // Calls L::run<PREC, FOLD, OUTF, REG>() for the specialisation `sp`.
 template <int PREC, bool FOLD, bool OUTF, class L>
 int dispatch_r(const GemmSpec &sp, const L &l) {
+  if (sp.reg == 3) return l.template run<PREC, FOLD, OUTF, 3>();
   if (sp.reg == 2) return l.template run<PREC, FOLD, OUTF, 2>();
   if (sp.reg == 1) return l.template run<PREC, FOLD, OUTF, 1>();
   return l.template run<PREC, FOLD, OUTF, 0>();
@@ -1205,12 +1230,12 @@ GemmSpec prepare_gemm(GemmArgs &g, int prec) {
   sp.outf = g.out_f32 != 0;
   const bool regular = g.mbits >= 6 && g.nbits >= 6 && g.kbits >= 6 && g.k.nruns >= 1 && g.k.bits[0] >= 4;
   const bool simple = g.m.nruns == 1 && g.n.nruns == 1 && g.k.nruns == 1;
-  sp.reg = regular ? (simple ? 2 : 1) : 0;
+  sp.reg = g.acc_mode ? 3 : regular ? (simple ? 2 : 1) : 0;
   return sp;
 }
 
 int gemm_spec_id(const GemmSpec &sp) {
-  return ((sp.prec * 2 + (sp.fold ? 1 : 0)) * 2 + (sp.outf ? 1 : 0)) * 3 + sp.reg;
+  return ((sp.prec * 2 + (sp.fold ? 1 : 0)) * 2 + (sp.outf ? 1 : 0)) * 4 + sp.reg;
 }
 
 int gemm_groups(const GemmArgs &g, const GemmSpec &sp) { return dispatch(sp, GroupsQuery{gemm_tiles(g)}); }

@@ -65,10 +65,12 @@ __device__ __forceinline__ void merge_tiles_body(const MergeArgs &a, int64_t til
   const int g = r / RB;
 
   const int64_t L = int64_t(1) << a.lbits;
+  const int64_t Lin = int64_t(1) << a.in_lbits;
   const int lsig_tiles = a.lbits - a.ts_bits;
   const int st = (int)(tile_id & ((int64_t(1) << lsig_tiles) - 1));
   const int64_t bt = tile_id >> lsig_tiles;
   const int64_t sigma = (int64_t(st) << a.ts_bits) + sl;
+  const int64_t sigma_in = a.in_lbits == a.lbits ? sigma : (int64_t)(a.lab_fixed | deposit((uint64_t)sigma, a.lab_keep));
   const int64_t b0 = bt << a.tb_bits;
 
   const int64_t ny = int64_t(1) << (a.mbits - a.ysplit_bits);  // y per work-group
@@ -91,7 +93,7 @@ __device__ __forceinline__ void merge_tiles_body(const MergeArgs &a, int64_t til
   for (int64_t y = g; y < ny; y += YG) {
     int64_t off[kMaxBPT];
 #pragma unroll
-    for (int i = 0; i < kMaxBPT; ++i) off[i] = i < BPT ? (int64_t)(xb[i] | z) * L + sigma : 0;
+    for (int i = 0; i < kMaxBPT; ++i) off[i] = i < BPT ? (int64_t)(xb[i] | z) * Lin + sigma_in : 0;
     if (a.in_f32) {
       const float *in = static_cast<const float *>(a.in);
       float v[kMaxBPT];
@@ -148,13 +150,17 @@ __device__ __forceinline__ void merge_tiles_body(const MergeArgs &a, int64_t til
 // states, four rows per iteration so that several loads are in flight.  The
 // work-group's FP64 partial sums go to partial[p][c].
 __device__ __forceinline__ void merge_rows_body(const MergeArgs &a, int64_t bx, int p) {
-  const int V = a.lbits >= 2 ? 4 : 1;
+  const int V = merge_vec(a);
   const int64_t L = int64_t(1) << a.lbits;
   const int64_t NC = int64_t(1) << (a.abits + a.lbits);
   const int64_t c0 = (bx * kThreads + threadIdx.x) * V;
   if (c0 >= NC) return;
   const int64_t b = c0 >> a.lbits;
-  const int64_t sigma = c0 & (L - 1);
+  const int64_t sigma_out = c0 & (L - 1);
+  // input label of the first of the V labels (the V are consecutive there)
+  const int64_t sigma =
+      a.in_lbits == a.lbits ? sigma_out : (int64_t)(a.lab_fixed | deposit((uint64_t)sigma_out, a.lab_keep));
+  const int64_t Lin = int64_t(1) << a.in_lbits;
   const uint64_t xb = a.fixed_val | deposit_run((uint64_t)b, a.active, a.act_lo);
   const int64_t ny = int64_t(1) << (a.mbits - a.ysplit_bits);
   const uint64_t nmerged = ~a.merged;
@@ -166,7 +172,7 @@ __device__ __forceinline__ void merge_rows_body(const MergeArgs &a, int64_t bx, 
     for (; y + 4 <= ny; y += 4) {
       int64_t r[4];
       for (int u = 0; u < 4; ++u) {
-        r[u] = (int64_t)(xb | z) * L + sigma;
+        r[u] = (int64_t)(xb | z) * Lin + sigma;
         z = ((z | nmerged) + 1) & a.merged;
       }
       if (V == 4) {
@@ -182,7 +188,7 @@ __device__ __forceinline__ void merge_rows_body(const MergeArgs &a, int64_t bx, 
       }
     }
     for (; y < ny; ++y) {
-      int64_t r0 = (int64_t)(xb | z) * L + sigma;
+      int64_t r0 = (int64_t)(xb | z) * Lin + sigma;
       z = ((z | nmerged) + 1) & a.merged;
       for (int q = 0; q < V; ++q) acc[q] += in[r0 + q];
     }
@@ -191,7 +197,7 @@ __device__ __forceinline__ void merge_rows_body(const MergeArgs &a, int64_t bx, 
     for (; y + 4 <= ny; y += 4) {
       int64_t r[4];
       for (int u = 0; u < 4; ++u) {
-        r[u] = (int64_t)(xb | z) * L + sigma;
+        r[u] = (int64_t)(xb | z) * Lin + sigma;
         z = ((z | nmerged) + 1) & a.merged;
       }
       if (V == 4) {
@@ -210,7 +216,7 @@ __device__ __forceinline__ void merge_rows_body(const MergeArgs &a, int64_t bx, 
       }
     }
     for (; y < ny; ++y) {
-      int64_t r0 = (int64_t)(xb | z) * L + sigma;
+      int64_t r0 = (int64_t)(xb | z) * Lin + sigma;
       z = ((z | nmerged) + 1) & a.merged;
       for (int q = 0; q < V; ++q) acc[q] += in[r0 + q];
     }
@@ -248,7 +254,7 @@ __device__ __forceinline__ void merge_finish_body(const MergeArgs &a, int64_t bl
 void shape_merge(MergeArgs &a) {
   if (a.mbits >= 6) {
     // streaming reduction over many merged states, then the partial sums
-    const int V = a.lbits >= 2 ? 4 : 1;
+    const int V = merge_vec(a);
     int64_t NC = int64_t(1) << (a.abits + a.lbits);
     int64_t bx = (NC / V + kThreads - 1) / kThreads;
     int ys = 0;
@@ -402,6 +408,7 @@ int64_t merge_partial_elems(int abits, int lbits, int mbits) {
   MergeArgs a{};
   a.abits = abits;
   a.lbits = lbits;
+  a.in_lbits = lbits;  // vector loads: the most partials a slice's merge takes
   a.mbits = mbits;
   shape_merge(a);
   return (int64_t(1) << (abits + lbits)) << a.ysplit_bits;

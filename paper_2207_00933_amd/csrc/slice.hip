@@ -11,9 +11,8 @@
 // 2^n_bits elements: copied in 16-byte units when a row holds at least 16
 // bytes, else in 4-byte words.
 //
-// slice_accumulate: add one slice's FP64 bins into FP64 running sums with
-// Neumaier compensation (the first slice starts them, the last writes
-// sum + compensation in the output precision).
+// The slices' bin vectors are added by the final contraction step itself
+// (its slice-accumulating epilogue), so no slice vector is stored.
 #include "common.hpp"
 
 namespace sqc {
@@ -53,33 +52,6 @@ __global__ __launch_bounds__(kThreads) void slice_rows4(SliceArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kThreads) void slice_accumulate(const double *__restrict__ bins, double *sum,
-                                                             double *comp, void *out, int out_f32,
-                                                             int first, int last, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += int64_t(gridDim.x) * kThreads) {
-    const double v = bins[i];
-    double s, c;
-    if (first) {
-      s = v;
-      c = 0.0;
-    } else {
-      s = sum[i];
-      c = comp[i];
-      const double t = s + v;
-      c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
-      s = t;
-    }
-    if (last) {
-      const double r = s + c;
-      if (out_f32) __builtin_nontemporal_store((float)r, static_cast<float *>(out) + i);
-      else static_cast<double *>(out)[i] = r;
-    } else {
-      sum[i] = s;
-      comp[i] = c;
-    }
-  }
-}
-
 int grid_for(int64_t units) {
   const int64_t g = (units + kThreads - 1) / kThreads;
   return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
@@ -98,13 +70,6 @@ void launch_slice_rows(const SliceArgs &a, hipStream_t s) {
     b.row_shift = a.row_bytes_log2 - 2;
     hipLaunchKernelGGL(slice_rows4, dim3(grid_for(b.rows << b.row_shift)), dim3(kThreads), 0, s, b);
   }
-}
-
-void launch_slice_accumulate(const double *bins, double *sum, double *comp, void *out, int out_f32, int first,
-                             int last, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(slice_accumulate, dim3(grid_for(n)), dim3(kThreads), 0, s, bins, sum, comp, out, out_f32,
-                     first, last, n);
 }
 
 }  // namespace sqc

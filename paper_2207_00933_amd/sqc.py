@@ -160,6 +160,9 @@ def lib():
                                          POINTER(c_uint64), ctypes.c_int64, c_int, P, c_int]),
             "sqc_recurse_workspace_bytes": (c_size_t, [POINTER(Tensor), c_int32, POINTER(Cut),
                                                        c_int32, POINTER(Masks), c_int]),
+            "sqc_recurse_slices": (c_int, [POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
+                                           POINTER(Masks), c_int, c_int32, c_size_t, POINTER(c_int32),
+                                           POINTER(c_int32), POINTER(c_size_t)]),
             "sqc_recurse": (c_int, [P, POINTER(Tensor), c_int32, POINTER(Cut), c_int32,
                                     POINTER(Masks), c_uint64, c_int32, c_int, P, c_int,
                                     POINTER(Masks), P, P]),
@@ -463,6 +466,20 @@ def recurse_workspace_bytes(att: Sequence[Tensor], g: Graph, masks, prec: int) -
     arr = tensor_array(att)
     m = masks_array(masks)
     return int(lib().sqc_recurse_workspace_bytes(arr, g.n_sub, g.cuts, g.n_cuts, m, prec))
+
+
+def recurse_slices(att: Sequence[Tensor], g: Graph, masks, prec: int, top_r: int,
+                   workspace_bytes: int):
+    """Cuts sqc_recurse slices under a workspace of that size (Sec. 6.3):
+    (cut ids in slice-digit order, bytes the chosen layout needs)."""
+    arr = tensor_array(att)
+    m = masks_array(masks)
+    sl = (c_int32 * MAX_SLICED)()
+    ns = c_int32()
+    need = c_size_t()
+    _check(lib().sqc_recurse_slices(arr, g.n_sub, g.cuts, g.n_cuts, m, prec, top_r, int(workspace_bytes), sl,
+                                    ctypes.byref(ns), ctypes.byref(need)))
+    return list(sl[:ns.value]), int(need.value)
 
 
 def recurse(ctx: int, att: Sequence[Tensor], g: Graph, scope, M: int, top_r: int, prec: int,

@@ -211,8 +211,11 @@ def _sliced_descs(bits, cuts, prec):
 
 
 def test_sliced_workspace_layout():
-    """Host planning of a sliced contraction (Sec. 6.3): the workspace covers
-    the sliced network, the gathered operands and three FP64 bin vectors."""
+    """Host planning of a sliced contraction (Sec. 6.3): the workspace is the
+    sliced network's, the gathered operands and, when something is sliced, two
+    FP64 bin vectors (running sums and compensations; the final step adds each
+    slice into them, so no slice vector is stored), up to 256-byte
+    alignment."""
     bits, cuts = [5, 3, 4], [(0, 1), (0, 1), (1, 2), (1, 2), (1, 2)]
     for prec in (sqc.F64, sqc.F32, sqc.BF16X3):
         g, descs, _ = _sliced_descs(bits, cuts, prec)
@@ -227,11 +230,11 @@ def test_sliced_workspace_layout():
                 s = sum(1 for k in sliced if i in cuts[k])
                 if s:
                     gathered += ((4 ** (deg - s)) << bits[i]) * elem
-            assert ws >= gathered + 3 * nb * 8
-            # the sliced network's own workspace is part of it
+            sums = 2 * nb * 8 if sliced else 0
             rest = [c for k, c in enumerate(cuts) if k not in sliced]
             g2, d2, _ = _sliced_descs(bits, rest, prec)
-            assert ws >= sqc.contract_workspace_bytes(d2, g2, prec) + gathered + 3 * nb * 8
+            own = sqc.contract_workspace_bytes(d2, g2, prec)
+            assert own + gathered + sums <= ws <= own + gathered + sums + 256 * 6
 
 
 @pytest.mark.parametrize("sliced", [[0, 0], [5], [-1], list(range(5)) + [0, 1, 2, 3]])
@@ -290,3 +293,47 @@ def test_search_workspace_covers_every_depth():
     bad = list(descs)
     bad[1] = sqc.tensor_desc(torch.zeros(1), 1, g.n_data[1], sqc.F32, sqc.LAYOUT_ATTRIBUTED)
     assert sqc.search_workspace_bytes(bad, g, M, 12, sqc.BF16X3) == 0
+
+
+def _deg10_descs(prec):
+    """Two subcircuits joined by ten cuts (degree 10 each; 3 and 4 data
+    bits), attributed layout; host planning only, so the buffers are dummies."""
+    import torch
+    bits, cuts = [3, 4], [(0, 1)] * 10
+    g = sqc.Graph([1, 1], [[], []], [(u, 0, v, 0) for u, v in cuts])
+    dummy = torch.zeros(1, dtype=torch.float64)
+    descs = [sqc.tensor_desc(dummy, 10, b, sqc.F64 if prec == sqc.F64 else sqc.F32, sqc.LAYOUT_ATTRIBUTED)
+             for b in bits]
+    return g, descs, bits, dummy
+
+
+@pytest.mark.parametrize("prec", [sqc.F64, sqc.F32, sqc.BF16X3])
+def test_recursion_slices_by_memory(prec):
+    """Memory-driven slicing of a recursion (Sec. 6.3): nothing is sliced when
+    the unsliced plan fits; under a smaller workspace the chooser slices the
+    fewest cuts (greedy: largest shrink of the merged inputs, the higher id
+    on ties; here every cut ties) whose layout fits, reports a need within the
+    budget and below the unsliced need; SQC_E_NOMEM when even SQC_MAX_SLICED
+    cuts do not fit."""
+    g, descs, bits, _ = _deg10_descs(prec)
+    M = 1 << 5
+    masks = sqc.assign_bins(bits, None, M)
+    assert [bin(m.active).count("1") for m in masks] == [2, 3]
+    full = sqc.recurse_workspace_bytes(descs, g, masks, prec)
+    sl, need = sqc.recurse_slices(descs, g, masks, prec, sqc.MAX_TOPR, full)
+    assert sl == [] and need == full
+    eb = 8 if prec == sqc.F64 else 4
+    merged = ((4 ** 10) << 2) * eb + ((4 ** 10) << 3) * eb
+    assert full >= merged
+    budget = 16 << 20
+    assert full > budget
+    sl, need = sqc.recurse_slices(descs, g, masks, prec, 16, budget)
+    s = len(sl)
+    assert sl == list(range(9, 9 - s, -1)) and need <= budget < full
+    # the layout: each subcircuit's slice of merged rows, two 2^5 FP64 vectors
+    assert need >= (merged >> (2 * s)) + 2 * M * 8
+    # one cut fewer would not fit: its merged rows alone exceed the budget
+    assert s >= 1 and (merged >> (2 * (s - 1))) > budget
+    with pytest.raises(sqc.SqcError) as e:
+        sqc.recurse_slices(descs, g, masks, prec, 16, 4096)
+    assert e.value.status == sqc.E_NOMEM

@@ -213,3 +213,69 @@ def test_contract_sliced_in_a_graph():
     finally:
         st.synchronize()
         s.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("pname,prec", PRECS)
+def test_recurse_sliced_by_memory_degree_ten(pname, prec):
+    """Memory-driven slicing inside a recursion (Sec. 6.3).  Two subcircuits
+    joined by ten cuts (degree 10, 4^10 labels; 3 and 4 data bits, random
+    signed entries), M = 2^5 so that each subcircuit also merges a bit.  The
+    unsliced recursion needs more than the context's 16 MiB workspace; the
+    sliced one fits, slices merged straight from the attributed tensors.
+    Every bin matches the oracle's sliced sum of the merged entries (and the
+    unsliced contraction) within the path's a-priori bound, and the top-R and
+    the bin sum are those of the returned bins."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import reconstruction as rc
+    from gpu_util import bins_from_masks
+    bits, cuts = [3, 4], [(0, 1)] * 10
+    cc = _View(2, cuts)
+    rng = np.random.default_rng(31 + prec)
+    Ts = [rng.standard_normal((4 ** 10, 1 << b)) for b in bits]
+    if prec != sqc.F64:
+        Ts = [T.astype(np.float32).astype(np.float64) for T in Ts]
+    g = sqc.Graph([1, 1], [[0] * b for b in bits], [(u, 0, v, 0) for u, v in cuts])
+    M = 1 << 5
+    masks = sqc.assign_bins(g.n_data, None, M)
+    groups = [bins_from_masks(masks[i], bits[i]) for i in range(2)]
+    merged = [rc.merge_entries(Ts[i], groups[i]) for i in range(2)]
+    budget = 16 << 20
+    aprec = sqc.F64 if prec == sqc.F64 else sqc.F32
+    dt = torch.float64 if aprec == sqc.F64 else torch.float32
+    bufs = [torch.from_numpy(np.ascontiguousarray(T.T)).to(dt).cuda() for T in Ts]  # [2^d][4^c]
+    att = [sqc.tensor_desc(b, 10, bits[i], aprec, sqc.LAYOUT_ATTRIBUTED) for i, b in enumerate(bufs)]
+    assert sqc.recurse_workspace_bytes(att, g, masks, prec) > budget
+    sliced, need = sqc.recurse_slices(att, g, masks, prec, 8, budget)
+    assert sliced and need <= budget
+    want = network.contract_sliced(merged, cc, sliced)
+    want_full = network.contract_all(merged, cc)
+    bound = network.contract_all([rc.merge_entries(np.abs(Ts[i]), groups[i]) for i in range(2)], cc)
+    say(f"sliced recursion {pname}: slices {sliced}, workspace {need} of {budget}")
+    s = runner.Session(0, budget)
+    try:
+        for bins_prec in (sqc.F64, sqc.F32):
+            bins = torch.full((M,), float("nan"), dtype=torch.float64 if bins_prec == sqc.F64 else torch.float32,
+                              device="cuda")
+            top = torch.empty(2 * 8, dtype=torch.float64, device="cuda")
+            bsum = torch.empty(1, dtype=torch.float64, device="cuda")
+            used = sqc.recurse(s.ctx, att, g, None, M, 8, prec, bins, bins_prec, top, bsum)
+            torch.cuda.synchronize()
+            assert [(m.active, m.merged) for m in used] == [(m.active, m.merged) for m in masks]
+            got = bins.double().cpu().numpy()
+            tol = TOL_REL[prec] * bound + (2.0 ** -24 * np.abs(want) if bins_prec == sqc.F32 else 0) + 1e-300
+            err = np.abs(got - want)
+            say(f"  bins {bins_prec}: max |gpu - oracle| {err.max():.3e} (bound {tol.min():.3e}..{tol.max():.3e})")
+            assert np.all(err <= tol)
+            assert np.all(np.abs(got - want_full) <= 2 * tol)
+            rec = top.cpu().numpy().view(np.uint64).reshape(-1, 2)
+            vals = top.cpu().numpy().reshape(-1, 2)[:, 0]
+            idx = rec[:, 1].astype(np.int64)
+            order = sorted(range(M), key=lambda k: (-got[k], k))[:8]
+            assert list(idx) == order and np.array_equal(vals, got[order])
+            # (the sum is taken over the FP64 values before they are stored)
+            rel = 2.0 ** -23 if bins_prec == sqc.F32 else 1e-12
+            assert abs(float(bsum.item()) - float(np.sum(got))) <= rel * float(np.sum(np.abs(got))) + 1e-300
+    finally:
+        s.close()
