@@ -601,8 +601,10 @@ sqc_status sqc_search(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
  * n_slots HIP streams (default priority), one context each, and the caller's
  * workspace buffer.  Requests are validated and planned by sqc_serve_submit.
  * Whenever a slot is idle, the waiting requests (in arrival order; a later
- * request that fits may pass an earlier one that does not) are shared among
- * the idle slots as batches, each limited by the largest free block of the
+ * request that fits may pass an earlier one that does not, but once a
+ * request has been passed over 8 times nothing behind it is admitted before
+ * it: aging, so a large request is not starved) are shared among the idle
+ * slots as batches, each limited by the largest free block of the
  * workspace; a batch runs as one set of launches whose kernels read the
  * requests' jobs from a table in device memory (merges, each GEMM level per
  * kernel specialisation, top-R), so a batch costs a few launches however many
@@ -636,6 +638,9 @@ typedef struct {
   int32_t max_batch;          /* most requests in one batch                  */
   uint64_t workspace_bytes, workspace_peak;  /* bytes in use, at most        */
   uint64_t batches;           /* batches launched                            */
+  double plan_seconds;        /* host time planning requests (submit)        */
+  double launch_seconds;      /* host time forming and enqueuing batches     */
+  uint64_t aged_holds;        /* batches cut short behind an aged request    */
 } sqc_serve_stats;
 
 /* Create a server on `device` with n_slots (1..64) streams using the caller's
@@ -658,6 +663,16 @@ size_t sqc_serve_footprint(sqc_server *srv, const sqc_request *req);
 /* Validate, plan and queue a request; SQC_E_NOMEM when its footprint exceeds
  * the whole workspace.  `ticket` identifies it in sqc_serve_poll / _wait. */
 sqc_status sqc_serve_submit(sqc_server *srv, const sqc_request *req, uint64_t *ticket);
+/* Submit n requests at once (a burst of arrivals): each is validated and
+ * planned as by sqc_serve_submit, then they are queued in order in shares
+ * of one batch per slot (the burst size over the slot count, at most the
+ * batch cap), the engine advancing after each share, so the burst leaves in
+ * full batches instead of the first requests leaving alone, and the first
+ * batches run while the rest are formed.  tickets[k] identifies
+ * reqs[k].  On an error (that of the first failing request) nothing is
+ * queued. */
+sqc_status sqc_serve_submit_many(sqc_server *srv, const sqc_request *reqs, int32_t n,
+                                 uint64_t *tickets);
 /* state: 0 waiting, 1 running, 2 done; an admission error is returned here. */
 sqc_status sqc_serve_poll(sqc_server *srv, uint64_t ticket, int32_t *state);
 /* Block until the request is done. */
@@ -668,6 +683,19 @@ sqc_status sqc_serve_wait(sqc_server *srv, uint64_t ticket);
  * A ticket handed out here is forgotten: later polls of it fail. */
 sqc_status sqc_serve_completed(sqc_server *srv, uint64_t *tickets, int32_t cap, int32_t *n);
 sqc_status sqc_serve_get_stats(sqc_server *srv, sqc_serve_stats *out);
+/* The engine's batching policy on its own (host only, no server needed), for
+ * tools and tests: n waiting requests in arrival order with their workspace
+ * and job-table bytes and skip counts; the batch takes requests while they
+ * fit `room` bytes (a batch of one needs no job table), at most max_batch; a
+ * request that does not fit may be passed by later ones, and one passed over
+ * 8 times or more stops the scan (*held = 1): nothing behind it is admitted
+ * first.  When a batch is formed, each request passed over gains one skip
+ * (skips is updated in place).  Writes the positions taken (ascending) to
+ * `picked` (capacity n) and their count to *n_picked (0: no batch).  Errors:
+ * SQC_E_ARG for NULL pointers, n < 0 or max_batch < 1. */
+sqc_status sqc_serve_pick_batch(const size_t *workspace_bytes, const size_t *table_bytes,
+                                int32_t *skips, int32_t n, size_t room, int32_t max_batch,
+                                int32_t *picked, int32_t *n_picked, int32_t *held);
 const char *sqc_serve_last_error(const sqc_server *srv);
 
 #ifdef __cplusplus

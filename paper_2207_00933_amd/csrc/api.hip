@@ -885,15 +885,30 @@ void enqueue_recursion(sqc_ctx *ctx, const RecursePlan &rp, const sqc_tensor *at
 
 namespace sqc {
 
+// The launches of one recursion shape, with every pointer relative: a
+// workspace offset (>= kCtlBytes), an offset into the device's unit constant
+// (< kCtlBytes, GEMM operands only), or null for the request's outputs, and
+// the fixed bits' values zero.  A request of that shape copies them and
+// fills in its workspace, outputs and fixed values (relocate()).
+struct RecursionTemplate {
+  RecursePlan rp;
+  Launches L;
+};
+
 struct CircuitTopo {
   Graph g;
   std::vector<sqc_tensor> att;
   mutable PlanCache plans;
+  // templates by shape: precision, bins precision, top_r, the launch
+  // tuning's version and every subcircuit's (fixed, active, merged) masks
+  mutable std::mutex tmu;
+  mutable std::map<std::vector<uint64_t>, std::shared_ptr<const RecursionTemplate>> templates;
 };
 
 struct PreparedRecursion {
   std::shared_ptr<const CircuitTopo> c;
-  RecursePlan rp;
+  std::shared_ptr<const RecursionTemplate> t;
+  std::vector<sqc_masks> masks;
   sqc_prec prec, bins_prec;
   void *bins, *top, *sum;
   int top_r;
@@ -921,7 +936,34 @@ PreparedPtr prepare_recursion(std::shared_ptr<const CircuitTopo> c, const sqc_ma
   check_storage_prec(bins_prec, "bins_prec");
   if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
   PreparedPtr p(new PreparedRecursion());
-  p->rp = plan_recursion(c->g, c->att.data(), scope, M, top_r, prec, &c->plans);
+  const int n_sub = c->g.n_sub;
+  std::vector<int> d(n_sub);
+  for (int i = 0; i < n_sub; ++i) d[i] = c->att[i].n_bits;
+  p->masks.resize(n_sub);
+  assign_bins(n_sub, d.data(), scope, M, p->masks.data());
+  std::vector<uint64_t> key{(uint64_t)prec, (uint64_t)bins_prec, (uint64_t)top_r, gemm_tune_version()};
+  for (const sqc_masks &m : p->masks) {
+    key.push_back(m.fixed);
+    key.push_back(m.active);
+    key.push_back(m.merged);
+  }
+  {
+    std::lock_guard<std::mutex> lk(c->tmu);
+    auto it = c->templates.find(key);
+    if (it != c->templates.end()) p->t = it->second;
+  }
+  if (!p->t) {
+    auto t = std::make_shared<RecursionTemplate>();
+    t->rp = plan_recursion(c->g, c->att.data(), scope, M, top_r, prec, &c->plans);
+    for (sqc_masks &m : t->rp.masks) m.fixed_val = 0;
+    // outputs: null bins; top-R and sum marked by their own non-null values
+    // (describe_contraction adds the top-R stage only for a non-null top)
+    t->L = describe_recursion(t->rp, c->att.data(), prec, nullptr, nullptr, nullptr, bins_prec, top_r,
+                              reinterpret_cast<void *>(uintptr_t(16)), reinterpret_cast<void *>(uintptr_t(32)));
+    std::lock_guard<std::mutex> lk(c->tmu);
+    if (c->templates.size() >= 4096) c->templates.clear();  // bounded
+    p->t = c->templates.emplace(key, std::move(t)).first->second;
+  }
   p->c = std::move(c);
   p->prec = prec;
   p->bins_prec = bins_prec;
@@ -932,22 +974,58 @@ PreparedPtr prepare_recursion(std::shared_ptr<const CircuitTopo> c, const sqc_ma
   return p;
 }
 
-size_t prepared_workspace(const PreparedRecursion &p) { return align256(p.rp.total); }
+size_t prepared_workspace(const PreparedRecursion &p) { return align256(p.t->rp.total); }
 
 size_t prepared_table_bytes(const PreparedRecursion &p) {
-  const size_t n_sub = p.rp.masks.size();
-  const size_t steps = p.rp.con.unit ? 1 : p.rp.con.plan.steps.size();
+  const size_t n_sub = p.t->rp.masks.size();
+  const size_t steps = p.t->rp.con.unit ? 1 : p.t->rp.con.plan.steps.size();
   return n_sub * sizeof(MergeArgs) + steps * sizeof(GemmArgs) + sizeof(TopRArgs) +
          sizeof(int) * (3 * n_sub + 2 * steps + 8) + 256 * (2 * steps + 8);
 }
 
-const sqc_masks *prepared_masks(const PreparedRecursion &p) { return p.rp.masks.data(); }
+const sqc_masks *prepared_masks(const PreparedRecursion &p) { return p.masks.data(); }
 
 namespace {
 
+// The request's launches: its shape's template with the workspace at ws, the
+// device's unit constant, the request's outputs and its fixed bits' values.
 Launches describe_prepared(sqc_ctx *ctx, const PreparedRecursion &p, char *ws) {
-  return describe_recursion(p.rp, p.c->att.data(), p.prec, ws, ctx->unit, p.bins, p.bins_prec, p.top_r,
-                            p.top, p.sum);
+  Launches L = p.t->L;
+  auto at = [ws](const void *rel) -> char * { return ws + reinterpret_cast<uintptr_t>(rel); };
+  for (size_t i = 0; i < L.merges.size(); ++i) {
+    MergeArgs &a = L.merges[i];
+    a.out = at(a.out);
+    a.partial = reinterpret_cast<double *>(at(a.partial));
+    a.fixed_val = p.masks[i].fixed_val;
+  }
+  const char *unit = reinterpret_cast<const char *>(ctx->unit);
+  auto operand = [&](const void *rel) -> const void * {
+    const uintptr_t v = reinterpret_cast<uintptr_t>(rel);
+    return v < kCtlBytes ? static_cast<const void *>(unit + v) : static_cast<const void *>(ws + v);
+  };
+  for (size_t si = 0; si < L.steps.size(); ++si) {
+    GemmArgs &g = L.steps[si];
+    g.A = operand(g.A);
+    g.B = operand(g.B);
+    g.C = si + 1 == L.steps.size() ? p.bins : static_cast<void *>(at(g.C));
+    if (g.stats) {
+      g.blk_max = reinterpret_cast<double *>(at(g.blk_max));
+      g.wg_stats = reinterpret_cast<double *>(at(g.wg_stats));
+    }
+  }
+  if (L.topr) {
+    TopRArgs &t = L.t;
+    t.C = p.bins;
+    t.blk_max = reinterpret_cast<const double *>(at(t.blk_max));
+    t.wg_stats = reinterpret_cast<const double *>(at(t.wg_stats));
+    t.tau_sum = reinterpret_cast<double *>(at(t.tau_sum));
+    t.slot_n = reinterpret_cast<int *>(at(t.slot_n));
+    t.slot_val = reinterpret_cast<double *>(at(t.slot_val));
+    t.slot_idx = reinterpret_cast<uint64_t *>(at(t.slot_idx));
+    t.top_out = static_cast<double *>(p.top);
+    t.sum_out = static_cast<double *>(p.sum);
+  }
+  return L;
 }
 
 // Host image of a batch's job tables (arrays 256-byte aligned).

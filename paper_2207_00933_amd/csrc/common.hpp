@@ -262,6 +262,9 @@ bool gemm_tuned(const GemmArgs &g, const GemmSpec &sp, GemmTuning &out);
 void gemm_tune_store(const GemmArgs &g, const GemmSpec &sp, const GemmTuning &t);
 void gemm_tune_reset();
 size_t gemm_tune_size();
+// Changes whenever the tuned launch choices do (cached launch descriptions
+// built before are stale).
+uint64_t gemm_tune_version();
 
 // Top-R selection over the final bins after a GEMM with statistics: the
 // compensated total sum and the R best bins (value descending, lower index

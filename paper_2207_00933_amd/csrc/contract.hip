@@ -1246,6 +1246,7 @@ int gemm_resident_cap(const GemmSpec &sp) { return dispatch(sp, GroupsQuery{int6
 namespace {
 std::mutex tune_mu;
 std::unordered_map<uint64_t, GemmTuning> tune_table;
+uint64_t tune_epoch = 0;  // changes whenever the table does
 
 void mix(uint64_t &h, int64_t v) {
   h ^= (uint64_t)v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
@@ -1290,16 +1291,23 @@ void gemm_tune_store(const GemmArgs &g, const GemmSpec &sp, const GemmTuning &t)
   const uint64_t k = gemm_tune_key(g, sp);
   std::lock_guard<std::mutex> lk(tune_mu);
   tune_table[k] = t;
+  ++tune_epoch;
 }
 
 void gemm_tune_reset() {
   std::lock_guard<std::mutex> lk(tune_mu);
   tune_table.clear();
+  ++tune_epoch;
 }
 
 size_t gemm_tune_size() {
   std::lock_guard<std::mutex> lk(tune_mu);
   return tune_table.size();
+}
+
+uint64_t gemm_tune_version() {
+  std::lock_guard<std::mutex> lk(tune_mu);
+  return tune_epoch;
 }
 
 void launch_gemm_spec(const GemmArgs &g, const GemmSpec &sp, int groups, hipStream_t s, hipEvent_t start,

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -33,13 +34,22 @@ constexpr size_t kAlign = 256;
 constexpr size_t kMinWorkspace = 4096;
 constexpr size_t kStagingBytes = size_t(2) << 20;  // pinned job-table image per slot
 constexpr int kMaxBatch = 128;                      // requests per batch
+// A request passed over this many times (it did not fit while later ones
+// did) stops later requests from being admitted until it runs, so the
+// memory the running batches free up goes to it (aging: no starvation).
+constexpr int kMaxSkips = 8;
 
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 struct Pending {
   uint64_t ticket = 0;
   sqc::PreparedPtr prep;
   size_t ws = 0, table = 0;  // workspace and job-table bytes (rounded)
+  int skips = 0;             // batches formed without it although it waited
 };
 
 struct Slot {
@@ -119,6 +129,40 @@ void give_block(sqc_server *s, size_t off, size_t len) {
 // request), then each request's workspace.
 size_t batch_bytes(size_t table, size_t ws_sum, int count) { return (count > 1 ? table : 0) + ws_sum; }
 
+// The batching policy (host only, no device state): from the waiting
+// requests in arrival order, take requests while they fit `room` (job tables
+// within `staging`), up to `target`; a request that does not fit may be
+// passed by later ones, and each pass counts against it; one passed over
+// kMaxSkips times stops the scan (nothing behind it is admitted first).
+// When a batch is formed, every request passed over gains one skip.  Returns
+// the count taken; `picked` gets their positions (ascending), `held` 1 when
+// an aged request stopped the scan, `table` / `ws_sum` the batch's sums.
+int pick_batch(const size_t *ws, const size_t *tab, int32_t *skips, int32_t n, size_t room, size_t staging,
+               int target, int32_t *picked, int32_t *held, size_t *table_out, size_t *ws_out) {
+  size_t table = 0, ws_sum = 0;
+  int count = 0;
+  std::vector<int32_t> passed;
+  *held = 0;
+  for (int32_t k = 0; k < n && count < target; ++k) {
+    const size_t t2 = table + tab[k], w2 = ws_sum + ws[k];
+    if (batch_bytes(t2, w2, count + 1) <= room && t2 <= staging) {
+      table = t2;
+      ws_sum = w2;
+      picked[count++] = k;
+    } else if (skips[k] >= kMaxSkips) {
+      *held = 1;  // aged: nothing behind it goes first
+      break;
+    } else {
+      passed.push_back(k);  // a later, smaller request may fit
+    }
+  }
+  if (count)
+    for (int32_t k : passed) skips[k] += 1;
+  *table_out = table;
+  *ws_out = ws_sum;
+  return count;
+}
+
 // Enqueue the slot's batch into the block at `off`.
 void launch_batch(sqc_server *s, Slot &sl, size_t off) {
   char *base = s->ws + off;
@@ -143,7 +187,8 @@ void launch_batch(sqc_server *s, Slot &sl, size_t off) {
 }
 
 // Retire finished batches; admit waiting requests in batches.
-sqc_status pump(sqc_server *s) {
+// (`want`: a batch size to aim for at least, when enough requests wait)
+sqc_status pump(sqc_server *s, int want = 0) {
   for (auto &sl : s->slots) {
     if (!sl.busy) continue;
     const hipError_t q = hipEventQuery(sl.done);
@@ -171,29 +216,49 @@ sqc_status pump(sqc_server *s) {
       }
     if (!slot) break;
     // share the waiting requests among the idle slots
-    const int target = std::min<int>(s->max_batch, (int)((s->waiting.size() + idle - 1) / idle));
+    const int target =
+        std::min<int>(s->max_batch, std::max<int>(want, (int)((s->waiting.size() + idle - 1) / idle)));
     const size_t room = largest_free(s);
     size_t table = 0, ws_sum = 0;
     int count = 0;
-    for (auto it = s->waiting.begin(); it != s->waiting.end() && count < target;) {
-      const size_t t2 = table + it->table, w2 = ws_sum + it->ws;
-      if (batch_bytes(t2, w2, count + 1) <= room && t2 <= kStagingBytes) {
-        table = t2;
-        ws_sum = w2;
-        ++count;
-        slot->batch.push_back(std::move(*it));
-        it = s->waiting.erase(it);
-      } else {
-        ++it;  // a later, smaller request may fit
-      }
+    std::vector<size_t> wsz, tsz;
+    std::vector<int32_t> skips;
+    for (const Pending &p : s->waiting) {
+      wsz.push_back(p.ws);
+      tsz.push_back(p.table);
+      skips.push_back(p.skips);
     }
+    std::vector<int32_t> picked(s->waiting.size());
+    int32_t held = 0;
+    count = pick_batch(wsz.data(), tsz.data(), skips.data(), (int32_t)wsz.size(), room, kStagingBytes, target,
+                       picked.data(), &held, &table, &ws_sum);
+    s->st.aged_holds += held;
     if (!count) break;
+    {
+      // move the picked requests into the slot's batch (in arrival order)
+      std::deque<Pending> rest;
+      size_t k = 0, q = 0;
+      for (auto &p : s->waiting) {
+        p.skips = skips[k];
+        if (q < (size_t)count && picked[q] == (int32_t)k) {
+          slot->batch.push_back(std::move(p));
+          ++q;
+        } else {
+          rest.push_back(std::move(p));
+        }
+        ++k;
+      }
+      s->waiting.swap(rest);
+    }
     const size_t len = batch_bytes(table, ws_sum, count);
     size_t off = 0;
     take_block(s, len, off);  // fits: len <= the largest free block
+    const double t0 = now_s();
     try {
       launch_batch(s, *slot, off);
+      s->st.launch_seconds += now_s() - t0;
     } catch (const sqc::Error &e) {
+      s->st.launch_seconds += now_s() - t0;
       give_block(s, off, len);
       for (auto &p : slot->batch) {
         s->state[p.ticket] = kFailed;
@@ -221,12 +286,15 @@ sqc_status pump(sqc_server *s) {
 sqc_status prepare(sqc_server *s, const sqc_request *req, Pending &p) {
   if (req->circuit < 0 || req->circuit >= (int)s->circuits.size())
     return fail(s, SQC_E_ARG, "unknown circuit id");
+  const double t0 = now_s();
   try {
     p.prep = sqc::prepare_recursion(s->circuits[req->circuit], req->scope, req->max_bins_M, req->top_r,
                                     req->prec, req->bins_dev, req->bins_prec, req->topr_dev, req->sum_dev);
   } catch (const sqc::Error &e) {
+    s->st.plan_seconds += now_s() - t0;
     return fail(s, e.code, e.msg);
   }
+  s->st.plan_seconds += now_s() - t0;
   p.ws = round_up(sqc::prepared_workspace(*p.prep));
   p.table = round_up(sqc::prepared_table_bytes(*p.prep));
   return SQC_OK;
@@ -317,6 +385,39 @@ sqc_status sqc_serve_submit(sqc_server *s, const sqc_request *req, uint64_t *tic
   return pump(s);
 }
 
+sqc_status sqc_serve_submit_many(sqc_server *s, const sqc_request *reqs, int32_t n, uint64_t *tickets) {
+  if (!s || n < 0 || (n > 0 && (!reqs || !tickets)))
+    return fail(s, SQC_E_ARG, "invalid argument to sqc_serve_submit_many");
+  std::vector<Pending> ps(n);
+  for (int32_t k = 0; k < n; ++k) {
+    const sqc_status rc = prepare(s, &reqs[k], ps[k]);
+    if (rc != SQC_OK) return rc;
+    if (ps[k].ws + ps[k].table > s->ws_bytes || ps[k].table > kStagingBytes)
+      return fail(s, SQC_E_NOMEM, "a request's footprint exceeds the server workspace");
+  }
+  // queue the burst in shares of one batch per slot, advancing after each so
+  // that the first batches run while the rest are formed
+  const int share = std::max<int>(1, std::min<int>(s->max_batch, (int)((n + s->slots.size() - 1) / s->slots.size())));
+  for (int32_t k = 0; k < n; ++k) {
+    const sqc_request *req = &reqs[k];
+    Pending &p = ps[k];
+    if (req->masks_out) {
+      const int ns = sqc::circuit_n_sub(*s->circuits[req->circuit]);
+      std::copy(sqc::prepared_masks(*p.prep), sqc::prepared_masks(*p.prep) + ns, req->masks_out);
+    }
+    p.ticket = s->next_ticket++;
+    s->state[p.ticket] = kWaiting;
+    tickets[k] = p.ticket;
+    s->waiting.push_back(std::move(p));
+    s->st.submitted += 1;
+    if ((k + 1) % share == 0 && k + 1 < n) {
+      const sqc_status rc = pump(s, share);
+      if (rc != SQC_OK) return rc;
+    }
+  }
+  return pump(s, share);
+}
+
 sqc_status sqc_serve_poll(sqc_server *s, uint64_t ticket, int32_t *state) {
   if (!s || !state) return fail(s, SQC_E_ARG, "invalid argument to sqc_serve_poll");
   const sqc_status rc = pump(s);
@@ -370,5 +471,17 @@ sqc_status sqc_serve_get_stats(sqc_server *s, sqc_serve_stats *out) {
 }
 
 const char *sqc_serve_last_error(const sqc_server *s) { return s ? s->err.c_str() : "no server"; }
+
+sqc_status sqc_serve_pick_batch(const size_t *workspace_bytes, const size_t *table_bytes, int32_t *skips,
+                                int32_t n, size_t room, int32_t max_batch, int32_t *picked, int32_t *n_picked,
+                                int32_t *held) {
+  if (n < 0 || max_batch < 1 || !n_picked || !held || (n > 0 && (!workspace_bytes || !table_bytes || !skips ||
+                                                                   !picked)))
+    return SQC_E_ARG;
+  size_t table = 0, ws = 0;
+  *n_picked = pick_batch(workspace_bytes, table_bytes, skips, n, room, kStagingBytes, max_batch, picked, held,
+                         &table, &ws);
+  return SQC_OK;
+}
 
 }  // extern "C"

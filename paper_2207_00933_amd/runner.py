@@ -170,6 +170,12 @@ class Server:
         self._live[t] = req
         return t
 
+    def submit_many(self, reqs: Sequence[sqc.Request]) -> List[int]:
+        ts = sqc.serve_submit_many(self.srv, reqs)
+        for t, r in zip(ts, reqs):
+            self._live[t] = r
+        return ts
+
     def poll(self, ticket: int) -> int:
         st = sqc.serve_poll(self.srv, ticket)
         if st == sqc.DONE:

@@ -90,7 +90,8 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", c_uint64), ("admitted", c_uint64), ("completed", c_uint64),
                 ("running", c_int32), ("queued", c_int32), ("max_running", c_int32),
                 ("max_batch", c_int32), ("workspace_bytes", c_uint64), ("workspace_peak", c_uint64),
-                ("batches", c_uint64)]
+                ("batches", c_uint64), ("plan_seconds", c_double), ("launch_seconds", c_double),
+                ("aged_holds", c_uint64)]
 
 
 WAITING, RUNNING, DONE = 0, 1, 2
@@ -194,9 +195,13 @@ def lib():
                                            POINTER(c_int32)]),
             "sqc_serve_footprint": (c_size_t, [P, POINTER(Request)]),
             "sqc_serve_submit": (c_int, [P, POINTER(Request), POINTER(c_uint64)]),
+            "sqc_serve_submit_many": (c_int, [P, POINTER(Request), c_int32, POINTER(c_uint64)]),
             "sqc_serve_poll": (c_int, [P, c_uint64, POINTER(c_int32)]),
             "sqc_serve_wait": (c_int, [P, c_uint64]),
             "sqc_serve_get_stats": (c_int, [P, POINTER(ServeStats)]),
+            "sqc_serve_pick_batch": (c_int, [POINTER(c_size_t), POINTER(c_size_t), POINTER(c_int32), c_int32,
+                                             c_size_t, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                             POINTER(c_int32)]),
             "sqc_serve_completed": (c_int, [P, POINTER(c_uint64), c_int32, POINTER(c_int32)]),
             "sqc_serve_last_error": (c_char_p, [P]),
         }
@@ -644,6 +649,16 @@ def serve_submit(srv: int, req: Request) -> int:
     return t.value
 
 
+def serve_submit_many(srv: int, reqs: Sequence[Request]) -> List[int]:
+    n = len(reqs)
+    arr = (Request * max(1, n))()
+    for k, r in enumerate(reqs):
+        arr[k] = r  # (a copy: the scope and masks_out pointers stay the caller's)
+    out = (c_uint64 * max(1, n))()
+    _check_srv(lib().sqc_serve_submit_many(srv, arr, n, out), srv)
+    return list(out[:n])
+
+
 def serve_poll(srv: int, ticket: int) -> int:
     st = c_int32()
     _check_srv(lib().sqc_serve_poll(srv, ticket, ctypes.byref(st)), srv)
@@ -659,6 +674,24 @@ def serve_completed(srv: int, cap: int = 256) -> List[int]:
     n = c_int32()
     _check_srv(lib().sqc_serve_completed(srv, buf, cap, ctypes.byref(n)), srv)
     return [buf[k] for k in range(n.value)]
+
+
+def serve_pick_batch(ws_bytes: Sequence[int], table_bytes: Sequence[int], skips: List[int], room: int,
+                     max_batch: int):
+    """The serving engine's batching policy: (positions taken, held by an
+    aged request); `skips` is updated in place."""
+    n = len(ws_bytes)
+    w = (c_size_t * max(1, n))(*ws_bytes)
+    t = (c_size_t * max(1, n))(*table_bytes)
+    sk = (c_int32 * max(1, n))(*skips)
+    out = (c_int32 * max(1, n))()
+    npk, held = c_int32(), c_int32()
+    st = lib().sqc_serve_pick_batch(w, t, sk, n, int(room), int(max_batch), out, ctypes.byref(npk),
+                                    ctypes.byref(held))
+    if st != OK:
+        raise SqcError(st, "sqc_serve_pick_batch: invalid argument")
+    skips[:] = list(sk[:n])
+    return list(out[:npk.value]), bool(held.value)
 
 
 def serve_get_stats(srv: int) -> ServeStats:

@@ -337,3 +337,52 @@ def test_recursion_slices_by_memory(prec):
     with pytest.raises(sqc.SqcError) as e:
         sqc.recurse_slices(descs, g, masks, prec, 16, 4096)
     assert e.value.status == sqc.E_NOMEM
+
+
+def test_serve_batching_policy_and_aging():
+    """The serving engine's batching policy (host only): requests are taken in
+    arrival order while they fit; a later request that fits may pass one that
+    does not, each pass counting against the passed one; after 8 passes it
+    holds the queue, so it is admitted first once memory frees up (no
+    starvation of a large request behind a stream of small ones)."""
+    big, small, tab = 1000, 100, 10
+    skips = [0, 0, 0]
+    # memory for small requests only: the big one (first) is passed over
+    picked, held = sqc.serve_pick_batch([big, small, small], [tab] * 3, skips, room=300, max_batch=8)
+    assert picked == [1, 2] and not held and skips == [1, 0, 0]
+    # a batch of one needs no job table
+    picked, _ = sqc.serve_pick_batch([small], [tab], [0], room=small, max_batch=8)
+    assert picked == [0]
+    # two need both job tables: 2 (small + tab) bytes
+    sk = [0, 0]
+    picked, _ = sqc.serve_pick_batch([small, small], [tab, tab], sk, room=2 * small + tab, max_batch=8)
+    assert picked == [0] and sk == [0, 1]
+    picked, _ = sqc.serve_pick_batch([small, small], [tab, tab], [0, 0], room=2 * (small + tab), max_batch=8)
+    assert picked == [0, 1]
+    # a stream of small requests behind the big one: it is passed 8 times
+    skips = [0]
+    rounds = 0
+    while True:
+        sk = skips + [0] * 3
+        picked, held = sqc.serve_pick_batch([big] + [small] * 3, [tab] * 4, sk, room=500, max_batch=8)
+        skips = sk[:1]
+        if held:
+            break
+        assert picked == [1, 2, 3]
+        rounds += 1
+        assert rounds <= 8
+    assert rounds == 8 and skips == [8] and picked == []
+    # once memory frees up it goes first, ahead of the small ones
+    sk = [8, 0, 0]
+    picked, held = sqc.serve_pick_batch([big, small, small], [tab] * 3, sk, room=big + 2 * small + 3 * tab,
+                                        max_batch=8)
+    assert picked[0] == 0 and not held
+    # max_batch caps the batch; nothing fits: no batch and no skips counted
+    sk = [0, 0, 0]
+    picked, _ = sqc.serve_pick_batch([small] * 3, [tab] * 3, sk, room=10 ** 6, max_batch=2)
+    assert picked == [0, 1]
+    sk = [0, 0]
+    picked, held = sqc.serve_pick_batch([big, big], [tab] * 2, sk, room=10, max_batch=8)
+    assert picked == [] and not held and sk == [0, 0]
+    with pytest.raises(sqc.SqcError):
+        sqc.serve_pick_batch([small], [tab], [0], room=10, max_batch=0)

@@ -32,7 +32,7 @@ def circuits():
         "chain3": configs.chain_brickwork(3, [4, 5, 4], [1, 2], 4, 11),
         "qaoa3": build_cut_circuit(planted_qaoa([4, 4, 4], seed=5)),
         "pool7": pool[7],
-        "pool2": pool[2],
+        "pool5": pool[5],
     }
 
 
@@ -162,6 +162,28 @@ def test_alone_equals_burst(setup):
     srv.close()
 
 
+def test_alone_equals_submit_many(setup):
+    """A burst submitted in one call is shared into batches as a whole (the
+    first requests do not leave in batches of one), with results bitwise
+    equal to the alone runs; requests of one shape share a cached launch
+    template, filled in per request."""
+    s, circ = setup
+    reqs = request_list(circ, 9, 64) + request_list(circ, 9, 16)  # repeated shapes
+    alone = run_alone(s, circ, reqs)
+    srv = runner.Server(0, n_slots=2, workspace_bytes=1 << 30)
+    ids = register_all(srv, circ)
+    served = make_server_requests(srv, ids, circ, reqs)
+    tickets = srv.submit_many([r[0] for r in served])
+    assert len(tickets) == len(reqs) == len(set(tickets))
+    for t in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    say(f"  submit_many: {st.batches} batches, largest {st.max_batch}")
+    assert st.completed == len(reqs) and st.max_batch >= len(reqs) // 2
+    check_same(alone, served, reqs)
+    srv.close()
+
+
 def test_alone_equals_arrivals_small_workspace(setup):
     """Requests arrive while others run; the workspace holds only a few at a
     time, so admission waits for memory as well as slots."""
@@ -238,14 +260,14 @@ def test_footprint_limits(setup):
     s, circ = setup
     srv = runner.Server(0, n_slots=2, workspace_bytes=1 << 16)
     ids = register_all(srv, circ)
-    req = ("pool2", 14, sqc.F32, 4, None)
+    req = ("pool5", 14, sqc.F32, 4, None)
     masks, bprec, bins, top, bsum = buffers(circ, req)
-    r = srv.request(ids[("pool2", sqc.F32)], None, 1 << 14, 4, sqc.F32, bins, bprec, top, bsum)
+    r = srv.request(ids[("pool5", sqc.F32)], None, 1 << 14, 4, sqc.F32, bins, bprec, top, bsum)
     assert srv.footprint(r) > (1 << 16)
     with pytest.raises(sqc.SqcError) as e:
         srv.submit(r)
     assert e.value.status == sqc.E_NOMEM
-    bad = srv.request(ids[("pool2", sqc.F32)], None, 1 << 14, 0, sqc.F32, bins, bprec, top, bsum)
+    bad = srv.request(ids[("pool5", sqc.F32)], None, 1 << 14, 0, sqc.F32, bins, bprec, top, bsum)
     with pytest.raises(sqc.SqcError) as e:
         srv.submit(bad)
     assert e.value.status == sqc.E_ARG

@@ -94,13 +94,26 @@ def bv(n_data: int, n_blocks: int, seed: int) -> CutCircuit:
     return cc
 
 
+# Pool anchors: the extremes of the serving pool's ranges, always present.
+POOL_QUBITS = (16, 80)
+POOL_CUTS = (2, 10)
+
+
 def serving_pool(seed: int = 4, count: int = 32,
                  max_width: int = 18) -> List[CutCircuit]:
-    """Seeded pool of brickwork chains and planted QAOA rings, 16-80 qubits,
-    2-5 subcircuits, 2-10 cuts, every subcircuit at most ``max_width`` wires
-    (so every variant can be simulated)."""
+    """Seeded pool of brickwork chains and planted QAOA rings spanning 16-80
+    qubits, 2-5 subcircuits and 2-10 cuts, every subcircuit at most
+    ``max_width`` wires (so every variant can be simulated).  With
+    ``count >= 3`` the pool starts with three anchors at the ranges' ends
+    (16 qubits with 2 cuts, 80 qubits, 10 cuts); the rest is drawn at random
+    within the ranges, and the realised ranges are checked."""
     rng = np.random.default_rng(seed)
     pool: List[CutCircuit] = []
+    if count >= 3:
+        for n_sub, d, moves in ((2, [8, 8], [2]), (5, [16] * 5, [1, 1, 1, 1]), (5, [12] * 5, [2, 3, 3, 2])):
+            cc = chain_brickwork(n_sub, d, moves, 4, int(rng.integers(1 << 30)))
+            cc.meta["name"] = f"pool{len(pool)}"
+            pool.append(cc)
     attempt = 0
     while len(pool) < count:
         attempt += 1
@@ -131,4 +144,13 @@ def serving_pool(seed: int = 4, count: int = 32,
             continue
         if attempt > 10000:
             raise RuntimeError("could not fill the serving pool")
+    ns = [cc.n for cc in pool]
+    ks = [len(cc.cuts) for cc in pool]
+    subs = [cc.n_sub for cc in pool]
+    widths = [max(cc.summary()["w"]) for cc in pool]
+    assert POOL_QUBITS[0] <= min(ns) and max(ns) <= POOL_QUBITS[1], ns
+    assert POOL_CUTS[0] <= min(ks) and max(ks) <= POOL_CUTS[1], ks
+    assert 2 <= min(subs) and max(subs) <= 5 and max(widths) <= max_width
+    if count >= 3:
+        assert (min(ns), max(ns)) == POOL_QUBITS and (min(ks), max(ks)) == POOL_CUTS, (ns, ks)
     return pool
