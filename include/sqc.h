@@ -515,9 +515,12 @@ sqc_status sqc_graph_destroy(sqc_graph *graph);
  * described as in sqc_recurse (its workspace from sqc_recurse_workspace_bytes),
  * it runs the recursion once, then times every GEMM step of it (`reps`
  * launches each, HIP events on the context's stream, waiting for the device)
- * over candidate launch choices: work-group counts of 1/4, 1/2, 1 and 2 times
- * the resident capacity and one per tile, and both tile orders when the step
- * has several m and n panels.  The fastest choice of each step is stored in a
+ * over candidate launch choices: two tile shapes when the step contracts at
+ * most 16 labels (K staged 64 deep, or 16 deep: the narrow tile), work-group
+ * counts of 1/4, 1/2, 1 and 2 times each kernel's resident capacity and one
+ * per tile, and both tile orders when the step has several m and n panels.
+ * Untuned, a step with K <= 16 takes the narrow tile.  The fastest choice of
+ * each step is stored in a
  * process-wide table keyed by the step's kernel specialisation, dimensions
  * and index maps, and every later launch of the same shape (sqc_contract,
  * sqc_recurse, sqc_search, the serving engine) uses it.  Tile order changes
@@ -525,11 +528,13 @@ sqc_status sqc_graph_destroy(sqc_graph *graph);
  * may differ in the last bits from an untuned run (every run with the same
  * table gives the same bits).  The recursion is run once more at the end, so
  * `bins_dev` holds its bins.  Blocks the calling thread.  `report` (optional)
- * receives the steps tuned, candidates timed and the summed step times with
- * the default and the chosen launches. */
+ * receives the steps tuned, candidates timed, the summed step times with
+ * the default and the chosen launches, and per step (the first 64) the
+ * chosen tile (0: 64 deep, 1: 16 deep), work-group count and tile order. */
 typedef struct {
   int32_t steps, candidates;
   double default_us, tuned_us;
+  int32_t step_tile[64], step_groups[64], step_nmajor[64];
 } sqc_tune_report;
 sqc_status sqc_autotune(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub,
                         const sqc_cut *cuts, int32_t n_cuts, const sqc_masks *scope,

@@ -445,10 +445,13 @@ void describe_contraction(Launches &L, const Contraction &c, const std::vector<c
       g.acc_sum = acc.sum;
       g.acc_comp = acc.comp;
     }
-    const GemmSpec sp = prepare_gemm(g, prec);
+    const GemmSpec base = prepare_gemm(g, prec);
+    GemmSpec sp = gemm_default_spec(g, base);
     int groups = gemm_groups(g, sp);
     GemmTuning tu;
-    if (gemm_tuned(g, sp, tu)) {
+    if (gemm_tuned(g, base, tu)) {  // (keyed by the base specialisation)
+      sp = base;
+      if (tu.narrow && gemm_narrow_ok(g, base)) sp.reg = 4;
       groups = (int)std::min<int64_t>(std::min<int64_t>(tu.groups, gemm_tiles(g)), kMaxGemmGroups);
       g.nmajor = (g.mbits > 6 && g.nbits > 6) ? tu.nmajor : 0;
     }
@@ -2458,41 +2461,55 @@ sqc_status sqc_autotune(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_su
   sqc_tune_report rep{};
   for (size_t si = 0; si < L.steps.size(); ++si) {
     const GemmArgs base = L.steps[si];
-    const GemmSpec &sp = L.specs[si];
+    const GemmSpec &used = L.specs[si];
+    GemmSpec sp = used;  // the specialisation the tuning table is keyed by
+    if (sp.reg == 4) sp.reg = 0;
     const int64_t tiles = gemm_tiles(base);
-    const int cap = gemm_resident_cap(sp);
-    // candidates: work-group counts around the resident capacity, both tile
-    // orders when there are several m and n panels
-    std::vector<int> counts;
-    for (int64_t c : {int64_t(cap) / 4, int64_t(cap) / 2, int64_t(cap), int64_t(cap) * 2, tiles}) {
-      const int v = (int)std::max<int64_t>(1, std::min<int64_t>({c, tiles, int64_t(kMaxGemmGroups)}));
-      if (std::find(counts.begin(), counts.end(), v) == counts.end()) counts.push_back(v);
-    }
+    // candidates: the tile shapes that apply, for each work-group counts
+    // around that kernel's resident capacity, both tile orders when there are
+    // several m and n panels
+    std::vector<int> shapes{0};
+    if (gemm_narrow_ok(base, sp)) shapes.push_back(1);
     std::vector<int> orders{base.nmajor};
     if (base.mbits > 6 && base.nbits > 6) orders.push_back(1 - base.nmajor);
     double best = 0.0, dflt = 0.0;
-    GemmTuning pick{L.groups[si], base.nmajor};
-    for (int nm : orders)
-      for (int cnt : counts) {
-        GemmArgs gg = base;
-        gg.nmajor = nm;
-        launch_gemm_spec(gg, sp, cnt, ctx->stream);  // warm
-        check_hip(hipEventRecord(e0, ctx->stream), "hipEventRecord");
-        for (int r = 0; r < reps; ++r) launch_gemm_spec(gg, sp, cnt, ctx->stream);
-        check_hip(hipEventRecord(e1, ctx->stream), "hipEventRecord");
-        after_launch("tuning launch");
-        check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
-        float ms = 0.f;
-        check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-        const double us = 1e3 * ms / reps;
-        const bool is_default = nm == base.nmajor && cnt == L.groups[si];
-        if (is_default) dflt = us;
-        ++rep.candidates;
-        if (best == 0.0 || us < best) {
-          best = us;
-          pick = GemmTuning{cnt, nm};
-        }
+    GemmTuning pick{L.groups[si], base.nmajor, used.reg == 4 ? 1 : 0};
+    for (int nw : shapes) {
+      GemmSpec ks = sp;
+      if (nw) ks.reg = 4;
+      const int cap = gemm_resident_cap(ks);
+      std::vector<int> counts;
+      for (int64_t c : {int64_t(cap) / 4, int64_t(cap) / 2, int64_t(cap), int64_t(cap) * 2, tiles}) {
+        const int v = (int)std::max<int64_t>(1, std::min<int64_t>({c, tiles, int64_t(kMaxGemmGroups)}));
+        if (std::find(counts.begin(), counts.end(), v) == counts.end()) counts.push_back(v);
       }
+      for (int nm : orders)
+        for (int cnt : counts) {
+          GemmArgs gg = base;
+          gg.nmajor = nm;
+          launch_gemm_spec(gg, ks, cnt, ctx->stream);  // warm
+          check_hip(hipEventRecord(e0, ctx->stream), "hipEventRecord");
+          for (int r = 0; r < reps; ++r) launch_gemm_spec(gg, ks, cnt, ctx->stream);
+          check_hip(hipEventRecord(e1, ctx->stream), "hipEventRecord");
+          after_launch("tuning launch");
+          check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+          float ms = 0.f;
+          check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+          const double us = 1e3 * ms / reps;
+          const bool is_default = ks.reg == used.reg && nm == base.nmajor && cnt == L.groups[si];
+          if (is_default) dflt = us;
+          ++rep.candidates;
+          if (best == 0.0 || us < best) {
+            best = us;
+            pick = GemmTuning{cnt, nm, nw};
+          }
+        }
+    }
+    if (si < 64) {
+      rep.step_tile[si] = pick.narrow;
+      rep.step_groups[si] = pick.groups;
+      rep.step_nmajor[si] = pick.nmajor;
+    }
     gemm_tune_store(base, sp, pick);
     rep.default_us += dflt;
     rep.tuned_us += best;

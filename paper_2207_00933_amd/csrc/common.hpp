@@ -229,11 +229,12 @@ struct GemmSpec {
   int prec;
   bool fold, outf;
   int reg;  // 0 general, 1 regular shape, 2 regular with single-run index
-            // maps, 3 general with the slice-accumulating epilogue
+            // maps, 3 general with the slice-accumulating epilogue, 4 general
+            // with K <= 16 staged 16 deep (the narrow tile)
 };
 // ...chosen after filling g's offset tables,
 GemmSpec prepare_gemm(GemmArgs &g, int prec);
-// a dense id of it (0 .. 47),
+// a dense id of it (0 .. 59),
 int gemm_spec_id(const GemmSpec &sp);
 // the work-groups launch_gemm would use (results, including the work-group
 // statistics, depend on this count),
@@ -256,7 +257,14 @@ void launch_gemm_grouped(const GemmSpec &sp, const GemmArgs *jobs_dev, const int
 struct GemmTuning {
   int groups;
   int nmajor;
+  int narrow;  // 1: the 16-deep K tile (K <= 16 only)
 };
+// The 16-deep K tile applies to this step (K <= 16, general index maps, a
+// plain store epilogue).
+bool gemm_narrow_ok(const GemmArgs &g, const GemmSpec &sp);
+// The launch choices a step takes untuned (the tile from the measured
+// default rule, the work-group count from the occupancy of that kernel).
+GemmSpec gemm_default_spec(const GemmArgs &g, const GemmSpec &sp);
 uint64_t gemm_tune_key(const GemmArgs &g, const GemmSpec &sp);
 bool gemm_tuned(const GemmArgs &g, const GemmSpec &sp, GemmTuning &out);
 void gemm_tune_store(const GemmArgs &g, const GemmSpec &sp, const GemmTuning &t);

@@ -47,6 +47,7 @@ constexpr int BK = 64;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 // Offsets by index map: strides are powers of two, so each run is a shift.
@@ -151,10 +152,14 @@ __device__ __forceinline__ Sched schedule(int ntiles, int b, int G) {
 // one shift (no loop over runs in the per-tile address arithmetic).
 // REG = 3: general index maps, and the final step of one slice of a sliced
 // contraction adds its result into FP64 running sums (GemmArgs::acc_mode).
+// REG = 4: general index maps with K <= 16, staged as one K stage of 16
+// labels instead of 64 (a narrower tile in K: a quarter of the staging
+// loads, LDS and barrier time of a short contraction).
 template <int PREC, bool FOLD, bool OUTF, int REG>
 __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
-  constexpr bool ACC = REG == 3;  // slice-accumulating epilogue
-  constexpr int RG = ACC ? 0 : REG;  // index-map class
+  constexpr bool ACC = REG == 3;     // slice-accumulating epilogue
+  constexpr bool NARROW = REG == 4;  // K <= 16: one K stage of 16 labels
+  constexpr int RG = (ACC || NARROW) ? 0 : REG;  // index-map class
   constexpr bool SIMPLE = RG == 2;
   auto mx = [&](const IndexMap &mp, uint32_t v) -> int64_t {
     if constexpr (SIMPLE) return (int64_t)v << mp.lx[0];
@@ -168,11 +173,12 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   typedef typename Tr<PREC>::Acc Acc;
   constexpr int NACC = Tr<PREC>::NACC;
   constexpr bool SPLIT = PREC == SQC_BF16X3;
+  constexpr int KB = NARROW ? 16 : BK;  // staged K depth
   constexpr int PAD = 8;    // bf16 row padding (keeps rows 16-byte aligned)
-  constexpr int LDK = BK + PAD;
-  constexpr int NJ = 16;    // staged elements per thread per operand
+  constexpr int LDK = KB + PAD;
+  constexpr int NJ = KB / 4;  // staged elements per thread per operand (rows NJ wave + j)
   // F32/F64: As[k][m], Bs[k][n]; BF16X3: Ah, Al [m][k], Bh, Bl [n][k]
-  constexpr int kHalf = SPLIT ? (2 * BM * LDK * 2) : (BK * BM * (int)sizeof(T));
+  constexpr int kHalf = SPLIT ? (2 * BM * LDK * 2) : (KB * BM * (int)sizeof(T));
   __shared__ __attribute__((aligned(16))) unsigned char lds[2 * kHalf];
 
   const int tid = threadIdx.x;
@@ -230,12 +236,12 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   // the 16 k rows 16 wave + j
   const int64_t a_lane = mx(g.m, lane);
   const int64_t b_lane = mx(g.n, lane);
-  const int64_t a_kw = mx(g.k, 16 * wave);
-  const int64_t b_kw = my(g.k, 16 * wave);
+  const int64_t a_kw = mx(g.k, NJ * wave);
+  const int64_t b_kw = my(g.k, NJ * wave);
   T av[NJ], bv[NJ];
-  // k offsets of rows j = 0..15: shifts when the lowest run of k spans >= 4
-  // bits (the usual case), else a table staged in LDS
-  const bool kfast = RG || (g.k.nruns >= 1 && g.k.bits[0] >= 4);
+  // k offsets of rows j = 0..NJ-1: shifts when the lowest run of k spans
+  // them (the usual case), else a table staged in LDS
+  const bool kfast = RG || (g.k.nruns >= 1 && (1 << g.k.bits[0]) >= NJ);
   const int sa = g.k.lx[0], sb = g.k.ly[0];
   __shared__ int64_t ktab[2][NJ];
   if (!kfast) {
@@ -245,8 +251,8 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
     }
     __syncthreads();
   }
-  // a full K stage needs no per-row bound; rows past K (K < 64) read offset 0
-  const bool kfull = RG || g.kbits >= 6;
+  // a full K stage needs no per-row bound; rows past K (K < KB) read offset 0
+  const bool kfull = RG || (1 << g.kbits) >= KB;
   auto load_rows = [&](const T *p, T *v, int which, int s_shift, uint32_t k0) {
     if (kfull && kfast) {
       // (the row step passes an empty asm statement, so its 16 multiples are
@@ -257,7 +263,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) v[j] = p[j * step];
     } else {
-      const int kr = (int)(k0 + 16 * wave);
+      const int kr = (int)(k0 + NJ * wave);
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const bool in = (uint32_t)(kr + j) < K;
@@ -293,7 +299,19 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
     if constexpr (!SPLIT) {
       T *S = reinterpret_cast<T *>(dst);
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) S[(16 * wave + j) * ld + lane] = v[j];
+      for (int j = 0; j < NJ; ++j) S[(NJ * wave + j) * ld + lane] = v[j];
+    } else if constexpr (NARROW) {
+      // 4 consecutive k of one column: 8 bytes of hi and of lo
+      v4bf h, l;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const __bf16 a = (__bf16)v[j];
+        h[j] = a;
+        l[j] = (__bf16)(v[j] - (float)a);
+      }
+      __bf16 *H = reinterpret_cast<__bf16 *>(dst) + lane * LDK + 4 * wave;
+      *reinterpret_cast<v4bf *>(H) = h;
+      *reinterpret_cast<v4bf *>(H + BM * LDK) = l;
     } else {
       // 16 consecutive k of one column: two 16-byte rows of hi and of lo
       v8bf h0, h1, l0, l1;
@@ -408,10 +426,10 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
     }
     // ---- MFMA on the staged stage ----
     const uint32_t k0 = (uint32_t)cur_ks << 6;
-    const int kend = (RG || (K - k0) >= (uint32_t)BK) ? BK : (int)(K - k0);
-    if (kend == BK) {
+    const int kend = (RG || (K - k0) >= (uint32_t)KB) ? KB : (int)(K - k0);
+    if (kend == KB) {
 #pragma unroll
-      for (int kk = 0; kk < BK / KSTEP; ++kk) mfma_step(kk);
+      for (int kk = 0; kk < KB / KSTEP; ++kk) mfma_step(kk);
     } else {
       for (int kk = 0; kk * KSTEP < kend; ++kk) mfma_step(kk);
     }
@@ -1156,6 +1174,7 @@ int resident_groups() {
 // Calls L::run<PREC, FOLD, OUTF, REG>() for the specialisation `sp`.
 template <int PREC, bool FOLD, bool OUTF, class L>
 int dispatch_r(const GemmSpec &sp, const L &l) {
+  if (sp.reg == 4) return l.template run<PREC, FOLD, OUTF, 4>();
   if (sp.reg == 3) return l.template run<PREC, FOLD, OUTF, 3>();
   if (sp.reg == 2) return l.template run<PREC, FOLD, OUTF, 2>();
   if (sp.reg == 1) return l.template run<PREC, FOLD, OUTF, 1>();
@@ -1234,8 +1253,18 @@ GemmSpec prepare_gemm(GemmArgs &g, int prec) {
   return sp;
 }
 
+bool gemm_narrow_ok(const GemmArgs &g, const GemmSpec &sp) {
+  return g.kbits <= 4 && sp.reg == 0 && !sp.fold && !g.acc_mode;
+}
+
+GemmSpec gemm_default_spec(const GemmArgs &g, const GemmSpec &sp) {
+  GemmSpec d = sp;
+  if (gemm_narrow_ok(g, sp)) d.reg = 4;
+  return d;
+}
+
 int gemm_spec_id(const GemmSpec &sp) {
-  return ((sp.prec * 2 + (sp.fold ? 1 : 0)) * 2 + (sp.outf ? 1 : 0)) * 4 + sp.reg;
+  return ((sp.prec * 2 + (sp.fold ? 1 : 0)) * 2 + (sp.outf ? 1 : 0)) * 5 + sp.reg;
 }
 
 int gemm_groups(const GemmArgs &g, const GemmSpec &sp) { return dispatch(sp, GroupsQuery{gemm_tiles(g)}); }
@@ -1322,7 +1351,7 @@ void launch_gemm_grouped(const GemmSpec &sp, const GemmArgs *jobs, const int *st
 
 int launch_gemm(const GemmArgs &g_in, int prec, hipStream_t s) {
   GemmArgs g = g_in;
-  const GemmSpec sp = prepare_gemm(g, prec);
+  const GemmSpec sp = gemm_default_spec(g, prepare_gemm(g, prec));
   const int groups = gemm_groups(g, sp);
   launch_gemm_spec(g, sp, groups, s);
   return groups;

@@ -76,7 +76,8 @@ class StageTime(ctypes.Structure):
 
 class TuneReport(ctypes.Structure):
     _fields_ = [("steps", c_int32), ("candidates", c_int32), ("default_us", c_double),
-                ("tuned_us", c_double)]
+                ("tuned_us", c_double), ("step_tile", c_int32 * 64), ("step_groups", c_int32 * 64),
+                ("step_nmajor", c_int32 * 64)]
 
 
 class Request(ctypes.Structure):

@@ -65,3 +65,34 @@ def test_tuning_changes_no_bin(session, name, prec):
     assert sqc.autotune_entries() == 0
     b2, t2, s2 = run(session, circ, prec, M)
     assert torch.equal(b2, b0) and s2 == s0
+
+
+def test_tile_shapes_of_short_contractions(session):
+    """The 200-qubit chain (16 subcircuits, every step contracts at most 16
+    labels): the tuner times both tile shapes (K staged 64 deep, and the
+    narrow 16-deep tile) for every step, records the choice per step, and the
+    choice changes no bin (the MFMA steps and their operands are the same)."""
+    cc = configs.large()
+    var = qpu.all_variants(cc)
+    circ = runner.Circuit.from_cut_circuit(session, cc, var, sqc.F64)
+    circ.attribute(sqc.F32)
+    M = 1 << 20
+    sqc.autotune_reset()
+    b0, t0, s0 = run(session, circ, sqc.BF16X3, M)
+    masks = sqc.assign_bins(circ.g.n_data, None, M)
+    session.ensure_workspace(sqc.recurse_workspace_bytes(circ.att, circ.g, masks, sqc.BF16X3))
+    bins = torch.empty_like(b0)
+    rep = sqc.autotune(session.ctx, circ.att, circ.g, None, M, sqc.BF16X3, bins, sqc.F32, reps=3)
+    torch.cuda.synchronize()
+    tiles = [rep.step_tile[i] for i in range(rep.steps)]
+    say(f"autotune large: {rep.steps} steps, {rep.candidates} candidates, default {rep.default_us:.1f} us "
+        f"-> tuned {rep.tuned_us:.1f} us; 16-deep tile chosen for {sum(tiles)} of {rep.steps} steps")
+    assert rep.steps == 15 and all(t in (0, 1) for t in tiles)
+    assert all(rep.step_groups[i] >= 1 for i in range(rep.steps))
+    assert rep.candidates >= 2 * rep.steps  # both shapes timed for every step
+    assert rep.tuned_us <= rep.default_us + 1e-9
+    b1, t1, s1 = run(session, circ, sqc.BF16X3, M)
+    assert torch.equal(b1, b0) and torch.equal(bins, b0)
+    assert torch.equal(t1[:32].view(torch.int64), t0[:32].view(torch.int64))
+    assert abs(s1 - s0) <= 1e-14 * max(1.0, abs(s0))
+    sqc.autotune_reset()
