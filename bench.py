@@ -186,7 +186,10 @@ def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph, check):
             s.ensure_workspace(sqc.recurse_workspace_bytes(circ.att, circ.g, masks, prec))
             rep = sqc.autotune(s.ctx, circ.att, circ.g, None, M, prec, rec.bins, bins_prec, reps=5)
             tune = {"steps": rep.steps, "candidates": rep.candidates,
-                    "default_us": rep.default_us, "tuned_us": rep.tuned_us}
+                    "default_us": rep.default_us, "tuned_us": rep.tuned_us,
+                    "per_step": [{"tile": "16-deep" if rep.step_tile[i] else "64-deep",
+                                  "groups": rep.step_groups[i], "nmajor": rep.step_nmajor[i]}
+                                 for i in range(min(rep.steps, 64))]}
             log(f"[bench] {pname}: autotune {rep.steps} steps, {rep.default_us:.1f} -> "
                 f"{rep.tuned_us:.1f} us")
         for _ in range(warmup):
