@@ -401,6 +401,10 @@ struct Launches {
   std::vector<GemmArgs> steps;
   std::vector<GemmSpec> specs;
   std::vector<int> groups;
+  // dependency level of each step: 0 when it reads only merged inputs, else
+  // one more than the steps whose results it reads (steps of one level are
+  // independent and write distinct intermediates: they may share a launch)
+  std::vector<int> level;
   bool topr = false;
   TopRArgs t{};
   int path_f32 = 1;
@@ -424,7 +428,16 @@ void describe_contraction(Launches &L, const Contraction &c, const std::vector<c
   size_t inter_base = base;
   size_t stats_base = base + align256(c.plan.inter_bytes);
   size_t nsteps = c.unit ? 1 : c.plan.steps.size();
+  std::vector<int> tdepth(c.plan.tensors.size(), 0);  // inputs 0, results 1 + their step's level
   for (size_t si = 0; si < nsteps; ++si) {
+    if (c.unit) {
+      L.level.push_back(0);
+    } else {
+      const Step &st = c.plan.steps[si];
+      const int lv = std::max(tdepth[st.a], tdepth[st.b]);
+      L.level.push_back(lv);
+      tdepth[st.c] = lv + 1;
+    }
     GemmArgs g = step_args(c, si, inputs, ws, inter_base, bins, bins_f32, unit);
     g.nmajor = gemm_nmajor(g);
     if (g.mbits > 31 || g.nbits > 31 || g.kbits > 31)
@@ -1112,26 +1125,31 @@ void enqueue_batch(sqc_ctx *ctx, PreparedRecursion *const *p, int n, char *const
     merge_pass(rows, 2, at);
   }
 
-  // GEMM steps level by level (a request's step s + 1 reads its step s), one
-  // launch per kernel specialisation within a level
-  size_t levels = 0;
-  for (auto &L : Ls) levels = std::max(levels, L.steps.size());
-  for (size_t lv = 0; lv < levels; ++lv) {
-    std::map<int, std::vector<int>> by_spec;  // spec id -> requests
+  // GEMM steps level by level (a step reads only results of lower levels),
+  // one launch per kernel specialisation within a level: independent steps
+  // of one request share it as well as those of different requests
+  int levels = 0;
+  for (auto &L : Ls)
+    for (int lv : L.level) levels = std::max(levels, lv + 1);
+  for (int lv = 0; lv < levels; ++lv) {
+    std::map<int, std::vector<std::pair<int, int>>> by_spec;  // spec id -> (request, step)
     for (int i = 0; i < n; ++i)
-      if (lv < Ls[i].steps.size()) by_spec[gemm_spec_id(Ls[i].specs[lv])].push_back(i);
+      for (size_t si = 0; si < Ls[i].steps.size(); ++si)
+        if (Ls[i].level[si] == lv) by_spec[gemm_spec_id(Ls[i].specs[si])].push_back({i, (int)si});
     for (auto &kv : by_spec) {
-      std::stable_sort(kv.second.begin(), kv.second.end(),
-                       [&](int a, int b) { return Ls[a].groups[lv] > Ls[b].groups[lv]; });
+      std::stable_sort(kv.second.begin(), kv.second.end(), [&](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+        return Ls[a.first].groups[a.second] > Ls[b.first].groups[b.second];
+      });
       std::vector<GemmArgs> jobs;
       std::vector<int64_t> nb;
-      for (int i : kv.second) {
-        jobs.push_back(Ls[i].steps[lv]);
-        nb.push_back(Ls[i].groups[lv]);
+      for (auto &rs : kv.second) {
+        jobs.push_back(Ls[rs.first].steps[rs.second]);
+        nb.push_back(Ls[rs.first].groups[rs.second]);
       }
       const std::vector<int> start = block_prefix(nb);
       const size_t at = tab.put(jobs.data(), jobs.size());
-      descs.push_back(GroupedDesc{1, kv.first, Ls[kv.second[0]].specs[lv], at,
+      const auto &f = kv.second[0];
+      descs.push_back(GroupedDesc{1, kv.first, Ls[f.first].specs[f.second], at,
                                   tab.put(start.data(), start.size()), (int)jobs.size(), start.back()});
     }
   }
@@ -1682,13 +1700,22 @@ SearchPlan plan_search(sqc_ctx *ctx, const Graph &g, const sqc_tensor *att, uint
   }
   if (mt.cap) sp.groups.push_back(mt);
   if (mr.cap) sp.groups.push_back(mr);
-  std::map<std::pair<int, int>, GemmSpec> gkeys;
-  for (const Launches &L : sp.L)
-    for (size_t s = 0; s < L.steps.size(); ++s) gkeys[{(int)s, gemm_spec_id(L.specs[s])}] = L.specs[s];
+  // GEMM groups by (level, specialisation), as many job slots as the most
+  // steps of that key in one depth's recursion
+  std::map<std::pair<int, int>, std::pair<GemmSpec, int>> gkeys;
+  for (const Launches &L : sp.L) {
+    std::map<std::pair<int, int>, int> count;
+    for (size_t s = 0; s < L.steps.size(); ++s) ++count[{L.level[s], gemm_spec_id(L.specs[s])}];
+    for (size_t s = 0; s < L.steps.size(); ++s) {
+      const std::pair<int, int> key{L.level[s], gemm_spec_id(L.specs[s])};
+      auto &e = gkeys.emplace(key, std::make_pair(L.specs[s], 0)).first->second;
+      e.second = std::max(e.second, count[key]);
+    }
+  }
   for (auto &kv : gkeys) {
-    LiveGroup gg{2, kv.first.first, kv.second};
+    LiveGroup gg{2, kv.first.first, kv.second.first};
     gg.spec_id = kv.first.second;
-    gg.cap = 1;
+    gg.cap = kv.second.second;
     sp.groups.push_back(gg);
   }
   LiveGroup tg{3, -1, GemmSpec{}};
@@ -1751,13 +1778,18 @@ SearchPlan plan_search(sqc_ctx *ctx, const Graph &g, const sqc_tensor *att, uint
           if (st1) st1[k] = total1;
         }
       } else if (lg.kind == 2) {
-        const bool has = lg.level < (int)L.steps.size() && gemm_spec_id(L.specs[lg.level]) == lg.spec_id;
-        if (has) {
-          std::memcpy(img + lg.jobs, &L.steps[lg.level], sizeof(GemmArgs));
-          total0 = L.groups[lg.level];
+        // this depth's steps of the group's level and specialisation, the
+        // larger launches first
+        std::vector<int> mine;
+        for (size_t s = 0; s < L.steps.size(); ++s)
+          if (L.level[s] == lg.level && gemm_spec_id(L.specs[s]) == lg.spec_id) mine.push_back((int)s);
+        std::stable_sort(mine.begin(), mine.end(), [&](int a, int b) { return L.groups[a] > L.groups[b]; });
+        for (size_t k = 0; k < mine.size(); ++k) {
+          std::memcpy(img + lg.jobs + k * sizeof(GemmArgs), &L.steps[mine[k]], sizeof(GemmArgs));
+          st0[k] = total0;
+          total0 += L.groups[mine[k]];
         }
-        st0[0] = 0;
-        st0[1] = total0;
+        for (int k = (int)mine.size(); k <= lg.cap; ++k) st0[k] = total0;
       } else {
         TopRArgs t = L.t;
         std::memcpy(img + lg.jobs, &t, sizeof(TopRArgs));
