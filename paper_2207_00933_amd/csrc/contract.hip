@@ -584,7 +584,13 @@ __global__ __launch_bounds__(kThreads) void gemm_grouped(const GemmArgs *__restr
 constexpr int kTW = 4;                    // waves of the top-R work-groups
 constexpr int kTThreads = 64 * kTW;
 constexpr int kNG = kTThreads;            // groups of GEMM work-groups
-constexpr int kBufCap = 2048;             // buffered entries per work-group
+// Buffered entries per work-group: a full buffer is cut back to the R best
+// by counting (each thread ranks one entry against all), which needs at most
+// one entry per thread; many small cuts that raise the running R-th best
+// early cost far less than sorting a large buffer when the top is flat (many
+// tied bins).  (+4: the counting loop reads four entries at a time.)
+constexpr int kCutAt = kTThreads;
+constexpr int kBufCap = kCutAt + 4;
 
 // Exclusive prefix of v over the work-group; `total` gets the sum.  The wave
 // prefix is rocPRIM's (cross-lane DPP moves, no LDS round trips).
@@ -836,18 +842,18 @@ struct TopBuf {
       int total;
       int at = block_scan_excl(__builtin_popcount(want), wsum, total);
       if (total == 0) break;
-      if (n + total > kBufCap && n > R) {
+      if (n + total > kCutAt && n > R) {
         cut(R);
         continue;
       }
-      const int room = kBufCap - n;
+      const int room = kCutAt - n;
       at += n;
 #pragma unroll
       for (int u = 0; u < NU; ++u)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           if ((want >> (4 * u + q)) & 1) {
-            if (at < kBufCap) {
+            if (at < kCutAt) {
               val[at] = v[u][q];
               idx[at] = ix[u][q];
               done |= 1u << (4 * u + q);
@@ -1095,7 +1101,7 @@ __device__ __forceinline__ void topr_rank_body(const TopRArgs &t) {
       ix[0][q] = t.slot_idx[ff];
       if (!(f < npos && ff % R < cn)) ix[0][q] = ~uint64_t(0);
     }
-    buf.add_many(v, ix, 1, tau, R, wsum, false);
+    buf.add_many(v, ix, 1, tau, R, wsum, true);
   }
   buf.cut(R);
   if (tid < R) {
