@@ -1048,6 +1048,9 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
     // with one, to set an R-th best); each listed sub-tile is checked again
     // against the running R-th best
     for (int q = 0; q < total;) {
+      // the list is in visiting order (larger maximum, then lower origin): once
+      // one cannot beat the running R-th best, none after it can
+      if (!may_improve(lmx[q], lorg[q])) break;
       const int nl = min((buf.have_bar || q > 0 || total <= kVisit) ? kVisit : 1, total - q);
       double v[kVisit][4];
       uint64_t ix[kVisit][4];
