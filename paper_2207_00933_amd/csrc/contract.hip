@@ -630,7 +630,7 @@ struct SubTileBins {
   int lmt, lnt, nmaj;
   bool shifts;        // both maps are single runs: offsets are shifts
   int lym, lyn;
-  int64_t o_lane[4];  // thread's bins e = tid + 256 q: (e % 32, e / 32)
+  int64_t o_lane[4];  // thread's bins: (tid % 32, 4 (tid / 32) + q)
   bool ok[4];
   uint64_t span;      // largest offset of a bin from its sub-tile's origin
   __device__ void init(const TopRArgs &t) {
@@ -642,17 +642,20 @@ struct SubTileBins {
     shifts = t.m.nruns == 1 && t.n.nruns == 1;
     lym = t.m.ly[0];
     lyn = t.n.ly[0];
-    // bins q and q + 1 differ by 8 rows: o_lane[q] = o(ml, nl0) + o(8 q)
-    // (nl0 = tid / 32 < 8 for 256 threads, disjoint bits)
+    // a thread holds four consecutive rows: o_lane[q] = o(ml, 4 nl0) + o(q)
+    // (nl0 = tid / 32 < 8 for 256 threads, disjoint bits), so in thread
+    // order the buffer fills row block by row block: the lowest bin indices
+    // of a sub-tile come first (on a flat top, where many bins tie, the first
+    // cut then already holds the best)
     const uint32_t ml = threadIdx.x & 31, nl0 = threadIdx.x >> 5;
-    const int64_t o0 = offset(t, ml, nl0);
-    const int64_t r8 = offset(t, 0, 8), r16 = offset(t, 0, 16);
+    const int64_t o0 = offset(t, ml, 4 * nl0);
+    const int64_t r1 = offset(t, 0, 1), r2 = offset(t, 0, 2);
     o_lane[0] = o0;
-    o_lane[1] = o0 + r8;
-    o_lane[2] = o0 + r16;
-    o_lane[3] = o0 + r8 + r16;
+    o_lane[1] = o0 + r1;
+    o_lane[2] = o0 + r2;
+    o_lane[3] = o0 + r1 + r2;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ok[q] = ml < M && nl0 + 8 * q < N;
+    for (int q = 0; q < 4; ++q) ok[q] = ml < M && 4 * nl0 + q < N;
     span = (uint64_t)offset(t, (M < 32 ? M : 32) - 1, (N < 32 ? N : 32) - 1);
   }
   // index of the sub-tile's origin bin, the lowest index in it, or ~0 for a
@@ -699,61 +702,11 @@ struct TopBuf {
   }
   double *tv;      // [SQC_MAX_TOPR] staging of a small selection
   uint64_t *ti;
-  // keep the R best, in order (better first): few entries are ranked by
-  // counting the better ones; of many, a few best are taken one at a time
-  // (work-group argmax), more are sorted by a bitonic network (padded to a
-  // power of two with entries worse than any bin)
+  // keep the R best, in order (better first): the buffer never holds more
+  // than one entry per thread, and each thread ranks its entry by counting
+  // the better ones
   __device__ void cut(int R) {
-    if (n > kTThreads && R <= 8) {
-      __shared__ double sel_v[kTW];
-      __shared__ uint64_t sel_i[kTW];
-      __shared__ int sel_e[kTW];
-      const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-      for (int r = 0; r < R; ++r) {
-        double bv = -INFINITY;
-        uint64_t bi = ~uint64_t(0);
-        int be = -1;
-        for (int e = threadIdx.x; e < n; e += kTThreads) {
-          const uint64_t ie = idx[e];
-          const double ve = val[e];
-          if (ie != ~uint64_t(0) && (be < 0 || better(ve, ie, bv, bi))) {
-            bv = ve;
-            bi = ie;
-            be = e;
-          }
-        }
-        for (int off = 32; off >= 1; off >>= 1) {
-          const double ov = __shfl_xor(bv, off);
-          const uint64_t oi = __shfl_xor(bi, off);
-          const int oe = __shfl_xor(be, off);
-          if (oe >= 0 && (be < 0 || better(ov, oi, bv, bi))) {
-            bv = ov;
-            bi = oi;
-            be = oe;
-          }
-        }
-        if (lane == 0) {
-          sel_v[w] = bv;
-          sel_i[w] = bi;
-          sel_e[w] = be;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          int q = -1;
-          for (int x = 0; x < kTW; ++x)
-            if (sel_e[x] >= 0 && (q < 0 || better(sel_v[x], sel_i[x], sel_v[q], sel_i[q]))) q = x;
-          tv[r] = sel_v[q];  // n > R: every round finds an entry
-          ti[r] = sel_i[q];
-          idx[sel_e[q]] = ~uint64_t(0);  // taken
-        }
-        __syncthreads();
-      }
-      if ((int)threadIdx.x < R) {
-        val[threadIdx.x] = tv[threadIdx.x];
-        idx[threadIdx.x] = ti[threadIdx.x];
-      }
-      __syncthreads();
-    } else if (n <= kTThreads) {
+    {
       const int e = threadIdx.x;
       double v = 0.0;
       uint64_t i = 0;
@@ -786,31 +739,6 @@ struct TopBuf {
         idx[e] = ti[e];
       }
       __syncthreads();
-    } else {
-      int P = 2;
-      while (P < n) P <<= 1;
-      for (int e = n + (int)threadIdx.x; e < P; e += kTThreads) {
-        val[e] = -INFINITY;
-        idx[e] = ~uint64_t(0);
-      }
-      __syncthreads();
-      for (int k = 2; k <= P; k <<= 1)
-        for (int j = k >> 1; j >= 1; j >>= 1) {
-          for (int p = threadIdx.x; p < (P >> 1); p += kTThreads) {
-            const int lo = ((p / j) * 2 * j) + (p % j), hi = lo + j;
-            const double vl = val[lo], vh = val[hi];
-            const uint64_t il = idx[lo], ih = idx[hi];
-            // better entry first in blocks with (lo & k) == 0, last in the others
-            const bool swap = ((lo & k) == 0) ? better(vh, ih, vl, il) : better(vl, il, vh, ih);
-            if (swap) {
-              val[lo] = vh;
-              val[hi] = vl;
-              idx[lo] = ih;
-              idx[hi] = il;
-            }
-          }
-          __syncthreads();
-        }
     }
     n = n < R ? n : R;
     if (n == R) {
