@@ -1032,7 +1032,7 @@ __device__ __forceinline__ void topr_rank_body(const TopRArgs &t) {
       ix[0][q] = t.slot_idx[ff];
       if (!(f < npos && ff % R < cn)) ix[0][q] = ~uint64_t(0);
     }
-    buf.add_many(v, ix, 1, tau, R, wsum, true);
+    buf.add_many(v, ix, 1, tau, R, wsum, false);
   }
   buf.cut(R);
   if (tid < R) {
