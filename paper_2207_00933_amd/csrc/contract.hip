@@ -155,6 +155,9 @@ __device__ __forceinline__ Sched schedule(int ntiles, int b, int G) {
 // REG = 4: general index maps with K <= 16, staged as one K stage of 16
 // labels instead of 64 (a narrower tile in K: a quarter of the staging
 // loads, LDS and barrier time of a short contraction).
+// s_waitcnt operand of vmcnt(0) alone (expcnt and lgkmcnt at their maxima)
+constexpr int kWaitVmem0 = 0x0F70;
+
 template <int PREC, bool FOLD, bool OUTF, int REG>
 __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   constexpr bool ACC = REG == 3;     // slice-accumulating epilogue
@@ -333,6 +336,17 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   };
 
   Acc acc[NACC];
+  // FP32 results of a tile go out one tile late, after the next tile is
+  // staged: their writes then drain while that tile is multiplied instead of
+  // holding up its staging (a wait for the staged loads counts every
+  // vector-memory operation still in flight, stores included)
+  constexpr bool DEFER = OUTF && !ACC && !FOLD && PREC != SQC_F64;
+  float pend[DEFER ? 16 : 1];
+  float *pendC = nullptr;
+  uint32_t pmw = 0, pnw = 0;
+  double pmax = 0.0;  // the sub-tile maximum, stored with the results
+  int ptile = 0;
+  bool pend_c = false, pend_max = false;
   constexpr int NE = NACC * (PREC == SQC_F64 ? 4 : 16);  // result elements per lane
   double S[FOLD ? NE : 1], Cc[FOLD ? NE : 1];
   auto reset = [&]() {
@@ -396,6 +410,26 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
     c_lane_n = my(g.n, 4 * (lane >> 5));
   }
   reset();
+  // the deferred stores of the last tile (the same elements and order as
+  // the epilogue's stores)
+  auto flush_pending = [&]() {
+    if constexpr (DEFER) {
+      const bool whole = RG || (g.mbits >= 5 && g.nbits >= 5);
+      int64_t nstep = (int64_t)1 << g.n.ly[0];
+      asm volatile("" : "+s"(nstep));
+      if (pend_c) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const uint32_t nl = 8 * (r >> 2) + (r & 3);
+          const uint32_t mloc = lane & 31, nloc = nl + 4 * (lane >> 5);
+          if (!whole && (pmw + mloc >= M || pnw + nloc >= N)) continue;
+          __builtin_nontemporal_store(pend[r], pendC + (SIMPLE ? (int64_t)nl * nstep : g.coff_n[r]));
+        }
+      }
+      if (pend_max && lane == 0) g.blk_max[(int64_t)ptile * 4 + wave] = pmax;
+      pend_c = pend_max = false;
+    }
+  };
 
   // with a single K stage an operand panel stays staged while consecutive
   // tiles share it
@@ -406,7 +440,16 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
   while (true) {
     if (need_a) stage(av, lds, BM);
     if (need_b) stage(bv, lds + kHalf, BN);
+    if constexpr (DEFER) {
+      // every load issued so far has been staged: say so to the compiler,
+      // whose own waits assume a skipped staging leaves loads in flight and
+      // would hold the next loads behind the deferred stores
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+    }
     __syncthreads();
+    if constexpr (DEFER) {
+      if (pend_c || pend_max) flush_pending();
+    }
     // ---- prefetch the next (tile, stage) into registers ----
     const int cur_tile = tile, cur_ks = ks;
     bool more;
@@ -455,6 +498,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
         // FP32 results go out as non-temporal stores (the FP32 and
         // split-BF16x3 steps measured faster so), FP64 results as ordinary
         // stores (non-temporal measured slower there)
+        int pr = 0;  // the element's index in pend
         auto put = [&](uint32_t mloc, uint32_t nloc, int64_t o, double v) {
           if (!whole && (mw + mloc >= M || nw + nloc >= N)) return;
           if constexpr (ACC) {
@@ -473,7 +517,8 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
             v = sm + cp;
           }
           const O st = (O)v;
-          if constexpr (OUTF) __builtin_nontemporal_store(st, C + o);
+          if constexpr (DEFER) pend[pr] = st;
+          else if constexpr (OUTF) __builtin_nontemporal_store(st, C + o);
           else C[o] = st;
           lsum += v;
           omax = fmax(omax, st);
@@ -499,7 +544,14 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
             double v;
             if constexpr (FOLD) v = S[r] + Cc[r];
             else v = (double)acc[0][r];
+            pr = r;
             put(lane & 31, nl + 4 * (lane >> 5), SIMPLE ? (int64_t)nl * nstep : g.coff_n[r], v);
+          }
+          if constexpr (DEFER) {
+            pendC = reinterpret_cast<float *>(C);
+            pmw = mw;
+            pnw = nw;
+            pend_c = true;
           }
         }
         lmax = omax;
@@ -515,7 +567,13 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
           WaveMax().reduce(lmax, m, max_st[wave], [](O x, O y) { return fmax(x, y); });
           lmax = m;
         }
-        if (lane == 0) g.blk_max[(int64_t)cur_tile * 4 + wave] = (double)lmax;
+        if constexpr (DEFER) {
+          pmax = (double)lmax;
+          ptile = cur_tile;
+          pend_max = true;
+        } else if (lane == 0) {
+          g.blk_max[(int64_t)cur_tile * 4 + wave] = (double)lmax;
+        }
         neumaier(wsum, wcmp, lsum);
         wmax = fmax(wmax, (double)lmax);
       }
@@ -524,11 +582,22 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g, int blk, int G) {
     if (!more) break;
     __syncthreads();  // LDS is rewritten by the next stage
   }
+  if constexpr (DEFER) {
+    if (pend_c || pend_max) flush_pending();
+  }
   write_wg_stats();
 }
 
+// Waves per SIMD the compiler must leave registers for: four (all that the
+// work-group's LDS allows) for the split-BF16x3 regular shapes with FP32
+// results, whose values held for the late stores would otherwise cost one.
 template <int PREC, bool FOLD, bool OUTF, int REG>
-__global__ __launch_bounds__(kThreads) void gemm(GemmArgs g) {
+constexpr int gemm_waves() {
+  return (PREC == SQC_BF16X3 && !FOLD && OUTF && (REG == 1 || REG == 2)) ? 4 : 1;
+}
+
+template <int PREC, bool FOLD, bool OUTF, int REG>
+__global__ __launch_bounds__(kThreads, (gemm_waves<PREC, FOLD, OUTF, REG>())) void gemm(GemmArgs g) {
   gemm_body<PREC, FOLD, OUTF, REG>(g, blockIdx.x, gridDim.x);
 }
 
@@ -548,7 +617,7 @@ __device__ __forceinline__ int find_job(const int *__restrict__ start, int n, in
 // serving engine): job j owns work-groups [start[j], start[j + 1]) and runs
 // exactly as the single launch with start[j + 1] - start[j] work-groups.
 template <int PREC, bool FOLD, bool OUTF, int REG>
-__global__ __launch_bounds__(kThreads) void gemm_grouped(const GemmArgs *__restrict__ jobs,
+__global__ __launch_bounds__(kThreads, (gemm_waves<PREC, FOLD, OUTF, REG>())) void gemm_grouped(const GemmArgs *__restrict__ jobs,
                                                           const int *__restrict__ start, int n) {
   if ((int)blockIdx.x >= start[n]) return;  // (a grid sized for a larger table)
   const int j = find_job(start, n, blockIdx.x);
