@@ -635,13 +635,15 @@ __global__ __launch_bounds__(kThreads, (gemm_waves<PREC, FOLD, OUTF, REG>())) vo
 //     R-th largest group maximum (R groups hold a bin >= tau each, so tau is
 //     no larger than the R-th largest bin), found by counting, for every
 //     group, the groups better than it.
-//     Work-group w then visits the sub-tiles of its runs of 256 (runs w,
-//     w + gather_groups, ...) whose maximum reaches tau (and the running R-th
-//     best), best first; where many do, those whose maximum R others in the
-//     run provably beat are skipped.  It keeps its R best bins in an LDS
-//     buffer: a bin enters when it reaches tau and beats the buffer's R-th
-//     best so far, which is fixed as soon as R bins are in; a full buffer is
-//     cut back to its R best by a bitonic sort.  Its R best go to slot w.
+//     Work-group w then visits the sub-tiles of its runs (runs w,
+//     w + gather_groups, ...; 64 to 256 sub-tiles each, so that every
+//     work-group has one when there are few) whose maximum reaches tau (and
+//     the running R-th best), best first; where many do, those whose maximum
+//     R others in the run provably beat are skipped.  It keeps its R best bins
+//     in an LDS buffer: a bin enters when it reaches tau and beats the
+//     buffer's R-th best so far, which is fixed as soon as R bins are in; a
+//     full buffer is cut back to its R best by counting.  Its R best go to
+//     slot w.
 //   rank (one work-group): the slots are merged the same way.
 // The order is strict (larger value, then lower index), so the result is
 // unique: deterministic, no atomics.  Ties at the top cost no more than
@@ -887,8 +889,12 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
   const int ng = G < kNG ? G : kNG;  // group g: GEMM work-groups [g G / ng, (g+1) G / ng)
   // the first run's sub-tile maxima, loaded now so that their latency hides
   // behind the threshold
-  const int sb_first = bid * kTThreads + tid;
-  const double mx_first = sb_first < t.nsub ? t.blk_max[sb_first] : -INFINITY;
+  // runs of `run` sub-tiles (64 to 256: as many work-groups as there are
+  // take part in the visits when the bins are few)
+  int run = 64;
+  while (run < kTThreads && (int64_t)run * nb < t.nsub) run <<= 1;
+  const int sb_first = bid * run + tid;
+  const double mx_first = tid < run && sb_first < t.nsub ? t.blk_max[sb_first] : -INFINITY;
 
   // ---- group maxima (and, in work-group 0, the total sum) ----
   double s = 0.0, c = 0.0, gm = -INFINITY;
@@ -977,11 +983,11 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
     if (!buf.have_bar || mxq > buf.bar_v) return true;
     return mxq == buf.bar_v && orgq < buf.bar_i;
   };
-  for (int base = bid * kTThreads; base < t.nsub; base += nb * kTThreads) {
+  for (int base = bid * run; base < t.nsub; base += nb * run) {
     const int sb = base + tid;
-    const uint64_t org = sb < t.nsub ? stb.origin(t, sb) : ~uint64_t(0);
+    const uint64_t org = tid < run && sb < t.nsub ? stb.origin(t, sb) : ~uint64_t(0);
     const bool holds = org != ~uint64_t(0);
-    const double mx = !holds ? -INFINITY : (base == bid * kTThreads ? mx_first : t.blk_max[sb]);
+    const double mx = !holds ? -INFINITY : (base == bid * run ? mx_first : t.blk_max[sb]);
     const int keep = (holds && mx >= tau && may_improve(mx, org)) ? 1 : 0;
     int total;
     const int at = block_scan_excl(keep, wsum, total);
