@@ -281,6 +281,9 @@ Plan make_plan(const Graph &g, const std::vector<int> &bits, const int *order,
   }
   std::vector<int> work;
   for (int i = 0; i < g.n_sub; ++i) work.push_back(i);
+  // depth of each tensor in the contraction tree (inputs 0): steps whose
+  // operands are all below a depth can share one launch
+  std::vector<int> depth(g.n_sub, 0);
   int64_t ws = 0;
   int step_no = 0;
   while (work.size() > 1) {
@@ -291,23 +294,35 @@ Plan make_plan(const Graph &g, const std::vector<int> &bits, const int *order,
       if (wi < 0 || wj < 0 || wi >= (int)work.size() || wj >= (int)work.size() || wi == wj)
         raise(SQC_E_ARG, "contraction order names an invalid position");
     } else {
-      // greedy: connected pairs first, then smallest result, then fewest mults
+      // greedy: connected pairs first, then smallest result, then fewest
+      // mults.  Results of at most kSmallStep elements count as one size: a
+      // step that small costs its launch latency, not its size, so among
+      // them the pair of shallowest operands goes first, which keeps the
+      // tree shallow (a chain contracts as a balanced tree rather than a
+      // sweep) and lets independent steps share launches.
+      constexpr double kSmallStep = 65536.0;
       bool best_conn = false;
-      double best_size = 0;
-      double best_m = 0;
+      double best_eff = 0, best_size = 0, best_m = 0;
+      int best_depth = 0;
       for (size_t i = 0; i < work.size(); ++i)
         for (size_t j = i + 1; j < work.size(); ++j) {
           PairEval e = eval_pair(p.tensors[work[i]], p.tensors[work[j]]);
           bool conn = e.shared > 0;
+          const double eff = std::max(e.result_elems, kSmallStep);
+          const int dep = std::max(depth[work[i]], depth[work[j]]);
           bool better = false;
           if (wi < 0) better = true;
           else if (conn != best_conn) better = conn;
+          else if (eff != best_eff) better = eff < best_eff;
+          else if (dep != best_depth) better = dep < best_depth;
           else if (e.result_elems != best_size) better = e.result_elems < best_size;
           else if (e.mults != best_m) better = e.mults < best_m;
           if (better) {
             wi = (int)i;
             wj = (int)j;
             best_conn = conn;
+            best_eff = eff;
+            best_depth = dep;
             best_size = e.result_elems;
             best_m = e.mults;
           }
@@ -373,6 +388,7 @@ Plan make_plan(const Graph &g, const std::vector<int> &bits, const int *order,
     }
     int tc = (int)p.tensors.size();
     p.tensors.push_back(C);
+    depth.push_back(std::max(depth[ta], depth[tb]) + 1);
     st.c = tc;
     p.steps.push_back(st);
     // working list: result replaces position wi, position wj is removed
