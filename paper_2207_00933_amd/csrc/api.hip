@@ -976,6 +976,7 @@ PreparedPtr prepare_recursion(std::shared_ptr<const CircuitTopo> c, const sqc_ma
     // (describe_contraction adds the top-R stage only for a non-null top)
     t->L = describe_recursion(t->rp, c->att.data(), prec, nullptr, nullptr, nullptr, bins_prec, top_r,
                               reinterpret_cast<void *>(uintptr_t(16)), reinterpret_cast<void *>(uintptr_t(32)));
+    for (MergeArgs &a : t->L.merges) merge_shape(a);  // (depends on the shape only)
     std::lock_guard<std::mutex> lk(c->tmu);
     if (c->templates.size() >= 4096) c->templates.clear();  // bounded
     p->t = c->templates.emplace(key, std::move(t)).first->second;
@@ -1003,44 +1004,49 @@ const sqc_masks *prepared_masks(const PreparedRecursion &p) { return p.masks.dat
 
 namespace {
 
-// The request's launches: its shape's template with the workspace at ws, the
-// device's unit constant, the request's outputs and its fixed bits' values.
-Launches describe_prepared(sqc_ctx *ctx, const PreparedRecursion &p, char *ws) {
-  Launches L = p.t->L;
-  auto at = [ws](const void *rel) -> char * { return ws + reinterpret_cast<uintptr_t>(rel); };
-  for (size_t i = 0; i < L.merges.size(); ++i) {
-    MergeArgs &a = L.merges[i];
-    a.out = at(a.out);
-    a.partial = reinterpret_cast<double *>(at(a.partial));
-    a.fixed_val = p.masks[i].fixed_val;
-  }
-  const char *unit = reinterpret_cast<const char *>(ctx->unit);
+// A template record made the request's: workspace offsets become addresses
+// at ws, offsets below kCtlBytes addresses in the device's unit constant,
+// output markers the request's outputs, and the fixed bits their values.
+void relocate_merge(MergeArgs &a, const PreparedRecursion &p, char *ws, size_t k) {
+  a.out = ws + reinterpret_cast<uintptr_t>(a.out);
+  a.partial = reinterpret_cast<double *>(ws + reinterpret_cast<uintptr_t>(a.partial));
+  a.fixed_val = p.masks[k].fixed_val;
+}
+
+void relocate_gemm(GemmArgs &g, const PreparedRecursion &p, char *ws, const char *unit, bool last) {
   auto operand = [&](const void *rel) -> const void * {
     const uintptr_t v = reinterpret_cast<uintptr_t>(rel);
     return v < kCtlBytes ? static_cast<const void *>(unit + v) : static_cast<const void *>(ws + v);
   };
-  for (size_t si = 0; si < L.steps.size(); ++si) {
-    GemmArgs &g = L.steps[si];
-    g.A = operand(g.A);
-    g.B = operand(g.B);
-    g.C = si + 1 == L.steps.size() ? p.bins : static_cast<void *>(at(g.C));
-    if (g.stats) {
-      g.blk_max = reinterpret_cast<double *>(at(g.blk_max));
-      g.wg_stats = reinterpret_cast<double *>(at(g.wg_stats));
-    }
+  g.A = operand(g.A);
+  g.B = operand(g.B);
+  g.C = last ? p.bins : static_cast<void *>(ws + reinterpret_cast<uintptr_t>(g.C));
+  if (g.stats) {
+    g.blk_max = reinterpret_cast<double *>(ws + reinterpret_cast<uintptr_t>(g.blk_max));
+    g.wg_stats = reinterpret_cast<double *>(ws + reinterpret_cast<uintptr_t>(g.wg_stats));
   }
-  if (L.topr) {
-    TopRArgs &t = L.t;
-    t.C = p.bins;
-    t.blk_max = reinterpret_cast<const double *>(at(t.blk_max));
-    t.wg_stats = reinterpret_cast<const double *>(at(t.wg_stats));
-    t.tau_sum = reinterpret_cast<double *>(at(t.tau_sum));
-    t.slot_n = reinterpret_cast<int *>(at(t.slot_n));
-    t.slot_val = reinterpret_cast<double *>(at(t.slot_val));
-    t.slot_idx = reinterpret_cast<uint64_t *>(at(t.slot_idx));
-    t.top_out = static_cast<double *>(p.top);
-    t.sum_out = static_cast<double *>(p.sum);
-  }
+}
+
+void relocate_topr(TopRArgs &t, const PreparedRecursion &p, char *ws) {
+  auto at = [ws](const void *rel) -> char * { return ws + reinterpret_cast<uintptr_t>(rel); };
+  t.C = p.bins;
+  t.blk_max = reinterpret_cast<const double *>(at(t.blk_max));
+  t.wg_stats = reinterpret_cast<const double *>(at(t.wg_stats));
+  t.tau_sum = reinterpret_cast<double *>(at(t.tau_sum));
+  t.slot_n = reinterpret_cast<int *>(at(t.slot_n));
+  t.slot_val = reinterpret_cast<double *>(at(t.slot_val));
+  t.slot_idx = reinterpret_cast<uint64_t *>(at(t.slot_idx));
+  t.top_out = static_cast<double *>(p.top);
+  t.sum_out = static_cast<double *>(p.sum);
+}
+
+// The request's launches: its shape's template made the request's.
+Launches describe_prepared(sqc_ctx *ctx, const PreparedRecursion &p, char *ws) {
+  Launches L = p.t->L;
+  for (size_t i = 0; i < L.merges.size(); ++i) relocate_merge(L.merges[i], p, ws, i);
+  const char *unit = reinterpret_cast<const char *>(ctx->unit);
+  for (size_t si = 0; si < L.steps.size(); ++si) relocate_gemm(L.steps[si], p, ws, unit, si + 1 == L.steps.size());
+  if (L.topr) relocate_topr(L.t, p, ws);
   return L;
 }
 
@@ -1048,13 +1054,23 @@ Launches describe_prepared(sqc_ctx *ctx, const PreparedRecursion &p, char *ws) {
 struct TableImage {
   char *host;
   size_t cap, off = 0;
+  // room for n records of T, written in place by the caller
   template <class T>
-  size_t put(const T *v, size_t n) {
+  size_t reserve(size_t n) {
     const size_t at = align256(off);
     const size_t bytes = n * sizeof(T);
     if (at + bytes > cap) raise(SQC_E_NOMEM, "batch job table exceeds its staging buffer");
-    std::memcpy(host + at, v, bytes);
     off = at + bytes;
+    return at;
+  }
+  template <class T>
+  T *rec(size_t at) {
+    return reinterpret_cast<T *>(host + at);
+  }
+  template <class T>
+  size_t put(const T *v, size_t n) {
+    const size_t at = reserve<T>(n);
+    std::memcpy(host + at, v, n * sizeof(T));
     return at;
   }
 };
@@ -1090,37 +1106,51 @@ void enqueue_prepared(sqc_ctx *ctx, const PreparedRecursion &p, char *ws) {
 void enqueue_batch(sqc_ctx *ctx, PreparedRecursion *const *p, int n, char *const *ws, char *table_dev,
                    size_t table_bytes, void *staging, size_t staging_bytes) {
   use_device(ctx);
-  std::vector<Launches> Ls;
-  Ls.reserve(n);
-  for (int i = 0; i < n; ++i) Ls.push_back(describe_prepared(ctx, *p[i], ws[i]));
+  // every record goes from the request's template straight to its place in
+  // the staging image, made the request's there (one copy per record)
   TableImage tab{static_cast<char *>(staging), std::min(table_bytes, staging_bytes)};
   std::vector<GroupedDesc> descs;
+  const char *unit = reinterpret_cast<const char *>(ctx->unit);
+  auto T = [&](int i) -> const Launches & { return p[i]->t->L; };
 
-  // merges: every subcircuit of every request, one launch per pass
-  std::vector<MergeArgs> tiles, rows;
-  for (auto &L : Ls)
-    for (MergeArgs a : L.merges) {
-      merge_shape(a);
-      (merge_pass_blocks(a, 0) ? tiles : rows).push_back(a);
+  // merges: every subcircuit of every request, one launch per pass (shapes
+  // were set when the template was made)
+  struct Ref {
+    int i, k;
+    int64_t blocks;
+  };
+  std::vector<Ref> tiles, rows;
+  for (int i = 0; i < n; ++i)
+    for (size_t k = 0; k < T(i).merges.size(); ++k) {
+      const MergeArgs &a = T(i).merges[k];
+      const int64_t b0 = merge_pass_blocks(a, 0);
+      if (b0) tiles.push_back(Ref{i, (int)k, b0});
+      else rows.push_back(Ref{i, (int)k, merge_pass_blocks(a, 1)});
     }
-  auto merge_pass = [&](const std::vector<MergeArgs> &jobs, int pass, size_t at) {
-    std::vector<int64_t> nb(jobs.size());
-    for (size_t k = 0; k < jobs.size(); ++k) nb[k] = merge_pass_blocks(jobs[k], pass);
+  // larger jobs first: their work-groups start first and the launch ends sooner
+  auto larger = [](const Ref &a, const Ref &b) { return a.blocks > b.blocks; };
+  std::stable_sort(tiles.begin(), tiles.end(), larger);
+  std::stable_sort(rows.begin(), rows.end(), larger);
+  auto put_merges = [&](const std::vector<Ref> &refs) {
+    const size_t at = tab.reserve<MergeArgs>(refs.size());
+    MergeArgs *d = tab.rec<MergeArgs>(at);
+    for (size_t q = 0; q < refs.size(); ++q) {
+      d[q] = T(refs[q].i).merges[refs[q].k];
+      relocate_merge(d[q], *p[refs[q].i], ws[refs[q].i], refs[q].k);
+    }
+    return at;
+  };
+  auto merge_pass = [&](const std::vector<Ref> &refs, int pass, size_t at) {
+    const MergeArgs *d = tab.rec<MergeArgs>(at);
+    std::vector<int64_t> nb(refs.size());
+    for (size_t q = 0; q < refs.size(); ++q) nb[q] = merge_pass_blocks(d[q], pass);
     const std::vector<int> start = block_prefix(nb);
     descs.push_back(GroupedDesc{0, pass, GemmSpec{}, at, tab.put(start.data(), start.size()),
-                                (int)jobs.size(), start.back()});
+                                (int)refs.size(), start.back()});
   };
-  // larger jobs first: their work-groups start first and the launch ends sooner
-  auto by_blocks = [](int pass) {
-    return [pass](const MergeArgs &a, const MergeArgs &b) {
-      return merge_pass_blocks(a, pass) > merge_pass_blocks(b, pass);
-    };
-  };
-  std::stable_sort(tiles.begin(), tiles.end(), by_blocks(0));
-  std::stable_sort(rows.begin(), rows.end(), by_blocks(1));
-  if (!tiles.empty()) merge_pass(tiles, 0, tab.put(tiles.data(), tiles.size()));
+  if (!tiles.empty()) merge_pass(tiles, 0, put_merges(tiles));
   if (!rows.empty()) {
-    const size_t at = tab.put(rows.data(), rows.size());
+    const size_t at = put_merges(rows);
     merge_pass(rows, 1, at);
     merge_pass(rows, 2, at);
   }
@@ -1129,44 +1159,51 @@ void enqueue_batch(sqc_ctx *ctx, PreparedRecursion *const *p, int n, char *const
   // one launch per kernel specialisation within a level: independent steps
   // of one request share it as well as those of different requests
   int levels = 0;
-  for (auto &L : Ls)
-    for (int lv : L.level) levels = std::max(levels, lv + 1);
+  for (int i = 0; i < n; ++i)
+    for (int lv : T(i).level) levels = std::max(levels, lv + 1);
   for (int lv = 0; lv < levels; ++lv) {
-    std::map<int, std::vector<std::pair<int, int>>> by_spec;  // spec id -> (request, step)
-    for (int i = 0; i < n; ++i)
-      for (size_t si = 0; si < Ls[i].steps.size(); ++si)
-        if (Ls[i].level[si] == lv) by_spec[gemm_spec_id(Ls[i].specs[si])].push_back({i, (int)si});
+    std::map<int, std::vector<Ref>> by_spec;  // spec id -> (request, step, work-groups)
+    for (int i = 0; i < n; ++i) {
+      const Launches &L = T(i);
+      for (size_t si = 0; si < L.steps.size(); ++si)
+        if (L.level[si] == lv) by_spec[gemm_spec_id(L.specs[si])].push_back(Ref{i, (int)si, L.groups[si]});
+    }
     for (auto &kv : by_spec) {
-      std::stable_sort(kv.second.begin(), kv.second.end(), [&](const std::pair<int, int> &a, const std::pair<int, int> &b) {
-        return Ls[a.first].groups[a.second] > Ls[b.first].groups[b.second];
-      });
-      std::vector<GemmArgs> jobs;
-      std::vector<int64_t> nb;
-      for (auto &rs : kv.second) {
-        jobs.push_back(Ls[rs.first].steps[rs.second]);
-        nb.push_back(Ls[rs.first].groups[rs.second]);
+      std::vector<Ref> &refs = kv.second;
+      std::stable_sort(refs.begin(), refs.end(), larger);
+      const size_t at = tab.reserve<GemmArgs>(refs.size());
+      GemmArgs *d = tab.rec<GemmArgs>(at);
+      std::vector<int64_t> nb(refs.size());
+      for (size_t q = 0; q < refs.size(); ++q) {
+        const Launches &L = T(refs[q].i);
+        d[q] = L.steps[refs[q].k];
+        relocate_gemm(d[q], *p[refs[q].i], ws[refs[q].i], unit, refs[q].k + 1 == (int)L.steps.size());
+        nb[q] = refs[q].blocks;
       }
       const std::vector<int> start = block_prefix(nb);
-      const size_t at = tab.put(jobs.data(), jobs.size());
-      const auto &f = kv.second[0];
-      descs.push_back(GroupedDesc{1, kv.first, Ls[f.first].specs[f.second], at,
-                                  tab.put(start.data(), start.size()), (int)jobs.size(), start.back()});
+      const Ref &f = refs[0];
+      descs.push_back(GroupedDesc{1, kv.first, T(f.i).specs[f.k], at, tab.put(start.data(), start.size()),
+                                  (int)refs.size(), start.back()});
     }
   }
 
   // top-R of every request, one launch per bins precision
   for (int outf = 0; outf < 2; ++outf) {
-    std::vector<TopRArgs> tops;
-    for (auto &L : Ls)
-      if (L.topr && L.t.out_f32 == outf) tops.push_back(L.t);
-    if (tops.empty()) continue;
-    std::stable_sort(tops.begin(), tops.end(),
-                     [](const TopRArgs &a, const TopRArgs &b) { return a.nsub > b.nsub; });
-    std::vector<int64_t> nb;
-    for (auto &t : tops) nb.push_back(t.gather_groups);
+    std::vector<Ref> refs;
+    for (int i = 0; i < n; ++i)
+      if (T(i).topr && T(i).t.out_f32 == outf) refs.push_back(Ref{i, 0, T(i).t.nsub});
+    if (refs.empty()) continue;
+    std::stable_sort(refs.begin(), refs.end(), larger);
+    const size_t at = tab.reserve<TopRArgs>(refs.size());
+    TopRArgs *d = tab.rec<TopRArgs>(at);
+    std::vector<int64_t> nb(refs.size());
+    for (size_t q = 0; q < refs.size(); ++q) {
+      d[q] = T(refs[q].i).t;
+      relocate_topr(d[q], *p[refs[q].i], ws[refs[q].i]);
+      nb[q] = d[q].gather_groups;
+    }
     const std::vector<int> start = block_prefix(nb);
-    const size_t at = tab.put(tops.data(), tops.size());
-    descs.push_back(GroupedDesc{2, outf, GemmSpec{}, at, tab.put(start.data(), start.size()), (int)tops.size(),
+    descs.push_back(GroupedDesc{2, outf, GemmSpec{}, at, tab.put(start.data(), start.size()), (int)refs.size(),
                                 start.back()});
   }
 
