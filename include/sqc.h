@@ -474,8 +474,10 @@ sqc_status sqc_recurse_noalloc(sqc_ctx *ctx, const sqc_tensor *attributed, int32
  * with M = 1; probs_dev[j] (probs_prec) receives the reconstructed value.
  * States are processed in batches whose merges, contraction steps and
  * selections share launches (job tables staged through the context's pinned
- * buffer); the call waits for the device after each batch, so it cannot be
- * recorded into a graph.  Repeated states are allowed.  Workspace:
+ * buffer); two batches are in flight at most (the host forms one while the
+ * device runs the other, and waits before reusing a batch's staging), and the
+ * call returns once the last batch has finished, so it cannot be recorded
+ * into a graph.  Repeated states are allowed.  Workspace:
  * sqc_query_states_workspace_bytes (independent of n_states).  Errors:
  * SQC_E_ARG for a NULL buffer, a state out of range or while recording, else
  * as sqc_recurse. */

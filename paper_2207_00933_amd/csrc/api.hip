@@ -75,7 +75,7 @@ namespace {
 constexpr size_t kCtlBytes = 4096;
 // Pinned host buffer of a context: small device results (search) and the
 // job tables of a subset query's batches.
-constexpr size_t kPinnedBytes = 1 << 20;
+constexpr size_t kPinnedBytes = 2 << 20;
 constexpr size_t kOffSearchTop = 256;    // SQC_MAX_TOPR x 16 bytes
 constexpr size_t kOffSearchSum = 256 + 16 * SQC_MAX_TOPR;
 
@@ -1341,7 +1341,7 @@ SliceArgs slice_args(const SlicedPlan &sp, int i, const sqc_tensor &t, void *out
 
 namespace {
 
-constexpr size_t kQueryStaging = kPinnedBytes;
+constexpr size_t kQueryStaging = kPinnedBytes / 2;  // per batch in flight (two)
 constexpr int kQueryMaxBatch = 128;
 
 // Every data bit fixed: the bin of one state.
@@ -1364,7 +1364,9 @@ struct QueryPlan {
   std::vector<int> d;
   int total_bits = 0;
   int batch = 1;
-  size_t req_ws = 0, table = 0, outs = 0, total = 0;
+  size_t req_ws = 0, table = 0, outs = 0;
+  size_t slot = 0;   // workspace of one batch in flight (job table, requests)
+  size_t total = 0;  // the control region and two slots
 };
 
 QueryPlan plan_query(const sqc_tensor *att, int32_t n_sub, const sqc_cut *cuts, int32_t n_cuts, sqc_prec prec) {
@@ -1384,7 +1386,8 @@ QueryPlan plan_query(const sqc_tensor *att, int32_t n_sub, const sqc_cut *cuts, 
   q.batch = (int)std::max<size_t>(1, std::min<size_t>(kQueryMaxBatch, kQueryStaging / tb));
   q.table = align256(tb * q.batch);
   q.outs = 256;  // per request: top-1 record and sum
-  q.total = kCtlBytes + q.table + (size_t)q.batch * (q.req_ws + q.outs);
+  q.slot = align256(q.table + (size_t)q.batch * (q.req_ws + q.outs));
+  q.total = kCtlBytes + 2 * q.slot;
   return q;
 }
 
@@ -2326,9 +2329,25 @@ sqc_status sqc_query_states(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t 
   need_ws(ctx, q.total);
   use_device(ctx);
   const size_t elem = probs_prec == SQC_F32 ? 4 : 8;
-  char *table = ctx->ws + kCtlBytes;
-  char *reqs = table + q.table;
-  for (int64_t j0 = 0; j0 < n_states; j0 += q.batch) {
+  // two batches in flight: batch k uses half k % 2 of the pinned staging
+  // buffer and slot k % 2 of the workspace, and the host forms batch k + 1
+  // while the device runs batch k; a half is rewritten only once the batch
+  // two before has finished with it (its event)
+  struct Events {  // returned to the pool on every exit
+    sqc_ctx *c;
+    hipEvent_t e[2];
+    ~Events() {
+      c->pool.push_back(e[0]);
+      c->pool.push_back(e[1]);
+    }
+  } ev{ctx, {take_event(ctx), take_event(ctx)}};
+  int64_t k = 0;
+  for (int64_t j0 = 0; j0 < n_states; j0 += q.batch, ++k) {
+    const int half = (int)(k & 1);
+    if (k >= 2) check_hip(hipEventSynchronize(ev.e[half]), "hipEventSynchronize");
+    char *table = ctx->ws + kCtlBytes + half * q.slot;
+    char *reqs = table + q.table;
+    char *staging = static_cast<char *>(ctx->pinned) + half * kQueryStaging;
     const int n = (int)std::min<int64_t>(q.batch, n_states - j0);
     std::vector<PreparedPtr> ps;
     std::vector<PreparedRecursion *> raw;
@@ -2342,10 +2361,10 @@ sqc_status sqc_query_states(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t 
       raw.push_back(ps.back().get());
       ws.push_back(w);
     }
-    enqueue_batch(ctx, raw.data(), n, ws.data(), table, q.table, ctx->pinned, kQueryStaging);
-    // the next batch rewrites the pinned staging buffer and the workspace
-    check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    enqueue_batch(ctx, raw.data(), n, ws.data(), table, q.table, staging, kQueryStaging);
+    check_hip(hipEventRecord(ev.e[half], ctx->stream), "hipEventRecord");
   }
+  check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
   return SQC_OK;
   SQC_CATCH(ctx)
 }
