@@ -883,6 +883,7 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
   __shared__ double lmx[kTThreads];
   __shared__ uint64_t lorg[kTThreads];
   __shared__ double wmax[kTW];
+  __shared__ double sw[kTThreads];  // work-group maxima that reach tau
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = t.top_r;
   const int G = t.ngroups;
@@ -898,6 +899,7 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
 
   // ---- group maxima (and, in work-group 0, the total sum) ----
   double s = 0.0, c = 0.0, gm = -INFINITY;
+  double wm[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};  // the group's work-group maxima
   if (tid < ng) {
     const int w0 = tid * G / ng, w1 = (tid + 1) * G / ng;
     for (int w = w0; w < w1; w += 4) {
@@ -911,6 +913,7 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
           neumaier(s, c, x[j][0]);
           c += x[j][1];
           gm = fmax(gm, x[j][2]);
+          if (w == w0) wm[j] = x[j][2];
         }
     }
   }
@@ -959,7 +962,46 @@ __device__ __forceinline__ void topr_gather_body(const TopRArgs &t, int bid, int
     s_tau = m;  // -inf with fewer groups than R
   }
   __syncthreads();
-  const double tau = s_tau;  // -inf with fewer groups than R
+  double tau = s_tau;  // -inf with fewer groups than R
+  // ---- refinement: the R-th largest GEMM work-group maximum, a tighter
+  // threshold (R work-groups hold a bin >= it each) when the top is flat and
+  // many groups reach tau.  Every work-group maximum that reaches tau is
+  // collected (at least R do) and ranked by counting, as above; skipped when
+  // a group holds more than four work-groups or more than kTThreads reach
+  // tau (tau stays valid). ----
+  if (G <= 4 * ng && tau > -INFINITY) {
+    int keepw = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) keepw += wm[j] >= tau ? 1 : 0;
+    int nw;
+    int at = block_scan_excl(keepw, wsum, nw);
+    if (nw <= kTThreads) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (wm[j] >= tau) sw[at++] = wm[j];
+      __syncthreads();
+      double cand2 = -INFINITY;
+      if (tid < nw) {
+        const double me = sw[tid];
+        int cnt = 0;
+        for (int j = 0; j < nw; ++j) cnt += sw[j] >= me ? 1 : 0;
+        if (cnt >= R) cand2 = me;
+      }
+      {
+        using WaveMax = rocprim::warp_reduce<double, 64>;
+        __shared__ typename WaveMax::storage_type max_st2[kTW];
+        double m;
+        WaveMax().reduce(cand2, m, max_st2[wave], rocprim::maximum<double>());
+        cand2 = m;
+      }
+      if (lane == 0) wmax[wave] = cand2;
+      __syncthreads();
+      double m = wmax[0];
+      for (int q = 1; q < kTW; ++q) m = fmax(m, wmax[q]);
+      tau = fmax(tau, m);
+      __syncthreads();  // (wmax and sw are not read again)
+    }
+  }
   if (bid == 0 && tid == 0) {
     double S = ps[0], Cc = pc[0];
     for (int q = 1; q < kTW; ++q) two_sum_merge(S, Cc, ps[q], pc[q]);
