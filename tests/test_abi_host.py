@@ -165,6 +165,42 @@ def test_cost_model_matches_oracle_on_workloads():
                                               rel=1e-12)
 
 
+def _plan_depth(n_sub, order, n_steps):
+    """Depth of the contraction tree of a plan given as (position, position)
+    pairs over the working list (the result replaces the first position, the
+    second is removed)."""
+    work, depth = list(range(n_sub)), {i: 0 for i in range(n_sub)}
+    nxt, deepest = n_sub, 0
+    for s in range(n_steps):
+        i, j = order[2 * s], order[2 * s + 1]
+        d = max(depth[work[i]], depth[work[j]]) + 1
+        deepest = max(deepest, d)
+        depth[nxt] = d
+        work[i] = nxt
+        work.pop(j)
+        nxt += 1
+    return deepest
+
+
+def test_planner_keeps_chains_of_small_steps_shallow():
+    """The 200-qubit chain (16 subcircuits, 24 cuts) with the active bits of a
+    recursion below the first (0 or 1 per subcircuit), where every step is
+    small (at most 2^16 result elements): the planner pairs shallow operands
+    first, so the tree has depth 5 (size first alone gives depth 11 here, a
+    sweep along the chain 15)."""
+    cc = configs.large()
+    n = cc.n_sub
+    cuts = [(c.up_sub, c.down_sub) for c in cc.cuts]
+    bits = [0] * 8 + [1] * 8
+    c = sqc.plan_cost(bits, cuts, None)
+    assert c.n_steps == n - 1
+    depth = _plan_depth(n, c.order, c.n_steps)
+    assert depth <= 5, depth
+    # with large subcircuits the sizes decide: no worse than the sweep
+    big = sqc.plan_cost([12] * n, cuts, None)
+    assert big.plan_mults <= sqc.plan_cost([12] * n, cuts, [0, 1] * (n - 1)).plan_mults
+
+
 def test_slicing_paper_example():
     qubits = EX["graph"]["qubits"]
     cuts = EX["graph"]["cuts"]

@@ -1,8 +1,10 @@
 """GPU parity of arbitrary-subset queries (Sec. 3: chosen states evaluated in
 one recursion without merging) against Eq. 1 evaluated state by state by the
 oracle, through the C interface.  Small physical circuits (every precision,
-random states plus the first, the last and a repeated one, more states than
-one batch holds) and the precision workload (24 qubits, 256 random states).
+random states plus the first, the last and a repeated one), 1000 states of a
+small circuit (eight batches of at most 128: the two batch slots are reused
+after their earlier batch finished), and the precision workload (24 qubits,
+256 random states).
 Tolerances: 1e-12 for FP64, 1e-6 for the FP32-MFMA and split-BF16x3 paths
 (physical data, probabilities <= 1); the 24-qubit states are also held to the
 path's a-priori bound (unit roundoff times the |T| contraction at the state)."""
@@ -68,6 +70,23 @@ def test_query_states_small(session, name, pname, prec):
     states.append(states[5])  # a repeated state
     want = rc.eval_bins(Ts, cc, np.array(states))
     say(f"query {name} {pname}: {len(states)} states")
+    got = _query(session, cc, var, prec, states)
+    err = np.abs(got - want).max()
+    say(f"  max |gpu - oracle| = {err:.3e}")
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("pname,prec", [("f64", sqc.F64), ("bf16x3", sqc.BF16X3)])
+def test_query_states_many_batches(session, pname, prec):
+    """More batches than slots: every state of every batch is right, so a
+    batch's staging and workspace were not rewritten while it still ran."""
+    cc = _cases()["chain4"]
+    var = qpu.all_variants(cc)
+    Ts = [rc.attribute(cc, i, var[i]) for i in range(cc.n_sub)]
+    rng = np.random.default_rng(23)
+    states = [int(x) for x in rng.integers(0, 1 << cc.n, size=1000)]
+    want = rc.eval_bins(Ts, cc, np.array(states))
+    say(f"query chain4 {pname}: {len(states)} states")
     got = _query(session, cc, var, prec, states)
     err = np.abs(got - want).max()
     say(f"  max |gpu - oracle| = {err:.3e}")
