@@ -176,8 +176,12 @@ def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph, check):
         bins_prec = sqc.F64 if prec == sqc.F64 else sqc.F32
         rec = runner.Recursion(circ, nbits, bins_prec, 16)
 
-        def step():
-            circ.attribute(att_prec)
+        # the step attributes straight into the merged layout of this
+        # full-output recursion (sqc_attribute_all_merged: its merge is a
+        # transposition, done by the attribution's stores); merged=False is
+        # the same step with a separate merge pass, timed below as well
+        def step(merged=True):
+            circ.attribute(att_prec, merged=merged)
             rec.run(prec, M)
 
         tune = None
@@ -226,6 +230,20 @@ def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph, check):
             evs[k + 1].record()
         torch.cuda.synchronize()
         lat = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(steps))
+        # the unfused step (attribution, then the merge kernel), timed the
+        # same way (the same dispatch events every FINAL_EVERY-th step)
+        for _ in range(warmup):
+            step(merged=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            sqc.ctx_set_timing(s.ctx, timed if k % FINAL_EVERY == 0 else 0)
+            step(merged=False)
+        torch.cuda.synchronize()
+        ums = (time.perf_counter() - t0) * 1e3 / steps
+        sqc.ctx_set_timing(s.ctx, 0)
+        sqc.ctx_timing(s.ctx, sqc.STAGE_FINAL, reset=True)
+        log(f"[bench] {pname}: unfused step (separate merge) {ums:.4f} ms/step")
         res = {
             "ms_per_step": ms,
             "bins_per_s": M / (ms * 1e-3),
@@ -236,6 +254,7 @@ def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph, check):
             "final_kernel_flops": fin.flops / max(1, fin.launches),
             "bins_sum": rec.sum.item(),
             "autotune": tune,
+            "unfused_ms_per_step": ums,
         }
         if graph:
             # the same step recorded once into a HIP graph and replayed: one

@@ -293,6 +293,23 @@ sqc_status sqc_attribute_all(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub,
                              const sqc_cut *cuts, int32_t n_cuts,
                              const void *const *variants_dev, sqc_prec in_prec,
                              sqc_tensor *outs);
+/* The attribution written straight in the merged layout (Sec. 2.1 and Sec. 4
+ * in one pass): outs[i] receives subcircuit i's tensor as sqc_merge would
+ * produce it for a recursion that keeps every data bit of the subcircuit
+ * active (nothing fixed or merged), [4^c][2^d] with the bins fastest, layout
+ * SQC_LAYOUT_MERGED, each value exactly the one sqc_attribute_all followed
+ * by that merge stores.  Such a tensor can be contracted by sqc_contract or
+ * passed to sqc_recurse for a recursion whose masks keep all its data bits
+ * active (a full-output recursion: M at least the product of the 2^d_i), in
+ * the path's operand precision (out->prec FP64 for SQC_F64, FP32 for the
+ * other paths); that recursion then reads it in place and runs no merge for
+ * it.  Other recursions, SQC_AUTO, slicing, the search, queries and serving
+ * need the attributed layout (SQC_E_ARG or SQC_E_SHAPE otherwise).
+ * Arguments as for sqc_attribute_all. */
+sqc_status sqc_attribute_all_merged(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub,
+                                    const sqc_cut *cuts, int32_t n_cuts,
+                                    const void *const *variants_dev, sqc_prec in_prec,
+                                    sqc_tensor *outs);
 
 /* ---- merging (Sec. 4) ------------------------------------------------------ */
 
@@ -368,9 +385,13 @@ sqc_status sqc_contract_sliced(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n
  * are written to `masks_out` (host, n_sub entries) before the call returns;
  * the device results are ready when the stream reaches them.
  * `attributed[i].prec` may differ from `prec` (SQC_F64 attributed with an
- * FP32 path is allowed).  prec = SQC_AUTO selects the precision first
- * (sqc_select_precision: waits for the device, not while recording a graph);
- * its workspace query covers every choice.
+ * FP32 path is allowed).  A tensor may instead be in the merged layout
+ * (sqc_attribute_all_merged) when the recursion keeps every data bit of its
+ * subcircuit active and it is stored in the path's operand precision: it is
+ * then read in place and not merged (else SQC_E_ARG).  prec = SQC_AUTO
+ * selects the precision first (sqc_select_precision: waits for the device,
+ * not while recording a graph; attributed layout only); its workspace query
+ * covers every choice.
  *
  * Memory-driven slicing (Sec. 6.3): when the context's workspace is smaller
  * than the unsliced recursion needs (sqc_recurse_workspace_bytes), the call
@@ -387,7 +408,9 @@ sqc_status sqc_contract_sliced(sqc_ctx *ctx, const sqc_tensor *merged, int32_t n
  * digit), so results are deterministic; they equal the unsliced results up
  * to rounding.  The sliced workspace holds each subcircuit's slice of merged
  * rows, the sliced network's intermediates and two 2^a FP64 vectors.  With
- * SQC_AUTO the precision selector's own pass must fit unsliced. */
+ * SQC_AUTO the precision selector's own pass must fit unsliced; a recursion
+ * with merged-layout inputs is not sliced (SQC_E_ARG when it would need to
+ * be). */
 size_t sqc_recurse_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub,
                                    const sqc_cut *cuts, int32_t n_cuts,
                                    const sqc_masks *masks, sqc_prec prec);

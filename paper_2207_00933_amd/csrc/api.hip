@@ -290,14 +290,40 @@ struct MergeLayout {
 };
 MergeLayout layout_merges(Bump &b, const sqc_tensor *att, const sqc_masks *masks, int n_sub, int eb) {
   MergeLayout L;
+  // (an input already in the merged layout is read in place: no buffers)
   for (int i = 0; i < n_sub; ++i)
-    L.merged_off.push_back(
-        b.take(((size_t)1 << (2 * att[i].n_labels + __builtin_popcountll(masks[i].active))) * eb));
+    L.merged_off.push_back(att[i].layout == SQC_LAYOUT_MERGED
+                               ? 0
+                               : b.take(((size_t)1 << (2 * att[i].n_labels + __builtin_popcountll(masks[i].active))) * eb));
   for (int i = 0; i < n_sub; ++i) {
-    const size_t part = merge_ws(att[i], masks[i]);
+    const size_t part = att[i].layout == SQC_LAYOUT_MERGED ? 0 : merge_ws(att[i], masks[i]);
     L.partial_off.push_back(part ? b.take(part) : 0);
   }
   return L;
+}
+
+// Inputs already in the merged layout (sqc_attribute_all_merged) serve a
+// recursion that keeps every data bit of their subcircuit active, in the
+// path's operand precision; returns whether there is any.
+bool check_merged_inputs(const sqc_tensor *att, const sqc_masks *masks, int n_sub, sqc_prec prec) {
+  bool any = false;
+  for (int i = 0; i < n_sub; ++i) {
+    if (att[i].layout != SQC_LAYOUT_MERGED) continue;
+    any = true;
+    const uint64_t all = att[i].n_bits >= 64 ? ~0ull : ((1ull << att[i].n_bits) - 1);
+    std::ostringstream m;
+    if (masks[i].fixed != 0 || masks[i].merged != 0 || masks[i].active != all) {
+      m << "tensor " << i << " is in the merged layout, which serves only a recursion that keeps every data bit "
+        << "of its subcircuit active (nothing fixed or merged)";
+      raise(SQC_E_ARG, m.str());
+    }
+    if (att[i].prec != (prec == SQC_F64 ? SQC_F64 : SQC_F32)) {
+      m << "tensor " << i << " is in the merged layout and must then be stored in the path's operand precision "
+        << "(FP64 for SQC_F64, FP32 for the other paths)";
+      raise(SQC_E_ARG, m.str());
+    }
+  }
+  return any;
 }
 
 struct Contraction {
@@ -562,7 +588,9 @@ std::vector<int> degrees_match(const Graph &g, const sqc_tensor *t, int layout) 
       s << "tensor " << i << " has no data";
       raise(SQC_E_ARG, s.str());
     }
-    if (t[i].layout != layout) {
+    const bool ok = layout >= 0 ? t[i].layout == layout
+                                : (t[i].layout == SQC_LAYOUT_ATTRIBUTED || t[i].layout == SQC_LAYOUT_MERGED);
+    if (!ok) {
       s << "tensor " << i << " has the wrong layout";
       raise(SQC_E_SHAPE, s.str());
     }
@@ -660,11 +688,14 @@ Launches describe_recursion(const RecursePlan &rp, const sqc_tensor *att, sqc_pr
   std::vector<const void *> inputs(n_sub);
   const int path_f32 = prec != SQC_F64;
   Launches L;
-  L.merges.resize(n_sub);
   for (int i = 0; i < n_sub; ++i) {
+    if (att[i].layout == SQC_LAYOUT_MERGED) {  // (checked by check_merged_inputs)
+      inputs[i] = att[i].data;
+      continue;
+    }
     void *out = ws + rp.ml.merged_off[i];
-    L.merges[i] = merge_args(att[i], rp.masks[i], out, path_f32,
-                             reinterpret_cast<double *>(ws + rp.ml.partial_off[i]));
+    L.merges.push_back(merge_args(att[i], rp.masks[i], out, path_f32,
+                                  reinterpret_cast<double *>(ws + rp.ml.partial_off[i])));
     inputs[i] = out;
   }
   describe_contraction(L, rp.con, inputs, ws, unit2, rp.con_base, bins, bins_prec == SQC_F32, prec,
@@ -2077,7 +2108,7 @@ namespace {
 
 // Arguments of one subcircuit's attribution (validates the output tensor).
 AttrArgs attr_args(const Graph &g, int sub_id, const void *variants_dev, sqc_prec in_prec,
-                   const sqc_tensor *out) {
+                   const sqc_tensor *out, bool merged = false) {
   if (!variants_dev) raise(SQC_E_ARG, "variants_dev is NULL");
   if (!out || !out->data) raise(SQC_E_ARG, "out or out->data is NULL");
   check_storage_prec(in_prec, "in_prec");
@@ -2107,6 +2138,7 @@ AttrArgs attr_args(const Graph &g, int sub_id, const void *variants_dev, sqc_pre
   }
   for (int j = 0; j < s.d; ++j) a.data_wire[j] = s.data_wire[j];
   a.scale = std::ldexp(1.0, -a.n_out);
+  a.out_merged = merged ? 1 : 0;
   return a;
 }
 
@@ -2123,7 +2155,7 @@ double attr_bytes(const Graph &g, int sub_id, const AttrArgs &a, double *reads) 
 void finish_attr_out(const AttrArgs &a, sqc_tensor *out) {
   out->n_labels = a.c;
   out->n_bits = a.d;
-  out->layout = SQC_LAYOUT_ATTRIBUTED;
+  out->layout = a.out_merged ? SQC_LAYOUT_MERGED : SQC_LAYOUT_ATTRIBUTED;
 }
 
 }  // namespace
@@ -2147,16 +2179,17 @@ sqc_status sqc_attribute(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, int32
   SQC_CATCH(ctx)
 }
 
-sqc_status sqc_attribute_all(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, const sqc_cut *cuts,
-                             int32_t n_cuts, const void *const *variants_dev, sqc_prec in_prec,
-                             sqc_tensor *outs) {
+namespace {
+
+sqc_status attribute_all(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, const sqc_cut *cuts, int32_t n_cuts,
+                         const void *const *variants_dev, sqc_prec in_prec, sqc_tensor *outs, bool merged) {
   SQC_TRY(ctx)
   Graph g = build_graph(subs, n_sub, cuts, n_cuts);
   if (!variants_dev || !outs) raise(SQC_E_ARG, "NULL argument");
   std::vector<AttrArgs> jobs;
   double bytes = 0, reads = 0;
   for (int i = 0; i < n_sub; ++i) {
-    jobs.push_back(attr_args(g, i, variants_dev[i], in_prec, &outs[i]));
+    jobs.push_back(attr_args(g, i, variants_dev[i], in_prec, &outs[i], merged));
     bytes += attr_bytes(g, i, jobs.back(), &reads);
   }
   use_device(ctx);
@@ -2167,6 +2200,20 @@ sqc_status sqc_attribute_all(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, c
   for (int i = 0; i < n_sub; ++i) finish_attr_out(jobs[i], &outs[i]);
   return SQC_OK;
   SQC_CATCH(ctx)
+}
+
+}  // namespace
+
+sqc_status sqc_attribute_all(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, const sqc_cut *cuts,
+                             int32_t n_cuts, const void *const *variants_dev, sqc_prec in_prec,
+                             sqc_tensor *outs) {
+  return attribute_all(ctx, subs, n_sub, cuts, n_cuts, variants_dev, in_prec, outs, false);
+}
+
+sqc_status sqc_attribute_all_merged(sqc_ctx *ctx, const sqc_sub *subs, int32_t n_sub, const sqc_cut *cuts,
+                                    int32_t n_cuts, const void *const *variants_dev, sqc_prec in_prec,
+                                    sqc_tensor *outs) {
+  return attribute_all(ctx, subs, n_sub, cuts, n_cuts, variants_dev, in_prec, outs, true);
 }
 
 size_t sqc_merge_workspace_bytes(const sqc_tensor *attributed, const sqc_masks *masks) {
@@ -2374,12 +2421,18 @@ size_t sqc_recurse_workspace_bytes(const sqc_tensor *attributed, int32_t n_sub, 
   try {
     Graph g = build_topology(n_sub, cuts, n_cuts);
     if (!attributed || !masks) return 0;
-    degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+    degrees_match(g, attributed, -1);
     // the masks given fix the bin counts: use them as the scope with M large
     std::vector<int> abits(n_sub);
     for (int i = 0; i < n_sub; ++i) abits[i] = __builtin_popcountll(masks[i].active);
     const bool autop = prec == SQC_AUTO;
-    if (autop) prec = SQC_F64;  // the largest of the choices
+    if (autop) {
+      for (int i = 0; i < n_sub; ++i)
+        if (attributed[i].layout == SQC_LAYOUT_MERGED)
+          raise(SQC_E_ARG, "precision selection (SQC_AUTO) needs attributed tensors, not merged-layout ones");
+      prec = SQC_F64;  // the largest of the choices
+    }
+    check_merged_inputs(attributed, masks, n_sub, prec);
     Bump b;
     layout_merges(b, attributed, masks, n_sub, prec == SQC_F64 ? 8 : 4);
     Contraction c = plan_for(g, abits, prec);
@@ -2410,7 +2463,10 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
   if (prec == SQC_AUTO) {
     check_storage_prec(bins_prec, "bins_prec");
     if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
-    degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+    degrees_match(g, attributed, -1);
+    for (int i = 0; i < n_sub; ++i)
+      if (attributed[i].layout == SQC_LAYOUT_MERGED)
+        raise(SQC_E_ARG, "precision selection (SQC_AUTO) needs attributed tensors, not merged-layout ones");
     double B = 0.0;
     prec = select_precision(ctx, g, attributed, scope, max_bins_M, &B);
     ctx->auto_choice = prec;
@@ -2419,11 +2475,15 @@ sqc_status sqc_recurse(sqc_ctx *ctx, const sqc_tensor *attributed, int32_t n_sub
   check_path_prec(prec);
   check_storage_prec(bins_prec, "bins_prec");
   if (top_r < 1 || top_r > SQC_MAX_TOPR) raise(SQC_E_ARG, "top_r must be in [1, 64]");
-  degrees_match(g, attributed, SQC_LAYOUT_ATTRIBUTED);
+  degrees_match(g, attributed, -1);
   RecursePlan rp = plan_recursion(g, attributed, scope, max_bins_M, top_r, prec, ctx_plans(ctx));
+  const bool pre_merged = check_merged_inputs(attributed, rp.masks.data(), n_sub, prec);
   if (!ctx->ws) need_ws(ctx, rp.total);
   size_t need = 0;
   const std::vector<int> sl = choose_slices(g, attributed, rp, prec, top_r, ctx->ws_bytes, &need);
+  if (!sl.empty() && pre_merged)
+    raise(SQC_E_ARG, "the recursion needs slicing to fit the workspace, which merges label rows from attributed "
+                     "tensors; merged-layout inputs cannot be sliced");
   use_device(ctx);
   if (sl.empty())
     enqueue_recursion(ctx, rp, attributed, prec, bins_dev, bins_prec, top_r, topr_dev, sum_dev);

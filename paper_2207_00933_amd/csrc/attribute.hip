@@ -52,6 +52,7 @@ struct AttrJob {
   int in_f32, out_f32;
   int w, d, c, n_in, n_out, xt_bits;
   int vec8;                 // a thread's 8 entries are consecutive in memory
+  int out_merged;           // output [4^c][2^d] (see AttrArgs)
   int in_lab[kMaxIn];       // label bit position in sigma of in-cut j
   int out_place[kMaxOut];   // variant place value of out-cut j's basis
   int out_lab[kMaxOut];     // label bit position in sigma of out-cut j
@@ -95,7 +96,13 @@ __device__ __forceinline__ void attribute_lds_body(const AttrJob &a, int blk, un
   uint32_t *slot = sout + NB;                                         // [NV] its outcome bits
   const int lnxt = a.d - a.xt_bits;
   const int bidx = blk >> lnxt;
-  const int64_t x0 = int64_t(blk & ((1 << lnxt) - 1)) << a.xt_bits;
+  // tile of data states: in the merged layout a label's tiles are adjacent
+  // in memory, so the tiles of eight consecutive work-groups (the eight XCDs
+  // take work-groups in turn) are spread: XCD k writes tiles k n/8 .. (k + 1)
+  // n/8 - 1 of each label, and its partial lines meet in its own L2
+  int xtile = blk & ((1 << lnxt) - 1);
+  if (a.out_merged && lnxt >= 3) xtile = ((xtile & 7) << (lnxt - 3)) | (xtile >> 3);
+  const int64_t x0 = int64_t(xtile) << a.xt_bits;
 
   // basis digits of this work-group: out-cut j measured in basis dig[j]
   // (Z = 0, X = 1, Y = 2)
@@ -299,14 +306,24 @@ __device__ __forceinline__ void attribute_lds_body(const AttrJob &a, int blk, un
   const int lst = 1 << (2 * jd + a.xt_bits + a.n_out);
 
   // every label assignment compatible with beta: q = (xt, v, s), s fastest
+  // ([2^d][4^c]: consecutive threads write consecutive labels), or
+  // q = (v, s, xt), xt fastest, in the merged layout
   const int lNS = 2 * a.n_in;
   const int64_t L = int64_t(1) << (2 * a.c);
   const int nq = (XT * NV) << lNS;
   for (int q = tid; q < nq; q += kThreads) {
-    const int sdx = q & (NS - 1);
-    const int rest = q >> lNS;
-    const int vv = rest & (NV - 1);
-    const int xt = rest >> nz;
+    int sdx, vv, xt;
+    if (a.out_merged) {
+      xt = q & (XT - 1);
+      const int rest = q >> a.xt_bits;
+      sdx = rest & (NS - 1);
+      vv = rest >> lNS;
+    } else {
+      sdx = q & (NS - 1);
+      const int rest = q >> lNS;
+      vv = rest & (NV - 1);
+      xt = rest >> nz;
+    }
     const int eo = (sdx * XT + xt) * NB + slot[vv];
     double val;
     if (lazy) {
@@ -320,7 +337,8 @@ __device__ __forceinline__ void attribute_lds_body(const AttrJob &a, int blk, un
       val = buf[phys(eo)];
     }
     val *= a.scale;
-    const int64_t o = (x0 + xt) * L + (sinl[sdx] | sout[vv]);
+    const int64_t lab = (int64_t)(sinl[sdx] | sout[vv]);
+    const int64_t o = a.out_merged ? (lab << a.d) + (x0 + xt) : (x0 + xt) * L + lab;
     if constexpr (OUT_F32) __builtin_nontemporal_store((float)val, static_cast<float *>(a.out) + o);
     else static_cast<double *>(a.out)[o] = val;
   }
@@ -364,6 +382,7 @@ AttrJob attr_job(const AttrArgs &a) {
   J.scale = a.scale;
   J.in_f32 = a.in_f32;
   J.out_f32 = a.out_f32;
+  J.out_merged = a.out_merged;
   J.w = a.w;
   J.d = a.d;
   J.c = a.c;
@@ -411,8 +430,9 @@ __global__ __launch_bounds__(kThreads) void attribute_direct(AttrArgs a) {
   const double C[4][4] = {{1, 1, 0, 0}, {-1, -1, 2, 0}, {-1, -1, 0, 2}, {1, -1, 0, 0}};
   for (int64_t o = int64_t(blockIdx.x) * kThreads + threadIdx.x; o < total;
        o += int64_t(gridDim.x) * kThreads) {
-    int64_t x = o >> (2 * a.c);
-    int64_t sigma = o & (L - 1);
+    // o runs over the output layout: [2^d][4^c], or [4^c][2^d] when merged
+    const int64_t x = a.out_merged ? o & ((int64_t(1) << a.d) - 1) : o >> (2 * a.c);
+    const int64_t sigma = a.out_merged ? o >> a.d : o & (L - 1);
     int64_t xo = 0;
     for (int j = 0; j < a.d; ++j)
       if ((x >> j) & 1) xo |= int64_t(1) << a.data_wire[j];

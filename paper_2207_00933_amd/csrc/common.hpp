@@ -123,7 +123,7 @@ constexpr int kMaxIncident = SQC_MAX_DEGREE;
 
 struct AttrArgs {
   const void *var;   // [V][2^w]
-  void *out;         // [2^d][4^c]
+  void *out;         // [2^d][4^c], or [4^c][2^d] when out_merged
   int in_f32, out_f32;
   int w, d, c;
   int n_in, n_out;
@@ -134,6 +134,10 @@ struct AttrArgs {
   int out_wire[kMaxIncident];  // wire of the j-th out-cut
   int data_wire[64];
   double scale;                // 2^-n_out
+  // 1: written in the merged layout of a recursion that keeps every data bit
+  // active ([4^c][2^d], bins fastest): the attribution and that recursion's
+  // merge (a transposition) in one pass
+  int out_merged;
 };
 // Enqueue the attribution of n subcircuits (those that fit the LDS stage
 // share launches of up to kAttrJobs jobs).

@@ -70,14 +70,15 @@ class Circuit:
     def from_cut_circuit(cls, session: Session, cc, variants, var_prec: int = sqc.F64):
         return cls(session, sqc.Graph.from_cut_circuit(cc), variants, var_prec)
 
-    def attribute(self, out_prec: int = sqc.F64) -> List[sqc.Tensor]:
+    def attribute(self, out_prec: int = sqc.F64, merged: bool = False) -> List[sqc.Tensor]:
         """Attribute every subcircuit (subcircuits that fit the on-chip stage
-        share one launch)."""
+        share one launch); merged=True writes the merged layout of a
+        full-output recursion instead (sqc_attribute_all_merged)."""
         if len(self.att_buf) != self.g.n_sub or self.att[0].prec != out_prec:
             self.att_buf = [_bytes_tensor(sqc.attribute_bytes(self.g, i, out_prec), self.s.device)
                             for i in range(self.g.n_sub)]
-        self.att = sqc.attribute_all(self.s.ctx, self.g, self.var, self.var_prec, self.att_buf,
-                                     out_prec)
+        fn = sqc.attribute_all_merged if merged else sqc.attribute_all
+        self.att = fn(self.s.ctx, self.g, self.var, self.var_prec, self.att_buf, out_prec)
         return self.att
 
     def attributed_numpy(self, i: int) -> np.ndarray:
@@ -85,8 +86,10 @@ class Circuit:
         t = self.att[i]
         n = (1 << t.n_bits) << (2 * t.n_labels)
         dt = _TORCH_DTYPE[t.prec]
-        x = self.att_buf[i][: n * (8 if t.prec == sqc.F64 else 4)].view(dt)
-        return x.double().cpu().numpy().reshape(1 << t.n_bits, 1 << (2 * t.n_labels))
+        x = self.att_buf[i][: n * (8 if t.prec == sqc.F64 else 4)].view(dt).double().cpu().numpy()
+        if t.layout == sqc.LAYOUT_MERGED:  # [4^c][2^d]
+            return x.reshape(1 << (2 * t.n_labels), 1 << t.n_bits).T.copy()
+        return x.reshape(1 << t.n_bits, 1 << (2 * t.n_labels))
 
 
 class Recursion:
@@ -108,7 +111,7 @@ class Recursion:
         # scope, M and precision: planning is host work)
         key = (prec, M, None if scope is None else tuple(sqc.masks_array(scope)[i].as_tuple()
                                                          for i in range(len(scope))),
-               tuple((t.prec, t.n_bits, t.n_labels) for t in c.att))
+               tuple((t.prec, t.n_bits, t.n_labels, t.layout) for t in c.att))
         need = self._ws.get(key)
         if need is None:
             masks = sqc.assign_bins(c.g.n_data, scope, M)

@@ -145,6 +145,8 @@ def lib():
                                       P, c_int, POINTER(Tensor)]),
             "sqc_attribute_all": (c_int, [P, POINTER(Sub), c_int32, POINTER(Cut), c_int32,
                                           POINTER(c_void_p), c_int, POINTER(Tensor)]),
+            "sqc_attribute_all_merged": (c_int, [P, POINTER(Sub), c_int32, POINTER(Cut), c_int32,
+                                                 POINTER(c_void_p), c_int, POINTER(Tensor)]),
             "sqc_merge_workspace_bytes": (c_size_t, [POINTER(Tensor), POINTER(Masks)]),
             "sqc_merge": (c_int, [P, POINTER(Tensor), POINTER(Masks), POINTER(Tensor)]),
             "sqc_contract_workspace_bytes": (c_size_t, [POINTER(Tensor), c_int32, POINTER(Cut),
@@ -410,6 +412,19 @@ def attribute_all(ctx: int, g: Graph, variants, in_prec: int, outs, out_prec: in
         arr[i].data = _ptr(outs[i])
         arr[i].prec = out_prec
     _check(lib().sqc_attribute_all(ctx, g.subs, n, g.cuts, g.n_cuts, vp, in_prec, arr), ctx)
+    return list(arr)
+
+
+def attribute_all_merged(ctx: int, g: Graph, variants, in_prec: int, outs, out_prec: int) -> List[Tensor]:
+    """sqc_attribute_all_merged: every subcircuit attributed straight into
+    the merged layout of a recursion that keeps all its data bits active."""
+    n = g.n_sub
+    vp = (c_void_p * n)(*[_ptr(v) for v in variants])
+    arr = (Tensor * n)()
+    for i in range(n):
+        arr[i].data = _ptr(outs[i])
+        arr[i].prec = out_prec
+    _check(lib().sqc_attribute_all_merged(ctx, g.subs, n, g.cuts, g.n_cuts, vp, in_prec, arr), ctx)
     return list(arr)
 
 
