@@ -339,8 +339,14 @@ __device__ __forceinline__ void attribute_lds_body(const AttrJob &a, int blk, un
     val *= a.scale;
     const int64_t lab = (int64_t)(sinl[sdx] | sout[vv]);
     const int64_t o = a.out_merged ? (lab << a.d) + (x0 + xt) : (x0 + xt) * L + lab;
-    if constexpr (OUT_F32) __builtin_nontemporal_store((float)val, static_cast<float *>(a.out) + o);
-    else static_cast<double *>(a.out)[o] = val;
+    // the merged layout's runs per work-group are short (XT states), so its
+    // stores go through L2, where neighbouring work-groups' runs meet
+    if constexpr (OUT_F32) {
+      if (a.out_merged) static_cast<float *>(a.out)[o] = (float)val;
+      else __builtin_nontemporal_store((float)val, static_cast<float *>(a.out) + o);
+    } else {
+      static_cast<double *>(a.out)[o] = val;
+    }
   }
 }
 
