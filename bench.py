@@ -131,7 +131,7 @@ def run_gpu(cc, var32, steps: int, warmup: int, precs, autotune: bool = True, gr
         return _run_gpu(cc, var32, steps, warmup, precs, autotune, graph, check)
 
 
-FINAL_EVERY = 4  # steps per final-contraction launch timed with dispatch events
+FINAL_EVERY = 16  # steps per final-contraction launch timed with dispatch events
 
 
 def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph, check):
@@ -214,7 +214,8 @@ def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph, check):
         t0 = time.perf_counter()
         timed = sqc.STAGE_FINAL | sqc.STAGE_CONTRACT
         for k in range(steps):
-            sqc.ctx_set_timing(s.ctx, timed if k % FINAL_EVERY == 0 else 0)
+            if k % FINAL_EVERY < 2:  # switched on for one step, then off
+                sqc.ctx_set_timing(s.ctx, timed if k % FINAL_EVERY == 0 else 0)
             step()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -237,7 +238,8 @@ def _run_gpu(cc, var32, steps, warmup, precs, autotune, graph, check):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
-            sqc.ctx_set_timing(s.ctx, timed if k % FINAL_EVERY == 0 else 0)
+            if k % FINAL_EVERY < 2:
+                sqc.ctx_set_timing(s.ctx, timed if k % FINAL_EVERY == 0 else 0)
             step(merged=False)
         torch.cuda.synchronize()
         ums = (time.perf_counter() - t0) * 1e3 / steps
@@ -739,7 +741,7 @@ def run_serving(n_req: int, slots: int, seed: int = 4, load: float = 0.7):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU work per worker for the oracle baseline")
