@@ -9,12 +9,14 @@ HBM: attribution of the three subcircuits, bin assignment, merge, the
 pairwise contraction into all 2^24 bins, the top-R bins and the FP64 bin sum.
 
 The step is timed for three contraction precisions (FP64 plain, FP32 MFMA,
-split-BF16x3 with an FP64-compensated final sum); ``value`` is the faster of
-the two fast forms, whose bins are also compared with the FP64 GPU path.
-The final contraction kernel of every fourth step, and the contraction step
-before it, are launched with HIP events recorded by their dispatch inside the
-timed loop (the final kernel's live duration, for the roofline fraction); per-step latencies (p50 / p99) come from a separate pass
-with an event per step, since per-step events cost several microseconds.  The CPU baseline is the FP64 oracle
+split-BF16x3 with an FP64-compensated final sum); ``value`` is the path the
+precision selector picks at the 1e-6 tolerance, and the fast paths' bins are
+also compared with the FP64 GPU path.  The final contraction kernel of every
+sixteenth step, and the contraction step before it, are launched with HIP
+events recorded by their dispatch inside the timed loop (the final kernel's
+live duration, for the roofline fraction); per-step latencies (p50 / p99)
+come from a separate pass with an event per step, since per-step events cost
+several microseconds.  The CPU baseline is the FP64 oracle
 (Eq. 1 evaluated bin by bin) on a bounded sample of bins, timed on the host's
 cores before the GPU is touched.
 
